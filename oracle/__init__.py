@@ -1,0 +1,386 @@
+"""FP64 CPU oracle of the dense registration objective (test infrastructure only).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark may
+import this package.  It never imports the GPU library and the GPU library never
+imports it; both receive the same seeded inputs from ``synth``.
+
+The element-wise work is in ``disco_oracle.c`` (plain loops, double precision).
+This module composes the joint objective (eq. 11 with beta = 0)
+
+    J(u) = D(u) + alpha S(u) + gamma Vhat(u) + delta K(u)
+
+its gradient, the Gauss-Newton matrix-vector product, the adaptive keypoint weight
+(Sec. II-D2: delta such that D = delta K at the start), and one Gauss-Newton step
+with a Jacobi-preconditioned CG solve and Armijo backtracking.
+
+Arrays: volumes float32 [Nz][Ny][Nx]; node fields [3][nz][ny][nx] (converted to
+float64 here); keypoints [n][3] in mm.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "disco_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "libdisco_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (double precision, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        D = ctypes.c_double
+        lib.or_image_gradient.argtypes = [P, P, P, P]
+        lib.or_image_gradient.restype = None
+        lib.or_sample_points.argtypes = [P, P, P, I64, P, P, P]
+        lib.or_sample_points.restype = None
+        lib.or_ngf.argtypes = [P, P, P, D, P, P, P, P, P, P, P, P]
+        lib.or_ngf.restype = D
+        lib.or_ngf_hv.argtypes = [P, P, P, P, P, P]
+        lib.or_ngf_hv.restype = None
+        lib.or_curvature.argtypes = [P, P, P, P, P]
+        lib.or_curvature.restype = D
+        lib.or_vcc.argtypes = [P, P, P, P, P, P, P, P, P]
+        lib.or_vcc.restype = D
+        lib.or_vcc_cell_expansion.argtypes = [P, P, P, P, P, P, P, P]
+        lib.or_vcc_cell_expansion.restype = None
+        lib.or_keypoints.argtypes = [P, P, I64, P, P, P, P, P, P, P]
+        lib.or_keypoints.restype = D
+        lib.or_det_voxels.argtypes = [P, P, P, P, P]
+        lib.or_det_voxels.restype = None
+        _lib = lib
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _i64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.int64))
+
+
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _f32(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+
+
+# ------------------------------------------------------------------------------------
+# element functions
+# ------------------------------------------------------------------------------------
+
+def image_gradient(img: np.ndarray, spacing) -> np.ndarray:
+    """Central-difference gradient with replicated border, [Nz][Ny][Nx][3] float64."""
+    img = _f32(img)
+    nz, ny, nx = img.shape
+    out = np.empty((nz, ny, nx, 3), np.float64)
+    _load().or_image_gradient(_p(_i64([nx, ny, nz])), _p(_f64(spacing)), _p(img), _p(out))
+    return out
+
+
+def sample_points(grad: np.ndarray, spacing, q: np.ndarray):
+    """Trilinear, zero-padded sampling of a [Nz][Ny][Nx][3] field at continuous voxel
+    indices q ([n][3], x,y,z order).  Returns (G [n][3], JG [n][3][3] = dG_c/dy_a)."""
+    grad = _f64(grad)
+    nz, ny, nx, _ = grad.shape
+    q = _f64(q).reshape(-1, 3)
+    G = np.empty((len(q), 3))
+    JG = np.empty((len(q), 3, 3))
+    _load().or_sample_points(_p(_i64([nx, ny, nz])), _p(_f64(spacing)), _p(grad), len(q), _p(q), _p(G), _p(JG))
+    return G, JG
+
+
+def node_shape(shape):
+    return tuple(int(s) // 4 + 1 for s in shape)
+
+
+def ngf(gR, gT, spacing, eta, u, m=(4, 4, 4), want=("g", "diag", "s", "r", "c")):
+    """NGF distance (eq. 1) and its derivatives.  Returns dict with D and the requested
+    arrays (g, diag: node fields; s: [N][3]; r, c: [N])."""
+    gR = _f64(gR)
+    gT = _f64(gT)
+    nz, ny, nx, _ = gR.shape
+    n = _i64([nx, ny, nz])
+    mm = _i64(m)
+    nn = [nx // m[0] + 1, ny // m[1] + 1, nz // m[2] + 1]
+    u = _f64(u)
+    assert u.shape == (3, nn[2], nn[1], nn[0]), (u.shape, nn)
+    g = np.empty((3, nn[2], nn[1], nn[0])) if "g" in want else None
+    diag = np.empty((3, nn[2], nn[1], nn[0])) if "diag" in want else None
+    s = np.empty((nz, ny, nx, 3)) if "s" in want else None
+    r = np.empty((nz, ny, nx)) if "r" in want else None
+    c = np.empty((nz, ny, nx)) if "c" in want else None
+    D = _load().or_ngf(_p(n), _p(_f64(spacing)), _p(mm), float(eta), _p(gR), _p(gT), _p(u),
+                       _p(g), _p(diag), _p(s), _p(r), _p(c))
+    return dict(D=D, g=g, diag=diag, s=s, r=r, c=c)
+
+
+def ngf_hv(s, spacing, v, m=(4, 4, 4)):
+    """Gauss-Newton product of the NGF term with the per-voxel vectors s."""
+    s = _f64(s)
+    nz, ny, nx, _ = s.shape
+    nn = [nx // m[0] + 1, ny // m[1] + 1, nz // m[2] + 1]
+    v = _f64(v)
+    out = np.empty((3, nn[2], nn[1], nn[0]))
+    _load().or_ngf_hv(_p(_i64([nx, ny, nz])), _p(_f64(spacing)), _p(_i64(m)), _p(s), _p(v), _p(out))
+    return out
+
+
+def curvature(w, H):
+    """S(w) (eq. 5 on the node grid), C_H L^T L w, C_H diag(L^T L)."""
+    w = _f64(w)
+    _, nz, ny, nx = w.shape
+    out = np.empty_like(w)
+    diag = np.empty_like(w)
+    S = _load().or_curvature(_p(_i64([nx, ny, nz])), _p(_f64(H)), _p(w), _p(out), _p(diag))
+    return dict(S=S, g=out, diag=diag)
+
+
+def vcc(u, H, v=None):
+    """Vhat (eq. 9), its gradient, GN diagonal, optional GN product, fold count, d range."""
+    u = _f64(u)
+    _, nz, ny, nx = u.shape
+    g = np.empty_like(u)
+    diag = np.empty_like(u)
+    Hv = np.empty_like(u) if v is not None else None
+    nfold = np.zeros(1, np.int64)
+    dmm = np.zeros(2)
+    V = _load().or_vcc(_p(_i64([nx, ny, nz])), _p(_f64(H)), _p(u), _p(None if v is None else _f64(v)),
+                       _p(g), _p(diag), _p(Hv), _p(nfold), _p(dmm))
+    return dict(V=V, g=g, diag=diag, Hv=Hv, nfold=int(nfold[0]), dmin=dmm[0], dmax=dmm[1])
+
+
+def vcc_cell_expansion(u, H, cell, xi):
+    """(alpha[64], d[64], exact det grad y) of one cell at local coordinate xi."""
+    u = _f64(u)
+    _, nz, ny, nx = u.shape
+    alpha = np.empty(64)
+    d = np.empty(64)
+    det = np.zeros(1)
+    _load().or_vcc_cell_expansion(_p(_i64([nx, ny, nz])), _p(_f64(H)), _p(u), _p(_i64(cell)), _p(_f64(xi)),
+                                  _p(alpha), _p(d), _p(det))
+    return alpha, d, float(det[0])
+
+
+def keypoints(u, H, x, t, v=None):
+    """K (eq. 10), 2 P^T res, diag 2 P^T P, optional 2 P^T P v."""
+    u = _f64(u)
+    _, nz, ny, nx = u.shape
+    x = _f64(x).reshape(-1, 3)
+    t = _f64(t).reshape(-1, 3)
+    g = np.empty_like(u)
+    diag = np.empty_like(u)
+    Hv = np.empty_like(u) if v is not None else None
+    K = _load().or_keypoints(_p(_i64([nx, ny, nz])), _p(_f64(H)), len(x), _p(x), _p(t), _p(u),
+                             _p(None if v is None else _f64(v)), _p(g), _p(diag), _p(Hv))
+    if np.isnan(K):
+        raise ValueError("keypoint outside the image domain")
+    return dict(K=K, g=g, diag=diag, Hv=Hv)
+
+
+def det_voxels(u, spacing, shape, m=(4, 4, 4)):
+    """Exact det(grad y) at every voxel centre (diagnostic)."""
+    nx, ny, nz = shape
+    out = np.empty((nz, ny, nx))
+    _load().or_det_voxels(_p(_i64([nx, ny, nz])), _p(_i64(m)), _p(_f64(spacing)), _p(_f64(u)), _p(out))
+    return out
+
+
+# ------------------------------------------------------------------------------------
+# composite problem: eq. 11 with beta = 0
+# ------------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Weights:
+    eta: float = 10.0
+    alpha: float = 1.0
+    gamma: float = 0.1
+    delta: float = 0.0
+
+
+class Problem:
+    """One registration pair: J(u) = D + alpha S + gamma Vhat + delta K."""
+
+    def __init__(self, R, T, spacing, kp_x=None, kp_t=None, weights: Weights = Weights(),
+                 u_ref=None, m=(4, 4, 4)):
+        self.spacing = tuple(float(s) for s in spacing)
+        self.m = tuple(int(a) for a in m)
+        self.shape = (R.shape[2], R.shape[1], R.shape[0])
+        self.H = tuple(self.spacing[a] * self.m[a] for a in range(3))
+        self.gR = image_gradient(R, self.spacing)
+        self.gT = image_gradient(T, self.spacing)
+        self.kp_x = None if kp_x is None else _f64(kp_x).reshape(-1, 3)
+        self.kp_t = None if kp_t is None else _f64(kp_t).reshape(-1, 3)
+        self.w = dataclasses.replace(weights)
+        nn = node_shape(self.shape)
+        self.nodes = nn
+        self.u_ref = np.zeros((3, nn[2], nn[1], nn[0])) if u_ref is None else _f64(u_ref)
+        self._s = None
+
+    # individual terms ---------------------------------------------------------------
+    def ngf(self, u, want=("g", "diag", "s", "r", "c")):
+        return ngf(self.gR, self.gT, self.spacing, self.w.eta, u, self.m, want)
+
+    def curvature(self, u):
+        return curvature(_f64(u) - self.u_ref, self.H)
+
+    def vcc(self, u, v=None):
+        return vcc(u, self.H, v)
+
+    def keypoints(self, u, v=None):
+        if self.kp_x is None or len(self.kp_x) == 0:
+            z = np.zeros_like(_f64(u))
+            return dict(K=0.0, g=z, diag=z.copy(), Hv=None if v is None else z.copy())
+        return keypoints(u, self.H, self.kp_x, self.kp_t, v)
+
+    def adaptive_delta(self, u0):
+        """delta such that D = delta K at the start of the registration (Sec. II-D2)."""
+        D = self.ngf(u0, want=())["D"]
+        K = self.keypoints(u0)["K"]
+        return D / K if K > 0 else 0.0
+
+    # joint objective -----------------------------------------------------------------
+    def objective(self, u):
+        """Terms and total of eq. 11 (beta = 0); total is +inf on a fold."""
+        w = self.w
+        D = self.ngf(u, want=())["D"]
+        S = self.curvature(u)["S"]
+        vc = self.vcc(u)
+        K = self.keypoints(u)["K"]
+        # Vhat = +inf on a fold (eq. 9); the term only exists when gamma > 0
+        folded = vc["nfold"] > 0 and w.gamma != 0.0
+        vterm = w.gamma * vc["V"] if w.gamma != 0.0 else 0.0
+        J = np.inf if folded else D + w.alpha * S + vterm + w.delta * K
+        return dict(J=J, D=D, S=S, V=vc["V"], K=K, nfold=vc["nfold"])
+
+    def linearise(self, u):
+        """Objective, gradient and GN diagonal at u; keeps s for gn_hv."""
+        w = self.w
+        nd = self.ngf(u, want=("g", "diag", "s"))
+        cv = self.curvature(u)
+        vc = self.vcc(u)
+        kp = self.keypoints(u)
+        self._s = nd["s"]
+        self._u = _f64(u).copy()
+        g = nd["g"] + w.alpha * cv["g"] + w.delta * kp["g"]
+        diag = nd["diag"] + w.alpha * cv["diag"] + w.delta * kp["diag"]
+        if w.gamma != 0.0:
+            g = g + w.gamma * vc["g"]
+            diag = diag + w.gamma * vc["diag"]
+        folded = vc["nfold"] > 0 and w.gamma != 0.0
+        vterm = w.gamma * vc["V"] if w.gamma != 0.0 else 0.0
+        J = np.inf if folded else nd["D"] + w.alpha * cv["S"] + vterm + w.delta * kp["K"]
+        return dict(J=J, D=nd["D"], S=cv["S"], V=vc["V"], K=kp["K"], nfold=vc["nfold"], g=g, diag=diag)
+
+    def gn_hv(self, v, terms=("D", "S", "V", "K")):
+        """Gauss-Newton matrix of eq. 11 times v, at the last linearisation point."""
+        assert self._s is not None, "call linearise first"
+        w = self.w
+        v = _f64(v)
+        out = np.zeros_like(v)
+        if "D" in terms:
+            out += ngf_hv(self._s, self.spacing, v, self.m)
+        if "S" in terms and w.alpha != 0.0:
+            out += w.alpha * curvature(v, self.H)["g"]
+        if "V" in terms and w.gamma != 0.0:
+            out += w.gamma * vcc(self._u, self.H, v)["Hv"]
+        if "K" in terms and w.delta != 0.0:
+            out += w.delta * self.keypoints(self._u, v)["Hv"]
+        return out
+
+
+# ------------------------------------------------------------------------------------
+# one Gauss-Newton step: Jacobi-PCG on H p = -g, then Armijo backtracking
+# ------------------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class StepParams:
+    pcg_iters: int = 20
+    pcg_tol: float = 0.0          # stop when |r| <= tol |g| (0: run all iterations)
+    ls_max: int = 10
+    armijo_c1: float = 1e-4
+    tau: float = 0.0              # optional damping tau I added to the GN matrix
+
+
+def pcg(hv, b, diag, iters, tol=0.0, tau=0.0):
+    """Jacobi-preconditioned CG for (H + tau I) x = b from x0 = 0.
+
+    Preconditioner M = diag(H) + tau + 1e-12 max(diag(H)).  Stops after `iters`
+    iterations, when |r| <= tol |b|, or when p^T H p <= 0 (breakdown)."""
+    M = diag + tau + 1e-12 * float(np.max(diag))
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = r / M
+    p = z.copy()
+    rz = float(np.sum(r * z))
+    bnorm = float(np.sqrt(np.sum(b * b)))
+    hist = []
+    breakdown = False
+    it = 0
+    while it < iters:
+        q = hv(p) + tau * p
+        pq = float(np.sum(p * q))
+        if not pq > 0.0:
+            breakdown = True
+            break
+        a = rz / pq
+        x = x + a * p
+        r = r - a * q
+        it += 1
+        rn = float(np.sqrt(np.sum(r * r)))
+        hist.append(rn)
+        if tol > 0.0 and rn <= tol * bnorm:
+            break
+        z = r / M
+        rz_new = float(np.sum(r * z))
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, dict(iters=it, breakdown=breakdown, res=hist)
+
+
+def gn_pcg_step(prob: Problem, u, params: StepParams = StepParams()):
+    """One GN step: linearise, solve H p = -g by Jacobi-PCG, Armijo line search on
+    t in {1, 1/2, ...} rejecting folded trial points.  Returns (u_new, report)."""
+    lin = prob.linearise(u)
+    g = lin["g"]
+    p, info = pcg(lambda v: prob.gn_hv(v), -g, lin["diag"], params.pcg_iters, params.pcg_tol, params.tau)
+    gtp = float(np.sum(g * p))
+    t = 1.0
+    accepted = False
+    trial = None
+    for _ in range(params.ls_max):
+        trial = prob.objective(_f64(u) + t * p)
+        if np.isfinite(trial["J"]) and trial["J"] <= lin["J"] + params.armijo_c1 * t * gtp:
+            accepted = True
+            break
+        t *= 0.5
+    u_new = _f64(u) + t * p if accepted else _f64(u).copy()
+    rep = dict(J=lin["J"], D=lin["D"], S=lin["S"], V=lin["V"], K=lin["K"],
+               gnorm=float(np.sqrt(np.sum(g * g))), t=t if accepted else 0.0, accepted=accepted,
+               p=p, gtp=gtp, pcg=info, trial=trial, g=g, diag=lin["diag"])
+    return u_new, rep
