@@ -1,0 +1,201 @@
+/*
+ * disco.h — C ABI of the MI355X (gfx950) library for the dense registration objective
+ * of Ruehaak et al., "Estimation of Large Motion in Lung CT by Integrating Regularized
+ * Keypoint Correspondences into Dense Deformable Registration" (arXiv 1807.00467).
+ *
+ * The library evaluates the joint objective of eq. 11 without the lung-boundary term,
+ *     J(u) = D(u) + alpha S(u) + gamma Vhat(u) + delta K(u),
+ * its gradient with respect to the control-grid displacement u, and matrix-free
+ * Gauss-Newton products, and runs one Gauss-Newton step (Jacobi-preconditioned CG plus
+ * Armijo backtracking).  The paper obtains the same quantities with matrix-free
+ * derivative rules (Sec. II-D, II-D3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Volumes have N = (Nx, Ny, Nz) voxels (x fastest) of spacing h = (hx, hy, hz) mm and
+ *   are float32 arrays [Nz][Ny][Nx].  Voxel (i,j,k) has its centre at ((i+1/2)hx, ...).
+ * - The deformation is y(x) = x + u(x), u trilinear (first-order B-spline) on a node
+ *   grid with 4 voxels per cell and axis (Sec. II-D1, II-D3): n_a = N_a/4 + 1 nodes per
+ *   axis at p * 4 h_a.  Every N_a must be a positive multiple of 4.
+ * - Node fields (u, v, gradients, diagonals, Hv) are float32 SoA [3][nz][ny][nx]
+ *   (component x, then y, then z), in mm (or the matching derived unit).
+ * - All array arguments are DEVICE pointers on the context's device, owned by the
+ *   caller, 4-byte aligned, not aliased with each other unless stated, and must stay
+ *   valid until the work queued on the stream has finished.  Exceptions (host
+ *   pointers) are stated per call.
+ * - Scalar results (double, int32_t) are written to DEVICE memory so that calls can be
+ *   recorded in a HIP graph; nothing synchronises the stream unless stated.
+ * - `stream` is a hipStream_t (NULL = the null stream).  One context per stream at a
+ *   time; a context is not thread safe.
+ * - Return value: DISCO_OK or a negative error code detected on the host before any
+ *   work is queued (nothing is written then), or DISCO_ERR_HIP - hipError_t when a HIP
+ *   call failed.  Numerical outcomes (fold, CG breakdown, line-search failure) are
+ *   reported through device status words, never through the return value.
+ */
+#ifndef DISCO_H
+#define DISCO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* host-detected errors */
+#define DISCO_OK 0
+#define DISCO_ERR_ARG (-1)       /* null pointer, bad enum, bad count */
+#define DISCO_ERR_SHAPE (-2)     /* N_a not a positive multiple of 4, keypoint outside the box, misaligned pointer */
+#define DISCO_ERR_STATE (-3)     /* images not set, or ngf_hessvec / gn_hessvec before a linearisation */
+#define DISCO_ERR_NONFINITE (-4) /* a scalar parameter is NaN/inf or out of its range */
+#define DISCO_ERR_NOMEM (-5)     /* device allocation failed */
+#define DISCO_ERR_HIP (-100)     /* returned as DISCO_ERR_HIP - (int)hipError_t */
+
+/* numerical status bits (device int32 status words) */
+#define DISCO_STATUS_FOLD 1          /* some coefficient d of eq. 8 is <= 0: Vhat = +inf (eq. 9) */
+#define DISCO_STATUS_PCG_BREAKDOWN 2 /* p^T H p <= 0 in the CG solve */
+#define DISCO_STATUS_LS_FAIL 4       /* no Armijo step accepted within ls_max trials */
+
+/* storage of the image-gradient volumes and of the per-voxel GN vectors */
+#define DISCO_STORAGE_FP32 0
+#define DISCO_STORAGE_FP16 1 /* half precision with a per-volume power-of-two scale */
+
+/* gn_pcg_step flags */
+#define DISCO_FLAG_LS_DEVICE 1 /* line search fully on the device (fixed ls_max trials, graph capturable) */
+
+/* which buffer disco_copy_buffer copies */
+#define DISCO_BUF_GRAD_R 0 /* grad R, float32 [Nz][Ny][Nx][3] */
+#define DISCO_BUF_GRAD_T 1 /* grad T, float32 [Nz][Ny][Nx][3] */
+#define DISCO_BUF_SCACHE 2 /* s_v of the last linearisation, float32 [Nz][Ny][Nx][3] */
+
+/* slots of the report written by gn_pcg_step (doubles) */
+#define DISCO_REP_J 0        /* J(u) at the start of the step */
+#define DISCO_REP_D 1
+#define DISCO_REP_S 2
+#define DISCO_REP_V 3
+#define DISCO_REP_K 4
+#define DISCO_REP_GNORM 5    /* |grad J(u)| */
+#define DISCO_REP_T 6        /* accepted step length (0 if none) */
+#define DISCO_REP_PCG_ITERS 7
+#define DISCO_REP_PCG_RES 8  /* final CG residual norm */
+#define DISCO_REP_GTP 9      /* g^T p */
+#define DISCO_REP_J_NEW 10   /* J at the accepted point (or last trial) */
+#define DISCO_REP_D_NEW 11
+#define DISCO_REP_S_NEW 12
+#define DISCO_REP_V_NEW 13
+#define DISCO_REP_K_NEW 14
+#define DISCO_REP_LS_TRIALS 15
+#define DISCO_REP_SIZE 16
+
+typedef struct {
+    int32_t n[3]; /* voxels Nx, Ny, Nz (multiples of 4) */
+    double h[3];  /* spacing in mm */
+} disco_geom;
+
+typedef struct {
+    double eta;       /* NGF edge parameter (eq. 1), HU/mm, > 0 */
+    double alpha;     /* curvature weight (eq. 11), >= 0 */
+    double gamma;     /* volume-change weight (eq. 11), >= 0 */
+    double delta;     /* keypoint weight (eq. 11), >= 0 */
+    double tau;       /* optional damping tau I added to the GN matrix, >= 0 */
+    double armijo_c1; /* Armijo constant, in (0, 1) */
+    double pcg_tol;   /* stop CG when |r| <= pcg_tol |g| (0: run pcg_iters) */
+    int32_t pcg_iters; /* CG iterations, >= 1 */
+    int32_t ls_max;    /* maximum number of line-search trials (t = 1, 1/2, ...), >= 1 */
+    int32_t flags;     /* DISCO_FLAG_* */
+} disco_params;
+
+typedef struct disco_ctx disco_ctx;
+typedef void *disco_stream; /* hipStream_t */
+
+/* Create a context for one image pair geometry on the current HIP device.  storage is
+   DISCO_STORAGE_FP32 or DISCO_STORAGE_FP16.  Allocates the derived volumes (grad R,
+   grad T, per-voxel GN vectors: 3 x 12 B per voxel in FP32, 3 x 6 B in FP16) and small
+   workspaces.  *out receives the context (NULL on error). */
+int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out);
+
+/* Free a context (synchronises the device first).  NULL is ignored. */
+void disco_destroy(disco_ctx *ctx);
+
+/* Set the fixed image R and moving image T (device float32 [Nz][Ny][Nx]) and build
+   their central-difference gradient volumes with replicated borders (the gradients of
+   eq. 1).  Invalidates the linearisation. */
+int disco_set_images(disco_ctx *ctx, const float *R, const float *T, disco_stream stream);
+
+/* Set n keypoints x_i and targets y_KP(x_i) of eq. 10 (HOST float32 [n][3], mm).  Every
+   x_i must lie in the closed box [0, N_a h_a] (else DISCO_ERR_SHAPE).  n = 0 clears
+   them.  Copies and bins them by control-grid cell; the host arrays may be reused on
+   return. */
+int disco_set_keypoints(disco_ctx *ctx, int32_t n, const float *x_mm, const float *t_mm, disco_stream stream);
+
+/* Set the prior displacement uhat of eq. 5 (device node field), or NULL for uhat = 0. */
+int disco_set_reference(disco_ctx *ctx, const float *u_ref, disco_stream stream);
+
+/* NGF distance of eq. 1 at displacement u: *D_dev = h_x h_y h_z sum_v (1 - r_v^2). */
+int ngf_eval(disco_ctx *ctx, double eta, const float *u, double *D_dev, disco_stream stream);
+
+/* NGF distance and its gradient g = dD/du (node field).  diag (nullable) receives the
+   diagonal of the Gauss-Newton matrix 2 h^3 J^T J.  Also records u as the
+   linearisation point and stores s_v = J_G^T dr/da per voxel for ngf_hessvec. */
+int ngf_grad(disco_ctx *ctx, double eta, const float *u, double *D_dev, float *g, float *diag,
+             disco_stream stream);
+
+/* Hv = 2 h^3 J^T (J v) of the NGF term at the last linearisation (ngf_grad or
+   gn_pcg_step); DISCO_ERR_STATE if there is none. */
+int ngf_hessvec(disco_ctx *ctx, const float *v, float *Hv, disco_stream stream);
+
+/* Curvature term of eq. 5 with weight alpha: w = u - u_ref (u_ref nullable: 0),
+   *S_dev = alpha S(u) (nullable), out = alpha C_H L^T L w (the gradient; nullable),
+   diag = alpha C_H diag(L^T L) (nullable).  Called with u = v and u_ref = NULL, out is
+   the (exact) Hessian product.  L is the node-grid Laplacian with vanishing second
+   differences at border nodes, C_H = 64 h_x h_y h_z. */
+int curvature_apply(disco_ctx *ctx, double alpha, const float *u, const float *u_ref, double *S_dev, float *out,
+                    float *diag, disco_stream stream);
+
+/* Volume-change control of eq. 7-9 with weight gamma at displacement u:
+   *V_dev = gamma Vhat(u) (+inf on a fold), g = gamma grad Vhat (nullable),
+   diag = gamma diag of the GN matrix C sum psi''(d) grad d grad d^T (nullable),
+   Hv = gamma GN matrix times v (v and Hv both NULL or both set),
+   *nfold_dev = number of coefficients d <= 0 (nullable). */
+int volchange_eval(disco_ctx *ctx, double gamma, const float *u, double *V_dev, float *g, float *diag, const float *v,
+                   float *Hv, int32_t *nfold_dev, disco_stream stream);
+
+/* Keypoint penalty of eq. 10 with weight delta: *K_dev = delta K(u) (nullable),
+   g = 2 delta P^T res (nullable), diag = 2 delta diag(P^T P) (nullable),
+   Hv = 2 delta P^T P v (v and Hv both NULL or both set). */
+int keypoint_penalty(disco_ctx *ctx, double delta, const float *u, double *K_dev, float *g, float *diag,
+                     const float *v, float *Hv, disco_stream stream);
+
+/* Full Gauss-Newton product of eq. 11 at the last linearisation:
+   Hv = H_D v + alpha C_H L^T L v + gamma H_V v + delta 2 P^T P v + tau v. */
+int gn_hessvec(disco_ctx *ctx, const disco_params *p, const float *v, float *Hv, disco_stream stream);
+
+/* One Gauss-Newton step of eq. 11 from u (updated in place on success):
+   linearise at u; solve (H + tau I) p = -grad J by Jacobi-PCG (x0 = 0, preconditioner
+   diag H + tau + 1e-12 max diag H, pcg_iters iterations or |r| <= pcg_tol |g|, stop on
+   p^T H p <= 0); Armijo backtracking t = 1, 1/2, ... (at most ls_max trials) accepting
+   the first t with J(u + t p) finite and <= J(u) + c1 t g^T p.  report_dev (nullable)
+   receives DISCO_REP_SIZE doubles; status_dev (nullable) the DISCO_STATUS_* bits.
+   Without DISCO_FLAG_LS_DEVICE the host waits for the stream once per line-search
+   trial; with it the call never synchronises and can be graph captured. */
+int gn_pcg_step(disco_ctx *ctx, const disco_params *p, float *u_inout, double *report_dev, int32_t *status_dev,
+                disco_stream stream);
+
+/* Copy a derived buffer (DISCO_BUF_*) to dst, converted to float32 [Nz][Ny][Nx][3]. */
+int disco_copy_buffer(disco_ctx *ctx, int32_t which, float *dst, disco_stream stream);
+
+/* Per-kernel timing with HIP events recorded on the launch stream.  enable = 1 starts
+   recording (clears counters), 0 stops.  disco_profile_read waits for the recorded
+   events and returns the number of launches and total milliseconds of one kernel
+   class: 0 = Gauss-Newton product pass over the voxels, 1 = gradient pass,
+   2 = objective-only pass, 3 = image gradients. */
+int disco_profile(disco_ctx *ctx, int32_t enable);
+int disco_profile_read(disco_ctx *ctx, int32_t kernel, int64_t *launches, double *ms_total);
+
+/* Human-readable text of a return code. */
+const char *disco_status_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DISCO_H */

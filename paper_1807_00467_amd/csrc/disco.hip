@@ -1,0 +1,778 @@
+// Host side of the C ABI declared in include/disco.h: context and workspace
+// management, argument validation, kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <utility>
+#include <vector>
+
+#include "disco.h"
+#include "kernels.hpp"
+#include "solver.hpp"
+
+using namespace disco;
+
+namespace {
+
+constexpr int kZC = 4;  // cells per brick along z
+
+struct EventPair {
+  hipEvent_t a, b;
+};
+
+struct Arena {
+  void *ptr = nullptr;
+};
+
+}  // namespace
+
+struct disco_ctx {
+  int device = 0;
+  int storage = DISCO_STORAGE_FP32;
+  Geo g{};
+  int64_t ncells = 0;
+  int64_t nwg = 0;         // brick workgroups
+  int64_t nodeblocks = 0;  // blocks of node-parallel kernels
+  // derived volumes
+  void *gR = nullptr, *gT = nullptr, *scache = nullptr;
+  float sR = 1.f, sT = 1.f;                 // dequantisation scales (FP16)
+  float sS_load = 1.f, sS_store = 1.f;      // s cache scales (FP16)
+  bool images = false;
+  bool lin = false;
+  double lin_eta = 0.0;
+  // node workspaces
+  float *u_lin = nullptr, *u_ref = nullptr, *Lw = nullptr;
+  float *vg = nullptr, *vdiag = nullptr, *vx = nullptr, *vr = nullptr, *vz = nullptr, *vp = nullptr, *vq = nullptr,
+        *vut = nullptr, *tmp0 = nullptr, *tmp1 = nullptr;
+  float *part = nullptr;
+  double *blk_brick = nullptr, *blk_node = nullptr, *sc = nullptr;
+  int *status = nullptr;
+  double *host_sc = nullptr;  // pinned
+  // keypoints
+  int32_t nkp = 0;
+  float *kloc = nullptr, *ktgt = nullptr;
+  int *kstart = nullptr;
+  // profiling
+  bool prof = false;
+  std::vector<EventPair> ev[4];
+};
+
+namespace {
+
+inline int hip_err(hipError_t e) { return DISCO_ERR_HIP - (int)e; }
+
+#define HIP_TRY(x)                      \
+  do {                                  \
+    hipError_t e_ = (x);                \
+    if (e_ != hipSuccess) return hip_err(e_); \
+  } while (0)
+
+inline bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+inline bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+inline hipStream_t S(disco_stream s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+struct ProfScope {
+  disco_ctx *c;
+  int k;
+  hipStream_t s;
+  EventPair e{};
+  bool on;
+  ProfScope(disco_ctx *c_, int k_, hipStream_t s_) : c(c_), k(k_), s(s_), on(c_->prof) {
+    if (on) {
+      (void)hipEventCreate(&e.a);
+      (void)hipEventCreate(&e.b);
+      (void)hipEventRecord(e.a, s);
+    }
+  }
+  ~ProfScope() {
+    if (on) {
+      (void)hipEventRecord(e.b, s);
+      c->ev[k].push_back(e);
+    }
+  }
+};
+
+void clear_profile(disco_ctx *c) {
+  for (auto &v : c->ev) {
+    for (auto &p : v) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+    v.clear();
+  }
+}
+
+// ------------------------------------------------------------------------------
+// brick kernel dispatch
+// ------------------------------------------------------------------------------
+template <class ST, int MODE>
+void launch_brick_mode(disco_ctx *c, bool ngf, bool vcc, bool kp, const BrickArgs<ST> &a, hipStream_t s) {
+  dim3 grid(c->g.nbx, c->g.nby, c->g.nbz);
+  const int key = (ngf ? 4 : 0) | (vcc ? 2 : 0) | (kp ? 1 : 0);
+  switch (key) {
+    case 7: hipLaunchKernelGGL((k_brick<ST, MODE, true, true, true, kZC>), grid, dim3(kWG), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_brick<ST, MODE, true, true, false, kZC>), grid, dim3(kWG), 0, s, a); break;
+    case 5: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, true, kZC>), grid, dim3(kWG), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(kWG), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_brick<ST, MODE, false, true, true, kZC>), grid, dim3(kWG), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_brick<ST, MODE, false, true, false, kZC>), grid, dim3(kWG), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_brick<ST, MODE, false, false, true, kZC>), grid, dim3(kWG), 0, s, a); break;
+    default: break;
+  }
+}
+
+struct BrickCall {
+  int mode;
+  bool ngf, vcc, kp;
+  float eta2;
+  float gamma, delta;
+  const float *u, *v;
+  float *out0, *out1;
+  const double *stop;
+};
+
+template <class ST>
+BrickArgs<ST> make_args(disco_ctx *c, const BrickCall &b) {
+  BrickArgs<ST> a{};
+  a.g = c->g;
+  a.gR = reinterpret_cast<const typename ST::elem *>(c->gR);
+  a.gT = reinterpret_cast<const typename ST::elem *>(c->gT);
+  a.sc = reinterpret_cast<typename ST::elem *>(c->scache);
+  a.sR = c->sR;
+  a.sT = c->sT;
+  a.sS_load = c->sS_load;
+  a.sS_store = c->sS_store;
+  a.u = b.u;
+  a.v = b.v;
+  a.kloc = c->kloc;
+  a.ktgt = c->ktgt;
+  a.kstart = c->kstart;
+  a.eta2 = b.eta2;
+  a.ngf_scale = (float)(2.0 * (double)c->g.hx * (double)c->g.hy * (double)c->g.hz);
+  a.gamma = b.gamma;
+  a.delta = b.delta;
+  a.out0 = b.out0;
+  a.out1 = b.out1;
+  a.part = c->part;
+  a.blocks = c->blk_brick;
+  a.stop = b.stop;
+  return a;
+}
+
+void launch_brick(disco_ctx *c, const BrickCall &b, hipStream_t s) {
+  const int pk = b.mode == M_HV ? 0 : (b.mode == M_GRAD ? 1 : 2);
+  ProfScope ps(c, pk, s);
+  if (c->storage == DISCO_STORAGE_FP16) {
+    auto a = make_args<F16x4>(c, b);
+    if (b.mode == M_EVAL) launch_brick_mode<F16x4, M_EVAL>(c, b.ngf, b.vcc, b.kp, a, s);
+    if (b.mode == M_GRAD) launch_brick_mode<F16x4, M_GRAD>(c, b.ngf, b.vcc, b.kp, a, s);
+    if (b.mode == M_HV) launch_brick_mode<F16x4, M_HV>(c, b.ngf, b.vcc, b.kp, a, s);
+  } else {
+    auto a = make_args<F32x3>(c, b);
+    if (b.mode == M_EVAL) launch_brick_mode<F32x3, M_EVAL>(c, b.ngf, b.vcc, b.kp, a, s);
+    if (b.mode == M_GRAD) launch_brick_mode<F32x3, M_GRAD>(c, b.ngf, b.vcc, b.kp, a, s);
+    if (b.mode == M_HV) launch_brick_mode<F32x3, M_HV>(c, b.ngf, b.vcc, b.kp, a, s);
+  }
+}
+
+void launch_reduce(const double *blocks, int64_t nb, int stride, int nvals, uint32_t max_mask, double *out,
+                   const double *stop, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, blocks, nb, stride, nvals, max_mask, out, stop);
+}
+
+// gather after a brick pass (F fields written by the brick kernel, nf produced)
+void launch_gather(disco_ctx *c, int F, int nf, float *out0, float *out1, const float *Lw, float curv_scale,
+                   int curv_diag, const float *tauv, float tau, const float *dotv, bool reduce, const double *stop,
+                   hipStream_t s) {
+  GatherArgs a{};
+  a.g = c->g;
+  a.F = F;
+  a.nf = nf;
+  a.part = c->part;
+  a.out0 = out0;
+  a.out1 = out1;
+  a.Lw = Lw;
+  a.curv_scale = curv_scale;
+  a.curv_diag = curv_diag;
+  a.tauv = tauv;
+  a.tau = tau;
+  a.dotv = dotv;
+  a.blocks = reduce ? c->blk_node : nullptr;
+  a.stop = stop;
+  hipLaunchKernelGGL((k_gather<kZC>), dim3(nblk(c->g.nnodes)), dim3(256), 0, s, a);
+}
+
+void launch_curv_L(disco_ctx *c, const float *a, const float *b, float *Lw, bool energy, const double *stop,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_curv_L, dim3(nblk(c->g.nnodes)), dim3(256), 0, s, c->g, a, b, Lw,
+                     energy ? c->blk_node : nullptr, stop);
+}
+
+double ch_of(const disco_ctx *c) { return (double)c->g.Hx * (double)c->g.Hy * (double)c->g.Hz; }
+
+int check_field(const void *p) {
+  if (!p) return DISCO_ERR_ARG;
+  if (!aligned4(p)) return DISCO_ERR_SHAPE;
+  return DISCO_OK;
+}
+
+int set_device(disco_ctx *c) {
+  HIP_TRY(hipSetDevice(c->device));
+  return DISCO_OK;
+}
+
+}  // namespace
+
+// ==============================================================================
+// C ABI
+// ==============================================================================
+extern "C" {
+
+const char *disco_status_string(int code) {
+  switch (code) {
+    case DISCO_OK: return "ok";
+    case DISCO_ERR_ARG: return "invalid argument (null pointer, bad enum or count)";
+    case DISCO_ERR_SHAPE: return "shape error (size not a positive multiple of 4, keypoint outside the image box, or misaligned pointer)";
+    case DISCO_ERR_STATE: return "state error (images not set or no linearisation yet)";
+    case DISCO_ERR_NONFINITE: return "non-finite or out-of-range scalar parameter";
+    case DISCO_ERR_NOMEM: return "device allocation failed";
+    default:
+      if (code <= DISCO_ERR_HIP) return hipGetErrorString((hipError_t)(DISCO_ERR_HIP - code));
+      return "unknown code";
+  }
+}
+
+void disco_destroy(disco_ctx *c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  clear_profile(c);
+  void *ptrs[] = {c->gR,  c->gT,  c->scache, c->u_lin, c->u_ref, c->Lw,   c->vg,   c->vdiag, c->vx,   c->vr,
+                  c->vz,  c->vp,  c->vq,     c->vut,   c->tmp0,  c->tmp1, c->part, c->blk_brick, c->blk_node,
+                  c->sc,  c->status, c->kloc, c->ktgt, c->kstart};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->host_sc) (void)hipHostFree(c->host_sc);
+  delete c;
+}
+
+int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
+  if (!out) return DISCO_ERR_ARG;
+  *out = nullptr;
+  if (!geom) return DISCO_ERR_ARG;
+  if (storage != DISCO_STORAGE_FP32 && storage != DISCO_STORAGE_FP16) return DISCO_ERR_ARG;
+  for (int a = 0; a < 3; ++a) {
+    if (geom->n[a] < 4 || geom->n[a] % 4 != 0) return DISCO_ERR_SHAPE;
+    if (!std::isfinite(geom->h[a]) || !(geom->h[a] > 0.0)) return DISCO_ERR_NONFINITE;
+  }
+  // 32-bit node/voxel coordinates; 64-bit linear indices
+  const int64_t nvox = (int64_t)geom->n[0] * geom->n[1] * geom->n[2];
+  if (nvox > ((int64_t)1 << 34)) return DISCO_ERR_SHAPE;
+
+  disco_ctx *c = new (std::nothrow) disco_ctx();
+  if (!c) return DISCO_ERR_NOMEM;
+  (void)hipGetDevice(&c->device);
+  c->storage = storage;
+  Geo &g = c->g;
+  g.nx = geom->n[0];
+  g.ny = geom->n[1];
+  g.nz = geom->n[2];
+  g.cx = g.nx / 4;
+  g.cy = g.ny / 4;
+  g.cz = g.nz / 4;
+  g.px = g.cx + 1;
+  g.py = g.cy + 1;
+  g.pz = g.cz + 1;
+  g.zc = kZC;
+  g.nbx = (g.cx + kBXC - 1) / kBXC;
+  g.nby = (g.cy + kBYC - 1) / kBYC;
+  g.nbz = (g.cz + kZC - 1) / kZC;
+  g.hx = (float)geom->h[0];
+  g.hy = (float)geom->h[1];
+  g.hz = (float)geom->h[2];
+  g.ihx = (float)(1.0 / geom->h[0]);
+  g.ihy = (float)(1.0 / geom->h[1]);
+  g.ihz = (float)(1.0 / geom->h[2]);
+  g.Hx = (float)(4.0 * geom->h[0]);
+  g.Hy = (float)(4.0 * geom->h[1]);
+  g.Hz = (float)(4.0 * geom->h[2]);
+  g.iHx = (float)(0.25 / geom->h[0]);
+  g.iHy = (float)(0.25 / geom->h[1]);
+  g.iHz = (float)(0.25 / geom->h[2]);
+  g.C = (float)(64.0 * geom->h[0] * geom->h[1] * geom->h[2]);
+  g.nvox = nvox;
+  g.nnodes = (int64_t)g.px * g.py * g.pz;
+  c->ncells = (int64_t)g.cx * g.cy * g.cz;
+  c->nwg = (int64_t)g.nbx * g.nby * g.nbz;
+  c->nodeblocks = nblk(g.nnodes);
+
+  const size_t vec3 = storage == DISCO_STORAGE_FP16 ? 8 : 12;  // bytes per voxel 3-vector
+  const size_t nf = 3 * (size_t)g.nnodes * sizeof(float);
+  bool okm = true;
+  auto alloc = [&](void **p, size_t bytes) {
+    if (!okm) return;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      *p = nullptr;
+      okm = false;
+    }
+  };
+  alloc(&c->gR, vec3 * (size_t)nvox);
+  alloc(&c->gT, vec3 * (size_t)nvox);
+  alloc(&c->scache, vec3 * (size_t)nvox);
+  float **nodebufs[] = {&c->u_lin, &c->Lw, &c->vg, &c->vdiag, &c->vx, &c->vr, &c->vz, &c->vp, &c->vq, &c->vut,
+                        &c->tmp0, &c->tmp1};
+  for (float **p : nodebufs) alloc(reinterpret_cast<void **>(p), nf);
+  alloc(reinterpret_cast<void **>(&c->part), sizeof(float) * (size_t)c->nwg * (kZC + 1) * 6 * kNBOX);
+  alloc(reinterpret_cast<void **>(&c->blk_brick), sizeof(double) * (size_t)c->nwg * BS_N);
+  // node-parallel reductions: 3 values per block over nnodes, or 2 per block over 3 nnodes
+  alloc(reinterpret_cast<void **>(&c->blk_node), sizeof(double) * ((size_t)c->nodeblocks * 6 + 16));
+  alloc(reinterpret_cast<void **>(&c->sc), sizeof(double) * SC_COUNT);
+  alloc(reinterpret_cast<void **>(&c->status), sizeof(int));
+  alloc(reinterpret_cast<void **>(&c->kstart), sizeof(int) * (size_t)(c->ncells + 1));
+  if (okm && hipHostMalloc(reinterpret_cast<void **>(&c->host_sc), sizeof(double) * SC_COUNT) != hipSuccess) {
+    c->host_sc = nullptr;
+    okm = false;
+  }
+  if (!okm) {
+    disco_destroy(c);
+    return DISCO_ERR_NOMEM;
+  }
+  if (hipMemset(c->kstart, 0, sizeof(int) * (size_t)(c->ncells + 1)) != hipSuccess ||
+      hipMemset(c->sc, 0, sizeof(double) * SC_COUNT) != hipSuccess ||
+      hipMemset(c->status, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    disco_destroy(c);
+    return DISCO_ERR_NOMEM;
+  }
+  *out = c;
+  return DISCO_OK;
+}
+
+int disco_set_images(disco_ctx *c, const float *R, const float *T, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_field(R)) || (e = check_field(T))) return e;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  const Geo &g = c->g;
+  ProfScope ps(c, 3, s);
+  if (c->storage == DISCO_STORAGE_FP16) {
+    // per-volume power-of-two scale so that max |grad| * scale <= 2^14
+    const unsigned nb = nblk(g.nvox);
+    double *blk = nullptr;
+    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&blk), sizeof(double) * nb, s));
+    float scales[2];
+    const float *imgs[2] = {R, T};
+    for (int k = 0; k < 2; ++k) {
+      hipLaunchKernelGGL(k_absmax_grad, dim3(nb), dim3(256), 0, s, g, imgs[k], blk);
+      launch_reduce(blk, nb, 1, 1, 1u, c->sc + SC_TMP0, nullptr, s);
+      double mx = 0.0;
+      HIP_TRY(hipMemcpyAsync(&mx, c->sc + SC_TMP0, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      int ex = 0;
+      if (mx > 0.0 && std::isfinite(mx)) ex = (int)std::floor(std::log2(16384.0 / mx));
+      ex = std::max(-100, std::min(100, ex));
+      scales[k] = std::ldexp(1.0f, ex);
+    }
+    HIP_TRY(hipFreeAsync(blk, s));
+    c->sR = 1.0f / scales[0];
+    c->sT = 1.0f / scales[1];
+    hipLaunchKernelGGL(k_imgrad<F16x4>, dim3(nb), dim3(256), 0, s, g, R, reinterpret_cast<__half *>(c->gR),
+                       scales[0]);
+    hipLaunchKernelGGL(k_imgrad<F16x4>, dim3(nb), dim3(256), 0, s, g, T, reinterpret_cast<__half *>(c->gT),
+                       scales[1]);
+  } else {
+    hipLaunchKernelGGL(k_imgrad<F32x3>, dim3(nblk(g.nvox)), dim3(256), 0, s, g, R,
+                       reinterpret_cast<float *>(c->gR), 1.0f);
+    hipLaunchKernelGGL(k_imgrad<F32x3>, dim3(nblk(g.nvox)), dim3(256), 0, s, g, T,
+                       reinterpret_cast<float *>(c->gT), 1.0f);
+  }
+  HIP_TRY(hipGetLastError());
+  c->images = true;
+  c->lin = false;
+  return DISCO_OK;
+}
+
+int disco_set_keypoints(disco_ctx *c, int32_t n, const float *x_mm, const float *t_mm, disco_stream stream) {
+  if (!c || n < 0) return DISCO_ERR_ARG;
+  if (n > 0 && (!x_mm || !t_mm)) return DISCO_ERR_ARG;
+  int e;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  const Geo &g = c->g;
+  const double H[3] = {4.0 * (double)g.hx, 4.0 * (double)g.hy, 4.0 * (double)g.hz};
+  const int ncell[3] = {g.cx, g.cy, g.cz};
+  std::vector<int64_t> cell(n);
+  std::vector<float> loc(3 * (size_t)n), tgt(3 * (size_t)n);
+  std::vector<int> order(n);
+  for (int32_t i = 0; i < n; ++i) {
+    int cidx[3];
+    for (int a = 0; a < 3; ++a) {
+      const double x = (double)x_mm[3 * i + a];
+      const double xi = x / H[a];
+      if (!(xi >= 0.0 && xi <= (double)ncell[a])) return DISCO_ERR_SHAPE;
+      int ci = (int)std::floor(xi);
+      if (ci > ncell[a] - 1) ci = ncell[a] - 1;
+      cidx[a] = ci;
+    }
+    if (!std::isfinite((double)t_mm[3 * i]) || !std::isfinite((double)t_mm[3 * i + 1]) ||
+        !std::isfinite((double)t_mm[3 * i + 2]))
+      return DISCO_ERR_NONFINITE;
+    cell[i] = ((int64_t)cidx[2] * g.cy + cidx[1]) * g.cx + cidx[0];
+    for (int a = 0; a < 3; ++a) {
+      const double origin = (double)cidx[a] * H[a];
+      loc[3 * i + a] = (float)((double)x_mm[3 * i + a] - origin);
+      tgt[3 * i + a] = (float)((double)t_mm[3 * i + a] - origin);
+    }
+  }
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cell[a] < cell[b]; });
+  std::vector<float> sloc(3 * (size_t)n), stgt(3 * (size_t)n);
+  std::vector<int> start((size_t)c->ncells + 1, 0);
+  for (int32_t k = 0; k < n; ++k) {
+    const int i = order[k];
+    for (int a = 0; a < 3; ++a) {
+      sloc[3 * k + a] = loc[3 * i + a];
+      stgt[3 * k + a] = tgt[3 * i + a];
+    }
+    start[cell[i] + 1]++;
+  }
+  for (int64_t q = 0; q < c->ncells; ++q) start[q + 1] += start[q];
+  HIP_TRY(hipStreamSynchronize(s));
+  if (c->kloc) (void)hipFree(c->kloc);
+  if (c->ktgt) (void)hipFree(c->ktgt);
+  c->kloc = c->ktgt = nullptr;
+  c->nkp = 0;
+  if (n > 0) {
+    if (hipMalloc(reinterpret_cast<void **>(&c->kloc), sizeof(float) * 3 * (size_t)n) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&c->ktgt), sizeof(float) * 3 * (size_t)n) != hipSuccess)
+      return DISCO_ERR_NOMEM;
+    HIP_TRY(hipMemcpy(c->kloc, sloc.data(), sizeof(float) * 3 * (size_t)n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->ktgt, stgt.data(), sizeof(float) * 3 * (size_t)n, hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipMemcpy(c->kstart, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice));
+  c->nkp = n;
+  return DISCO_OK;
+}
+
+int disco_set_reference(disco_ctx *c, const float *u_ref, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  int e;
+  if ((e = set_device(c))) return e;
+  if (!u_ref) {
+    if (c->u_ref) {
+      HIP_TRY(hipStreamSynchronize(S(stream)));
+      (void)hipFree(c->u_ref);
+    }
+    c->u_ref = nullptr;
+    return DISCO_OK;
+  }
+  if ((e = check_field(u_ref))) return e;
+  if (!c->u_ref && hipMalloc(reinterpret_cast<void **>(&c->u_ref), 3 * sizeof(float) * (size_t)c->g.nnodes) != hipSuccess)
+    return DISCO_ERR_NOMEM;
+  HIP_TRY(hipMemcpyAsync(c->u_ref, u_ref, 3 * sizeof(float) * (size_t)c->g.nnodes, hipMemcpyDeviceToDevice,
+                         S(stream)));
+  return DISCO_OK;
+}
+
+int ngf_eval(disco_ctx *c, double eta, const float *u, double *D_dev, disco_stream stream) {
+  if (!c || !D_dev) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_field(u))) return e;
+  if (!std::isfinite(eta) || !(eta > 0.0)) return DISCO_ERR_NONFINITE;
+  if (!c->images) return DISCO_ERR_STATE;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  BrickCall b{M_EVAL, true, false, false, (float)(eta * eta), 0.f, 0.f, u, nullptr, nullptr, nullptr, nullptr};
+  launch_brick(c, b, s);
+  launch_reduce(c->blk_brick, c->nwg, BS_N, 1, 0u, c->sc + SC_TMP0, nullptr, s);
+  hipLaunchKernelGGL(k_write_scalar, dim3(1), dim3(1), 0, s, c->sc + SC_TMP0,
+                     (double)c->g.hx * (double)c->g.hy * (double)c->g.hz, D_dev, (const double *)nullptr, 0);
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+int ngf_grad(disco_ctx *c, double eta, const float *u, double *D_dev, float *g, float *diag, disco_stream stream) {
+  if (!c || !D_dev) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_field(u)) || (e = check_field(g))) return e;
+  if (diag && !aligned4(diag)) return DISCO_ERR_SHAPE;
+  if (!std::isfinite(eta) || !(eta > 0.0)) return DISCO_ERR_NONFINITE;
+  if (!c->images) return DISCO_ERR_STATE;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  float *d1 = diag ? diag : c->tmp1;
+  BrickCall b{M_GRAD, true, false, false, (float)(eta * eta), 0.f, 0.f, u, nullptr, g, d1, nullptr};
+  launch_brick(c, b, s);
+  launch_reduce(c->blk_brick, c->nwg, BS_N, 1, 0u, c->sc + SC_TMP0, nullptr, s);
+  hipLaunchKernelGGL(k_write_scalar, dim3(1), dim3(1), 0, s, c->sc + SC_TMP0,
+                     (double)c->g.hx * (double)c->g.hy * (double)c->g.hz, D_dev, (const double *)nullptr, 0);
+  launch_gather(c, 2, 2, g, d1, nullptr, 0.f, 0, nullptr, 0.f, nullptr, false, nullptr, s);
+  HIP_TRY(hipMemcpyAsync(c->u_lin, u, 3 * sizeof(float) * (size_t)c->g.nnodes, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipGetLastError());
+  c->lin = true;
+  c->lin_eta = eta;
+  return DISCO_OK;
+}
+
+int ngf_hessvec(disco_ctx *c, const float *v, float *Hv, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_field(v)) || (e = check_field(Hv))) return e;
+  if (!c->lin) return DISCO_ERR_STATE;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  BrickCall b{M_HV, true, false, false, 0.f, 0.f, 0.f, c->u_lin, v, Hv, nullptr, nullptr};
+  launch_brick(c, b, s);
+  launch_gather(c, 1, 1, Hv, nullptr, nullptr, 0.f, 0, nullptr, 0.f, nullptr, false, nullptr, s);
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+int curvature_apply(disco_ctx *c, double alpha, const float *u, const float *u_ref, double *S_dev, float *out,
+                    float *diag, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_field(u))) return e;
+  if ((u_ref && !aligned4(u_ref)) || (out && !aligned4(out)) || (diag && !aligned4(diag))) return DISCO_ERR_SHAPE;
+  if (!finite_nonneg(alpha)) return DISCO_ERR_NONFINITE;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  const double CH = ch_of(c);
+  launch_curv_L(c, u, u_ref, c->Lw, S_dev != nullptr, nullptr, s);
+  if (S_dev) {
+    launch_reduce(c->blk_node, c->nodeblocks, 1, 1, 0u, c->sc + SC_TMP0, nullptr, s);
+    hipLaunchKernelGGL(k_write_scalar, dim3(1), dim3(1), 0, s, c->sc + SC_TMP0, 0.5 * CH * alpha, S_dev,
+                       (const double *)nullptr, 0);
+  }
+  if (out || diag) {
+    float *o0 = out ? out : c->tmp0;
+    float *o1 = diag ? diag : c->tmp1;
+    launch_gather(c, 0, diag ? 2 : 1, o0, o1, c->Lw, (float)(alpha * CH), diag ? 1 : 0, nullptr, 0.f, nullptr,
+                  false, nullptr, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+static int cell_term(disco_ctx *c, bool vcc, double w, const float *u, double *E_dev, float *g, float *diag,
+                     const float *v, float *Hv, int32_t *nfold_dev, hipStream_t s) {
+  int e;
+  if ((e = check_field(u))) return e;
+  if ((g && !aligned4(g)) || (diag && !aligned4(diag)) || (v && !aligned4(v)) || (Hv && !aligned4(Hv)))
+    return DISCO_ERR_SHAPE;
+  if ((v == nullptr) != (Hv == nullptr)) return DISCO_ERR_ARG;
+  if (!finite_nonneg(w)) return DISCO_ERR_NONFINITE;
+  if ((e = set_device(c))) return e;
+  const float wf = (float)w;
+  if (E_dev || nfold_dev || g || diag) {
+    const bool grad = g || diag;
+    BrickCall b{grad ? M_GRAD : M_EVAL, false, vcc, !vcc, 0.f, vcc ? wf : 0.f, vcc ? 0.f : wf, u, nullptr,
+                g ? g : c->tmp0, diag ? diag : c->tmp1, nullptr};
+    launch_brick(c, b, s);
+    launch_reduce(c->blk_brick, c->nwg, BS_N, BS_N, 0u, c->sc + SC_TMP0, nullptr, s);
+    // SC_TMP0.. = D, V, K, folds
+    if (E_dev)
+      hipLaunchKernelGGL(k_write_scalar, dim3(1), dim3(1), 0, s, c->sc + SC_TMP0 + (vcc ? BS_V : BS_K), w, E_dev,
+                         (const double *)(c->sc + SC_TMP0 + BS_FOLD), vcc ? 1 : 0);
+    if (nfold_dev) hipLaunchKernelGGL(k_write_int, dim3(1), dim3(1), 0, s, c->sc + SC_TMP0 + BS_FOLD, nfold_dev);
+    if (grad) launch_gather(c, 2, 2, g ? g : c->tmp0, diag ? diag : c->tmp1, nullptr, 0.f, 0, nullptr, 0.f, nullptr,
+                            false, nullptr, s);
+  }
+  if (v) {
+    BrickCall b{M_HV, false, vcc, !vcc, 0.f, vcc ? wf : 0.f, vcc ? 0.f : wf, u, v, Hv, nullptr, nullptr};
+    launch_brick(c, b, s);
+    launch_gather(c, 1, 1, Hv, nullptr, nullptr, 0.f, 0, nullptr, 0.f, nullptr, false, nullptr, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+int volchange_eval(disco_ctx *c, double gamma, const float *u, double *V_dev, float *g, float *diag, const float *v,
+                   float *Hv, int32_t *nfold_dev, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  return cell_term(c, true, gamma, u, V_dev, g, diag, v, Hv, nfold_dev, S(stream));
+}
+
+int keypoint_penalty(disco_ctx *c, double delta, const float *u, double *K_dev, float *g, float *diag,
+                     const float *v, float *Hv, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  return cell_term(c, false, delta, u, K_dev, g, diag, v, Hv, nullptr, S(stream));
+}
+
+static int check_params(const disco_params *p) {
+  if (!p) return DISCO_ERR_ARG;
+  if (!std::isfinite(p->eta) || !(p->eta > 0.0)) return DISCO_ERR_NONFINITE;
+  if (!finite_nonneg(p->alpha) || !finite_nonneg(p->gamma) || !finite_nonneg(p->delta) || !finite_nonneg(p->tau) ||
+      !finite_nonneg(p->pcg_tol))
+    return DISCO_ERR_NONFINITE;
+  if (!std::isfinite(p->armijo_c1) || !(p->armijo_c1 > 0.0 && p->armijo_c1 < 1.0)) return DISCO_ERR_NONFINITE;
+  if (p->pcg_iters < 1 || p->ls_max < 1 || p->ls_max > 60) return DISCO_ERR_ARG;
+  return DISCO_OK;
+}
+
+// H v at the context's linearisation, all terms of eq. 11; optional per-block <v, Hv>
+static void gn_hv_launch(disco_ctx *c, const disco_params *p, const float *v, float *Hv, bool dot,
+                         const double *stop, hipStream_t s) {
+  const bool vcc = p->gamma != 0.0;
+  const bool kp = p->delta != 0.0 && c->nkp > 0;
+  const bool curv = p->alpha != 0.0;
+  if (curv) launch_curv_L(c, v, nullptr, c->Lw, false, stop, s);
+  BrickCall b{M_HV, true, vcc, kp, 0.f, (float)p->gamma, (float)p->delta, c->u_lin, v, Hv, nullptr, stop};
+  launch_brick(c, b, s);
+  launch_gather(c, 1, 1, Hv, nullptr, curv ? c->Lw : nullptr, (float)(p->alpha * ch_of(c)), 0,
+                p->tau != 0.0 ? v : nullptr, (float)p->tau, dot ? v : nullptr, dot, stop, s);
+}
+
+int gn_hessvec(disco_ctx *c, const disco_params *p, const float *v, float *Hv, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_params(p))) return e;
+  if ((e = check_field(v)) || (e = check_field(Hv))) return e;
+  if (!c->lin) return DISCO_ERR_STATE;
+  if ((e = set_device(c))) return e;
+  gn_hv_launch(c, p, v, Hv, false, nullptr, S(stream));
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+int gn_pcg_step(disco_ctx *c, const disco_params *p, float *u, double *report_dev, int32_t *status_dev,
+                disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_params(p))) return e;
+  if ((e = check_field(u))) return e;
+  if ((report_dev && ((reinterpret_cast<uintptr_t>(report_dev) & 7u) != 0)) ||
+      (status_dev && !aligned4(status_dev)))
+    return DISCO_ERR_SHAPE;
+  if (!c->images) return DISCO_ERR_STATE;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  const Geo &g = c->g;
+  const int64_t n3 = 3 * g.nnodes;
+  const unsigned nb3 = nblk(n3);
+  double *sc = c->sc;
+  const double CH = ch_of(c);
+  Weights w{p->alpha, p->gamma, p->delta, CH};
+  const bool vcc = p->gamma != 0.0;
+  const bool kp = p->delta != 0.0 && c->nkp > 0;
+  const bool curv = p->alpha != 0.0;
+  const float eta2 = (float)(p->eta * p->eta);
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, c->status);
+
+  // ---- linearise at u: J, grad J, diag of the GN matrix, s cache --------------------
+  launch_curv_L(c, u, c->u_ref, c->Lw, true, nullptr, s);
+  launch_reduce(c->blk_node, c->nodeblocks, 1, 1, 0u, sc + SC_SRAW, nullptr, s);
+  {
+    BrickCall b{M_GRAD, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, u, nullptr, c->vg, c->vdiag, nullptr};
+    launch_brick(c, b, s);
+  }
+  launch_reduce(c->blk_brick, c->nwg, BS_N, BS_N, 0u, sc + SC_TMP0, nullptr, s);
+  launch_gather(c, 2, 2, c->vg, c->vdiag, curv ? c->Lw : nullptr, (float)(p->alpha * CH), curv ? 1 : 0, nullptr, 0.f,
+                nullptr, true, nullptr, s);
+  launch_reduce(c->blk_node, c->nodeblocks, 3, 3, 2u, sc + SC_DOT, nullptr, s);  // dot (unused), max diag, |g|^2
+  HIP_TRY(hipMemcpyAsync(c->u_lin, u, sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
+  // move the brick reductions into place: D = h^3 sum c, V, K, folds
+  hipLaunchKernelGGL(k_lin_move, dim3(1), dim3(1), 0, s, sc, (double)g.hx * (double)g.hy * (double)g.hz);
+  hipLaunchKernelGGL(k_lin_post, dim3(1), dim3(1), 0, s, sc, w, c->status);
+  c->lin = true;
+  c->lin_eta = p->eta;
+
+  // ---- Jacobi-PCG on (H + tau I) x = -g ----------------------------------------------
+  hipLaunchKernelGGL(k_pcg_init, dim3(nb3), dim3(256), 0, s, n3, c->vg, c->vdiag, sc, (float)p->tau, c->vx, c->vr,
+                     c->vz, c->vp, c->blk_node);
+  launch_reduce(c->blk_node, nb3, 2, 2, 0u, sc + SC_TMP0, nullptr, s);
+  hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(1), 0, s, sc);
+  const double *stop = sc + SC_STOP;
+  for (int it = 0; it < p->pcg_iters; ++it) {
+    gn_hv_launch(c, p, c->vp, c->vq, true, stop, s);
+    launch_reduce(c->blk_node, c->nodeblocks, 3, 1, 0u, sc + SC_DOT, stop, s);
+    hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1), 0, s, sc, c->status);
+    hipLaunchKernelGGL(k_pcg_update, dim3(nb3), dim3(256), 0, s, n3, sc, c->vdiag, (float)p->tau, c->vp, c->vq,
+                       c->vx, c->vr, c->vz, c->blk_node);
+    launch_reduce(c->blk_node, nb3, 2, 2, 0u, sc + SC_TMP0, stop, s);
+    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1), 0, s, sc, p->pcg_tol);
+    if (it + 1 < p->pcg_iters) hipLaunchKernelGGL(k_pcg_p, dim3(nb3), dim3(256), 0, s, n3, sc, c->vz, c->vp);
+  }
+
+  // ---- Armijo line search on J(u + t x) ------------------------------------------------
+  hipLaunchKernelGGL(k_dot, dim3(nb3), dim3(256), 0, s, n3, c->vg, c->vx, c->blk_node);
+  launch_reduce(c->blk_node, nb3, 1, 1, 0u, sc + SC_TMP0, nullptr, s);
+  hipLaunchKernelGGL(k_ls_begin, dim3(1), dim3(1), 0, s, sc);
+  const double *acc = sc + SC_ACCEPT;
+  const bool dev_ls = (p->flags & DISCO_FLAG_LS_DEVICE) != 0;
+  for (int t = 0; t < p->ls_max; ++t) {
+    hipLaunchKernelGGL(k_ls_point, dim3(nb3), dim3(256), 0, s, n3, sc, t, u, c->vx, c->vut);
+    launch_curv_L(c, c->vut, c->u_ref, c->Lw, true, acc, s);
+    launch_reduce(c->blk_node, c->nodeblocks, 1, 1, 0u, sc + SC_TSRAW, acc, s);
+    BrickCall b{M_EVAL, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, c->vut, nullptr, nullptr, nullptr, acc};
+    launch_brick(c, b, s);
+    launch_reduce(c->blk_brick, c->nwg, BS_N, BS_N, 0u, sc + SC_TMP0, acc, s);
+    hipLaunchKernelGGL(k_ls_move, dim3(1), dim3(1), 0, s, sc, (double)g.hx * (double)g.hy * (double)g.hz);
+    hipLaunchKernelGGL(k_ls_decide, dim3(1), dim3(1), 0, s, sc, w, p->armijo_c1);
+    if (!dev_ls) {
+      HIP_TRY(hipMemcpyAsync(c->host_sc, sc + SC_ACCEPT, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (c->host_sc[0] != 0.0) break;
+    }
+  }
+  hipLaunchKernelGGL(k_ls_finish, dim3(nb3), dim3(256), 0, s, n3, sc, c->vut, u);
+  hipLaunchKernelGGL(k_report, dim3(1), dim3(1), 0, s, sc, w, report_dev, c->status, status_dev);
+  HIP_TRY(hipGetLastError());
+  // the s cache and u_lin now describe the linearisation point of this step
+  return DISCO_OK;
+}
+
+int disco_copy_buffer(disco_ctx *c, int32_t which, float *dst, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_field(dst))) return e;
+  if (which < 0 || which > 2) return DISCO_ERR_ARG;
+  if (which < 2 && !c->images) return DISCO_ERR_STATE;
+  if (which == 2 && !c->lin) return DISCO_ERR_STATE;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  const void *src = which == 0 ? c->gR : (which == 1 ? c->gT : c->scache);
+  const float sc = which == 0 ? c->sR : (which == 1 ? c->sT : c->sS_load);
+  if (c->storage == DISCO_STORAGE_FP16)
+    hipLaunchKernelGGL(k_unpack3<F16x4>, dim3(nblk(c->g.nvox)), dim3(256), 0, s, c->g,
+                       reinterpret_cast<const __half *>(src), sc, dst);
+  else
+    hipLaunchKernelGGL(k_unpack3<F32x3>, dim3(nblk(c->g.nvox)), dim3(256), 0, s, c->g,
+                       reinterpret_cast<const float *>(src), 1.0f, dst);
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+int disco_profile(disco_ctx *c, int32_t enable) {
+  if (!c) return DISCO_ERR_ARG;
+  if (enable) {
+    (void)hipDeviceSynchronize();
+    clear_profile(c);
+  }
+  c->prof = enable != 0;
+  return DISCO_OK;
+}
+
+int disco_profile_read(disco_ctx *c, int32_t kernel, int64_t *launches, double *ms_total) {
+  if (!c || !launches || !ms_total || kernel < 0 || kernel > 3) return DISCO_ERR_ARG;
+  double tot = 0.0;
+  for (auto &p : c->ev[kernel]) {
+    HIP_TRY(hipEventSynchronize(p.b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p.a, p.b));
+    tot += ms;
+  }
+  *launches = (int64_t)c->ev[kernel].size();
+  *ms_total = tot;
+  return DISCO_OK;
+}
+
+}  // extern "C"

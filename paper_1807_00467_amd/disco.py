@@ -1,0 +1,278 @@
+"""Thin ctypes binding of libdisco.so (the C ABI in include/disco.h).
+
+Argument marshalling only: every step of the objective, its derivatives and the
+Gauss-Newton step runs in the HIP kernels of the library.  PyTorch provides device
+memory and the current HIP stream.  There is no CPU fallback: importing this module
+raises if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdisco.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'` "
+                      "(hipcc, gfx950); there is no CPU fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ---- constants (mirror include/disco.h) -------------------------------------------------
+OK = 0
+ERR_ARG, ERR_SHAPE, ERR_STATE, ERR_NONFINITE, ERR_NOMEM, ERR_HIP = -1, -2, -3, -4, -5, -100
+STATUS_FOLD, STATUS_PCG_BREAKDOWN, STATUS_LS_FAIL = 1, 2, 4
+STORAGE_FP32, STORAGE_FP16 = 0, 1
+FLAG_LS_DEVICE = 1
+BUF_GRAD_R, BUF_GRAD_T, BUF_SCACHE = 0, 1, 2
+REPORT_FIELDS = ["J", "D", "S", "V", "K", "gnorm", "t", "pcg_iters", "pcg_res", "gtp",
+                 "J_new", "D_new", "S_new", "V_new", "K_new", "ls_trials"]
+PROF_HV, PROF_GRAD, PROF_EVAL, PROF_IMGRAD = 0, 1, 2, 3
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("h", ctypes.c_double * 3)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("eta", ctypes.c_double), ("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("delta", ctypes.c_double), ("tau", ctypes.c_double), ("armijo_c1", ctypes.c_double),
+                ("pcg_tol", ctypes.c_double), ("pcg_iters", ctypes.c_int32), ("ls_max", ctypes.c_int32),
+                ("flags", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int32
+
+_SIGS = {
+    "disco_create": ([ctypes.POINTER(_Geom), _I, ctypes.POINTER(_P)], ctypes.c_int),
+    "disco_destroy": ([_P], None),
+    "disco_set_images": ([_P, _P, _P, _P], ctypes.c_int),
+    "disco_set_keypoints": ([_P, _I, _P, _P, _P], ctypes.c_int),
+    "disco_set_reference": ([_P, _P, _P], ctypes.c_int),
+    "ngf_eval": ([_P, _D, _P, _P, _P], ctypes.c_int),
+    "ngf_grad": ([_P, _D, _P, _P, _P, _P, _P], ctypes.c_int),
+    "ngf_hessvec": ([_P, _P, _P, _P], ctypes.c_int),
+    "curvature_apply": ([_P, _D, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "volchange_eval": ([_P, _D, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "keypoint_penalty": ([_P, _D, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "gn_hessvec": ([_P, ctypes.POINTER(_Params), _P, _P, _P], ctypes.c_int),
+    "gn_pcg_step": ([_P, ctypes.POINTER(_Params), _P, _P, _P, _P], ctypes.c_int),
+    "disco_copy_buffer": ([_P, _I, _P, _P], ctypes.c_int),
+    "disco_profile": ([_P, _I], ctypes.c_int),
+    "disco_profile_read": ([_P, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D)], ctypes.c_int),
+    "disco_status_string": ([ctypes.c_int], ctypes.c_char_p),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTS = tuple(_SIGS)
+
+
+class DiscoError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {_lib.disco_status_string(code).decode()} (code {code})")
+
+
+def _check(code: int, where: str):
+    if code != OK:
+        raise DiscoError(code, where)
+
+
+@dataclasses.dataclass
+class Params:
+    eta: float = 10.0
+    alpha: float = 1.0
+    gamma: float = 0.1
+    delta: float = 0.0
+    tau: float = 0.0
+    armijo_c1: float = 1e-4
+    pcg_tol: float = 0.0
+    pcg_iters: int = 20
+    ls_max: int = 10
+    flags: int = 0
+
+    def c(self) -> _Params:
+        return _Params(self.eta, self.alpha, self.gamma, self.delta, self.tau, self.armijo_c1, self.pcg_tol,
+                       self.pcg_iters, self.ls_max, self.flags)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Disco:
+    """One image-pair context on the current (or given) HIP device."""
+
+    def __init__(self, shape: Sequence[int], spacing: Sequence[float], storage: str = "fp32",
+                 device: Optional[torch.device] = None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.shape = tuple(int(s) for s in shape)
+        self.spacing = tuple(float(h) for h in spacing)
+        nx, ny, nz = self.shape
+        self.nodes = (nx // 4 + 1, ny // 4 + 1, nz // 4 + 1)
+        self.storage = STORAGE_FP16 if storage == "fp16" else STORAGE_FP32
+        geom = _Geom((ctypes.c_int32 * 3)(*self.shape), (ctypes.c_double * 3)(*self.spacing))
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.disco_create(ctypes.byref(geom), self.storage, ctypes.byref(h)), "disco_create")
+        self._h = h
+        self._scalars = torch.zeros(64, dtype=torch.float64, device=self.device)
+        self._ints = torch.zeros(8, dtype=torch.int32, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.disco_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- helpers ------------------------------------------------------------------------
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def node_field(self) -> torch.Tensor:
+        nx, ny, nz = self.nodes
+        return torch.empty((3, nz, ny, nx), dtype=torch.float32, device=self.device)
+
+    def _field(self, t: torch.Tensor, name: str) -> torch.Tensor:
+        nx, ny, nz = self.nodes
+        if t.device != self.device or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 tensor on {self.device}")
+        if tuple(t.shape) != (3, nz, ny, nx):
+            raise ValueError(f"{name} must have shape (3, {nz}, {ny}, {nx}), got {tuple(t.shape)}")
+        return t
+
+    def _volume(self, t: torch.Tensor, name: str) -> torch.Tensor:
+        nx, ny, nz = self.shape
+        if t.device != self.device or t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 tensor on {self.device}")
+        if tuple(t.shape) != (nz, ny, nx):
+            raise ValueError(f"{name} must have shape ({nz}, {ny}, {nx}), got {tuple(t.shape)}")
+        return t
+
+    # ---- state --------------------------------------------------------------------------
+    def set_images(self, R: torch.Tensor, T: torch.Tensor):
+        _check(_lib.disco_set_images(self._h, _ptr(self._volume(R, "R")), _ptr(self._volume(T, "T")),
+                                     self._stream()), "disco_set_images")
+
+    def set_keypoints(self, x_mm, t_mm):
+        import numpy as np
+        x = np.ascontiguousarray(np.asarray(x_mm, dtype=np.float32).reshape(-1, 3))
+        t = np.ascontiguousarray(np.asarray(t_mm, dtype=np.float32).reshape(-1, 3))
+        if x.shape != t.shape:
+            raise ValueError("keypoints and targets differ in shape")
+        _check(_lib.disco_set_keypoints(self._h, len(x), x.ctypes.data_as(_P), t.ctypes.data_as(_P),
+                                        self._stream()), "disco_set_keypoints")
+
+    def set_reference(self, u_ref: Optional[torch.Tensor]):
+        _check(_lib.disco_set_reference(self._h, _ptr(None if u_ref is None else self._field(u_ref, "u_ref")),
+                                        self._stream()), "disco_set_reference")
+
+    # ---- single terms -------------------------------------------------------------------
+    def ngf_eval(self, u: torch.Tensor, eta: float) -> torch.Tensor:
+        D = self._scalars[0:1]
+        _check(_lib.ngf_eval(self._h, eta, _ptr(self._field(u, "u")), _ptr(D), self._stream()), "ngf_eval")
+        return D.clone()
+
+    def ngf_grad(self, u: torch.Tensor, eta: float, diag: bool = True):
+        g = self.node_field()
+        d = self.node_field() if diag else None
+        D = self._scalars[1:2]
+        _check(_lib.ngf_grad(self._h, eta, _ptr(self._field(u, "u")), _ptr(D), _ptr(g), _ptr(d), self._stream()),
+               "ngf_grad")
+        return D.clone(), g, d
+
+    def ngf_hessvec(self, v: torch.Tensor) -> torch.Tensor:
+        out = self.node_field()
+        _check(_lib.ngf_hessvec(self._h, _ptr(self._field(v, "v")), _ptr(out), self._stream()), "ngf_hessvec")
+        return out
+
+    def curvature_apply(self, alpha: float, u: torch.Tensor, u_ref: Optional[torch.Tensor] = None,
+                        energy: bool = True, grad: bool = True, diag: bool = False):
+        S = self._scalars[2:3] if energy else None
+        out = self.node_field() if grad else None
+        d = self.node_field() if diag else None
+        _check(_lib.curvature_apply(self._h, alpha, _ptr(self._field(u, "u")),
+                                    _ptr(None if u_ref is None else self._field(u_ref, "u_ref")), _ptr(S), _ptr(out),
+                                    _ptr(d), self._stream()), "curvature_apply")
+        return (None if S is None else S.clone()), out, d
+
+    def volchange_eval(self, gamma: float, u: torch.Tensor, v: Optional[torch.Tensor] = None,
+                       energy: bool = True, grad: bool = True, diag: bool = True):
+        V = self._scalars[3:4] if energy else None
+        g = self.node_field() if grad else None
+        d = self.node_field() if diag else None
+        Hv = self.node_field() if v is not None else None
+        nf = self._ints[0:1]
+        _check(_lib.volchange_eval(self._h, gamma, _ptr(self._field(u, "u")), _ptr(V), _ptr(g), _ptr(d),
+                                   _ptr(None if v is None else self._field(v, "v")), _ptr(Hv), _ptr(nf),
+                                   self._stream()), "volchange_eval")
+        return dict(V=None if V is None else V.clone(), g=g, diag=d, Hv=Hv, nfold=nf.clone())
+
+    def keypoint_penalty(self, delta: float, u: torch.Tensor, v: Optional[torch.Tensor] = None,
+                         energy: bool = True, grad: bool = True, diag: bool = True):
+        K = self._scalars[4:5] if energy else None
+        g = self.node_field() if grad else None
+        d = self.node_field() if diag else None
+        Hv = self.node_field() if v is not None else None
+        _check(_lib.keypoint_penalty(self._h, delta, _ptr(self._field(u, "u")), _ptr(K), _ptr(g), _ptr(d),
+                                     _ptr(None if v is None else self._field(v, "v")), _ptr(Hv), self._stream()),
+               "keypoint_penalty")
+        return dict(K=None if K is None else K.clone(), g=g, diag=d, Hv=Hv)
+
+    # ---- Gauss-Newton ---------------------------------------------------------------------
+    def gn_hessvec(self, params: Params, v: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self.node_field() if out is None else out
+        p = params.c()
+        _check(_lib.gn_hessvec(self._h, ctypes.byref(p), _ptr(self._field(v, "v")), _ptr(out), self._stream()),
+               "gn_hessvec")
+        return out
+
+    def gn_pcg_step(self, params: Params, u: torch.Tensor, report: Optional[torch.Tensor] = None,
+                    status: Optional[torch.Tensor] = None):
+        """One GN step in place on u.  Returns (report tensor [16] float64, status int32 tensor)."""
+        rep = torch.zeros(16, dtype=torch.float64, device=self.device) if report is None else report
+        st = torch.zeros(1, dtype=torch.int32, device=self.device) if status is None else status
+        p = params.c()
+        _check(_lib.gn_pcg_step(self._h, ctypes.byref(p), _ptr(self._field(u, "u")), _ptr(rep), _ptr(st),
+                                self._stream()), "gn_pcg_step")
+        return rep, st
+
+    @staticmethod
+    def report_dict(rep: torch.Tensor) -> dict:
+        vals = rep.cpu().tolist()
+        return dict(zip(REPORT_FIELDS, vals))
+
+    # ---- buffers and profiling -----------------------------------------------------------
+    def copy_buffer(self, which: int) -> torch.Tensor:
+        nx, ny, nz = self.shape
+        out = torch.empty((nz, ny, nx, 3), dtype=torch.float32, device=self.device)
+        _check(_lib.disco_copy_buffer(self._h, which, _ptr(out), self._stream()), "disco_copy_buffer")
+        return out
+
+    def profile(self, enable: bool):
+        _check(_lib.disco_profile(self._h, 1 if enable else 0), "disco_profile")
+
+    def profile_read(self, kernel: int):
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        _check(_lib.disco_profile_read(self._h, kernel, ctypes.byref(n), ctypes.byref(ms)), "disco_profile_read")
+        return n.value, ms.value
+
+
+def status_string(code: int) -> str:
+    return _lib.disco_status_string(code).decode()
