@@ -1,0 +1,192 @@
+"""Benchmark of the dense DIS-CO objective hot path on one MI355X.
+
+One step = one pass of the whole path on the 512 x 512 x 128 (0.7 x 0.7 x 2.5 mm)
+synthetic lung-CT pair: image gradients of R and T, then one Gauss-Newton step from
+the true displacement (linearisation: objective, gradient, GN diagonal and the
+per-voxel GN vectors; 20 Jacobi-PCG iterations, each one full GN product of eq. 11;
+Armijo line search).  The step's inputs are resident in HBM before timing starts.
+
+value = GN products per second over the timed steps (20 per step).  The roofline
+entry is for the dominant kernel, the voxel-brick GN-product pass, timed with HIP
+events on its launch stream during the timed steps.  The CPU baseline times the FP64
+oracle on a bounded sample of the same workload (GN products at full size).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GN Hv products/s + Gvoxel/s at 512²×128; achieved HBM GB/s vs 8 TB/s peak"
+HBM_PEAK_GBS = 8000.0
+PCG_ITERS = 20
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def traffic_from_profiles(kernel_tag):
+    """HBM bytes per launch measured by rocprofv3 counters (committed summary), if any."""
+    path = os.path.join(ROOT, "profiles", "counters_" + kernel_tag + ".json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            return json.load(f).get("traffic_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(d, params, budget_s=25.0):
+    """The FP64 oracle, as it stands, on a bounded sample: one linearisation (untimed)
+    then as many full-size GN products as fit in the budget (at least one)."""
+    import numpy as np
+    import oracle
+    P = oracle.Problem(d["R"], d["T"], d["spacing"], d["kp_x"], d["kp_t"],
+                       oracle.Weights(eta=params.eta, alpha=params.alpha, gamma=params.gamma, delta=params.delta))
+    t0 = time.perf_counter()
+    P.linearise(d["u_true"].astype(np.float64))
+    t_lin = time.perf_counter() - t0
+    v = d["v"].astype(np.float64)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        P.gn_hv(v)
+        n += 1
+        el = time.perf_counter() - t0
+        if el + el / n > budget_s or n >= 16:
+            break
+    return dict(value=n / el, unit="Hv/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{n} full GN products of eq. 11 at 512x512x128 (FP64 C oracle) after one "
+                       f"linearisation ({t_lin:.1f} s, untimed); {el:.1f} s timed")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="cfg1")
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_1807_00467_amd import disco
+
+    log(f"[bench] generating {args.config} ...")
+    t0 = time.perf_counter()
+    d = synth.make_pair(args.config)
+    log(f"[bench] generated in {time.perf_counter() - t0:.1f} s; shape {d['shape']} spacing {d['spacing']}")
+    dev = torch.device("cuda:0")
+    R = torch.from_numpy(d["R"]).to(dev)
+    T = torch.from_numpy(d["T"]).to(dev)
+    u_true = torch.from_numpy(d["u_true"]).to(dev)
+    ctx = disco.Disco(d["shape"], d["spacing"], storage=args.storage, device=dev)
+    ctx.set_images(R, T)
+    ctx.set_keypoints(d["kp_x"], d["kp_t"])
+    zero = torch.zeros_like(u_true)
+    # adaptive keypoint weight: D = delta K at the start (u = 0)
+    D0 = ctx.ngf_eval(zero, 10.0).item()
+    K0 = ctx.keypoint_penalty(1.0, zero, grad=False, diag=False)["K"].item()
+    params = disco.Params(eta=10.0, alpha=1.0, gamma=0.1, delta=D0 / K0 if K0 > 0 else 0.0,
+                          pcg_iters=PCG_ITERS, pcg_tol=0.0, ls_max=10)
+    log(f"[bench] delta = {params.delta:.4g}")
+    u = torch.empty_like(u_true)
+    rep = torch.zeros(16, dtype=torch.float64, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def step():
+        u.copy_(u_true)
+        ctx.set_images(R, T)
+        ctx.gn_pcg_step(params, u, rep, st)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.profile(False)
+    n_hv, ms_hv = ctx.profile_read(disco.PROF_HV)
+    n_gr, ms_gr = ctx.profile_read(disco.PROF_GRAD)
+    n_ev, ms_ev = ctx.profile_read(disco.PROF_EVAL)
+    n_ig, ms_ig = ctx.profile_read(disco.PROF_IMGRAD)
+    r = disco.Disco.report_dict(rep)
+    log(f"[bench] last step report: {r}; status {int(st.item())}")
+
+    nvox = int(np.prod(d["shape"]))
+    nx, ny, nz = ctx.nodes
+    nnodes = nx * ny * nz
+    bpv = 12 if args.storage == "fp32" else 8
+    hv_bytes = bpv * nvox + 36 * nnodes           # s stream + v, u (VCC) read + Hv write
+    hv_s = ms_hv / max(n_hv, 1) / 1e3
+    achieved = hv_bytes / hv_s / 1e9
+    hv_total = PCG_ITERS * args.steps
+    value = hv_total / elapsed
+    kernel_tag = f"brick_hv_{args.config}_{args.storage}"
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Hv/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage == "fp32" else "f16-storage/f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.config}: R,T {d['shape'][0]}x{d['shape'][1]}x{d['shape'][2]} at "
+                        f"{d['spacing'][0]}x{d['spacing'][1]}x{d['spacing'][2]} mm, node grid {nx}x{ny}x{nz}, "
+                        f"{len(d['kp_x'])} keypoints; step = image gradients + GN step "
+                        f"(linearise + {PCG_ITERS} PCG GN products + Armijo)",
+            "eta": params.eta, "alpha": params.alpha, "gamma": params.gamma, "delta": params.delta,
+            "storage": args.storage,
+        },
+        "gvoxel_per_s_hv_kernel": nvox / hv_s / 1e9,
+        "hv_kernel_us": hv_s * 1e6,
+        "grad_kernel_us": 1e3 * ms_gr / max(n_gr, 1),
+        "eval_kernel_us": 1e3 * ms_ev / max(n_ev, 1),
+        "imgrad_kernel_us": 1e3 * ms_ig / max(n_ig, 1),
+        "launches": {"hv": n_hv, "grad": n_gr, "eval": n_ev, "imgrad": n_ig},
+        "roofline": {
+            "kernel": "k_brick<HV> (NGF + VCC + keypoint GN product pass)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_from_profiles(kernel_tag),
+            "algorithmic_bytes_per_launch": hv_bytes,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(d, params)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

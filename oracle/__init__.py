@@ -70,8 +70,15 @@ def _load():
         lib.or_keypoints.restype = D
         lib.or_det_voxels.argtypes = [P, P, P, P, P]
         lib.or_det_voxels.restype = None
+        lib.or_num_threads.argtypes = []
+        lib.or_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def num_threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(_load().or_num_threads())
 
 
 def _p(a: Optional[np.ndarray]):

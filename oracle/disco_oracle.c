@@ -28,6 +28,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define IDX3(i, j, k, nx, ny) ((((int64_t)(k)) * (ny) + (j)) * (nx) + (i))
 
@@ -677,4 +680,14 @@ void or_det_voxels(const int64_t *n, const int64_t *m, const double *h, const do
                 or_vcc_cell_expansion(nn, H, u, cell, xi, alpha, d, &de);
                 det[IDX3(i, j, k, n[0], n[1])] = de;
             }
+}
+
+/* number of threads the parallel loops use (for reporting) */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
