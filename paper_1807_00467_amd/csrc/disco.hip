@@ -19,7 +19,8 @@ using namespace disco;
 
 namespace {
 
-constexpr int kZC = 4;  // cells per brick along z
+constexpr int kZC = 4;          // cells per brick along z
+constexpr int kUpdBlocks = 256;  // workgroups of the grid-stride CG vector kernels
 
 struct EventPair {
   hipEvent_t a, b;
@@ -51,6 +52,7 @@ struct disco_ctx {
         *vut = nullptr, *tmp0 = nullptr, *tmp1 = nullptr;
   float *part = nullptr;
   double *blk_brick = nullptr, *blk_node = nullptr, *sc = nullptr;
+  double *blk_curv = nullptr, *blk_upd = nullptr;
   int *status = nullptr;
   double *host_sc = nullptr;  // pinned
   // keypoints
@@ -78,6 +80,12 @@ inline bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 inline hipStream_t S(disco_stream s) { return reinterpret_cast<hipStream_t>(s); }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// 3-D grid of 64 x 4 thread blocks over the node grid
+inline dim3 node_grid(const Geo &g) { return dim3((g.px + 63) / 64, (g.py + 3) / 4, g.pz); }
+inline int64_t node_blocks(const Geo &g) { return (int64_t)((g.px + 63) / 64) * ((g.py + 3) / 4) * g.pz; }
+// 3-D grid over the voxels (rows of 256)
+inline dim3 vox_grid(const Geo &g) { return dim3((g.nx + 255) / 256, g.ny, g.nz); }
 
 struct ProfScope {
   disco_ctx *c;
@@ -183,12 +191,40 @@ void launch_brick(disco_ctx *c, const BrickCall &b, hipStream_t s) {
   }
 }
 
+double ch_of(const disco_ctx *c) { return (double)c->g.Hx * (double)c->g.Hy * (double)c->g.Hz; }
+double h3_of(const disco_ctx *c) { return (double)c->g.hx * (double)c->g.hy * (double)c->g.hz; }
+
+PostArgs post_args(disco_ctx *c, double alpha = 0.0, double gamma = 0.0, double delta = 0.0) {
+  PostArgs a{};
+  a.sc = c->sc;
+  a.status = c->status;
+  a.alpha = alpha;
+  a.gamma = gamma;
+  a.delta = delta;
+  a.CH = ch_of(c);
+  a.h3 = h3_of(c);
+  return a;
+}
+
+RedSrc src_brick(disco_ctx *c, double *out) { return RedSrc{c->blk_brick, c->nwg, BS_N, BS_N, 0u, out}; }
+RedSrc src_curv(disco_ctx *c, double *out) { return RedSrc{c->blk_curv, c->nodeblocks, 1, 1, 0u, out}; }
+// gather blocks: <dotv,out0>, max out1, |out0|^2
+RedSrc src_gather(disco_ctx *c, double *out) { return RedSrc{c->blk_node, c->nodeblocks, 3, 3, 2u, out}; }
+RedSrc src_pairs(const double *blocks, int64_t nb, int nvals, double *out) { return RedSrc{blocks, nb, 2, nvals, 0u, out}; }
+
+void launch_finish(int post, const PostArgs &pa, const double *stop, hipStream_t s, RedSrc s0, RedSrc s1 = RedSrc{},
+                   RedSrc s2 = RedSrc{}) {
+  const int n = s2.blocks ? 3 : (s1.blocks ? 2 : 1);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(1024), 0, s, s0, s1, s2, n, post, pa, stop);
+}
+
 void launch_reduce(const double *blocks, int64_t nb, int stride, int nvals, uint32_t max_mask, double *out,
                    const double *stop, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, s, blocks, nb, stride, nvals, max_mask, out, stop);
 }
 
-// gather after a brick pass (F fields written by the brick kernel, nf produced)
+// gather after a brick pass (F fields written by the brick kernel, nf produced); with
+// `reduce` it writes per-block <dotv, out0>, max out1, |out0|^2 to blk_node
 void launch_gather(disco_ctx *c, int F, int nf, float *out0, float *out1, const float *Lw, float curv_scale,
                    int curv_diag, const float *tauv, float tau, const float *dotv, bool reduce, const double *stop,
                    hipStream_t s) {
@@ -207,16 +243,27 @@ void launch_gather(disco_ctx *c, int F, int nf, float *out0, float *out1, const 
   a.dotv = dotv;
   a.blocks = reduce ? c->blk_node : nullptr;
   a.stop = stop;
-  hipLaunchKernelGGL((k_gather<kZC>), dim3(nblk(c->g.nnodes)), dim3(256), 0, s, a);
+  const dim3 grid = node_grid(c->g);
+  const bool curv = Lw != nullptr;
+#define GATHER(Fv, NFv, CV) hipLaunchKernelGGL((k_gather<kZC, Fv, NFv, CV>), grid, dim3(256), 0, s, a)
+  if (F == 2 && nf == 2) {
+    if (curv) GATHER(2, 2, true); else GATHER(2, 2, false);
+  } else if (F == 1 && nf == 1) {
+    if (curv) GATHER(1, 1, true); else GATHER(1, 1, false);
+  } else if (F == 0 && nf == 2) {
+    if (curv) GATHER(0, 2, true); else GATHER(0, 2, false);
+  } else {
+    if (curv) GATHER(0, 1, true); else GATHER(0, 1, false);
+  }
+#undef GATHER
 }
 
+// L w with w = a - b; with `energy` it writes per-block sum (L w)^2 to blk_curv
 void launch_curv_L(disco_ctx *c, const float *a, const float *b, float *Lw, bool energy, const double *stop,
                    hipStream_t s) {
-  hipLaunchKernelGGL(k_curv_L, dim3(nblk(c->g.nnodes)), dim3(256), 0, s, c->g, a, b, Lw,
-                     energy ? c->blk_node : nullptr, stop);
+  hipLaunchKernelGGL(k_curv_L, node_grid(c->g), dim3(256), 0, s, c->g, a, b, Lw, energy ? c->blk_curv : nullptr,
+                     stop);
 }
-
-double ch_of(const disco_ctx *c) { return (double)c->g.Hx * (double)c->g.Hy * (double)c->g.Hz; }
 
 int check_field(const void *p) {
   if (!p) return DISCO_ERR_ARG;
@@ -257,7 +304,7 @@ void disco_destroy(disco_ctx *c) {
   clear_profile(c);
   void *ptrs[] = {c->gR,  c->gT,  c->scache, c->u_lin, c->u_ref, c->Lw,   c->vg,   c->vdiag, c->vx,   c->vr,
                   c->vz,  c->vp,  c->vq,     c->vut,   c->tmp0,  c->tmp1, c->part, c->blk_brick, c->blk_node,
-                  c->sc,  c->status, c->kloc, c->ktgt, c->kstart};
+                  c->sc,  c->status, c->kloc, c->ktgt, c->kstart, c->blk_curv, c->blk_upd};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->host_sc) (void)hipHostFree(c->host_sc);
@@ -275,7 +322,7 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
   }
   // 32-bit node/voxel coordinates; 64-bit linear indices
   const int64_t nvox = (int64_t)geom->n[0] * geom->n[1] * geom->n[2];
-  if (nvox > ((int64_t)1 << 34)) return DISCO_ERR_SHAPE;
+  if (nvox >= ((int64_t)1 << 31)) return DISCO_ERR_SHAPE;
 
   disco_ctx *c = new (std::nothrow) disco_ctx();
   if (!c) return DISCO_ERR_NOMEM;
@@ -312,7 +359,7 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
   g.nnodes = (int64_t)g.px * g.py * g.pz;
   c->ncells = (int64_t)g.cx * g.cy * g.cz;
   c->nwg = (int64_t)g.nbx * g.nby * g.nbz;
-  c->nodeblocks = nblk(g.nnodes);
+  c->nodeblocks = node_blocks(g);
 
   const size_t vec3 = storage == DISCO_STORAGE_FP16 ? 8 : 12;  // bytes per voxel 3-vector
   const size_t nf = 3 * (size_t)g.nnodes * sizeof(float);
@@ -336,6 +383,8 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
   alloc(reinterpret_cast<void **>(&c->blk_node), sizeof(double) * ((size_t)c->nodeblocks * 6 + 16));
   alloc(reinterpret_cast<void **>(&c->sc), sizeof(double) * SC_COUNT);
   alloc(reinterpret_cast<void **>(&c->status), sizeof(int));
+  alloc(reinterpret_cast<void **>(&c->blk_curv), sizeof(double) * (size_t)c->nodeblocks);
+  alloc(reinterpret_cast<void **>(&c->blk_upd), sizeof(double) * 2 * kUpdBlocks);
   alloc(reinterpret_cast<void **>(&c->kstart), sizeof(int) * (size_t)(c->ncells + 1));
   if (okm && hipHostMalloc(reinterpret_cast<void **>(&c->host_sc), sizeof(double) * SC_COUNT) != hipSuccess) {
     c->host_sc = nullptr;
@@ -347,7 +396,8 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
   }
   if (hipMemset(c->kstart, 0, sizeof(int) * (size_t)(c->ncells + 1)) != hipSuccess ||
       hipMemset(c->sc, 0, sizeof(double) * SC_COUNT) != hipSuccess ||
-      hipMemset(c->status, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      hipMemset(c->status, 0, sizeof(int)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
     disco_destroy(c);
     return DISCO_ERR_NOMEM;
   }
@@ -384,15 +434,15 @@ int disco_set_images(disco_ctx *c, const float *R, const float *T, disco_stream 
     HIP_TRY(hipFreeAsync(blk, s));
     c->sR = 1.0f / scales[0];
     c->sT = 1.0f / scales[1];
-    hipLaunchKernelGGL(k_imgrad<F16x4>, dim3(nb), dim3(256), 0, s, g, R, reinterpret_cast<__half *>(c->gR),
+    hipLaunchKernelGGL(k_imgrad<F16x4>, vox_grid(g), dim3(256), 0, s, g, R, reinterpret_cast<__half *>(c->gR),
                        scales[0]);
-    hipLaunchKernelGGL(k_imgrad<F16x4>, dim3(nb), dim3(256), 0, s, g, T, reinterpret_cast<__half *>(c->gT),
+    hipLaunchKernelGGL(k_imgrad<F16x4>, vox_grid(g), dim3(256), 0, s, g, T, reinterpret_cast<__half *>(c->gT),
                        scales[1]);
   } else {
-    hipLaunchKernelGGL(k_imgrad<F32x3>, dim3(nblk(g.nvox)), dim3(256), 0, s, g, R,
-                       reinterpret_cast<float *>(c->gR), 1.0f);
-    hipLaunchKernelGGL(k_imgrad<F32x3>, dim3(nblk(g.nvox)), dim3(256), 0, s, g, T,
-                       reinterpret_cast<float *>(c->gT), 1.0f);
+    hipLaunchKernelGGL(k_imgrad<F32x3>, vox_grid(g), dim3(256), 0, s, g, R, reinterpret_cast<float *>(c->gR),
+                       1.0f);
+    hipLaunchKernelGGL(k_imgrad<F32x3>, vox_grid(g), dim3(256), 0, s, g, T, reinterpret_cast<float *>(c->gT),
+                       1.0f);
   }
   HIP_TRY(hipGetLastError());
   c->images = true;
@@ -490,11 +540,13 @@ int ngf_eval(disco_ctx *c, double eta, const float *u, double *D_dev, disco_stre
   if (!c->images) return DISCO_ERR_STATE;
   if ((e = set_device(c))) return e;
   hipStream_t s = S(stream);
+  PostArgs pa = post_args(c);
+  pa.dst = D_dev;
+  pa.idx = BS_D;
+  pa.scale = h3_of(c);
   BrickCall b{M_EVAL, true, false, false, (float)(eta * eta), 0.f, 0.f, u, nullptr, nullptr, nullptr, nullptr};
   launch_brick(c, b, s);
-  launch_reduce(c->blk_brick, c->nwg, BS_N, 1, 0u, c->sc + SC_TMP0, nullptr, s);
-  hipLaunchKernelGGL(k_write_scalar, dim3(1), dim3(1), 0, s, c->sc + SC_TMP0,
-                     (double)c->g.hx * (double)c->g.hy * (double)c->g.hz, D_dev, (const double *)nullptr, 0);
+  launch_finish(POST_WRITE, pa, nullptr, s, src_brick(c, c->sc + SC_TMP0));
   HIP_TRY(hipGetLastError());
   return DISCO_OK;
 }
@@ -509,11 +561,13 @@ int ngf_grad(disco_ctx *c, double eta, const float *u, double *D_dev, float *g, 
   if ((e = set_device(c))) return e;
   hipStream_t s = S(stream);
   float *d1 = diag ? diag : c->tmp1;
+  PostArgs pa = post_args(c);
+  pa.dst = D_dev;
+  pa.idx = BS_D;
+  pa.scale = h3_of(c);
   BrickCall b{M_GRAD, true, false, false, (float)(eta * eta), 0.f, 0.f, u, nullptr, g, d1, nullptr};
   launch_brick(c, b, s);
-  launch_reduce(c->blk_brick, c->nwg, BS_N, 1, 0u, c->sc + SC_TMP0, nullptr, s);
-  hipLaunchKernelGGL(k_write_scalar, dim3(1), dim3(1), 0, s, c->sc + SC_TMP0,
-                     (double)c->g.hx * (double)c->g.hy * (double)c->g.hz, D_dev, (const double *)nullptr, 0);
+  launch_finish(POST_WRITE, pa, nullptr, s, src_brick(c, c->sc + SC_TMP0));
   launch_gather(c, 2, 2, g, d1, nullptr, 0.f, 0, nullptr, 0.f, nullptr, false, nullptr, s);
   HIP_TRY(hipMemcpyAsync(c->u_lin, u, 3 * sizeof(float) * (size_t)c->g.nnodes, hipMemcpyDeviceToDevice, s));
   HIP_TRY(hipGetLastError());
@@ -546,12 +600,12 @@ int curvature_apply(disco_ctx *c, double alpha, const float *u, const float *u_r
   if ((e = set_device(c))) return e;
   hipStream_t s = S(stream);
   const double CH = ch_of(c);
+  PostArgs pa = post_args(c);
+  pa.dst = S_dev;
+  pa.idx = 0;
+  pa.scale = 0.5 * CH * alpha;
   launch_curv_L(c, u, u_ref, c->Lw, S_dev != nullptr, nullptr, s);
-  if (S_dev) {
-    launch_reduce(c->blk_node, c->nodeblocks, 1, 1, 0u, c->sc + SC_TMP0, nullptr, s);
-    hipLaunchKernelGGL(k_write_scalar, dim3(1), dim3(1), 0, s, c->sc + SC_TMP0, 0.5 * CH * alpha, S_dev,
-                       (const double *)nullptr, 0);
-  }
+  if (S_dev) launch_finish(POST_WRITE, pa, nullptr, s, src_curv(c, c->sc + SC_TMP0));
   if (out || diag) {
     float *o0 = out ? out : c->tmp0;
     float *o1 = diag ? diag : c->tmp1;
@@ -574,17 +628,20 @@ static int cell_term(disco_ctx *c, bool vcc, double w, const float *u, double *E
   const float wf = (float)w;
   if (E_dev || nfold_dev || g || diag) {
     const bool grad = g || diag;
+    PostArgs pa = post_args(c);
+    pa.dst = E_dev;
+    pa.idst = nfold_dev;
+    pa.idx = vcc ? BS_V : BS_K;
+    pa.fold_idx = BS_FOLD;
+    pa.fold_inf = vcc ? 1 : 0;
+    pa.scale = w;
     BrickCall b{grad ? M_GRAD : M_EVAL, false, vcc, !vcc, 0.f, vcc ? wf : 0.f, vcc ? 0.f : wf, u, nullptr,
                 g ? g : c->tmp0, diag ? diag : c->tmp1, nullptr};
     launch_brick(c, b, s);
-    launch_reduce(c->blk_brick, c->nwg, BS_N, BS_N, 0u, c->sc + SC_TMP0, nullptr, s);
-    // SC_TMP0.. = D, V, K, folds
-    if (E_dev)
-      hipLaunchKernelGGL(k_write_scalar, dim3(1), dim3(1), 0, s, c->sc + SC_TMP0 + (vcc ? BS_V : BS_K), w, E_dev,
-                         (const double *)(c->sc + SC_TMP0 + BS_FOLD), vcc ? 1 : 0);
-    if (nfold_dev) hipLaunchKernelGGL(k_write_int, dim3(1), dim3(1), 0, s, c->sc + SC_TMP0 + BS_FOLD, nfold_dev);
-    if (grad) launch_gather(c, 2, 2, g ? g : c->tmp0, diag ? diag : c->tmp1, nullptr, 0.f, 0, nullptr, 0.f, nullptr,
-                            false, nullptr, s);
+    launch_finish(POST_WRITE, pa, nullptr, s, src_brick(c, c->sc + SC_TMP0));
+    if (grad)
+      launch_gather(c, 2, 2, g ? g : c->tmp0, diag ? diag : c->tmp1, nullptr, 0.f, 0, nullptr, 0.f, nullptr, false,
+                    nullptr, s);
   }
   if (v) {
     BrickCall b{M_HV, false, vcc, !vcc, 0.f, vcc ? wf : 0.f, vcc ? 0.f : wf, u, v, Hv, nullptr, nullptr};
@@ -618,7 +675,8 @@ static int check_params(const disco_params *p) {
   return DISCO_OK;
 }
 
-// H v at the context's linearisation, all terms of eq. 11; optional per-block <v, Hv>
+// H v at the context's linearisation, all terms of eq. 11; with `dot` the gather also
+// writes per-block <v, Hv> (blk_node, stride 3)
 static void gn_hv_launch(disco_ctx *c, const disco_params *p, const float *v, float *Hv, bool dot,
                          const double *stop, hipStream_t s) {
   const bool vcc = p->gamma != 0.0;
@@ -660,63 +718,54 @@ int gn_pcg_step(disco_ctx *c, const disco_params *p, float *u, double *report_de
   const unsigned nb3 = nblk(n3);
   double *sc = c->sc;
   const double CH = ch_of(c);
-  Weights w{p->alpha, p->gamma, p->delta, CH};
   const bool vcc = p->gamma != 0.0;
   const bool kp = p->delta != 0.0 && c->nkp > 0;
   const bool curv = p->alpha != 0.0;
   const float eta2 = (float)(p->eta * p->eta);
+  PostArgs pa = post_args(c, p->alpha, p->gamma, p->delta);
+  pa.c1 = p->armijo_c1;
+  pa.tol = p->pcg_tol;
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, c->status);
 
   // ---- linearise at u: J, grad J, diag of the GN matrix, s cache --------------------
   launch_curv_L(c, u, c->u_ref, c->Lw, true, nullptr, s);
-  launch_reduce(c->blk_node, c->nodeblocks, 1, 1, 0u, sc + SC_SRAW, nullptr, s);
   {
     BrickCall b{M_GRAD, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, u, nullptr, c->vg, c->vdiag, nullptr};
     launch_brick(c, b, s);
   }
-  launch_reduce(c->blk_brick, c->nwg, BS_N, BS_N, 0u, sc + SC_TMP0, nullptr, s);
   launch_gather(c, 2, 2, c->vg, c->vdiag, curv ? c->Lw : nullptr, (float)(p->alpha * CH), curv ? 1 : 0, nullptr, 0.f,
                 nullptr, true, nullptr, s);
-  launch_reduce(c->blk_node, c->nodeblocks, 3, 3, 2u, sc + SC_DOT, nullptr, s);  // dot (unused), max diag, |g|^2
+  // D, V, K, folds; sum (L(u - uhat))^2; max diag, |g|^2 -> J
+  launch_finish(POST_LIN_BRICK, pa, nullptr, s, src_brick(c, sc + SC_TMP0), src_curv(c, sc + SC_SRAW),
+                src_gather(c, sc + SC_DOT));
   HIP_TRY(hipMemcpyAsync(c->u_lin, u, sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
-  // move the brick reductions into place: D = h^3 sum c, V, K, folds
-  hipLaunchKernelGGL(k_lin_move, dim3(1), dim3(1), 0, s, sc, (double)g.hx * (double)g.hy * (double)g.hz);
-  hipLaunchKernelGGL(k_lin_post, dim3(1), dim3(1), 0, s, sc, w, c->status);
   c->lin = true;
   c->lin_eta = p->eta;
 
   // ---- Jacobi-PCG on (H + tau I) x = -g ----------------------------------------------
   hipLaunchKernelGGL(k_pcg_init, dim3(nb3), dim3(256), 0, s, n3, c->vg, c->vdiag, sc, (float)p->tau, c->vx, c->vr,
                      c->vz, c->vp, c->blk_node);
-  launch_reduce(c->blk_node, nb3, 2, 2, 0u, sc + SC_TMP0, nullptr, s);
-  hipLaunchKernelGGL(k_pcg_start, dim3(1), dim3(1), 0, s, sc);
+  launch_finish(POST_PCG_START, pa, nullptr, s, src_pairs(c->blk_node, nb3, 2, sc + SC_TMP0));
   const double *stop = sc + SC_STOP;
   for (int it = 0; it < p->pcg_iters; ++it) {
     gn_hv_launch(c, p, c->vp, c->vq, true, stop, s);
-    launch_reduce(c->blk_node, c->nodeblocks, 3, 1, 0u, sc + SC_DOT, stop, s);
-    hipLaunchKernelGGL(k_pcg_alpha, dim3(1), dim3(1), 0, s, sc, c->status);
-    hipLaunchKernelGGL(k_pcg_update, dim3(nb3), dim3(256), 0, s, n3, sc, c->vdiag, (float)p->tau, c->vp, c->vq,
-                       c->vx, c->vr, c->vz, c->blk_node);
-    launch_reduce(c->blk_node, nb3, 2, 2, 0u, sc + SC_TMP0, stop, s);
-    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(1), 0, s, sc, p->pcg_tol);
-    if (it + 1 < p->pcg_iters) hipLaunchKernelGGL(k_pcg_p, dim3(nb3), dim3(256), 0, s, n3, sc, c->vz, c->vp);
+    hipLaunchKernelGGL(k_pcg_update, dim3(kUpdBlocks), dim3(256), 0, s, n3, sc, it, c->blk_node, c->nodeblocks,
+                       c->vdiag, (float)p->tau, c->vp, c->vq, c->vx, c->vr, c->vz, c->blk_upd, c->status);
+    hipLaunchKernelGGL(k_pcg_p, dim3(kUpdBlocks), dim3(256), 0, s, n3, sc, it, it + 1 == p->pcg_iters ? 1 : 0,
+                       p->pcg_tol, c->blk_upd, (int64_t)kUpdBlocks, c->vz, c->vp);
   }
 
   // ---- Armijo line search on J(u + t x) ------------------------------------------------
   hipLaunchKernelGGL(k_dot, dim3(nb3), dim3(256), 0, s, n3, c->vg, c->vx, c->blk_node);
-  launch_reduce(c->blk_node, nb3, 1, 1, 0u, sc + SC_TMP0, nullptr, s);
-  hipLaunchKernelGGL(k_ls_begin, dim3(1), dim3(1), 0, s, sc);
+  launch_finish(POST_LS_BEGIN, pa, nullptr, s, src_pairs(c->blk_node, nb3, 1, sc + SC_TMP0));
   const double *acc = sc + SC_ACCEPT;
   const bool dev_ls = (p->flags & DISCO_FLAG_LS_DEVICE) != 0;
   for (int t = 0; t < p->ls_max; ++t) {
     hipLaunchKernelGGL(k_ls_point, dim3(nb3), dim3(256), 0, s, n3, sc, t, u, c->vx, c->vut);
     launch_curv_L(c, c->vut, c->u_ref, c->Lw, true, acc, s);
-    launch_reduce(c->blk_node, c->nodeblocks, 1, 1, 0u, sc + SC_TSRAW, acc, s);
     BrickCall b{M_EVAL, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, c->vut, nullptr, nullptr, nullptr, acc};
     launch_brick(c, b, s);
-    launch_reduce(c->blk_brick, c->nwg, BS_N, BS_N, 0u, sc + SC_TMP0, acc, s);
-    hipLaunchKernelGGL(k_ls_move, dim3(1), dim3(1), 0, s, sc, (double)g.hx * (double)g.hy * (double)g.hz);
-    hipLaunchKernelGGL(k_ls_decide, dim3(1), dim3(1), 0, s, sc, w, p->armijo_c1);
+    launch_finish(POST_LS_BRICK, pa, acc, s, src_brick(c, sc + SC_TMP0), src_curv(c, sc + SC_TSRAW));
     if (!dev_ls) {
       HIP_TRY(hipMemcpyAsync(c->host_sc, sc + SC_ACCEPT, sizeof(double), hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
@@ -724,7 +773,7 @@ int gn_pcg_step(disco_ctx *c, const disco_params *p, float *u, double *report_de
     }
   }
   hipLaunchKernelGGL(k_ls_finish, dim3(nb3), dim3(256), 0, s, n3, sc, c->vut, u);
-  hipLaunchKernelGGL(k_report, dim3(1), dim3(1), 0, s, sc, w, report_dev, c->status, status_dev);
+  hipLaunchKernelGGL(k_report, dim3(1), dim3(1), 0, s, sc, CH, report_dev, c->status, status_dev);
   HIP_TRY(hipGetLastError());
   // the s cache and u_lin now describe the linearisation point of this step
   return DISCO_OK;

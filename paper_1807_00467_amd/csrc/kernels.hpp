@@ -48,6 +48,19 @@ struct Geo {
 // Storage of the per-voxel 3-vectors (image gradients, GN vectors s).
 struct F32x3 {
   typedef float elem;
+  static constexpr int W = 3;  // elements per voxel
+  __device__ static inline void loadp(const float *q, float s, float o[3]) {
+    o[0] = q[0];
+    o[1] = q[1];
+    o[2] = q[2];
+    (void)s;
+  }
+  __device__ static inline void storep(float *q, float s, const float v[3]) {
+    q[0] = v[0];
+    q[1] = v[1];
+    q[2] = v[2];
+    (void)s;
+  }
   __device__ static inline void load(const float *p, int64_t i, float s, float o[3]) {
     const float *q = p + 3 * i;
     o[0] = q[0];
@@ -67,6 +80,25 @@ struct F32x3 {
 // half precision, 4 halfs (8 B) per voxel, value = stored * s (s: per-volume power of two)
 struct F16x4 {
   typedef __half elem;
+  static constexpr int W = 4;  // elements per voxel
+  __device__ static inline void loadp(const __half *q, float s, float o[3]) {
+    const uint2 w = *reinterpret_cast<const uint2 *>(q);
+    __half2 a = *reinterpret_cast<const __half2 *>(&w.x);
+    __half2 b = *reinterpret_cast<const __half2 *>(&w.y);
+    float2 fa = __half22float2(a);
+    float2 fb = __half22float2(b);
+    o[0] = fa.x * s;
+    o[1] = fa.y * s;
+    o[2] = fb.x * s;
+  }
+  __device__ static inline void storep(__half *q, float s, const float v[3]) {
+    __half2 a = __floats2half2_rn(v[0] * s, v[1] * s);
+    __half2 b = __floats2half2_rn(v[2] * s, 0.0f);
+    uint2 w;
+    w.x = *reinterpret_cast<const uint32_t *>(&a);
+    w.y = *reinterpret_cast<const uint32_t *>(&b);
+    *reinterpret_cast<uint2 *>(q) = w;
+  }
   __device__ static inline void load(const __half *p, int64_t i, float s, float o[3]) {
     const uint2 w = *reinterpret_cast<const uint2 *>(p + 4 * i);
     __half2 a = *reinterpret_cast<const __half2 *>(&w.x);
@@ -86,6 +118,212 @@ struct F16x4 {
     *reinterpret_cast<uint2 *>(p + 4 * i) = w;
   }
 };
+
+
+// ---------------------------------------------------------------------------------
+// quad (4-lane) sums with DPP quad permutations: xor 1 = [1,0,3,2], xor 2 = [2,3,0,1]
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ float dpp_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_xor2(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float quad_sum(float v) {
+  v = v + dpp_xor1(v);
+  return v + dpp_xor2(v);
+}
+
+// hardware reciprocal (about 1 ulp); the IEEE division sequence is not needed here
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ bool is_face(int l, int b, int nb, int B) {
+  return (l == 0 && b > 0) || (l == B && b + 1 < nb);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------------
+// Scalar post-operations run after a reduction (solver bookkeeping on device scalars)
+// ---------------------------------------------------------------------------------
+enum {
+  POST_NONE = 0,
+  POST_WRITE,      // dst = out[idx] * scale (+inf if fold_inf and out[fold_idx] > 0); idst = out[fold_idx]
+  POST_LIN_BRICK,  // linearisation: D, V, K, folds -> sc; J; fold status
+  POST_LS_BRICK,   // line-search trial: D, V, K, folds -> sc; Armijo decision
+  POST_PCG_START,  // <r,z>, <r,r> of the initial residual
+  POST_PCG_ALPHA,  // p^T H p -> step length or breakdown
+  POST_PCG_BETA,   // <r,z>, <r,r> after the update -> beta, convergence
+  POST_LS_BEGIN,   // g^T p -> start of the line search
+  POST_STORE       // out values only
+};
+
+struct PostArgs {
+  double *sc;         // device scalar slots (solver state)
+  int *status;        // device status word
+  double alpha, gamma, delta, CH, h3;  // objective weights, C_H, voxel volume
+  double c1, tol;     // Armijo constant, CG tolerance
+  double *dst;        // POST_WRITE destination (nullable)
+  int32_t *idst;      // POST_WRITE fold-count destination (nullable)
+  double scale;
+  int idx, fold_idx, fold_inf;
+};
+
+
+// the objective from reduced terms; a fold counts only when gamma > 0 (then J = +inf)
+__device__ inline double total_J(const PostArgs &w, double D, double Sraw, double V, double K, double nfold) {
+  if (w.gamma != 0.0 && nfold > 0.0) return INFINITY;
+  return D + w.alpha * 0.5 * w.CH * Sraw + (w.gamma != 0.0 ? w.gamma * V : 0.0) + w.delta * K;
+}
+
+// slots of the device scalar array used by the Gauss-Newton step
+enum {
+  SC_D = 0, SC_SRAW, SC_V, SC_K, SC_NFOLD,      // linearisation: D, sum (Lw)^2, C sum psi, sum |res|^2, folds
+  SC_DOT, SC_MAXDIAG, SC_GG,                   // gather reductions: <dotv,out>, max diag, |out|^2
+  SC_J, SC_RZ, SC_RZ1, SC_ALPHA, SC_BETA, SC_RR, SC_BB, SC_STOP, SC_ITERS, SC_BREAK,
+  SC_GTP, SC_TTRY, SC_ACCEPT, SC_TACC, SC_TRIALS,
+  SC_TD, SC_TSRAW, SC_TV, SC_TK, SC_TNFOLD,    // trial point reductions
+  SC_JT, SC_DT, SC_ST, SC_VT, SC_KT,           // accepted (or last) trial values
+  SC_TMP0, SC_TMP1, SC_TMP2, SC_TMP3, SC_TMP4,
+  SC_COUNT = 48
+};
+
+__device__ inline void run_post(int post, const PostArgs &a, const double *r) {
+  double *sc = a.sc;
+  switch (post) {
+    case POST_WRITE: {
+      double v = r[a.idx] * a.scale;
+      if (a.fold_inf && r[a.fold_idx] > 0.0) v = INFINITY;
+      if (a.dst) *a.dst = v;
+      if (a.idst) *a.idst = (int32_t)r[a.fold_idx];
+      break;
+    }
+    case POST_LIN_BRICK:
+      sc[SC_D] = r[0] * a.h3;
+      sc[SC_V] = r[1];
+      sc[SC_K] = r[2];
+      sc[SC_NFOLD] = r[3];
+      sc[SC_J] = total_J(a, sc[SC_D], sc[SC_SRAW], sc[SC_V], sc[SC_K], sc[SC_NFOLD]);
+      if (a.status && a.gamma != 0.0 && sc[SC_NFOLD] > 0.0) *a.status |= 1;
+      break;
+    case POST_LS_BRICK: {
+      if (sc[SC_ACCEPT] != 0.0) break;
+      sc[SC_TD] = r[0] * a.h3;
+      sc[SC_TV] = r[1];
+      sc[SC_TK] = r[2];
+      sc[SC_TNFOLD] = r[3];
+      const double t = sc[SC_TTRY];
+      const double Jt = total_J(a, sc[SC_TD], sc[SC_TSRAW], sc[SC_TV], sc[SC_TK], sc[SC_TNFOLD]);
+      sc[SC_TRIALS] += 1.0;
+      sc[SC_JT] = Jt;
+      sc[SC_DT] = sc[SC_TD];
+      sc[SC_ST] = 0.5 * a.CH * sc[SC_TSRAW];
+      sc[SC_VT] = sc[SC_TV];
+      sc[SC_KT] = sc[SC_TK];
+      if (isfinite(Jt) && Jt <= sc[SC_J] + a.c1 * t * sc[SC_GTP]) {
+        sc[SC_ACCEPT] = 1.0;
+        sc[SC_TACC] = t;
+      }
+      break;
+    }
+    case POST_PCG_START:
+      sc[SC_RZ] = r[0];
+      sc[SC_BB] = r[1];
+      sc[SC_RR] = r[1];
+      sc[SC_STOP] = 0.0;
+      sc[SC_ITERS] = 0.0;
+      sc[SC_BREAK] = 0.0;
+      break;
+    case POST_PCG_ALPHA:
+      if (sc[SC_STOP] != 0.0) break;
+      if (!(r[0] > 0.0)) {
+        sc[SC_STOP] = 1.0;
+        sc[SC_BREAK] = 1.0;
+        if (a.status) *a.status |= 2;
+      } else {
+        sc[SC_ALPHA] = sc[SC_RZ] / r[0];
+      }
+      break;
+    case POST_PCG_BETA:
+      if (sc[SC_STOP] != 0.0) break;
+      sc[SC_RR] = r[1];
+      sc[SC_ITERS] += 1.0;
+      sc[SC_BETA] = r[0] / sc[SC_RZ];
+      sc[SC_RZ] = r[0];
+      if (a.tol > 0.0 && sqrt(sc[SC_RR]) <= a.tol * sqrt(sc[SC_BB])) sc[SC_STOP] = 1.0;
+      break;
+    case POST_LS_BEGIN:
+      sc[SC_GTP] = r[0];
+      sc[SC_ACCEPT] = 0.0;
+      sc[SC_TACC] = 0.0;
+      sc[SC_TRIALS] = 0.0;
+      sc[SC_JT] = INFINITY;
+      break;
+    default:
+      break;
+  }
+}
+
+// One source of a single-workgroup reduction: out[k] = sum (or max) over b of
+// blocks[b * stride + k], k < nvals.
+struct RedSrc {
+  const double *blocks;
+  int64_t nb;
+  int stride, nvals;
+  unsigned max_mask;  // bit k: value k is a maximum instead of a sum
+  double *out;
+};
+
+// Reduce up to three sources in a fixed order (one workgroup of 1024 threads), then run
+// the scalar post-operation.  Deterministic; no inter-workgroup communication.
+__global__ __launch_bounds__(1024) void k_finish(RedSrc s0, RedSrc s1, RedSrc s2, int nsrc, int post, PostArgs pa,
+                                                 const double *stop) {
+  __shared__ double red[1024];
+  if (stop && *stop != 0.0) return;
+  const int t = threadIdx.x;
+  const RedSrc srcs[3] = {s0, s1, s2};
+  for (int q = 0; q < nsrc; ++q) {
+    const RedSrc &S = srcs[q];
+    for (int k = 0; k < S.nvals; ++k) {
+      const bool mx = (S.max_mask >> k) & 1u;
+      double acc = mx ? -INFINITY : 0.0;
+      for (int64_t b = t; b < S.nb; b += 1024) {
+        const double x = S.blocks[b * S.stride + k];
+        acc = mx ? fmax(acc, x) : acc + x;
+      }
+      red[t] = acc;
+      __syncthreads();
+      for (int w = 512; w > 0; w >>= 1) {
+        if (t < w) red[t] = mx ? fmax(red[t], red[t + w]) : red[t] + red[t + w];
+        __syncthreads();
+      }
+      if (t == 0) S.out[k] = red[0];
+      __syncthreads();
+    }
+  }
+  if (t == 0) run_post(post, pa, srcs[0].out);
+}
+
+// Sum of n partials, computed identically by every workgroup that calls it (fixed
+// order: per-thread strided sums, then a fixed tree over the 256 threads).
+__device__ inline double block_sum_all(const double *blocks, int64_t n, int stride, int k, double *red) {
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  for (int64_t b = t; b < n; b += 256) acc += blocks[b * stride + k];
+  red[t] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
 
 template <class ST>
 struct BrickArgs {
@@ -109,41 +347,20 @@ struct BrickArgs {
   const double *stop;           // if non-null and *stop != 0 the launch does nothing
 };
 
-// ---------------------------------------------------------------------------------
-// quad (4-lane) sums with DPP quad permutations: xor 1 = [1,0,3,2], xor 2 = [2,3,0,1]
-// ---------------------------------------------------------------------------------
-__device__ __forceinline__ float dpp_xor1(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float dpp_xor2(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float quad_sum(float v) {
-  v = v + dpp_xor1(v);
-  return v + dpp_xor2(v);
-}
-
-__device__ __forceinline__ bool is_face(int l, int b, int nb, int B) {
-  return (l == 0 && b > 0) || (l == B && b + 1 < nb);
-}
-
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// node plane pz of the 2 x 2 corner nodes (cx..cx+1, cy..cy+1) of a cell, [j][i][c]
-__device__ __forceinline__ void load_plane(const float *f, const Geo &g, int cx, int cy, int pz, bool ok,
-                                           float o[2][2][3]) {
+// node plane of the 2 x 2 corner nodes of a lane's cell, [j][i][c]: fb points at the
+// lane's (cx, cy) node of plane 0 (node 0 for lanes outside the grid, whose values are
+// discarded), poff is the uniform offset of the plane.  No branches, no 64-bit products.
+__device__ __forceinline__ void load_plane(const float *fb, int64_t poff, const Geo &g, bool ok, float o[2][2][3]) {
+  const float *p = fb + poff;
 #pragma unroll
   for (int j = 0; j < 2; ++j)
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int64_t n = ((int64_t)pz * g.py + cy + j) * g.px + cx + i;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) o[j][i][c] = ok ? f[c * g.nnodes + n] : 0.0f;
-    }
+      for (int c = 0; c < 3; ++c) {
+        const float x = p[c * g.nnodes + j * g.px + i];
+        o[j][i][c] = ok ? x : 0.0f;
+      }
 }
 
 // ---------------------------------------------------------------------------------
@@ -169,6 +386,10 @@ __device__ __forceinline__ void sample_grad(const typename ST::elem *gT, float s
   const bool vx0 = (unsigned)i0[0] < (unsigned)g.nx, vx1 = (unsigned)(i0[0] + 1) < (unsigned)g.nx;
   const bool vy0 = (unsigned)i0[1] < (unsigned)g.ny, vy1 = (unsigned)(i0[1] + 1) < (unsigned)g.ny;
   const bool vz0 = (unsigned)i0[2] < (unsigned)g.nz, vz1 = (unsigned)(i0[2] + 1) < (unsigned)g.nz;
+  // zero padding: corners outside the volume read a clamped voxel and are discarded
+  const int X[2] = {min(max(i0[0], 0), g.nx - 1), min(max(i0[0] + 1, 0), g.nx - 1)};
+  const int Y[2] = {min(max(i0[1], 0), g.ny - 1) * g.nx, min(max(i0[1] + 1, 0), g.ny - 1) * g.nx};
+  const int Z[2] = {min(max(i0[2], 0), g.nz - 1) * (g.nx * g.ny), min(max(i0[2] + 1, 0), g.nz - 1) * (g.nx * g.ny)};
   float cv[2][2][2][3];  // [z][y][x][c]
 #pragma unroll
   for (int cz = 0; cz < 2; ++cz)
@@ -177,12 +398,11 @@ __device__ __forceinline__ void sample_grad(const typename ST::elem *gT, float s
 #pragma unroll
       for (int cx = 0; cx < 2; ++cx) {
         const bool ok = (cz ? vz1 : vz0) && (cy ? vy1 : vy0) && (cx ? vx1 : vx0);
-        if (ok) {
-          const int64_t vi = ((int64_t)(i0[2] + cz) * g.ny + (i0[1] + cy)) * g.nx + (i0[0] + cx);
-          ST::load(gT, vi, sT, cv[cz][cy][cx]);
-        } else {
-          cv[cz][cy][cx][0] = cv[cz][cy][cx][1] = cv[cz][cy][cx][2] = 0.0f;
-        }
+        const unsigned vi = (unsigned)(Z[cz] + Y[cy] + X[cx]);
+        float t3[3];
+        ST::loadp(gT + (uint64_t)vi * ST::W, sT, t3);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) cv[cz][cy][cx][c] = ok ? t3[c] : 0.0f;
       }
   // x, then y, then z; derivatives from differences of the lower-order interpolants
   float gx[2][2][3], dx[2][2][3];
@@ -214,16 +434,11 @@ __device__ __forceinline__ void sample_grad(const typename ST::elem *gT, float s
 }
 
 // ---------------------------------------------------------------------------------
-// Per-cell terms: volume change control (eq. 7-9) and keypoints (eq. 10).
-// Lane q of a quad handles the 16 coefficients d_abc with c = q (e3 edge (i,j) =
-// (q & 1, q >> 1)) and the keypoints q, q+4, ... of the cell.  Results are corner
-// contributions cc[f][k][j][i][comp] of this lane (summed over the quad by the caller).
+// Per-cell terms, one thread per cell: volume change control (eq. 7-9, all 64
+// coefficients of eq. 8) and keypoints (eq. 10).  Corner values are [k][j][i][c];
+// results are corner contributions out[f][k][j][i][c] (f = 0: gradient or GN product,
+// f = 1: GN diagonal), already multiplied by the term weight w.
 // ---------------------------------------------------------------------------------
-struct CellCorners {
-  float u[2][2][2][3];  // [k][j][i][c] displacement at the 8 corners
-  float v[2][2][2][3];  // direction (M_HV)
-};
-
 __device__ __forceinline__ void cross3(const float a[3], const float b[3], float o[3]) {
   o[0] = a[1] * b[2] - a[2] * b[1];
   o[1] = a[2] * b[0] - a[0] * b[2];
@@ -233,125 +448,96 @@ __device__ __forceinline__ float dot3(const float a[3], const float b[3]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// edge vectors of a trilinear cell from its corner values x (+ the cell size h on the
+// edge's own axis): e1[j+2k] = x_1jk - x_0jk, e2[i+2k] = x_i1k - x_i0k, e3[i+2j] = x_ij1 - x_ij0
+__device__ __forceinline__ void cell_edges(const float x[2][2][2][3], float hx, float hy, float hz, float e1[4][3],
+                                           float e2[4][3], float e3[4][3]) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        e1[t + 2 * r][c] = x[r][t][1][c] - x[r][t][0][c] + (c == 0 ? hx : 0.0f);
+        e2[t + 2 * r][c] = x[r][1][t][c] - x[r][0][t][c] + (c == 1 ? hy : 0.0f);
+        e3[t + 2 * r][c] = x[1][r][t][c] - x[0][r][t][c] + (c == 2 ? hz : 0.0f);
+      }
+}
+
 template <int MODE>
-__device__ __forceinline__ void vcc_cell(const Geo &g, int q, const CellCorners &cc, float w,
+__device__ __forceinline__ void vcc_cell(const Geo &g, const float u[2][2][2][3], const float v[2][2][2][3], float w,
                                          float out[2][2][2][2][3], double &sV, int &nfold) {
-  // edge vectors of y = X + u: e1_(j,k) = y_1jk - y_0jk = H_x e_x + u_1jk - u_0jk, etc.
-  float e1[4][3], e2[4][3], e3[3];
+  // y = X + u on the cell: e1_(j,k) = H_x e_x + u_1jk - u_0jk, and alike
+  float e1[4][3], e2[4][3], e3[4][3];
+  cell_edges(u, g.Hx, g.Hy, g.Hz, e1, e2, e3);
+  float de1[4][3], de2[4][3], de3[4][3];
+  if (MODE == M_HV) cell_edges(v, 0.0f, 0.0f, 0.0f, de1, de2, de3);
+  const float iC = frcp(g.C);
+  float G1[4][3] = {}, G2[4][3] = {}, G3[4][3] = {};  // dVhat/d(edge) or GN product per edge
 #pragma unroll
-  for (int k = 0; k < 2; ++k)
+  for (int c3 = 0; c3 < 4; ++c3) {
+    float x23[4][3], x31[4][3];
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int b = 0; b < 4; ++b) cross3(e2[b], e3[c3], x23[b]);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) e1[j + 2 * k][c] = cc.u[k][j][1][c] - cc.u[k][j][0][c] + (c == 0 ? g.Hx : 0.0f);
+    for (int a = 0; a < 4; ++a) cross3(e3[c3], e1[a], x31[a]);
 #pragma unroll
-  for (int k = 0; k < 2; ++k)
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) e2[i + 2 * k][c] = cc.u[k][1][i][c] - cc.u[k][0][i][c] + (c == 1 ? g.Hy : 0.0f);
-  const int qi = q & 1, qj = q >> 1;
-  // this lane's e3 edge, selected without dynamic register indexing
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    float e[4];
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-      for (int ii = 0; ii < 2; ++ii) e[ii + 2 * jj] = cc.u[1][jj][ii][c] - cc.u[0][jj][ii][c];
-    e3[c] = (q == 0 ? e[0] : q == 1 ? e[1] : q == 2 ? e[2] : e[3]) + (c == 2 ? g.Hz : 0.0f);
-  }
-
-  float de1[4][3], de2[4][3], de3[3];
-  if (MODE == M_HV) {
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) de1[j + 2 * k][c] = cc.v[k][j][1][c] - cc.v[k][j][0][c];
-#pragma unroll
-    for (int k = 0; k < 2; ++k)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) de2[i + 2 * k][c] = cc.v[k][1][i][c] - cc.v[k][0][i][c];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      float e[4];
-#pragma unroll
-      for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-        for (int ii = 0; ii < 2; ++ii) e[ii + 2 * jj] = cc.v[1][jj][ii][c] - cc.v[0][jj][ii][c];
-      de3[c] = q == 0 ? e[0] : q == 1 ? e[1] : q == 2 ? e[2] : e[3];
-    }
-  }
-
-  const float iC = 1.0f / g.C;
-  float x23[4][3], x31[4][3];
-#pragma unroll
-  for (int b = 0; b < 4; ++b) cross3(e2[b], e3, x23[b]);
-#pragma unroll
-  for (int a = 0; a < 4; ++a) cross3(e3, e1[a], x31[a]);
-
-  float G1[4][3] = {}, G2[4][3] = {}, G3[3] = {};
-  // GN diagonal contributions go straight to the corners
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      float x12[3];
-      cross3(e1[a], e2[b], x12);
-      const float d = dot3(e1[a], x23[b]) * iC;
-      if (!(d > 0.0f)) {
-        if (MODE != M_HV) ++nfold;
-        continue;
-      }
-      const float id = 1.0f / d;
-      if (MODE == M_EVAL || MODE == M_GRAD) sV += (double)(d - 2.0f + id);
-      if (MODE == M_GRAD) {
-        const float p1 = 1.0f - id * id;  // psi'
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          G1[a][c] += p1 * x23[b][c];
-          G2[b][c] += p1 * x31[a][c];
-          G3[c] += p1 * x12[c];
+      for (int b = 0; b < 4; ++b) {
+        float x12[3];
+        cross3(e1[a], e2[b], x12);
+        // d_abc = det[e1_a, e2_b, e3_c] / C; terms with d <= 0 (a fold) only count
+        const float d = dot3(e1[a], x23[b]) * iC;
+        const bool pos = d > 0.0f;
+        if (MODE != M_HV) nfold += pos ? 0 : 1;
+        const float id = pos ? frcp(d) : 0.0f;
+        if (MODE == M_EVAL || MODE == M_GRAD) {
+          const float dm1 = d - 1.0f;
+          sV += (double)(pos ? dm1 * dm1 * id : 0.0f);  // psi(d) = (d - 1)^2 / d
         }
-        // diag: C psi'' (dd/dy_n)^2 with dd/dy_n the signed sum of the cross products of
-        // the edges of this term that contain corner n, divided by C
-        const float p2 = 2.0f * id * id * id * w * iC;  // psi''/C, times the weight
-        const int ja = a & 1, ka = a >> 1, ib = b & 1, kb = b >> 1;
+        float coef = 0.0f;
+        if (MODE == M_GRAD) coef = pos ? 1.0f - id * id : 0.0f;  // psi'(d)
+        if (MODE == M_HV) {
+          // psi''(d) (grad d . v), grad d . v = (de1.x23 + de2.x31 + de3.x12) / C
+          const float jv = (dot3(de1[a], x23[b]) + dot3(de2[b], x31[a]) + dot3(de3[c3], x12)) * iC;
+          coef = 2.0f * id * id * id * jv;
+        }
+        if (MODE == M_GRAD || MODE == M_HV) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
+          for (int c = 0; c < 3; ++c) {
+            G1[a][c] += coef * x23[b][c];
+            G2[b][c] += coef * x31[a][c];
+            G3[c3][c] += coef * x12[c];
+          }
+        }
+        if (MODE == M_GRAD) {
+          // GN diagonal: C psi''(d) (dd/dy_n)^2, dd/dy_n = signed sum over the edges of this
+          // term through corner n of the cross product of the other two edges, over C
+          const float p2 = 2.0f * id * id * id * w * iC;
+          const int ja = a & 1, ka = a >> 1, ib = b & 1, kb = b >> 1, ic = c3 & 1, jc = c3 >> 1;
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+          for (int k = 0; k < 2; ++k)
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-              const bool in1 = (j == ja) && (k == ka);
-              const bool in2 = (i == ib) && (k == kb);
-              const bool in3 = (i == qi) && (j == qj);
-              if (!(in1 || in2 || in3)) continue;
-              const float s1 = in1 ? (i ? 1.0f : -1.0f) : 0.0f;
-              const float s2 = in2 ? (j ? 1.0f : -1.0f) : 0.0f;
-              const float s3 = in3 ? (k ? 1.0f : -1.0f) : 0.0f;
+            for (int j = 0; j < 2; ++j)
 #pragma unroll
-              for (int c = 0; c < 3; ++c) {
-                const float dd = s1 * x23[b][c] + s2 * x31[a][c] + s3 * x12[c];
-                out[1][k][j][i][c] += p2 * dd * dd;
+              for (int i = 0; i < 2; ++i) {
+                const bool in1 = (j == ja) && (k == ka);
+                const bool in2 = (i == ib) && (k == kb);
+                const bool in3 = (i == ic) && (j == jc);
+                if (!(in1 || in2 || in3)) continue;
+                const float s1 = in1 ? (i ? 1.0f : -1.0f) : 0.0f;
+                const float s2 = in2 ? (j ? 1.0f : -1.0f) : 0.0f;
+                const float s3 = in3 ? (k ? 1.0f : -1.0f) : 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                  const float dd = s1 * x23[b][c] + s2 * x31[a][c] + s3 * x12[c];
+                  out[1][k][j][i][c] += p2 * dd * dd;
+                }
               }
-            }
-      }
-      if (MODE == M_HV) {
-        const float jv = (dot3(de1[a], x23[b]) + dot3(de2[b], x31[a]) + dot3(de3, x12)) * iC;
-        const float coef = 2.0f * id * id * id * jv;  // psi''(d) (grad d . v)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          G1[a][c] += coef * x23[b][c];
-          G2[b][c] += coef * x31[a][c];
-          G3[c] += coef * x12[c];
         }
       }
-    }
+  }
   if (MODE == M_GRAD || MODE == M_HV) {
     // edges -> corners: +G on the far node of the edge, -G on the near node
 #pragma unroll
@@ -362,17 +548,18 @@ __device__ __forceinline__ void vcc_cell(const Geo &g, int q, const CellCorners 
         for (int i = 0; i < 2; ++i)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            float acc = (i ? G1[j + 2 * k][c] : -G1[j + 2 * k][c]) + (j ? G2[i + 2 * k][c] : -G2[i + 2 * k][c]);
-            if (i == qi && j == qj) acc += k ? G3[c] : -G3[c];
+            const float acc = (i ? G1[j + 2 * k][c] : -G1[j + 2 * k][c]) + (j ? G2[i + 2 * k][c] : -G2[i + 2 * k][c]) +
+                              (k ? G3[i + 2 * j][c] : -G3[i + 2 * j][c]);
             out[0][k][j][i][c] += w * acc;
           }
   }
 }
 
 template <int MODE>
-__device__ __forceinline__ void kp_cell(const Geo &g, int q, int ks, int ke, const float *kloc, const float *ktgt,
-                                        const CellCorners &cc, float w, float out[2][2][2][2][3], double &sK) {
-  for (int kk = ks + q; kk < ke; kk += 4) {
+__device__ __forceinline__ void kp_cell(const Geo &g, int ks, int ke, const float *kloc, const float *ktgt,
+                                        const float u[2][2][2][3], const float v[2][2][2][3], float w,
+                                        float out[2][2][2][2][3], double &sK) {
+  for (int kk = ks; kk < ke; ++kk) {
     float xl[3], tl[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -389,29 +576,19 @@ __device__ __forceinline__ void kp_cell(const Geo &g, int q, int ks, int ke, con
         for (int i = 0; i < 2; ++i)
           wt[k][j][i] = (i ? t0 : 1.0f - t0) * (j ? t1 : 1.0f - t1) * (k ? t2 : 1.0f - t2);
     float val[3];
-    if (MODE == M_HV) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        float pv = 0.0f;
+    for (int c = 0; c < 3; ++c) {
+      float acc = MODE == M_HV ? 0.0f : xl[c];
 #pragma unroll
-        for (int k = 0; k < 2; ++k)
+      for (int k = 0; k < 2; ++k)
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int i = 0; i < 2; ++i) pv += wt[k][j][i] * cc.v[k][j][i][c];
-        val[c] = 2.0f * w * pv;
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        float y = xl[c];
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int i = 0; i < 2; ++i) y += wt[k][j][i] * cc.u[k][j][i][c];
-        const float res = y - tl[c];
+          for (int i = 0; i < 2; ++i) acc += wt[k][j][i] * (MODE == M_HV ? v[k][j][i][c] : u[k][j][i][c]);
+      if (MODE == M_HV) {
+        val[c] = 2.0f * w * acc;  // 2 delta (P v)(x_i)
+      } else {
+        const float res = acc - tl[c];  // y(x_i) - y_KP(x_i), relative to the cell origin
         sK += (double)res * (double)res;
         val[c] = 2.0f * w * res;
       }
@@ -432,6 +609,23 @@ __device__ __forceinline__ void kp_cell(const Geo &g, int q, int ks, int ke, con
   }
 }
 
+// the 8 corner values of a cell, [k][j][i][c]; fb points at the cell's (0,0,0) corner
+// (node 0 for threads outside the grid, whose values are discarded)
+__device__ __forceinline__ void load_corners(const float *fb, const Geo &g, bool ok, float o[2][2][2][3]) {
+  const int64_t pxy = (int64_t)g.px * g.py;
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float x = fb[c * g.nnodes + k * pxy + j * g.px + i];
+          o[k][j][i][c] = ok ? x : 0.0f;
+        }
+}
+
 // ---------------------------------------------------------------------------------
 // The voxel-brick kernel.
 // ---------------------------------------------------------------------------------
@@ -440,7 +634,12 @@ __global__ __launch_bounds__(kWG) void k_brick(BrickArgs<ST> A) {
   constexpr int F = (MODE == M_GRAD) ? 2 : ((MODE == M_HV) ? 1 : 0);
   constexpr int FS = F > 0 ? F : 1;
   constexpr bool CELLT = VCC || KP;
-  __shared__ float lds[4][2][FS * 3][2][16];  // [wave][jn][field*3+c][A/B][quad]
+  constexpr bool NGF_OUT = NGF && F > 0;
+  constexpr bool CELL_OUT = CELLT && F > 0;
+  // NGF node planes of the brick, staged per wave: [plane][wave][jn][field*3+c][A/B][quad]
+  __shared__ float lds[NGF_OUT ? ZC + 1 : 1][4][2][FS * 3][2][16];
+  // per-cell corner contributions: [field*24 + corner*3 + c][cell of the brick]
+  __shared__ float cbuf[CELL_OUT ? FS * 24 : 1][CELL_OUT ? 64 * ZC : 1];
   __shared__ double lred[4][BS_N];
 
   if (A.stop && *A.stop != 0.0) return;
@@ -456,231 +655,192 @@ __global__ __launch_bounds__(kWG) void k_brick(BrickArgs<ST> A) {
   const bool ok = (cx < g.cx) && (cy < g.cy);
   const float xi = (q + 0.5f) * 0.25f;
   const int64_t brick = ((int64_t)bz * g.nby + by) * g.nbx + bx;
+  const int64_t pxy = (int64_t)g.px * g.py;
+  const int64_t nxy = (int64_t)g.nx * g.ny;
 
-  // corner values of this lane's cell, rolled along z: [k][j][i][c]
-  CellCorners cc;
-  float tmp[2][2][3];
-  const float *U = A.u;
-  const float *V = A.v;
-  const bool need_u = (MODE != M_HV) || VCC;
-  const bool need_v = (MODE == M_HV);
-  if (need_u) {
-    load_plane(U, g, cx, cy, cz0, ok, tmp);
+  // NGF: node values of this lane's cell, rolled along z: [k][j][i][c] (u, or v for M_HV)
+  float nc[2][2][2][3];
+  const float *NF = (MODE == M_HV) ? A.v : A.u;
+  const float *NB = NF + (ok ? (int64_t)cy * g.px + cx : 0);
+  if (NGF) {
+    float tmp[2][2][3];
+    load_plane(NB, (int64_t)cz0 * pxy, g, ok, tmp);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) cc.u[0][j][i][c] = tmp[j][i][c];
-  }
-  if (need_v) {
-    load_plane(V, g, cx, cy, cz0, ok, tmp);
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) cc.v[0][j][i][c] = tmp[j][i][c];
+        for (int c = 0; c < 3; ++c) nc[0][j][i][c] = tmp[j][i][c];
   }
 
-  float carN[FS][2][3] = {};          // NGF, per lane before the x reduction: [f][jn][c]
-  float carC[FS][2][2][3] = {};       // cell terms, quad-uniform: [f][jn][i][c]
+  float carN[FS][2][3] = {};  // NGF, per lane before the x reduction: [f][jn][c]
   double sD = 0.0, sV = 0.0, sK = 0.0;
   int nfold = 0;
   const float sc_ngf = A.ngf_scale;
+  const float sg0 = (MODE == M_GRAD) ? -sc_ngf : sc_ngf;  // field 0: -2h^3 r s (gradient) or 2h^3 (GN)
+  const float wA0 = (1.0f - xi) * sg0, wB0 = xi * sg0;
+  const float wA1 = (1.0f - xi) * (1.0f - xi) * sc_ngf, wB1 = xi * xi * sc_ngf;
 
-  auto emit = [&](int zl, const float nv[FS][2][3], const float cv[FS][2][2][3]) {
-    if constexpr (F > 0) {
+  // stage NGF node plane zl of this wave: x-reduce over the quad (A: node cx, B: node cx+1)
+  auto stage = [&](int zl, const float nv[FS][2][3]) {
+    if constexpr (NGF_OUT) {
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        // field 1 (diagonal) uses squared weights
-        const float wA = (f == 0) ? (1.0f - xi) : (1.0f - xi) * (1.0f - xi);
-        const float wB = (f == 0) ? xi : xi * xi;
-        const float s = (MODE == M_GRAD && f == 0) ? -sc_ngf : sc_ngf;
+        const float wA = f == 0 ? wA0 : wA1;  // field 1 (diagonal) uses squared weights
+        const float wB = f == 0 ? wB0 : wB1;
 #pragma unroll
         for (int jn = 0; jn < 2; ++jn)
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            float a = 0.0f, b = 0.0f;
-            if (NGF) {
-              a = quad_sum(nv[f][jn][c] * (wA * s));
-              b = quad_sum(nv[f][jn][c] * (wB * s));
-            }
-            if (CELLT) {
-              a += cv[f][jn][0][c];
-              b += cv[f][jn][1][c];
-            }
+            const float a = quad_sum(nv[f][jn][c] * wA);
+            const float b = quad_sum(nv[f][jn][c] * wB);
             if (q == 0) {
-              lds[wave][jn][f * 3 + c][0][xq] = a;
-              lds[wave][jn][f * 3 + c][1][xq] = b;
+              lds[zl][wave][jn][f * 3 + c][0][xq] = a;
+              lds[zl][wave][jn][f * 3 + c][1][xq] = b;
             }
           }
       }
-      __syncthreads();
-      const int pzn = cz0 + zl;
-      const bool zface = is_face(zl, bz, g.nbz, ZC);
-      for (int e = threadIdx.x; e < F * 3 * kNBOX; e += kWG) {
-        const int xl = e % 17, yl = (e / 17) % 5, fc = e / kNBOX;
-        float val = 0.0f;
-        if (yl < 4) {
-          if (xl < 16) val += lds[yl][0][fc][0][xl];
-          if (xl > 0) val += lds[yl][0][fc][1][xl - 1];
-        }
-        if (yl > 0) {
-          if (xl < 16) val += lds[yl - 1][1][fc][0][xl];
-          if (xl > 0) val += lds[yl - 1][1][fc][1][xl - 1];
-        }
-        const int pxn = bx * kBXC + xl, pyn = by * kBYC + yl;
-        if (pxn > g.cx || pyn > g.cy) continue;
-        const bool face = zface || is_face(xl, bx, g.nbx, kBXC) || is_face(yl, by, g.nby, kBYC);
-        if (face) {
-          A.part[((brick * (ZC + 1) + zl) * (F * 3) + fc) * kNBOX + yl * 17 + xl] = val;
-        } else {
-          const int f = fc / 3, c = fc - 3 * f;
-          float *o = f == 0 ? A.out0 : A.out1;
-          o[c * g.nnodes + ((int64_t)pzn * g.py + pyn) * g.px + pxn] = val;
-        }
-      }
-      __syncthreads();
     }
   };
 
   for (int czi = cz0; czi < cz1; ++czi) {
-    // corners of the next node plane
-    if (need_u) {
-      load_plane(U, g, cx, cy, czi + 1, ok, tmp);
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) cc.u[1][j][i][c] = tmp[j][i][c];
-    }
-    if (need_v) {
-      load_plane(V, g, cx, cy, czi + 1, ok, tmp);
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) cc.v[1][j][i][c] = tmp[j][i][c];
-    }
-
+    const int zl = czi - cz0;
     float accN[FS][2][2][3] = {};  // [f][kn][jn][c]
-    if (NGF && ok) {
-      // node values interpolated along x at this lane's voxel: fx[k][j][c]
-      float fx[2][2][3];
-#pragma unroll
-      for (int k = 0; k < 2; ++k)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const float a0 = (MODE == M_HV) ? cc.v[k][j][0][c] : cc.u[k][j][0][c];
-            const float a1 = (MODE == M_HV) ? cc.v[k][j][1][c] : cc.u[k][j][1][c];
-            fx[k][j][c] = a0 + xi * (a1 - a0);
-          }
-      auto zrow = [&](const int kv) {
-        const float wz = (kv + 0.5f) * 0.25f;
-        const int iz = czi * 4 + kv;
-        float fz[2][3];
+    if (NGF) {
+      {
+        float tmp[2][2][3];
+        load_plane(NB, (int64_t)(czi + 1) * pxy, g, ok, tmp);
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) fz[j][c] = fx[0][j][c] + wz * (fx[1][j][c] - fx[0][j][c]);
-        float accY[FS][2][3] = {};
+          for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int jv = 0; jv < 4; ++jv) {
-          const float wy = (jv + 0.5f) * 0.25f;
-          const int iy = cy * 4 + jv;
-          const int64_t vox = ((int64_t)iz * g.ny + iy) * g.nx + ix;
-          float f3[3];
+            for (int c = 0; c < 3; ++c) nc[1][j][i][c] = tmp[j][i][c];
+      }
+      if (ok) {
+        // node values interpolated along x at this lane's voxel: fx[k][j][c]
+        float fx[2][2][3];
 #pragma unroll
-          for (int c = 0; c < 3; ++c) f3[c] = fz[0][c] + wy * (fz[1][c] - fz[0][c]);
-          if (MODE == M_HV) {
-            float s[3];
-            ST::load(A.sc, vox, A.sS_load, s);
-            const float w = s[0] * f3[0] + s[1] * f3[1] + s[2] * f3[2];
+        for (int k = 0; k < 2; ++k)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              const float t = w * s[c];
-              accY[0][0][c] += (1.0f - wy) * t;
-              accY[0][1][c] += wy * t;
-            }
-          } else {
-            // displacement in voxel units: q = index + u/h
-            const float uh[3] = {f3[0] * g.ihx, f3[1] * g.ihy, f3[2] * g.ihz};
-            float a[3], JG[3][3], b[3];
-            sample_grad<ST>(A.gT, A.sT, g, ix, iy, iz, uh, a, JG);
-            ST::load(A.gR, vox, A.sR, b);
-            const float e2 = A.eta2;
-            const float Da = e2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
-            const float Db = e2 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-            const float P = e2 + a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-            const float dab[3] = {a[0] - b[0], a[1] - b[1], a[2] - b[2]};
-            float axb[3];
-            cross3(a, b, axb);
-            const float DD = Da * Db;
-            const float cvox = (e2 * dot3(dab, dab) + dot3(axb, axb)) / DD;
-            sD += (double)cvox;
-            if (MODE == M_GRAD) {
-              const float isq = rsqrtf(DD);
-              const float r = P * isq;
-              const float pda = P / Da;
-              float dr[3], s[3];
+          for (int j = 0; j < 2; ++j)
 #pragma unroll
-              for (int c = 0; c < 3; ++c) dr[c] = (b[c] - pda * a[c]) * isq;
+            for (int c = 0; c < 3; ++c) fx[k][j][c] = nc[k][j][0][c] + xi * (nc[k][j][1][c] - nc[k][j][0][c]);
+        // first voxel of this lane in the layer; voxel (kv, jv) is vbase + kv*nx*ny + jv*nx,
+        // the offset being the same for the whole wave
+        const int64_t vbase = ((int64_t)(czi * 4) * g.ny + cy * 4) * g.nx + ix;
+        const typename ST::elem *sp = A.sc + vbase * ST::W;
+        const typename ST::elem *rp = A.gR + vbase * ST::W;
+        auto zrow = [&](const int kv) {
+          const float wz = (kv + 0.5f) * 0.25f;
+          const int iz = czi * 4 + kv;
+          float fz[2][3];
 #pragma unroll
-              for (int c = 0; c < 3; ++c) s[c] = JG[0][c] * dr[0] + JG[1][c] * dr[1] + JG[2][c] * dr[2];
-              ST::store(A.sc, vox, A.sS_store, s);
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) fz[j][c] = fx[0][j][c] + wz * (fx[1][j][c] - fx[0][j][c]);
+          float accY[FS][2][3] = {};
+#pragma unroll
+          for (int jv = 0; jv < 4; ++jv) {
+            const float wy = (jv + 0.5f) * 0.25f;
+            const int iy = cy * 4 + jv;
+            const int64_t voff = (kv * nxy + jv * g.nx) * ST::W;  // wave-uniform
+            float f3[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f3[c] = fz[0][c] + wy * (fz[1][c] - fz[0][c]);
+            if (MODE == M_HV) {
+              float s[3];
+              ST::loadp(sp + voff, A.sS_load, s);
+              const float w = s[0] * f3[0] + s[1] * f3[1] + s[2] * f3[2];
 #pragma unroll
               for (int c = 0; c < 3; ++c) {
-                const float t = r * s[c];
+                const float t = w * s[c];
                 accY[0][0][c] += (1.0f - wy) * t;
                 accY[0][1][c] += wy * t;
-                const float t2 = s[c] * s[c];
-                accY[FS - 1][0][c] += (1.0f - wy) * (1.0f - wy) * t2;
-                accY[FS - 1][1][c] += wy * wy * t2;
+              }
+            } else {
+              // displacement in voxel units: q = index + u/h
+              const float uh[3] = {f3[0] * g.ihx, f3[1] * g.ihy, f3[2] * g.ihz};
+              float a[3], JG[3][3], b[3];
+              sample_grad<ST>(A.gT, A.sT, g, ix, iy, iz, uh, a, JG);
+              ST::loadp(rp + voff, A.sR, b);
+              const float e2 = A.eta2;
+              const float Da = e2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+              const float Db = e2 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+              const float P = e2 + a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+              const float dab[3] = {a[0] - b[0], a[1] - b[1], a[2] - b[2]};
+              float axb[3];
+              cross3(a, b, axb);
+              const float DD = Da * Db;
+              // 1 - r^2 without cancellation (Lagrange's identity)
+              const float cvox = (e2 * dot3(dab, dab) + dot3(axb, axb)) * frcp(DD);
+              sD += (double)cvox;
+              if (MODE == M_GRAD) {
+                const float isq = rsqrtf(DD);
+                const float r = P * isq;
+                const float pda = P * frcp(Da);
+                float dr[3], s[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) dr[c] = (b[c] - pda * a[c]) * isq;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) s[c] = JG[0][c] * dr[0] + JG[1][c] * dr[1] + JG[2][c] * dr[2];
+                ST::storep(const_cast<typename ST::elem *>(sp) + voff, A.sS_store, s);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                  const float t = r * s[c];
+                  accY[0][0][c] += (1.0f - wy) * t;
+                  accY[0][1][c] += wy * t;
+                  const float t2 = s[c] * s[c];
+                  accY[FS - 1][0][c] += (1.0f - wy) * (1.0f - wy) * t2;
+                  accY[FS - 1][1][c] += wy * wy * t2;
+                }
               }
             }
           }
-        }
-        if (F > 0) {
+          if (F > 0) {
 #pragma unroll
-          for (int jn = 0; jn < 2; ++jn)
+            for (int jn = 0; jn < 2; ++jn)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              accN[0][0][jn][c] += (1.0f - wz) * accY[0][jn][c];
-              accN[0][1][jn][c] += wz * accY[0][jn][c];
-              if (F == 2) {
-                accN[FS - 1][0][jn][c] += (1.0f - wz) * (1.0f - wz) * accY[FS - 1][jn][c];
-                accN[FS - 1][1][jn][c] += wz * wz * accY[FS - 1][jn][c];
+              for (int c = 0; c < 3; ++c) {
+                accN[0][0][jn][c] += (1.0f - wz) * accY[0][jn][c];
+                accN[0][1][jn][c] += wz * accY[0][jn][c];
+                if (F == 2) {
+                  accN[FS - 1][0][jn][c] += (1.0f - wz) * (1.0f - wz) * accY[FS - 1][jn][c];
+                  accN[FS - 1][1][jn][c] += wz * wz * accY[FS - 1][jn][c];
+                }
               }
-            }
-        }
-      };
-      if constexpr (MODE == M_HV) {
+          }
+        };
+        if constexpr (MODE == M_HV) {
 #pragma unroll
-        for (int kv = 0; kv < 4; ++kv) zrow(kv);
-      } else {
+          for (int kv = 0; kv < 4; ++kv) zrow(kv);
+        } else {
 #pragma unroll 1
-        for (int kv = 0; kv < 4; ++kv) zrow(kv);
+          for (int kv = 0; kv < 4; ++kv) zrow(kv);
+        }
       }
     }
 
-    // per-cell terms of this layer: corner contributions [f][k][j][i][c]
-    float cterm[FS][2][2][2][3] = {};
-    if (CELLT) {
-      float ct[2][2][2][2][3] = {};
-      if (ok) {
-        if (VCC) vcc_cell<MODE>(g, q, cc, A.gamma, ct, sV, nfold);
+    // cell terms of this layer: wave zl % 4 takes its 64 cells, one per lane
+    if (CELLT && (zl & 3) == wave) {
+      const int lx = lane & 15, ly = lane >> 4;
+      const int ccx = bx * kBXC + lx, ccy = by * kBYC + ly;
+      const bool cok = ccx < g.cx && ccy < g.cy;
+      const int64_t cbase = cok ? (int64_t)czi * pxy + (int64_t)ccy * g.px + ccx : 0;
+      float ucor[2][2][2][3], vcor[2][2][2][3];
+      const bool need_u = (MODE != M_HV) || VCC;
+      if (need_u) load_corners(A.u + cbase, g, cok, ucor);
+      if (MODE == M_HV) load_corners(A.v + cbase, g, cok, vcor);
+      float ct[FS][2][2][2][3] = {};
+      if (cok) {
+        if (VCC) vcc_cell<MODE>(g, ucor, vcor, A.gamma, ct, sV, nfold);
         if (KP) {
-          const int64_t cell = ((int64_t)czi * g.cy + cy) * g.cx + cx;
+          const int64_t cell = ((int64_t)czi * g.cy + ccy) * g.cx + ccx;
           const int ks = A.kstart[cell], ke = A.kstart[cell + 1];
-          if (ke > ks) kp_cell<MODE>(g, q, ks, ke, A.kloc, A.ktgt, cc, A.delta, ct, sK);
+          if (ke > ks) kp_cell<MODE>(g, ks, ke, A.kloc, A.ktgt, ucor, vcor, A.delta, ct, sK);
         }
       }
-      if (F > 0) {
+      if constexpr (CELL_OUT) {
 #pragma unroll
         for (int f = 0; f < F; ++f)
 #pragma unroll
@@ -690,13 +850,13 @@ __global__ __launch_bounds__(kWG) void k_brick(BrickArgs<ST> A) {
 #pragma unroll
               for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) cterm[f][k][j][i][c] = quad_sum(ct[f][k][j][i][c]);
+                for (int c = 0; c < 3; ++c) cbuf[f * 24 + (i + 2 * j + 4 * k) * 3 + c][zl * 64 + lane] = ct[f][k][j][i][c];
       }
     }
 
-    if (F > 0) {
+    if (NGF_OUT) {
       // node plane czi is complete: carried part + this layer's lower plane
-      float nv[FS][2][3], cv[FS][2][2][3];
+      float nv[FS][2][3];
 #pragma unroll
       for (int f = 0; f < FS; ++f)
 #pragma unroll
@@ -705,33 +865,67 @@ __global__ __launch_bounds__(kWG) void k_brick(BrickArgs<ST> A) {
           for (int c = 0; c < 3; ++c) {
             nv[f][jn][c] = carN[f][jn][c] + accN[f][0][jn][c];
             carN[f][jn][c] = accN[f][1][jn][c];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-              cv[f][jn][i][c] = carC[f][jn][i][c] + cterm[f][0][jn][i][c];
-              carC[f][jn][i][c] = cterm[f][1][jn][i][c];
-            }
           }
-      emit(czi - cz0, nv, cv);
+      stage(zl, nv);
     }
-    // roll the corners
-    if (need_u) {
+    if (NGF) {
+      // roll the node values
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int c = 0; c < 3; ++c) cc.u[0][j][i][c] = cc.u[1][j][i][c];
-    }
-    if (need_v) {
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) cc.v[0][j][i][c] = cc.v[1][j][i][c];
+          for (int c = 0; c < 3; ++c) nc[0][j][i][c] = nc[1][j][i][c];
     }
   }
-  if (F > 0) emit(cz1 - cz0, carN, carC);
+
+  if constexpr (F > 0) {
+    const int nl = cz1 - cz0;  // cell layers of this brick
+    if (NGF_OUT) stage(nl, carN);
+    __syncthreads();
+    // combine in a fixed order and write every node plane of the brick: interior nodes
+    // directly, brick-face nodes to the partial buffer
+    const int total = (nl + 1) * F * 3 * kNBOX;
+    for (int e = threadIdx.x; e < total; e += kWG) {
+      const int xl = e % 17, yl = (e / 17) % 5, fc = (e / kNBOX) % (F * 3), zl = e / (kNBOX * F * 3);
+      float val = 0.0f;
+      if (NGF_OUT) {
+        if (yl < 4) {
+          if (xl < 16) val += lds[zl][yl][0][fc][0][xl];
+          if (xl > 0) val += lds[zl][yl][0][fc][1][xl - 1];
+        }
+        if (yl > 0) {
+          if (xl < 16) val += lds[zl][yl - 1][1][fc][0][xl];
+          if (xl > 0) val += lds[zl][yl - 1][1][fc][1][xl - 1];
+        }
+      }
+      if (CELL_OUT) {
+        const int f = fc / 3, c = fc - 3 * f;
+#pragma unroll
+        for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+          for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+            for (int di = 0; di < 2; ++di) {
+              // cell (xl-1+di, yl-1+dj, zl-1+dk) touches this node at its corner (1-di, 1-dj, 1-dk)
+              const int ci = xl - 1 + di, cj = yl - 1 + dj, ck = zl - 1 + dk;
+              if (ci < 0 || ci >= 16 || cj < 0 || cj >= 4 || ck < 0 || ck >= nl) continue;
+              const int corner = (1 - di) + 2 * (1 - dj) + 4 * (1 - dk);
+              val += cbuf[f * 24 + corner * 3 + c][ck * 64 + cj * 16 + ci];
+            }
+      }
+      const int pxn = bx * kBXC + xl, pyn = by * kBYC + yl, pzn = cz0 + zl;
+      if (pxn > g.cx || pyn > g.cy) continue;
+      const bool face = is_face(zl, bz, g.nbz, ZC) || is_face(xl, bx, g.nbx, kBXC) || is_face(yl, by, g.nby, kBYC);
+      if (face) {
+        A.part[((brick * (ZC + 1) + zl) * (F * 3) + fc) * kNBOX + yl * 17 + xl] = val;
+      } else {
+        const int f = fc / 3, c = fc - 3 * f;
+        float *o = f == 0 ? A.out0 : A.out1;
+        o[c * g.nnodes + ((int64_t)pzn * g.py + pyn) * g.px + pxn] = val;
+      }
+    }
+  }
 
   // workgroup scalars in a fixed order
   if (MODE != M_HV) {
@@ -767,7 +961,7 @@ struct GatherArgs {
   const float *tauv;     // adds tau * tauv to field 0 (nullable)
   float tau;
   const float *dotv;     // per-block <dotv, out0> (nullable)
-  double *blocks;        // [nblocks][2]: <dotv,out0>, and for nf = 2: max(out1), <out0,out0>
+  double *blocks;        // [nblocks][3]: <dotv,out0>, max(out1), <out0,out0>
   const double *stop;
 };
 
@@ -787,94 +981,124 @@ __device__ __forceinline__ int brick_cands(int p, int B, int nb, int b[2], int l
   return n;
 }
 
-template <int ZC>
+// F: fields the brick kernel wrote (0: none ran), NF: fields produced (1 or 2),
+// CURV: add curvature (field 0, and its diagonal to field 1 when NF = 2)
+template <int ZC, int F, int NF, bool CURV>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
-  __shared__ double red[256];
+  __shared__ double red[3][256];
   if (A.stop && *A.stop != 0.0) return;
   const Geo &g = A.g;
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const float *__restrict__ part = A.part;
+  const float *__restrict__ Lw = A.Lw;
+  const float *__restrict__ tauv = A.tauv;
+  const float *__restrict__ dotv = A.dotv;
+  float *__restrict__ out0 = A.out0;
+  float *__restrict__ out1 = A.out1;
+  // block (64 x 4 threads) covers nodes x in [64 bx, 64 bx + 64), y in [4 by, 4 by + 4), plane bz
+  const int px = blockIdx.x * 64 + (threadIdx.x & 63), py = blockIdx.y * 4 + (threadIdx.x >> 6), pz = blockIdx.z;
+  const int64_t bid = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   double dsum = 0.0, dmax = 0.0, gsq = 0.0;
-  if (n < g.nnodes) {
-    const int px = (int)(n % g.px), py = (int)((n / g.px) % g.py), pz = (int)(n / ((int64_t)g.px * g.py));
-    int bxs[2], lxs[2], bys[2], lys[2], bzs[2], lzs[2];
-    int nbx = 0, nby = 0, nbz = 0;
-    bool shared = false;
-    if (A.F > 0) {
-      nbx = brick_cands(px, kBXC, g.nbx, bxs, lxs);
-      nby = brick_cands(py, kBYC, g.nby, bys, lys);
-      nbz = brick_cands(pz, ZC, g.nbz, bzs, lzs);
-      shared = nbx > 1 || nby > 1 || nbz > 1;
-    }
-    for (int f = 0; f < A.nf; ++f) {
-      float *o = f == 0 ? A.out0 : A.out1;
-      for (int c = 0; c < 3; ++c) {
-        const int64_t oi = c * g.nnodes + n;
-        float val = 0.0f;
-        if (A.F > f) {
-          if (shared) {
-            for (int iz = 0; iz < nbz; ++iz)
-              for (int iy = 0; iy < nby; ++iy)
-                for (int ixx = 0; ixx < nbx; ++ixx) {
-                  const int64_t brick = ((int64_t)bzs[iz] * g.nby + bys[iy]) * g.nbx + bxs[ixx];
-                  val += A.part[((brick * (ZC + 1) + lzs[iz]) * (A.F * 3) + f * 3 + c) * kNBOX + lys[iy] * 17 +
-                                lxs[ixx]];
-                }
-          } else {
-            val = o[oi];
-          }
-        }
-        if (f == 0 && A.Lw) {
-          // (L^T z)(p) = sum_a [chi_a(p-e_a) z(p-e_a) - 2 chi_a(p) z(p) + chi_a(p+e_a) z(p+e_a)] / H_a^2
-          const float *z = A.Lw + c * g.nnodes;
-          const int pp[3] = {px, py, pz};
-          const int nn[3] = {g.px, g.py, g.pz};
-          const int64_t st[3] = {1, g.px, (int64_t)g.px * g.py};
-          const float ih2[3] = {g.iHx * g.iHx, g.iHy * g.iHy, g.iHz * g.iHz};
-          float acc = 0.0f;
+  if (px < g.px && py < g.py) {
+    const int64_t n = ((int64_t)pz * g.py + py) * g.px + px;
+    float val[NF][3];
+    // brick kernel part: interior nodes were written directly, face nodes are summed here
+    if (F > 0) {
+      int bxs[2], lxs[2], bys[2], lys[2], bzs[2], lzs[2];
+      const int nbx = brick_cands(px, kBXC, g.nbx, bxs, lxs);
+      const int nby = brick_cands(py, kBYC, g.nby, bys, lys);
+      const int nbz = brick_cands(pz, ZC, g.nbz, bzs, lzs);
+      if (nbx > 1 || nby > 1 || nbz > 1) {
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            float t = -2.0f * chi(pp[a], nn[a]) * z[n];
-            if (pp[a] > 0 && chi(pp[a] - 1, nn[a])) t += z[n - st[a]];
-            if (pp[a] < nn[a] - 1 && chi(pp[a] + 1, nn[a])) t += z[n + st[a]];
-            acc += t * ih2[a];
-          }
-          val += A.curv_scale * acc;
-        }
-        if (f == 1 && A.curv_diag) {
-          const int pp[3] = {px, py, pz};
-          const int nn[3] = {g.px, g.py, g.pz};
-          const float ih2[3] = {g.iHx * g.iHx, g.iHy * g.iHy, g.iHz * g.iHz};
-          float centre = 0.0f, side = 0.0f;
+        for (int f = 0; f < NF; ++f)
 #pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            centre += 2.0f * chi(pp[a], nn[a]) * ih2[a];
-            const int nb = (pp[a] > 0 ? chi(pp[a] - 1, nn[a]) : 0) + (pp[a] < nn[a] - 1 ? chi(pp[a] + 1, nn[a]) : 0);
-            side += nb * ih2[a] * ih2[a];
-          }
-          val += A.curv_scale * (centre * centre + side);
-        }
-        if (f == 0 && A.tauv) val += A.tau * A.tauv[oi];
-        o[oi] = val;
-        if (f == 0 && A.dotv) dsum += (double)A.dotv[oi] * (double)val;
-        if (f == 0) gsq += (double)val * (double)val;
-        if (f == 1) dmax = fmax(dmax, (double)val);
+          for (int c = 0; c < 3; ++c) val[f][c] = 0.0f;
+        for (int iz = 0; iz < nbz; ++iz)
+          for (int iy = 0; iy < nby; ++iy)
+            for (int ixx = 0; ixx < nbx; ++ixx) {
+              const int64_t brick = ((int64_t)bzs[iz] * g.nby + bys[iy]) * g.nbx + bxs[ixx];
+              const float *pp = part + (brick * (ZC + 1) + lzs[iz]) * (F * 3) * kNBOX + lys[iy] * 17 + lxs[ixx];
+#pragma unroll
+              for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) val[f][c] += (f < F) ? pp[(f * 3 + c) * kNBOX] : 0.0f;
+            }
+      } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) val[f][c] = (f < F) ? (f == 0 ? out0 : out1)[c * g.nnodes + n] : 0.0f;
       }
+    } else {
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) val[f][c] = 0.0f;
+    }
+    if (CURV) {
+      // alpha C_H (L^T z)(p), (L^T z)(p) = sum_a [chi_a(p-e_a) z(p-e_a) - 2 chi_a(p) z(p) + chi_a(p+e_a) z(p+e_a)] / H_a^2
+      const int pp[3] = {px, py, pz};
+      const int nn[3] = {g.px, g.py, g.pz};
+      const int64_t st[3] = {1, g.px, (int64_t)g.px * g.py};
+      const float ih2[3] = {g.iHx * g.iHx, g.iHy * g.iHy, g.iHz * g.iHz};
+      float wc = 0.0f, wm[3], wp[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        wc += -2.0f * chi(pp[a], nn[a]) * ih2[a];
+        wm[a] = (pp[a] > 0 && chi(pp[a] - 1, nn[a])) ? ih2[a] : 0.0f;
+        wp[a] = (pp[a] < nn[a] - 1 && chi(pp[a] + 1, nn[a])) ? ih2[a] : 0.0f;
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float *z = Lw + c * g.nnodes + n;
+        float acc = wc * z[0];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          // neighbours outside the grid have zero weight; read the centre instead
+          acc += wm[a] * z[wm[a] != 0.0f ? -st[a] : 0];
+          acc += wp[a] * z[wp[a] != 0.0f ? st[a] : 0];
+        }
+        val[0][c] += A.curv_scale * acc;
+      }
+      if (NF == 2 && A.curv_diag) {
+        float side = 0.0f;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) side += (wm[a] + wp[a]) * ih2[a];
+        const float d = A.curv_scale * (wc * wc + side);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) val[NF - 1][c] += d;
+      }
+    }
+    if (tauv) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) val[0][c] += A.tau * tauv[c * g.nnodes + n];
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) (f == 0 ? out0 : out1)[c * g.nnodes + n] = val[f][c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (dotv) dsum += (double)dotv[c * g.nnodes + n] * (double)val[0][c];
+      gsq += (double)val[0][c] * (double)val[0][c];
+      if (NF == 2) dmax = fmax(dmax, (double)val[NF - 1][c]);
     }
   }
   if (A.blocks) {
     // fixed-order tree reductions
     const int t = threadIdx.x;
-    double vals[3] = {dsum, dmax, gsq};
-    for (int k = 0; k < 3; ++k) {
-      red[t] = vals[k];
-      __syncthreads();
-      for (int s = 128; s > 0; s >>= 1) {
-        if (t < s) red[t] = (k == 1) ? fmax(red[t], red[t + s]) : red[t] + red[t + s];
-        __syncthreads();
+    red[0][t] = dsum;
+    red[1][t] = dmax;
+    red[2][t] = gsq;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (t < s) {
+        red[0][t] += red[0][t + s];
+        red[1][t] = fmax(red[1][t], red[1][t + s]);
+        red[2][t] += red[2][t + s];
       }
-      if (t == 0) A.blocks[blockIdx.x * 3 + k] = red[0];
       __syncthreads();
     }
+    if (t < 3) A.blocks[bid * 3 + t] = red[t][0];
   }
 }
 
@@ -883,10 +1107,11 @@ __global__ __launch_bounds__(256) void k_curv_L(Geo g, const float *a, const flo
                                                 const double *stop) {
   __shared__ double red[256];
   if (stop && *stop != 0.0) return;
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int px = blockIdx.x * 64 + (threadIdx.x & 63), py = blockIdx.y * 4 + (threadIdx.x >> 6), pz = blockIdx.z;
+  const int64_t n = ((int64_t)pz * g.py + py) * g.px + px;
+  const int64_t bid = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
   double e = 0.0;
-  if (n < g.nnodes) {
-    const int px = (int)(n % g.px), py = (int)((n / g.px) % g.py), pz = (int)(n / ((int64_t)g.px * g.py));
+  if (px < g.px && py < g.py) {
     const int pp[3] = {px, py, pz};
     const int nn[3] = {g.px, g.py, g.pz};
     const int64_t st[3] = {1, g.px, (int64_t)g.px * g.py};
@@ -911,16 +1136,16 @@ __global__ __launch_bounds__(256) void k_curv_L(Geo g, const float *a, const flo
       if (t < s) red[t] += red[t + s];
       __syncthreads();
     }
-    if (t == 0) blocks[blockIdx.x] = red[0];
+    if (t == 0) blocks[bid] = red[0];
   }
 }
 
 // central-difference image gradient with replicated border, stored as ST
 template <class ST>
 __global__ __launch_bounds__(256) void k_imgrad(Geo g, const float *img, typename ST::elem *out, float sq) {
-  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (v >= g.nvox) return;
-  const int i = (int)(v % g.nx), j = (int)((v / g.nx) % g.ny), k = (int)(v / ((int64_t)g.nx * g.ny));
+  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= g.nx) return;
+  const int64_t v = ((int64_t)k * g.ny + j) * g.nx + i;
   const int64_t sx = 1, sy = g.nx, sz = (int64_t)g.nx * g.ny;
   const int64_t xm = i > 0 ? v - sx : v, xp = i < g.nx - 1 ? v + sx : v;
   const int64_t ym = j > 0 ? v - sy : v, yp = j < g.ny - 1 ? v + sy : v;

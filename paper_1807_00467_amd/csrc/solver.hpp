@@ -1,43 +1,46 @@
-// Device kernels of the Gauss-Newton step: Jacobi-PCG vector updates, scalar
-// bookkeeping and the Armijo line search, all driven by device scalars so that a
-// whole step can run without host round trips.
+// Device kernels of the Gauss-Newton step: Jacobi-PCG vector updates and the Armijo
+// line search, driven by device scalars (SC_* slots) so that a whole step runs without
+// host round trips.  Inside the CG loop every workgroup of a consumer kernel reduces
+// the producer's per-block partials itself (same fixed order everywhere); the other
+// scalar bookkeeping runs in the single-workgroup k_finish (run_post).
 #pragma once
 #include "kernels.hpp"
 
 namespace disco {
 
-// slots of the device scalar array
-enum {
-  SC_D = 0, SC_SRAW, SC_V, SC_K, SC_NFOLD,      // linearisation: D, sum (Lw)^2, C sum psi, sum |res|^2, folds
-  SC_DOT, SC_MAXDIAG, SC_GG,                   // gather reductions: <dotv,out>, max diag, |out|^2
-  SC_J, SC_RZ, SC_PQ, SC_ALPHA, SC_BETA, SC_RR, SC_BB, SC_STOP, SC_ITERS, SC_BREAK,
-  SC_GTP, SC_TTRY, SC_ACCEPT, SC_TACC, SC_TRIALS,
-  SC_TD, SC_TSRAW, SC_TV, SC_TK, SC_TNFOLD,    // trial point reductions
-  SC_JT, SC_DT, SC_ST, SC_VT, SC_KT,           // accepted (or last) trial values
-  SC_TMP0, SC_TMP1, SC_TMP2,
-  SC_COUNT = 48
-};
-
-struct Weights {
-  double alpha, gamma, delta, CH;  // CH = H_x H_y H_z
-};
-
-// J from the reduced terms; a fold counts only when gamma > 0
-__device__ inline double total_J(const Weights &w, double D, double Sraw, double V, double K, double nfold) {
-  if (w.gamma != 0.0 && nfold > 0.0) return INFINITY;
-  return D + w.alpha * 0.5 * w.CH * Sraw + (w.gamma != 0.0 ? w.gamma * V : 0.0) + w.delta * K;
+// the stop flag read once per workgroup (another workgroup of the same launch may set
+// it), so that the whole workgroup takes the same branch before any barrier
+__device__ inline bool block_stopped(const double *sc) {
+  __shared__ int s_stop;
+  if (threadIdx.x == 0) s_stop = sc[SC_STOP] != 0.0;
+  __syncthreads();
+  return s_stop != 0;
 }
 
-__global__ void k_lin_post(double *sc, Weights w, int *status) {
-  sc[SC_J] = total_J(w, sc[SC_D], sc[SC_SRAW], sc[SC_V], sc[SC_K], sc[SC_NFOLD]);
-  if (status && w.gamma != 0.0 && sc[SC_NFOLD] > 0.0) *status |= 1;
+// per-block sums of two values over 256 threads (fixed tree)
+__device__ inline void block_pair_sum(double x, double y, double *blocks, int64_t bid) {
+  __shared__ double red[2][256];
+  const int t = threadIdx.x;
+  red[0][t] = x;
+  red[1][t] = y;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      red[0][t] += red[0][t + s];
+      red[1][t] += red[1][t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    blocks[2 * bid] = red[0][0];
+    blocks[2 * bid + 1] = red[1][0];
+  }
 }
 
 // x = 0, r = -g, z = r / M, p = z; per-block <r,z>, <r,r>
 __global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const float *g, const float *diag, const double *sc,
                                                   float tau, float *x, float *r, float *z, float *p,
                                                   double *blocks) {
-  __shared__ double red[2][256];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double rz = 0.0, rr = 0.0;
   if (i < n) {
@@ -51,119 +54,78 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const float *g, con
     rz = (double)ri * (double)zi;
     rr = (double)ri * (double)ri;
   }
-  const int t = threadIdx.x;
-  red[0][t] = rz;
-  red[1][t] = rr;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) {
-      red[0][t] += red[0][t + s];
-      red[1][t] += red[1][t + s];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    blocks[2 * blockIdx.x] = red[0][0];
-    blocks[2 * blockIdx.x + 1] = red[1][0];
-  }
+  block_pair_sum(rz, rr, blocks, blockIdx.x);
 }
 
-// after reducing <r,z>, <r,r> of the initial residual
-__global__ void k_pcg_start(double *sc) {
-  sc[SC_RZ] = sc[SC_TMP0];
-  sc[SC_BB] = sc[SC_TMP1];
-  sc[SC_RR] = sc[SC_TMP1];
-  sc[SC_STOP] = 0.0;
-  sc[SC_ITERS] = 0.0;
-  sc[SC_BREAK] = 0.0;
-}
-
-// alpha = rz / pq, or breakdown
-__global__ void k_pcg_alpha(double *sc, int *status) {
-  if (sc[SC_STOP] != 0.0) return;
-  const double pq = sc[SC_DOT];
+// CG iteration, part 1 (grid-stride, few workgroups): every workgroup reduces the
+// per-block <p, H p> of the product pass itself (same fixed order everywhere), so no
+// separate reduction launch is needed.  alpha = <r,z> / <p,Hp>; x += alpha p,
+// r -= alpha q, z = r / M; per-workgroup <r,z>, <r,r>.  <r,z> of this iteration is in
+// slot SC_RZ + (it & 1).
+__global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *sc, int it, const double *pq_blocks,
+                                                    int64_t pq_nb, const float *diag, float tau, const float *p,
+                                                    const float *q, float *x, float *r, float *z, double *blocks,
+                                                    int *status) {
+  __shared__ double red[256];
+  if (block_stopped(sc)) return;
+  const double pq = block_sum_all(pq_blocks, pq_nb, 3, 0, red);
   if (!(pq > 0.0)) {
-    sc[SC_STOP] = 1.0;
-    sc[SC_BREAK] = 1.0;
-    if (status) *status |= 2;
+    // breakdown: every workgroup sees the same pq and skips the update
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc[SC_STOP] = 1.0;
+      sc[SC_BREAK] = 1.0;
+      *status |= 2;
+    }
     return;
   }
-  sc[SC_ALPHA] = sc[SC_RZ] / pq;
-}
-
-// x += a p; r -= a q; z = r / M; per-block <r,z>, <r,r>
-__global__ __launch_bounds__(256) void k_pcg_update(int64_t n, const double *sc, const float *diag, float tau,
-                                                    const float *p, const float *q, float *x, float *r, float *z,
-                                                    double *blocks) {
-  __shared__ double red[2][256];
-  if (sc[SC_STOP] != 0.0) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const float a = (float)sc[SC_ALPHA];
+  const double alpha = sc[SC_RZ + (it & 1)] / pq;
+  const float a = (float)alpha;
+  const float M0 = tau + (float)(1e-12 * sc[SC_MAXDIAG]);
   double rz = 0.0, rr = 0.0;
-  if (i < n) {
-    const float M = diag[i] + tau + (float)(1e-12 * sc[SC_MAXDIAG]);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float M = diag[i] + M0;
     x[i] += a * p[i];
     const float ri = r[i] - a * q[i];
     r[i] = ri;
     const float zi = ri / M;
     z[i] = zi;
-    rz = (double)ri * (double)zi;
-    rr = (double)ri * (double)ri;
+    rz += (double)ri * (double)zi;
+    rr += (double)ri * (double)ri;
   }
-  const int t = threadIdx.x;
-  red[0][t] = rz;
-  red[1][t] = rr;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) {
-      red[0][t] += red[0][t + s];
-      red[1][t] += red[1][t + s];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    blocks[2 * blockIdx.x] = red[0][0];
-    blocks[2 * blockIdx.x + 1] = red[1][0];
-  }
+  block_pair_sum(rz, rr, blocks, blockIdx.x);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[SC_ALPHA] = alpha;
 }
 
-// beta = rz_new / rz; convergence test
-__global__ void k_pcg_beta(double *sc, double tol) {
-  if (sc[SC_STOP] != 0.0) return;
-  const double rz_new = sc[SC_TMP0];
-  sc[SC_RR] = sc[SC_TMP1];
-  sc[SC_ITERS] += 1.0;
-  sc[SC_BETA] = rz_new / sc[SC_RZ];
-  sc[SC_RZ] = rz_new;
-  if (tol > 0.0 && sqrt(sc[SC_RR]) <= tol * sqrt(sc[SC_BB])) sc[SC_STOP] = 1.0;
-}
-
-__global__ __launch_bounds__(256) void k_pcg_p(int64_t n, const double *sc, const float *z, float *p) {
-  if (sc[SC_STOP] != 0.0) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) p[i] = z[i] + (float)sc[SC_BETA] * p[i];
+// CG iteration, part 2: every workgroup reduces the <r,z>, <r,r> partials of part 1;
+// beta = <r,z>_new / <r,z>; p = z + beta p unless this was the last iteration or the
+// tolerance is met.  Workgroup 0 records the scalars for the next iteration.
+__global__ __launch_bounds__(256) void k_pcg_p(int64_t n, double *sc, int it, int last, double tol,
+                                               const double *blocks, int64_t nb, const float *z, float *p) {
+  __shared__ double red[256];
+  if (block_stopped(sc)) return;
+  const double rz_new = block_sum_all(blocks, nb, 2, 0, red);
+  const double rr = block_sum_all(blocks, nb, 2, 1, red);
+  const double beta = rz_new / sc[SC_RZ + (it & 1)];
+  const bool conv = tol > 0.0 && sqrt(rr) <= tol * sqrt(sc[SC_BB]);
+  if (!last && !conv) {
+    const float b = (float)beta;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+      p[i] = z[i] + b * p[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[SC_RZ + ((it + 1) & 1)] = rz_new;
+    sc[SC_RR] = rr;
+    sc[SC_BETA] = beta;
+    sc[SC_ITERS] = (double)(it + 1);
+    if (conv) sc[SC_STOP] = 1.0;
+  }
 }
 
 // per-block <a, b>
 __global__ __launch_bounds__(256) void k_dot(int64_t n, const float *a, const float *b, double *blocks) {
-  __shared__ double red[256];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int t = threadIdx.x;
-  red[t] = i < n ? (double)a[i] * (double)b[i] : 0.0;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  if (t == 0) blocks[blockIdx.x] = red[0];
-}
-
-__global__ void k_ls_begin(double *sc) {
-  sc[SC_GTP] = sc[SC_TMP0];
-  sc[SC_ACCEPT] = 0.0;
-  sc[SC_TACC] = 0.0;
-  sc[SC_TRIALS] = 0.0;
-  sc[SC_JT] = INFINITY;
+  const double x = i < n ? (double)a[i] * (double)b[i] : 0.0;
+  block_pair_sum(x, 0.0, blocks, blockIdx.x);
 }
 
 // trial point ut = u + t x with t = 2^-trial
@@ -176,35 +138,18 @@ __global__ __launch_bounds__(256) void k_ls_point(int64_t n, double *sc, int tri
   if (i == 0) sc[SC_TTRY] = (double)t;
 }
 
-// Armijo test of the trial just evaluated (reductions in SC_TD..SC_TNFOLD)
-__global__ void k_ls_decide(double *sc, Weights w, double c1) {
-  if (sc[SC_ACCEPT] != 0.0) return;
-  const double t = sc[SC_TTRY];
-  const double Jt = total_J(w, sc[SC_TD], sc[SC_TSRAW], sc[SC_TV], sc[SC_TK], sc[SC_TNFOLD]);
-  sc[SC_TRIALS] += 1.0;
-  sc[SC_JT] = Jt;
-  sc[SC_DT] = sc[SC_TD];
-  sc[SC_ST] = 0.5 * w.CH * sc[SC_TSRAW];
-  sc[SC_VT] = sc[SC_TV];
-  sc[SC_KT] = sc[SC_TK];
-  if (isfinite(Jt) && Jt <= sc[SC_J] + c1 * t * sc[SC_GTP]) {
-    sc[SC_ACCEPT] = 1.0;
-    sc[SC_TACC] = t;
-  }
-}
-
-// accept: u = ut; report and status
+// accept: u = ut
 __global__ __launch_bounds__(256) void k_ls_finish(int64_t n, const double *sc, const float *ut, float *u) {
   if (sc[SC_ACCEPT] == 0.0) return;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < n) u[i] = ut[i];
 }
 
-__global__ void k_report(const double *sc, Weights w, double *rep, int *status, int *status_out) {
+__global__ void k_report(const double *sc, double CH, double *rep, int *status, int *status_out) {
   if (rep) {
     rep[0] = sc[SC_J];
     rep[1] = sc[SC_D];
-    rep[2] = 0.5 * w.CH * sc[SC_SRAW];
+    rep[2] = 0.5 * CH * sc[SC_SRAW];
     rep[3] = sc[SC_NFOLD] > 0.0 ? INFINITY : sc[SC_V];
     rep[4] = sc[SC_K];
     rep[5] = sqrt(sc[SC_GG]);
@@ -223,31 +168,6 @@ __global__ void k_report(const double *sc, Weights w, double *rep, int *status, 
   if (status_out) *status_out = *status;
 }
 
-// brick reductions (SC_TMP0 + BS_*) -> linearisation slots
-__global__ void k_lin_move(double *sc, double h3) {
-  sc[SC_D] = sc[SC_TMP0 + BS_D] * h3;
-  sc[SC_V] = sc[SC_TMP0 + BS_V];
-  sc[SC_K] = sc[SC_TMP0 + BS_K];
-  sc[SC_NFOLD] = sc[SC_TMP0 + BS_FOLD];
-}
-
-// brick reductions -> trial slots (skipped once a trial was accepted)
-__global__ void k_ls_move(double *sc, double h3) {
-  if (sc[SC_ACCEPT] != 0.0) return;
-  sc[SC_TD] = sc[SC_TMP0 + BS_D] * h3;
-  sc[SC_TV] = sc[SC_TMP0 + BS_V];
-  sc[SC_TK] = sc[SC_TMP0 + BS_K];
-  sc[SC_TNFOLD] = sc[SC_TMP0 + BS_FOLD];
-}
-
 __global__ void k_clear_status(int *status) { *status = 0; }
-
-// small scalar helpers for the single-term entry points
-__global__ void k_write_scalar(const double *src, double scale, double *dst, const double *fold, int fold_inf) {
-  double v = *src * scale;
-  if (fold_inf && fold && *fold > 0.0) v = INFINITY;
-  *dst = v;
-}
-__global__ void k_write_int(const double *src, int32_t *dst) { *dst = (int32_t)(*src); }
 
 }  // namespace disco
