@@ -43,6 +43,7 @@ struct disco_ctx {
   void *gR = nullptr, *gT = nullptr, *scache = nullptr;
   float sR = 1.f, sT = 1.f;                 // dequantisation scales (FP16)
   float sS_load = 1.f, sS_store = 1.f;      // s cache scales (FP16)
+  double max_gT = 0.0;                      // max |grad T| component (FP16 storage)
   bool images = false;
   bool lin = false;
   double lin_eta = 0.0;
@@ -179,10 +180,10 @@ void launch_brick(disco_ctx *c, const BrickCall &b, hipStream_t s) {
   const int pk = b.mode == M_HV ? 0 : (b.mode == M_GRAD ? 1 : 2);
   ProfScope ps(c, pk, s);
   if (c->storage == DISCO_STORAGE_FP16) {
-    auto a = make_args<F16x4>(c, b);
-    if (b.mode == M_EVAL) launch_brick_mode<F16x4, M_EVAL>(c, b.ngf, b.vcc, b.kp, a, s);
-    if (b.mode == M_GRAD) launch_brick_mode<F16x4, M_GRAD>(c, b.ngf, b.vcc, b.kp, a, s);
-    if (b.mode == M_HV) launch_brick_mode<F16x4, M_HV>(c, b.ngf, b.vcc, b.kp, a, s);
+    auto a = make_args<F16x3>(c, b);
+    if (b.mode == M_EVAL) launch_brick_mode<F16x3, M_EVAL>(c, b.ngf, b.vcc, b.kp, a, s);
+    if (b.mode == M_GRAD) launch_brick_mode<F16x3, M_GRAD>(c, b.ngf, b.vcc, b.kp, a, s);
+    if (b.mode == M_HV) launch_brick_mode<F16x3, M_HV>(c, b.ngf, b.vcc, b.kp, a, s);
   } else {
     auto a = make_args<F32x3>(c, b);
     if (b.mode == M_EVAL) launch_brick_mode<F32x3, M_EVAL>(c, b.ngf, b.vcc, b.kp, a, s);
@@ -263,6 +264,20 @@ void launch_curv_L(disco_ctx *c, const float *a, const float *b, float *Lw, bool
                    hipStream_t s) {
   hipLaunchKernelGGL(k_curv_L, node_grid(c->g), dim3(256), 0, s, c->g, a, b, Lw, energy ? c->blk_curv : nullptr,
                      stop);
+}
+
+// FP16 s cache: |s_c| <= sum_a |JG[a][c]| |dr/da_a| <= sqrt(3) (2 max|grad T| / h_min) (2 / eta),
+// since |dr/da| <= 2 / sqrt(eta^2 + |a|^2); the power-of-two scale keeps that bound below
+// 2^15 (largest half is 65504), so no value overflows and typical values stay normal.
+void set_s_scale(disco_ctx *c, double eta) {
+  if (c->storage != DISCO_STORAGE_FP16) return;
+  const double hmin = std::min((double)c->g.hx, std::min((double)c->g.hy, (double)c->g.hz));
+  const double bound = 4.0 * std::sqrt(3.0) * c->max_gT / (hmin * eta);
+  int ex = 0;
+  if (bound > 0.0 && std::isfinite(bound)) ex = (int)std::floor(std::log2(32768.0 / bound));
+  ex = std::max(-100, std::min(100, ex));
+  c->sS_store = std::ldexp(1.0f, ex);
+  c->sS_load = std::ldexp(1.0f, -ex);
 }
 
 int check_field(const void *p) {
@@ -361,7 +376,7 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
   c->nwg = (int64_t)g.nbx * g.nby * g.nbz;
   c->nodeblocks = node_blocks(g);
 
-  const size_t vec3 = storage == DISCO_STORAGE_FP16 ? 8 : 12;  // bytes per voxel 3-vector
+  const size_t vec3 = storage == DISCO_STORAGE_FP16 ? 6 : 12;  // bytes per voxel 3-vector
   const size_t nf = 3 * (size_t)g.nnodes * sizeof(float);
   bool okm = true;
   auto alloc = [&](void **p, size_t bytes) {
@@ -371,9 +386,10 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
       okm = false;
     }
   };
-  alloc(&c->gR, vec3 * (size_t)nvox);
-  alloc(&c->gT, vec3 * (size_t)nvox);
-  alloc(&c->scache, vec3 * (size_t)nvox);
+  // 16 bytes of padding: the FP16 layout reads each voxel with an aligned 8-byte load
+  alloc(&c->gR, vec3 * (size_t)nvox + 16);
+  alloc(&c->gT, vec3 * (size_t)nvox + 16);
+  alloc(&c->scache, vec3 * (size_t)nvox + 16);
   float **nodebufs[] = {&c->u_lin, &c->Lw, &c->vg, &c->vdiag, &c->vx, &c->vr, &c->vz, &c->vp, &c->vq, &c->vut,
                         &c->tmp0, &c->tmp1};
   for (float **p : nodebufs) alloc(reinterpret_cast<void **>(p), nf);
@@ -419,6 +435,7 @@ int disco_set_images(disco_ctx *c, const float *R, const float *T, disco_stream 
     double *blk = nullptr;
     HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&blk), sizeof(double) * nb, s));
     float scales[2];
+    double maxes[2] = {0.0, 0.0};
     const float *imgs[2] = {R, T};
     for (int k = 0; k < 2; ++k) {
       hipLaunchKernelGGL(k_absmax_grad, dim3(nb), dim3(256), 0, s, g, imgs[k], blk);
@@ -430,13 +447,15 @@ int disco_set_images(disco_ctx *c, const float *R, const float *T, disco_stream 
       if (mx > 0.0 && std::isfinite(mx)) ex = (int)std::floor(std::log2(16384.0 / mx));
       ex = std::max(-100, std::min(100, ex));
       scales[k] = std::ldexp(1.0f, ex);
+      maxes[k] = mx;
     }
     HIP_TRY(hipFreeAsync(blk, s));
     c->sR = 1.0f / scales[0];
     c->sT = 1.0f / scales[1];
-    hipLaunchKernelGGL(k_imgrad<F16x4>, vox_grid(g), dim3(256), 0, s, g, R, reinterpret_cast<__half *>(c->gR),
+    c->max_gT = maxes[1];
+    hipLaunchKernelGGL(k_imgrad<F16x3>, vox_grid(g), dim3(256), 0, s, g, R, reinterpret_cast<__half *>(c->gR),
                        scales[0]);
-    hipLaunchKernelGGL(k_imgrad<F16x4>, vox_grid(g), dim3(256), 0, s, g, T, reinterpret_cast<__half *>(c->gT),
+    hipLaunchKernelGGL(k_imgrad<F16x3>, vox_grid(g), dim3(256), 0, s, g, T, reinterpret_cast<__half *>(c->gT),
                        scales[1]);
   } else {
     hipLaunchKernelGGL(k_imgrad<F32x3>, vox_grid(g), dim3(256), 0, s, g, R, reinterpret_cast<float *>(c->gR),
@@ -561,6 +580,7 @@ int ngf_grad(disco_ctx *c, double eta, const float *u, double *D_dev, float *g, 
   if ((e = set_device(c))) return e;
   hipStream_t s = S(stream);
   float *d1 = diag ? diag : c->tmp1;
+  set_s_scale(c, eta);
   PostArgs pa = post_args(c);
   pa.dst = D_dev;
   pa.idx = BS_D;
@@ -728,6 +748,7 @@ int gn_pcg_step(disco_ctx *c, const disco_params *p, float *u, double *report_de
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, c->status);
 
   // ---- linearise at u: J, grad J, diag of the GN matrix, s cache --------------------
+  set_s_scale(c, p->eta);
   launch_curv_L(c, u, c->u_ref, c->Lw, true, nullptr, s);
   {
     BrickCall b{M_GRAD, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, u, nullptr, c->vg, c->vdiag, nullptr};
@@ -791,7 +812,7 @@ int disco_copy_buffer(disco_ctx *c, int32_t which, float *dst, disco_stream stre
   const void *src = which == 0 ? c->gR : (which == 1 ? c->gT : c->scache);
   const float sc = which == 0 ? c->sR : (which == 1 ? c->sT : c->sS_load);
   if (c->storage == DISCO_STORAGE_FP16)
-    hipLaunchKernelGGL(k_unpack3<F16x4>, dim3(nblk(c->g.nvox)), dim3(256), 0, s, c->g,
+    hipLaunchKernelGGL(k_unpack3<F16x3>, dim3(nblk(c->g.nvox)), dim3(256), 0, s, c->g,
                        reinterpret_cast<const __half *>(src), sc, dst);
   else
     hipLaunchKernelGGL(k_unpack3<F32x3>, dim3(nblk(c->g.nvox)), dim3(256), 0, s, c->g,

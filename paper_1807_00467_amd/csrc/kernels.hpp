@@ -77,46 +77,28 @@ struct F32x3 {
   }
 };
 
-// half precision, 4 halfs (8 B) per voxel, value = stored * s (s: per-volume power of two)
-struct F16x4 {
+// half precision, 3 halfs (6 B) per voxel, value = stored * s (s: per-volume power of two).
+// A voxel starts at a 2- or 4-byte boundary: it is read with one 4-byte-aligned 8-byte
+// load and a shift.  Buffers carry 16 bytes of padding so the last voxel's load stays in
+// bounds.
+struct F16x3 {
   typedef __half elem;
-  static constexpr int W = 4;  // elements per voxel
+  static constexpr int W = 3;  // elements per voxel
   __device__ static inline void loadp(const __half *q, float s, float o[3]) {
-    const uint2 w = *reinterpret_cast<const uint2 *>(q);
-    __half2 a = *reinterpret_cast<const __half2 *>(&w.x);
-    __half2 b = *reinterpret_cast<const __half2 *>(&w.y);
-    float2 fa = __half22float2(a);
-    float2 fb = __half22float2(b);
-    o[0] = fa.x * s;
-    o[1] = fa.y * s;
-    o[2] = fb.x * s;
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(q);
+    const uint2 w = *reinterpret_cast<const uint2 *>(addr & ~(uintptr_t)3);
+    const uint64_t v = ((uint64_t)w.y << 32 | w.x) >> ((addr & 3u) * 8u);
+    o[0] = __half2float(__ushort_as_half((unsigned short)(v & 0xFFFFu))) * s;
+    o[1] = __half2float(__ushort_as_half((unsigned short)((v >> 16) & 0xFFFFu))) * s;
+    o[2] = __half2float(__ushort_as_half((unsigned short)((v >> 32) & 0xFFFFu))) * s;
   }
   __device__ static inline void storep(__half *q, float s, const float v[3]) {
-    __half2 a = __floats2half2_rn(v[0] * s, v[1] * s);
-    __half2 b = __floats2half2_rn(v[2] * s, 0.0f);
-    uint2 w;
-    w.x = *reinterpret_cast<const uint32_t *>(&a);
-    w.y = *reinterpret_cast<const uint32_t *>(&b);
-    *reinterpret_cast<uint2 *>(q) = w;
+    q[0] = __float2half_rn(v[0] * s);
+    q[1] = __float2half_rn(v[1] * s);
+    q[2] = __float2half_rn(v[2] * s);
   }
-  __device__ static inline void load(const __half *p, int64_t i, float s, float o[3]) {
-    const uint2 w = *reinterpret_cast<const uint2 *>(p + 4 * i);
-    __half2 a = *reinterpret_cast<const __half2 *>(&w.x);
-    __half2 b = *reinterpret_cast<const __half2 *>(&w.y);
-    float2 fa = __half22float2(a);
-    float2 fb = __half22float2(b);
-    o[0] = fa.x * s;
-    o[1] = fa.y * s;
-    o[2] = fb.x * s;
-  }
-  __device__ static inline void store(__half *p, int64_t i, float s, const float v[3]) {
-    __half2 a = __floats2half2_rn(v[0] * s, v[1] * s);
-    __half2 b = __floats2half2_rn(v[2] * s, 0.0f);
-    uint2 w;
-    w.x = *reinterpret_cast<const uint32_t *>(&a);
-    w.y = *reinterpret_cast<const uint32_t *>(&b);
-    *reinterpret_cast<uint2 *>(p + 4 * i) = w;
-  }
+  __device__ static inline void load(const __half *p, int64_t i, float s, float o[3]) { loadp(p + 3 * i, s, o); }
+  __device__ static inline void store(__half *p, int64_t i, float s, const float v[3]) { storep(p + 3 * i, s, v); }
 };
 
 
@@ -474,6 +456,7 @@ __device__ __forceinline__ void vcc_cell(const Geo &g, const float u[2][2][2][3]
   if (MODE == M_HV) cell_edges(v, 0.0f, 0.0f, 0.0f, de1, de2, de3);
   const float iC = frcp(g.C);
   float G1[4][3] = {}, G2[4][3] = {}, G3[4][3] = {};  // dVhat/d(edge) or GN product per edge
+  float D1[MODE == M_GRAD ? 4 : 1][3] = {}, D2[MODE == M_GRAD ? 4 : 1][3] = {}, D3[MODE == M_GRAD ? 4 : 1][3] = {};
 #pragma unroll
   for (int c3 = 0; c3 < 4; ++c3) {
     float x23[4][3], x31[4][3];
@@ -512,31 +495,46 @@ __device__ __forceinline__ void vcc_cell(const Geo &g, const float u[2][2][2][3]
           }
         }
         if (MODE == M_GRAD) {
-          // GN diagonal: C psi''(d) (dd/dy_n)^2, dd/dy_n = signed sum over the edges of this
-          // term through corner n of the cross product of the other two edges, over C
+          // GN diagonal: C psi''(d) (dd/dy_n)^2, dd/dy_n = (sum over the edges of this term
+          // through corner n of +-(cross product of the other two edges)) / C.  The square
+          // splits into per-edge squares (accumulated per edge) and cross products of two
+          // edges at their shared corner (which exists iff the indices below agree).
           const float p2 = 2.0f * id * id * id * w * iC;
           const int ja = a & 1, ka = a >> 1, ib = b & 1, kb = b >> 1, ic = c3 & 1, jc = c3 >> 1;
 #pragma unroll
-          for (int k = 0; k < 2; ++k)
+          for (int c = 0; c < 3; ++c) {
+            D1[a][c] += p2 * x23[b][c] * x23[b][c];
+            D2[b][c] += p2 * x31[a][c] * x31[a][c];
+            D3[c3][c] += p2 * x12[c] * x12[c];
+          }
+          if (ka == kb) {  // e1_a and e2_b meet at corner (ib, ja, ka)
+            const float sg = (ib ? 2.0f : -2.0f) * (ja ? 1.0f : -1.0f) * p2;
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
+            for (int c = 0; c < 3; ++c) out[1][ka][ja][ib][c] += sg * x23[b][c] * x31[a][c];
+          }
+          if (ja == jc) {  // e1_a and e3_c meet at corner (ic, ja, ka)
+            const float sg = (ic ? 2.0f : -2.0f) * (ka ? 1.0f : -1.0f) * p2;
 #pragma unroll
-              for (int i = 0; i < 2; ++i) {
-                const bool in1 = (j == ja) && (k == ka);
-                const bool in2 = (i == ib) && (k == kb);
-                const bool in3 = (i == ic) && (j == jc);
-                if (!(in1 || in2 || in3)) continue;
-                const float s1 = in1 ? (i ? 1.0f : -1.0f) : 0.0f;
-                const float s2 = in2 ? (j ? 1.0f : -1.0f) : 0.0f;
-                const float s3 = in3 ? (k ? 1.0f : -1.0f) : 0.0f;
+            for (int c = 0; c < 3; ++c) out[1][ka][ja][ic][c] += sg * x23[b][c] * x12[c];
+          }
+          if (ib == ic) {  // e2_b and e3_c meet at corner (ib, jc, kb)
+            const float sg = (jc ? 2.0f : -2.0f) * (kb ? 1.0f : -1.0f) * p2;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                  const float dd = s1 * x23[b][c] + s2 * x31[a][c] + s3 * x12[c];
-                  out[1][k][j][i][c] += p2 * dd * dd;
-                }
-              }
+            for (int c = 0; c < 3; ++c) out[1][kb][jc][ib][c] += sg * x31[a][c] * x12[c];
+          }
         }
       }
+  }
+  if (MODE == M_GRAD) {
+    // per-edge squares to both corners of the edge
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) out[1][k][j][i][c] += D1[j + 2 * k][c] + D2[i + 2 * k][c] + D3[i + 2 * j][c];
   }
   if (MODE == M_GRAD || MODE == M_HV) {
     // edges -> corners: +G on the far node of the edge, -G on the near node

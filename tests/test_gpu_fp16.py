@@ -1,0 +1,83 @@
+"""FP16 storage form: grad R, grad T and the per-voxel GN vectors stored as half precision
+with per-volume power-of-two scales, arithmetic in FP32, reductions in FP64.
+
+Errors are measured against the FP64 oracle (i) on the original inputs and (ii) on
+gradient volumes quantised to FP16 here on the CPU with the same scale rule
+(max |x| 2^k <= 2^14), which separates the storage rounding from the arithmetic.
+The bounds asserted are the documented accuracy of this form (half precision keeps 11
+significant bits, about 5e-4 relative per stored value).
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def quantise(g):
+    """FP16 storage emulated on the CPU: power-of-two scale with max |x| 2^k <= 2^14."""
+    mx = float(np.max(np.abs(g)))
+    k = int(np.floor(np.log2(16384.0 / mx))) if mx > 0 else 0
+    s = 2.0 ** k
+    return (g * s).astype(np.float16).astype(np.float64) / s
+
+
+@pytest.fixture(scope="module")
+def disco():
+    from paper_1807_00467_amd import disco as d
+    return d
+
+
+@pytest.mark.parametrize("shape,spacing,seed", [((32, 24, 20), (1.5, 1.5, 2.0), 11), ((76, 36, 28), (1.2, 1.4, 2.2), 12)])
+def test_fp16_storage_errors(disco, shape, spacing, seed):
+    say(f"[fp16] shape={shape}")
+    d = synth.small_pair(shape=shape, spacing=spacing, seed=seed, n_tubes=8, n_kp=40, field_max=4.0)
+    ctx = disco.Disco(d["shape"], d["spacing"], storage="fp16", device=DEV)
+    ctx.set_images(torch.from_numpy(d["R"]).to(DEV), torch.from_numpy(d["T"]).to(DEV))
+    u = torch.from_numpy(d["u_true"]).to(DEV)
+    v = torch.from_numpy(d["v"]).to(DEV)
+    eta = 10.0
+    D, g, diag = ctx.ngf_grad(u, eta)
+    hv = ctx.ngf_hessvec(v)
+    D = D.item()
+    g = g.cpu().numpy()
+    hv = hv.cpu().numpy()
+    gR = oracle.image_gradient(d["R"], d["spacing"])
+    gT = oracle.image_gradient(d["T"], d["spacing"])
+    uu = d["u_true"].astype(np.float64)
+    for name, (a, b) in {"original": (gR, gT), "fp16-rounded": (quantise(gR), quantise(gT))}.items():
+        ref = oracle.ngf(a, b, d["spacing"], eta, uu, want=("g", "s"))
+        ref_hv = oracle.ngf_hv(ref["s"], d["spacing"], d["v"])
+        eD = abs(D - ref["D"]) / ref["D"]
+        eg = rel_l2(g, ref["g"])
+        eh = rel_l2(hv, ref_hv)
+        say(f"  vs oracle on {name} inputs: D rel {eD:.2e}  grad rel-L2 {eg:.2e}  Hv rel-L2 {eh:.2e}")
+        assert eD < 2e-3 and eg < 2e-2 and eh < 2e-2, (name, eD, eg, eh)
+
+
+def test_fp16_gn_step_runs_and_decreases(disco):
+    say("[fp16 gn step]")
+    d = synth.small_pair(shape=(32, 24, 20), spacing=(1.5, 1.5, 2.0), seed=11, n_tubes=8, n_kp=40, field_max=4.0)
+    ctx = disco.Disco(d["shape"], d["spacing"], storage="fp16", device=DEV)
+    ctx.set_images(torch.from_numpy(d["R"]).to(DEV), torch.from_numpy(d["T"]).to(DEV))
+    ctx.set_keypoints(d["kp_x"], d["kp_t"])
+    u = torch.zeros_like(torch.from_numpy(d["u_true"])).to(DEV)
+    p = disco.Params(eta=10.0, alpha=1.0, gamma=0.1, delta=2.0, pcg_iters=10)
+    rep, st = ctx.gn_pcg_step(p, u)
+    r = disco.Disco.report_dict(rep)
+    assert int(st.item()) == 0 and r["J_new"] < r["J"]
