@@ -98,6 +98,34 @@ static void sample_vec(const int64_t *n, const double *h, const double *g, const
             }
 }
 
+/* Same sampling with the integer corner i0 of the sample point given (t = q - i0). */
+static void sample_vec_at(const int64_t *n, const double *h, const double *g, const double q[3],
+                          const int64_t i0[3], double G[3], double JG[3][3])
+{
+    double t[3];
+    for (int a = 0; a < 3; ++a) t[a] = q[a] - (double)i0[a];
+    for (int c = 0; c < 3; ++c) {
+        G[c] = 0.0;
+        JG[c][0] = JG[c][1] = JG[c][2] = 0.0;
+    }
+    for (int cz = 0; cz < 2; ++cz)
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+                int64_t ii = i0[0] + cx, jj = i0[1] + cy, kk = i0[2] + cz;
+                if (ii < 0 || ii >= n[0] || jj < 0 || jj >= n[1] || kk < 0 || kk >= n[2]) continue;
+                double wx = cx ? t[0] : 1.0 - t[0], dwx = cx ? 1.0 : -1.0;
+                double wy = cy ? t[1] : 1.0 - t[1], dwy = cy ? 1.0 : -1.0;
+                double wz = cz ? t[2] : 1.0 - t[2], dwz = cz ? 1.0 : -1.0;
+                const double *gv = g + 3 * IDX3(ii, jj, kk, n[0], n[1]);
+                for (int c = 0; c < 3; ++c) {
+                    G[c] += wx * wy * wz * gv[c];
+                    JG[c][0] += dwx * wy * wz * gv[c] / h[0];
+                    JG[c][1] += wx * dwy * wz * gv[c] / h[1];
+                    JG[c][2] += wx * wy * dwz * gv[c] / h[2];
+                }
+            }
+}
+
 void or_sample_points(const int64_t *n, const double *h, const double *g, int64_t npts,
                       const double *q, double *G, double *JG)
 {
@@ -161,6 +189,42 @@ static void scatter_voxel(const int64_t *nn, const int64_t *m, double *f, int64_
             }
 }
 
+/* ------------------------------------------------------------------------------ */
+/* Which cell of the moving-image grid holds a sample point is an integer decision     */
+/* taken by floating point: where q is within rounding of an integer the left and     */
+/* right cells give different derivatives J_G.  The paper fixes no precision, so the   */
+/* decision is taken in the GPU library's precision and evaluation order (single      */
+/* precision; the node displacements interpolated along x, then z, then y, one fused  */
+/* multiply-add each; then multiplied by 1/h rounded to single precision), while all   */
+/* arithmetic of the oracle stays in double precision.  Returns the lower corner i0.  */
+/* ------------------------------------------------------------------------------ */
+static void decide_cells_f32(const int64_t *nn, const int64_t *m, const int64_t *n, const double *h,
+                             const double *u, int64_t i, int64_t j, int64_t k, int64_t out[3])
+{
+    const int64_t nnodes = nn[0] * nn[1] * nn[2];
+    const int64_t idx[3] = {i, j, k};
+    const int64_t c0 = i / m[0], c1 = j / m[1], c2 = k / m[2];
+    const float wx = ((float)(i % m[0]) + 0.5f) / (float)m[0];
+    const float wy = ((float)(j % m[1]) + 0.5f) / (float)m[1];
+    const float wz = ((float)(k % m[2]) + 0.5f) / (float)m[2];
+    for (int a = 0; a < 3; ++a) {
+        const double *f = u + a * nnodes;
+        float fx[2][2]; /* [z][y] */
+        for (int kz = 0; kz < 2; ++kz)
+            for (int jy = 0; jy < 2; ++jy) {
+                const float a0 = (float)f[IDX3(c0, c1 + jy, c2 + kz, nn[0], nn[1])];
+                const float a1 = (float)f[IDX3(c0 + 1, c1 + jy, c2 + kz, nn[0], nn[1])];
+                fx[kz][jy] = fmaf(wx, a1 - a0, a0);
+            }
+        float fz[2];
+        for (int jy = 0; jy < 2; ++jy) fz[jy] = fmaf(wz, fx[1][jy] - fx[0][jy], fx[0][jy]);
+        const float f3 = fmaf(wy, fz[1] - fz[0], fz[0]);
+        const float uh = f3 * (float)(1.0 / h[a]);
+        const float d = fminf(fmaxf(uh, (float)(-2 - idx[a])), (float)(n[a] + 1 - idx[a]));
+        out[a] = idx[a] + (int64_t)floorf(d);
+    }
+}
+
 static void node_counts(const int64_t *n, const int64_t *m, int64_t nn[3])
 {
     for (int a = 0; a < 3; ++a) nn[a] = n[a] / m[a] + 1;
@@ -207,7 +271,9 @@ double or_ngf(const int64_t *n, const double *h, const int64_t *m, double eta, c
                 q[0] = (double)i + uv[0] / h[0];
                 q[1] = (double)j + uv[1] / h[1];
                 q[2] = (double)k + uv[2] / h[2];
-                sample_vec(n, h, gT, q, a, JG);
+                int64_t i0[3];
+                decide_cells_f32(nn, m, n, h, u, i, j, k, i0);
+                sample_vec_at(n, h, gT, q, i0, a, JG);
                 const double *b = gR + 3 * v;
                 double Da = e2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
                 double Db = e2 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2];

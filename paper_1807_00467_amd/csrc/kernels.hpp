@@ -723,7 +723,7 @@ __global__ __launch_bounds__(kWG) void k_brick(BrickArgs<ST> A) {
 #pragma unroll
           for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) fx[k][j][c] = nc[k][j][0][c] + xi * (nc[k][j][1][c] - nc[k][j][0][c]);
+            for (int c = 0; c < 3; ++c) fx[k][j][c] = __builtin_fmaf(xi, nc[k][j][1][c] - nc[k][j][0][c], nc[k][j][0][c]);
         // first voxel of this lane in the layer; voxel (kv, jv) is vbase + kv*nx*ny + jv*nx,
         // the offset being the same for the whole wave
         const int64_t vbase = ((int64_t)(czi * 4) * g.ny + cy * 4) * g.nx + ix;
@@ -736,7 +736,7 @@ __global__ __launch_bounds__(kWG) void k_brick(BrickArgs<ST> A) {
 #pragma unroll
           for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) fz[j][c] = fx[0][j][c] + wz * (fx[1][j][c] - fx[0][j][c]);
+            for (int c = 0; c < 3; ++c) fz[j][c] = __builtin_fmaf(wz, fx[1][j][c] - fx[0][j][c], fx[0][j][c]);
           float accY[FS][2][3] = {};
 #pragma unroll
           for (int jv = 0; jv < 4; ++jv) {
@@ -745,7 +745,7 @@ __global__ __launch_bounds__(kWG) void k_brick(BrickArgs<ST> A) {
             const int64_t voff = (kv * nxy + jv * g.nx) * ST::W;  // wave-uniform
             float f3[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) f3[c] = fz[0][c] + wy * (fz[1][c] - fz[0][c]);
+            for (int c = 0; c < 3; ++c) f3[c] = __builtin_fmaf(wy, fz[1][c] - fz[0][c], fz[0][c]);
             if (MODE == M_HV) {
               float s[3];
               ST::loadp(sp + voff, A.sS_load, s);
@@ -757,7 +757,9 @@ __global__ __launch_bounds__(kWG) void k_brick(BrickArgs<ST> A) {
                 accY[0][1][c] += wy * t;
               }
             } else {
-              // displacement in voxel units: q = index + u/h
+              // displacement in voxel units: q = index + u/h.  The displacement is interpolated
+              // in a fixed order (x, then z, then y, one fused multiply-add each) so that the
+              // cell holding the sample point is a reproducible FP32 decision.
               const float uh[3] = {f3[0] * g.ihx, f3[1] * g.ihy, f3[2] * g.ihz};
               float a[3], JG[3][3], b[3];
               sample_grad<ST>(A.gT, A.sT, g, ix, iy, iz, uh, a, JG);

@@ -1,0 +1,116 @@
+"""Full-size parity on the workloads the benchmark times.
+
+512 x 512 x 128 at 0.7 x 0.7 x 2.5 mm (node grid 129 x 129 x 33, 2000 keypoints), FP32
+storage, linearised at the true displacement with the benchmark's weights: the whole
+gradient, GN diagonal and GN product fields and one full GN step are compared with the
+FP64 oracle.  512 x 512 x 256 at 0.7 x 0.7 x 1.25 mm checks the largest case in both
+storage forms.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+DEV = torch.device("cuda:0")
+ETA, ALPHA, GAMMA = 10.0, 1.0, 0.1
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def rel(a, b):
+    return abs(float(a) - float(b)) / abs(float(b))
+
+
+@pytest.fixture(scope="module")
+def disco():
+    from paper_1807_00467_amd import disco as d
+    return d
+
+
+@pytest.fixture(scope="module")
+def cfg1(disco):
+    say("[fullsize] generating 512x512x128 ...")
+    d = synth.make_pair("cfg1")
+    P = oracle.Problem(d["R"], d["T"], d["spacing"], d["kp_x"], d["kp_t"],
+                       oracle.Weights(eta=ETA, alpha=ALPHA, gamma=GAMMA))
+    P.w.delta = P.adaptive_delta(np.zeros(d["u_true"].shape))
+    ctx = disco.Disco(d["shape"], d["spacing"], device=DEV)
+    ctx.set_images(torch.from_numpy(d["R"]).to(DEV), torch.from_numpy(d["T"]).to(DEV))
+    ctx.set_keypoints(d["kp_x"], d["kp_t"])
+    params = disco.Params(eta=ETA, alpha=ALPHA, gamma=GAMMA, delta=P.w.delta, pcg_iters=20)
+    return d, P, ctx, params
+
+
+def test_fullsize_adaptive_delta(cfg1):
+    d, P, ctx, params = cfg1
+    say("[fullsize] delta")
+    z = torch.zeros((3,) + tuple(ctx.nodes[::-1]), device=DEV)
+    D0 = ctx.ngf_eval(z, ETA).item()
+    K0 = ctx.keypoint_penalty(1.0, z, grad=False, diag=False)["K"].item()
+    assert rel(D0 / K0, P.w.delta) < 1e-5
+
+
+def test_fullsize_linearisation_and_gn_product(cfg1, disco):
+    d, P, ctx, params = cfg1
+    say("[fullsize] ngf_grad + gn_hessvec at u_true")
+    u = torch.from_numpy(d["u_true"]).to(DEV)
+    D, g, diag = ctx.ngf_grad(u, ETA)
+    hv = ctx.gn_hessvec(params, torch.from_numpy(d["v"]).to(DEV)).cpu().numpy()
+    lin = P.linearise(d["u_true"].astype(np.float64))
+    nd = P.ngf(d["u_true"], want=("g", "diag"))
+    ref_hv = P.gn_hv(d["v"].astype(np.float64))
+    eD, eg, ediag, ehv = rel(D.item(), lin["D"]), rel_l2(g.cpu().numpy(), nd["g"]), \
+        rel_l2(diag.cpu().numpy(), nd["diag"]), rel_l2(hv, ref_hv)
+    say(f"  D rel {eD:.2e}  grad rel-L2 {eg:.2e}  diag rel-L2 {ediag:.2e}  GN Hv rel-L2 {ehv:.2e}")
+    assert eD < 1e-5 and eg < 1e-4 and ediag < 1e-4 and ehv < 1e-4
+
+
+def test_fullsize_gn_step(cfg1, disco):
+    d, P, ctx, params = cfg1
+    say("[fullsize] gn_pcg_step from u_true")
+    u = torch.from_numpy(d["u_true"]).to(DEV)
+    rep, st = ctx.gn_pcg_step(params, u)
+    r = disco.Disco.report_dict(rep)
+    u1, ref = oracle.gn_pcg_step(P, d["u_true"].astype(np.float64), oracle.StepParams(pcg_iters=20))
+    say(f"  gpu J {r['J']:.8e} t={r['t']} J_new {r['J_new']:.8e}; oracle J {ref['J']:.8e} t={ref['t']} "
+        f"J_new {ref['trial']['J']:.8e}")
+    assert int(st.item()) == 0
+    for k in ("J", "D", "S", "V", "K"):
+        assert rel(r[k], ref[k]) < 1e-5, k
+    assert r["t"] == ref["t"]
+    step = u.cpu().numpy().astype(np.float64) - d["u_true"]
+    es = rel_l2(step, u1 - d["u_true"])
+    say(f"  step rel-L2 {es:.2e}")
+    assert es < 1e-3
+    assert rel(r["J_new"], ref["trial"]["J"]) < 1e-4
+
+
+@pytest.mark.parametrize("storage,tol_D,tol_f", [("fp32", 1e-5, 1e-4), ("fp16", 1e-4, 3e-3)])
+def test_largest_case_both_storages(disco, storage, tol_D, tol_f):
+    say(f"[fullsize] 512x512x256 storage={storage}")
+    d = synth.make_pair("cfg4")
+    ctx = disco.Disco(d["shape"], d["spacing"], storage=storage, device=DEV)
+    ctx.set_images(torch.from_numpy(d["R"]).to(DEV), torch.from_numpy(d["T"]).to(DEV))
+    u = torch.from_numpy(d["u_true"]).to(DEV)
+    D, g, _ = ctx.ngf_grad(u, ETA)
+    hv = ctx.ngf_hessvec(torch.from_numpy(d["v"]).to(DEV)).cpu().numpy()
+    gR = oracle.image_gradient(d["R"], d["spacing"])
+    gT = oracle.image_gradient(d["T"], d["spacing"])
+    ref = oracle.ngf(gR, gT, d["spacing"], ETA, d["u_true"], want=("g", "s"))
+    ref_hv = oracle.ngf_hv(ref["s"], d["spacing"], d["v"])
+    eD, eg, eh = rel(D.item(), ref["D"]), rel_l2(g.cpu().numpy(), ref["g"]), rel_l2(hv, ref_hv)
+    say(f"  D rel {eD:.2e}  grad rel-L2 {eg:.2e}  NGF Hv rel-L2 {eh:.2e}")
+    assert eD < tol_D and eg < tol_f and eh < tol_f
+    ctx.close()
