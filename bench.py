@@ -12,6 +12,7 @@ events on its launch stream during the timed steps.  The CPU baseline times the 
 oracle on a bounded sample of the same workload (GN products at full size).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                       [--storage fp32|fp16] [--calib-copy-mib M]
 """
 import argparse
 import json
@@ -31,15 +32,37 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ["paper_1807_00467_amd/csrc/kernels.hpp", "paper_1807_00467_amd/csrc/disco.hip",
+                  "paper_1807_00467_amd/csrc/solver.hpp", "paper_1807_00467_amd/build.py"]
+
+
+def kernel_source_hash():
+    """sha256 over the sources the measured kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profiles(kernel_tag):
-    """HBM bytes per launch measured by rocprofv3 counters (committed summary), if any."""
-    path = os.path.join(ROOT, "profiles", "counters_" + kernel_tag + ".json")
+    """HBM bytes per launch from the committed rocprofv3 counter summary of this kernel
+    and workload; None when there is none or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", "counters_" + kernel_tag + ".md")
     if not os.path.exists(path):
         return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != kernel_source_hash():
+        return None
     try:
-        with open(path) as f:
-            return json.load(f).get("traffic_bytes_per_launch")
-    except Exception:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
         return None
 
 
@@ -75,7 +98,13 @@ def main():
     ap.add_argument("--config", default="cfg1")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (HBM counter calibration)")
+    ap.add_argument("--print-source-hash", action="store_true")
     args = ap.parse_args()
+    if args.print_source_hash:
+        print(kernel_source_hash())
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -85,6 +114,16 @@ def main():
     import torch
     import synth
     from paper_1807_00467_amd import disco
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calib_copy_mib} MiB read + {args.calib_copy_mib} MiB written")
+        del src, dst
 
     log(f"[bench] generating {args.config} ...")
     t0 = time.perf_counter()
@@ -135,13 +174,13 @@ def main():
     nvox = int(np.prod(d["shape"]))
     nx, ny, nz = ctx.nodes
     nnodes = nx * ny * nz
-    bpv = 12 if args.storage == "fp32" else 8
+    bpv = 12 if args.storage == "fp32" else 6
     hv_bytes = bpv * nvox + 36 * nnodes           # s stream + v, u (VCC) read + Hv write
     hv_s = ms_hv / max(n_hv, 1) / 1e3
     achieved = hv_bytes / hv_s / 1e9
     hv_total = PCG_ITERS * args.steps
     value = hv_total / elapsed
-    kernel_tag = f"brick_hv_{args.config}_{args.storage}"
+    kernel_tag = f"brick_hv_{d['shape'][0]}x{d['shape'][1]}x{d['shape'][2]}_{args.storage}"
     out = {
         "metric": METRIC,
         "value": value,

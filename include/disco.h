@@ -143,6 +143,13 @@ int ngf_grad(disco_ctx *ctx, double eta, const float *u, double *D_dev, float *g
    gn_pcg_step); DISCO_ERR_STATE if there is none. */
 int ngf_hessvec(disco_ctx *ctx, const float *v, float *Hv, disco_stream stream);
 
+/* Derivative of the NGF distance of eq. 1 with respect to the moving image values at
+   displacement u: dT (device float32 [Nz][Ny][Nx]) = dD/dT, through the trilinear
+   sampling of grad T and its central-difference stencil.  The scatter to warped
+   positions uses float atomics, so the last bits of dT may differ between runs.  Needs
+   images set; allocates a [N][3] float32 work volume on the first call. */
+int ngf_grad_T(disco_ctx *ctx, double eta, const float *u, float *dT, disco_stream stream);
+
 /* Curvature term of eq. 5 with weight alpha: w = u - u_ref (u_ref nullable: 0),
    *S_dev = alpha S(u) (nullable), out = alpha C_H L^T L w (the gradient; nullable),
    diag = alpha C_H diag(L^T L) (nullable).  Called with u = v and u_ref = NULL, out is

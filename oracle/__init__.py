@@ -70,6 +70,8 @@ def _load():
         lib.or_keypoints.restype = D
         lib.or_det_voxels.argtypes = [P, P, P, P, P]
         lib.or_det_voxels.restype = None
+        lib.or_ngf_grad_T.argtypes = [P, P, P, D, P, P, P, P]
+        lib.or_ngf_grad_T.restype = None
         lib.or_num_threads.argtypes = []
         lib.or_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -145,6 +147,17 @@ def ngf(gR, gT, spacing, eta, u, m=(4, 4, 4), want=("g", "diag", "s", "r", "c"))
     D = _load().or_ngf(_p(n), _p(_f64(spacing)), _p(mm), float(eta), _p(gR), _p(gT), _p(u),
                        _p(g), _p(diag), _p(s), _p(r), _p(c))
     return dict(D=D, g=g, diag=diag, s=s, r=r, c=c)
+
+
+def ngf_grad_T(gR, gT, spacing, eta, u, m=(4, 4, 4)):
+    """dD/dT (eq. 1 through the gradient stencil and the trilinear sampling), [Nz][Ny][Nx]."""
+    gR = _f64(gR)
+    gT = _f64(gT)
+    nz, ny, nx, _ = gR.shape
+    out = np.empty((nz, ny, nx))
+    _load().or_ngf_grad_T(_p(_i64([nx, ny, nz])), _p(_f64(spacing)), _p(_i64(m)), float(eta), _p(gR), _p(gT),
+                          _p(_f64(u)), _p(out))
+    return out
 
 
 def ngf_hv(s, spacing, v, m=(4, 4, 4)):

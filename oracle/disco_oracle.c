@@ -757,3 +757,84 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------------ */
+/* Derivative of the NGF distance (eq. 1) with respect to the moving image values.   */
+/* D depends on T only through a_v = G(y_v), the trilinear sample of grad T, so       */
+/*   dD/d(grad T)[p] = sum_v w_{v,p} (-2 h^3 r_v dr/da_v)   (w: trilinear weights),   */
+/* and grad T is the central-difference stencil of T with replicated borders, so     */
+/*   dD/dT = stencil^T (dD/d grad T).                                                 */
+/* Output dT is [N] (same layout as T).                                              */
+/* ------------------------------------------------------------------------------ */
+void or_ngf_grad_T(const int64_t *n, const double *h, const int64_t *m, double eta, const double *gR,
+                   const double *gT, const double *u, double *dT)
+{
+    const int64_t nx = n[0], ny = n[1], nz = n[2];
+    const int64_t nvox = nx * ny * nz;
+    int64_t nn[3];
+    node_counts(n, m, nn);
+    const double h3 = h[0] * h[1] * h[2];
+    const double e2 = eta * eta;
+    double *wv = (double *)malloc(sizeof(double) * 3 * nvox); /* -2 h^3 r dr/da per voxel */
+    int64_t *cell = (int64_t *)malloc(sizeof(int64_t) * 3 * nvox);
+    double *qq = (double *)malloc(sizeof(double) * 3 * nvox);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                const int64_t v = IDX3(i, j, k, nx, ny);
+                double uv[3], q[3], a[3], JG[3][3];
+                interp_voxel(nn, m, u, i, j, k, uv);
+                q[0] = (double)i + uv[0] / h[0];
+                q[1] = (double)j + uv[1] / h[1];
+                q[2] = (double)k + uv[2] / h[2];
+                int64_t i0[3];
+                decide_cells_f32(nn, m, n, h, u, i, j, k, i0);
+                sample_vec_at(n, h, gT, q, i0, a, JG);
+                const double *b = gR + 3 * v;
+                double Da = e2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+                double Db = e2 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+                double P = e2 + a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+                double sq = sqrt(Da * Db);
+                double r = P / sq;
+                for (int t = 0; t < 3; ++t) {
+                    wv[3 * v + t] = -2.0 * h3 * r * (b[t] - (P / Da) * a[t]) / sq;
+                    cell[3 * v + t] = i0[t];
+                    qq[3 * v + t] = q[t];
+                }
+            }
+    /* scatter onto the grad-T grid with the trilinear weights (zero outside) */
+    double *W = (double *)calloc((size_t)(3 * nvox), sizeof(double));
+    for (int64_t v = 0; v < nvox; ++v) {
+        double t[3];
+        for (int a = 0; a < 3; ++a) t[a] = qq[3 * v + a] - (double)cell[3 * v + a];
+        for (int cz = 0; cz < 2; ++cz)
+            for (int cy = 0; cy < 2; ++cy)
+                for (int cx = 0; cx < 2; ++cx) {
+                    int64_t ii = cell[3 * v] + cx, jj = cell[3 * v + 1] + cy, kk = cell[3 * v + 2] + cz;
+                    if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || kk < 0 || kk >= nz) continue;
+                    double w = (cx ? t[0] : 1.0 - t[0]) * (cy ? t[1] : 1.0 - t[1]) * (cz ? t[2] : 1.0 - t[2]);
+                    for (int c = 0; c < 3; ++c) W[3 * IDX3(ii, jj, kk, nx, ny) + c] += w * wv[3 * v + c];
+                }
+    }
+    /* transpose of (grad I)_a[i] = (I[clamp(i+e_a)] - I[clamp(i-e_a)]) / (2 h_a) */
+    memset(dT, 0, sizeof(double) * nvox);
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                const int64_t v = IDX3(i, j, k, nx, ny);
+                int64_t ip = i < nx - 1 ? i + 1 : nx - 1, im = i > 0 ? i - 1 : 0;
+                int64_t jp = j < ny - 1 ? j + 1 : ny - 1, jm = j > 0 ? j - 1 : 0;
+                int64_t kp = k < nz - 1 ? k + 1 : nz - 1, km = k > 0 ? k - 1 : 0;
+                dT[IDX3(ip, j, k, nx, ny)] += W[3 * v] / (2.0 * h[0]);
+                dT[IDX3(im, j, k, nx, ny)] -= W[3 * v] / (2.0 * h[0]);
+                dT[IDX3(i, jp, k, nx, ny)] += W[3 * v + 1] / (2.0 * h[1]);
+                dT[IDX3(i, jm, k, nx, ny)] -= W[3 * v + 1] / (2.0 * h[1]);
+                dT[IDX3(i, j, kp, nx, ny)] += W[3 * v + 2] / (2.0 * h[2]);
+                dT[IDX3(i, j, km, nx, ny)] -= W[3 * v + 2] / (2.0 * h[2]);
+            }
+    free(W);
+    free(wv);
+    free(cell);
+    free(qq);
+}

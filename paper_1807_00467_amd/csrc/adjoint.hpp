@@ -1,0 +1,110 @@
+// Derivative of the NGF distance (eq. 1) with respect to the moving image T, for the
+// differentiable loss.  D depends on T through a_v = G(y_v), the trilinear sample of
+// grad T at the warped voxel centre, and grad T is the central-difference stencil of T:
+//   dD/d(grad T)[p] = sum_v w_{v,p} (-2 h^3 r_v dr/da_v),   dD/dT = stencil^T(dD/d grad T).
+// The first step scatters to warped positions, so it uses float atomics: the result is
+// exact up to FP32 rounding, but its summation order (hence its last bits) is not fixed.
+#pragma once
+#include "kernels.hpp"
+
+namespace disco {
+
+__global__ __launch_bounds__(256) void k_fill(int64_t n, float *p, float v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// one thread per voxel (rows of 256 along x)
+template <class ST>
+__global__ __launch_bounds__(256) void k_adjT_scatter(Geo g, const typename ST::elem *gR, const typename ST::elem *gT,
+                                                      float sR, float sT, const float *u, float eta2, float h3x2,
+                                                      float *W) {
+  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= g.nx) return;
+  const int64_t v = ((int64_t)k * g.ny + j) * g.nx + i;
+  // displacement at the voxel: node values interpolated along x, then z, then y (one
+  // fused multiply-add each), as in the brick kernel, so the sample cell is identical
+  const int cx = i >> 2, cy = j >> 2, cz = k >> 2;
+  const float wx = ((i & 3) + 0.5f) * 0.25f, wy = ((j & 3) + 0.5f) * 0.25f, wz = ((k & 3) + 0.5f) * 0.25f;
+  const int64_t pxy = (int64_t)g.px * g.py;
+  const int64_t n0 = (int64_t)cz * pxy + (int64_t)cy * g.px + cx;
+  float f3[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float *f = u + c * g.nnodes + n0;
+    float fx[2][2];
+#pragma unroll
+    for (int kz = 0; kz < 2; ++kz)
+#pragma unroll
+      for (int jy = 0; jy < 2; ++jy) {
+        const float a0 = f[kz * pxy + jy * g.px], a1 = f[kz * pxy + jy * g.px + 1];
+        fx[kz][jy] = __builtin_fmaf(wx, a1 - a0, a0);
+      }
+    float fz[2];
+#pragma unroll
+    for (int jy = 0; jy < 2; ++jy) fz[jy] = __builtin_fmaf(wz, fx[1][jy] - fx[0][jy], fx[0][jy]);
+    f3[c] = __builtin_fmaf(wy, fz[1] - fz[0], fz[0]);
+  }
+  const float uh[3] = {f3[0] * g.ihx, f3[1] * g.ihy, f3[2] * g.ihz};
+  float a[3], JG[3][3], b[3];
+  sample_grad<ST>(gT, sT, g, i, j, k, uh, a, JG);
+  ST::loadp(gR + v * ST::W, sR, b);
+  const float Da = eta2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+  const float Db = eta2 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+  const float P = eta2 + a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+  const float isq = rsqrtf(Da * Db);
+  const float r = P * isq;
+  const float pda = P * frcp(Da);
+  float w[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) w[c] = -h3x2 * r * (b[c] - pda * a[c]) * isq;
+  // the same corners and weights as the sample (zero outside the volume)
+  const int idx[3] = {i, j, k};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  int i0[3];
+  float t[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const float d = fminf(fmaxf(uh[ax], (float)(-2 - idx[ax])), (float)(n[ax] + 1 - idx[ax]));
+    const float fl = floorf(d);
+    t[ax] = d - fl;
+    i0[ax] = idx[ax] + (int)fl;
+  }
+#pragma unroll
+  for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 2; ++dx) {
+        const int xi = i0[0] + dx, yi = i0[1] + dy, zi = i0[2] + dz;
+        if ((unsigned)xi >= (unsigned)g.nx || (unsigned)yi >= (unsigned)g.ny || (unsigned)zi >= (unsigned)g.nz) continue;
+        const float wt = (dx ? t[0] : 1.0f - t[0]) * (dy ? t[1] : 1.0f - t[1]) * (dz ? t[2] : 1.0f - t[2]);
+        float *o = W + 3 * (((int64_t)zi * g.ny + yi) * g.nx + xi);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) atomicAdd(o + c, wt * w[c]);
+      }
+}
+
+// dT = transpose of (grad I)_a[i] = (I[clamp(i+e_a)] - I[clamp(i-e_a)]) / (2 h_a) applied to W
+__global__ __launch_bounds__(256) void k_adjT_stencil(Geo g, const float *W, float *dT) {
+  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+  if (i >= g.nx) return;
+  const int64_t v = ((int64_t)k * g.ny + j) * g.nx + i;
+  const int idx[3] = {i, j, k};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  const int64_t st[3] = {1, g.nx, (int64_t)g.nx * g.ny};
+  const float ih2[3] = {0.5f * g.ihx, 0.5f * g.ihy, 0.5f * g.ihz};
+  float acc = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float s = 0.0f;
+    if (idx[a] > 0) s += W[3 * (v - st[a]) + a];          // voxel i - e_a reads I[i] as its "+" neighbour
+    if (idx[a] == n[a] - 1) s += W[3 * v + a];           // replicated border: i's "+" neighbour is i itself
+    if (idx[a] < n[a] - 1) s -= W[3 * (v + st[a]) + a];   // voxel i + e_a reads I[i] as its "-" neighbour
+    if (idx[a] == 0) s -= W[3 * v + a];                  // replicated border: i's "-" neighbour is i itself
+    acc += s * ih2[a];
+  }
+  dT[v] = acc;
+}
+
+}  // namespace disco

@@ -14,6 +14,7 @@
 #include "disco.h"
 #include "kernels.hpp"
 #include "solver.hpp"
+#include "adjoint.hpp"
 
 using namespace disco;
 
@@ -54,6 +55,7 @@ struct disco_ctx {
   float *part = nullptr;
   double *blk_brick = nullptr, *blk_node = nullptr, *sc = nullptr;
   double *blk_curv = nullptr, *blk_upd = nullptr;
+  float *adjW = nullptr;  // dD/d(grad T) accumulator of ngf_grad_T, [N][3] (allocated on first use)
   int *status = nullptr;
   double *host_sc = nullptr;  // pinned
   // keypoints
@@ -319,7 +321,7 @@ void disco_destroy(disco_ctx *c) {
   clear_profile(c);
   void *ptrs[] = {c->gR,  c->gT,  c->scache, c->u_lin, c->u_ref, c->Lw,   c->vg,   c->vdiag, c->vx,   c->vr,
                   c->vz,  c->vp,  c->vq,     c->vut,   c->tmp0,  c->tmp1, c->part, c->blk_brick, c->blk_node,
-                  c->sc,  c->status, c->kloc, c->ktgt, c->kstart, c->blk_curv, c->blk_upd};
+                  c->sc,  c->status, c->kloc, c->ktgt, c->kstart, c->blk_curv, c->blk_upd, c->adjW};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->host_sc) (void)hipHostFree(c->host_sc);
@@ -797,6 +799,37 @@ int gn_pcg_step(disco_ctx *c, const disco_params *p, float *u, double *report_de
   hipLaunchKernelGGL(k_report, dim3(1), dim3(1), 0, s, sc, CH, report_dev, c->status, status_dev);
   HIP_TRY(hipGetLastError());
   // the s cache and u_lin now describe the linearisation point of this step
+  return DISCO_OK;
+}
+
+int ngf_grad_T(disco_ctx *c, double eta, const float *u, float *dT, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_field(u)) || (e = check_field(dT))) return e;
+  if (!std::isfinite(eta) || !(eta > 0.0)) return DISCO_ERR_NONFINITE;
+  if (!c->images) return DISCO_ERR_STATE;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  const Geo &g = c->g;
+  if (!c->adjW) {
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hipMalloc(reinterpret_cast<void **>(&c->adjW), sizeof(float) * 3 * (size_t)g.nvox) != hipSuccess) {
+      c->adjW = nullptr;
+      return DISCO_ERR_NOMEM;
+    }
+  }
+  hipLaunchKernelGGL(k_fill, dim3(nblk(3 * g.nvox)), dim3(256), 0, s, 3 * g.nvox, c->adjW, 0.0f);
+  const float h3x2 = (float)(2.0 * h3_of(c));
+  if (c->storage == DISCO_STORAGE_FP16)
+    hipLaunchKernelGGL(k_adjT_scatter<F16x3>, vox_grid(g), dim3(256), 0, s, g,
+                       reinterpret_cast<const __half *>(c->gR), reinterpret_cast<const __half *>(c->gT), c->sR, c->sT,
+                       u, (float)(eta * eta), h3x2, c->adjW);
+  else
+    hipLaunchKernelGGL(k_adjT_scatter<F32x3>, vox_grid(g), dim3(256), 0, s, g,
+                       reinterpret_cast<const float *>(c->gR), reinterpret_cast<const float *>(c->gT), 1.0f, 1.0f, u,
+                       (float)(eta * eta), h3x2, c->adjW);
+  hipLaunchKernelGGL(k_adjT_stencil, vox_grid(g), dim3(256), 0, s, g, c->adjW, dT);
+  HIP_TRY(hipGetLastError());
   return DISCO_OK;
 }
 

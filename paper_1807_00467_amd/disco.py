@@ -59,6 +59,7 @@ _SIGS = {
     "ngf_eval": ([_P, _D, _P, _P, _P], ctypes.c_int),
     "ngf_grad": ([_P, _D, _P, _P, _P, _P, _P], ctypes.c_int),
     "ngf_hessvec": ([_P, _P, _P, _P], ctypes.c_int),
+    "ngf_grad_T": ([_P, _D, _P, _P, _P], ctypes.c_int),
     "curvature_apply": ([_P, _D, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "volchange_eval": ([_P, _D, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "keypoint_penalty": ([_P, _D, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -199,6 +200,13 @@ class Disco:
     def ngf_hessvec(self, v: torch.Tensor) -> torch.Tensor:
         out = self.node_field()
         _check(_lib.ngf_hessvec(self._h, _ptr(self._field(v, "v")), _ptr(out), self._stream()), "ngf_hessvec")
+        return out
+
+    def ngf_grad_T(self, u: torch.Tensor, eta: float) -> torch.Tensor:
+        """dD/dT at displacement u (volume [Nz][Ny][Nx])."""
+        nx, ny, nz = self.shape
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.device)
+        _check(_lib.ngf_grad_T(self._h, eta, _ptr(self._field(u, "u")), _ptr(out), self._stream()), "ngf_grad_T")
         return out
 
     def curvature_apply(self, alpha: float, u: torch.Tensor, u_ref: Optional[torch.Tensor] = None,

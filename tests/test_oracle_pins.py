@@ -564,3 +564,36 @@ def test_line_search_rejects_folding_step():
     bad[0, 1, 1, 1] = -20.0
     o = P.objective(u + bad)
     assert np.isinf(o["J"]) and o["nfold"] > 0
+
+
+# ---------------------------------------------------------------------------------
+# derivative with respect to the moving image (differentiation form)
+# ---------------------------------------------------------------------------------
+
+def test_ngf_grad_T_matches_finite_differences_in_T():
+    """dD/dT by central differences of D in single voxel values of T (D recomputed
+    from scratch: gradient image, sampling, NGF)."""
+    d = small_case(8, shape=(16, 12, 12))
+    h = d["spacing"]
+    u = d["u_true"].astype(np.float64) * 0.8 + 0.017
+    gR = oracle.image_gradient(d["R"], h)
+    T = d["T"].astype(np.float64)
+    dT = oracle.ngf_grad_T(gR, oracle.image_gradient(T.astype(np.float32), h), h, 10.0, u)
+
+    def D_of(Tv):
+        # image_gradient of the oracle takes float32 input: do the stencil in float64 here
+        return oracle.ngf(gR, conv_gradient(Tv, h), h, 10.0, u, want=())["D"]
+
+    r = rng(30)
+    scale = np.max(np.abs(dT))
+    for _ in range(25):
+        idx = tuple(int(r.integers(0, s)) for s in T.shape)
+        best = np.inf
+        for eps in (1e-2, 1e-3, 1e-4):
+            Tp = T.copy()
+            Tm = T.copy()
+            Tp[idx] += eps
+            Tm[idx] -= eps
+            fd = (D_of(Tp) - D_of(Tm)) / (2 * eps)
+            best = min(best, abs(fd - dT[idx]) / max(abs(dT[idx]), 1e-3 * scale))
+        assert best < 1e-5, (idx, best)
