@@ -21,7 +21,6 @@ using namespace disco;
 namespace {
 
 constexpr int kZC = 4;          // cells per brick along z
-constexpr int kUpdBlocks = 256;  // workgroups of the grid-stride CG vector kernels
 
 struct EventPair {
   hipEvent_t a, b;
@@ -51,7 +50,7 @@ struct disco_ctx {
   // node workspaces
   float *u_lin = nullptr, *u_ref = nullptr, *Lw = nullptr;
   float *vg = nullptr, *vdiag = nullptr, *vx = nullptr, *vr = nullptr, *vz = nullptr, *vp = nullptr, *vq = nullptr,
-        *vut = nullptr, *tmp0 = nullptr, *tmp1 = nullptr;
+        *vut = nullptr, *tmp0 = nullptr, *tmp1 = nullptr, *vp2 = nullptr, *vinvm = nullptr;
   float *part = nullptr;
   double *blk_brick = nullptr, *blk_node = nullptr, *sc = nullptr;
   double *blk_curv = nullptr, *blk_upd = nullptr;
@@ -87,6 +86,9 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 // 3-D grid of 64 x 4 thread blocks over the node grid
 inline dim3 node_grid(const Geo &g) { return dim3((g.px + 63) / 64, (g.py + 3) / 4, g.pz); }
 inline int64_t node_blocks(const Geo &g) { return (int64_t)((g.px + 63) / 64) * ((g.py + 3) / 4) * g.pz; }
+// workgroups of the CG vector update, and the grid of the fused p update + L p pass
+inline int64_t upd_blocks(const Geo &g) { return (3 * g.nnodes + 256 * kUpdK - 1) / (256 * kUpdK); }
+inline dim3 lp_grid(const Geo &g) { return dim3((g.px + 63) / 64, (g.py + 3) / 4, (g.pz + kLpZ - 1) / kLpZ); }
 // 3-D grid over the voxels (rows of 256)
 inline dim3 vox_grid(const Geo &g) { return dim3((g.nx + 255) / 256, g.ny, g.nz); }
 
@@ -321,7 +323,7 @@ void disco_destroy(disco_ctx *c) {
   clear_profile(c);
   void *ptrs[] = {c->gR,  c->gT,  c->scache, c->u_lin, c->u_ref, c->Lw,   c->vg,   c->vdiag, c->vx,   c->vr,
                   c->vz,  c->vp,  c->vq,     c->vut,   c->tmp0,  c->tmp1, c->part, c->blk_brick, c->blk_node,
-                  c->sc,  c->status, c->kloc, c->ktgt, c->kstart, c->blk_curv, c->blk_upd, c->adjW};
+                  c->sc,  c->status, c->kloc, c->ktgt, c->kstart, c->blk_curv, c->blk_upd, c->adjW, c->vp2, c->vinvm};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->host_sc) (void)hipHostFree(c->host_sc);
@@ -393,7 +395,7 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
   alloc(&c->gT, vec3 * (size_t)nvox + 16);
   alloc(&c->scache, vec3 * (size_t)nvox + 16);
   float **nodebufs[] = {&c->u_lin, &c->Lw, &c->vg, &c->vdiag, &c->vx, &c->vr, &c->vz, &c->vp, &c->vq, &c->vut,
-                        &c->tmp0, &c->tmp1};
+                        &c->tmp0, &c->tmp1, &c->vp2, &c->vinvm};
   for (float **p : nodebufs) alloc(reinterpret_cast<void **>(p), nf);
   alloc(reinterpret_cast<void **>(&c->part), sizeof(float) * (size_t)c->nwg * (kZC + 1) * 6 * kNBOX);
   alloc(reinterpret_cast<void **>(&c->blk_brick), sizeof(double) * (size_t)c->nwg * BS_N);
@@ -402,7 +404,7 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
   alloc(reinterpret_cast<void **>(&c->sc), sizeof(double) * SC_COUNT);
   alloc(reinterpret_cast<void **>(&c->status), sizeof(int));
   alloc(reinterpret_cast<void **>(&c->blk_curv), sizeof(double) * (size_t)c->nodeblocks);
-  alloc(reinterpret_cast<void **>(&c->blk_upd), sizeof(double) * 2 * kUpdBlocks);
+  alloc(reinterpret_cast<void **>(&c->blk_upd), sizeof(double) * 2 * (size_t)upd_blocks(g));
   alloc(reinterpret_cast<void **>(&c->kstart), sizeof(int) * (size_t)(c->ncells + 1));
   if (okm && hipHostMalloc(reinterpret_cast<void **>(&c->host_sc), sizeof(double) * SC_COUNT) != hipSuccess) {
     c->host_sc = nullptr;
@@ -699,16 +701,23 @@ static int check_params(const disco_params *p) {
 
 // H v at the context's linearisation, all terms of eq. 11; with `dot` the gather also
 // writes per-block <v, Hv> (blk_node, stride 3)
-static void gn_hv_launch(disco_ctx *c, const disco_params *p, const float *v, float *Hv, bool dot,
-                         const double *stop, hipStream_t s) {
+// GN product after L v is in c->Lw: brick pass (NGF, VCC, keypoints), then the gather
+// (face nodes, curvature, damping, optional per-block <v, Hv>)
+static void gn_hv_body(disco_ctx *c, const disco_params *p, const float *v, float *Hv, bool dot,
+                       const double *stop, hipStream_t s) {
   const bool vcc = p->gamma != 0.0;
   const bool kp = p->delta != 0.0 && c->nkp > 0;
   const bool curv = p->alpha != 0.0;
-  if (curv) launch_curv_L(c, v, nullptr, c->Lw, false, stop, s);
   BrickCall b{M_HV, true, vcc, kp, 0.f, (float)p->gamma, (float)p->delta, c->u_lin, v, Hv, nullptr, stop};
   launch_brick(c, b, s);
   launch_gather(c, 1, 1, Hv, nullptr, curv ? c->Lw : nullptr, (float)(p->alpha * ch_of(c)), 0,
                 p->tau != 0.0 ? v : nullptr, (float)p->tau, dot ? v : nullptr, dot, stop, s);
+}
+
+static void gn_hv_launch(disco_ctx *c, const disco_params *p, const float *v, float *Hv, bool dot,
+                         const double *stop, hipStream_t s) {
+  if (p->alpha != 0.0) launch_curv_L(c, v, nullptr, c->Lw, false, stop, s);
+  gn_hv_body(c, p, v, Hv, dot, stop, s);
 }
 
 int gn_hessvec(disco_ctx *c, const disco_params *p, const float *v, float *Hv, disco_stream stream) {
@@ -767,20 +776,29 @@ int gn_pcg_step(disco_ctx *c, const disco_params *p, float *u, double *report_de
 
   // ---- Jacobi-PCG on (H + tau I) x = -g ----------------------------------------------
   hipLaunchKernelGGL(k_pcg_init, dim3(nb3), dim3(256), 0, s, n3, c->vg, c->vdiag, sc, (float)p->tau, c->vx, c->vr,
-                     c->vz, c->vp, c->blk_node);
+                     c->vz, c->vp, c->vinvm, c->blk_node);
   launch_finish(POST_PCG_START, pa, nullptr, s, src_pairs(c->blk_node, nb3, 2, sc + SC_TMP0));
   const double *stop = sc + SC_STOP;
+  const int64_t nbu = upd_blocks(g);
+  float *P[2] = {c->vp, c->vp2};  // search direction, alternating between iterations
   for (int it = 0; it < p->pcg_iters; ++it) {
-    gn_hv_launch(c, p, c->vp, c->vq, true, stop, s);
-    hipLaunchKernelGGL(k_pcg_update, dim3(kUpdBlocks), dim3(256), 0, s, n3, sc, it, c->blk_node, c->nodeblocks,
-                       c->vdiag, (float)p->tau, c->vp, c->vq, c->vx, c->vr, c->vz, c->blk_upd, c->status);
-    hipLaunchKernelGGL(k_pcg_p, dim3(kUpdBlocks), dim3(256), 0, s, n3, sc, it, it + 1 == p->pcg_iters ? 1 : 0,
-                       p->pcg_tol, c->blk_upd, (int64_t)kUpdBlocks, c->vz, c->vp);
+    float *pv = P[it & 1];
+    if (it == 0) {
+      if (curv) launch_curv_L(c, pv, nullptr, c->Lw, false, stop, s);
+    } else {
+      // beta, convergence test, p = z + beta p and L p in one pass
+      hipLaunchKernelGGL(k_curv_Lp, lp_grid(g), dim3(256), 0, s, g, it, sc, p->pcg_tol, c->blk_upd, nbu, c->vz,
+                         P[(it - 1) & 1], pv, c->Lw);
+    }
+    gn_hv_body(c, p, pv, c->vq, true, stop, s);
+    hipLaunchKernelGGL(k_pcg_update, dim3((unsigned)nbu), dim3(256), 0, s, n3, sc, it, c->blk_node, c->nodeblocks,
+                       c->vinvm, pv, c->vq, c->vx, c->vr, c->vz, c->blk_upd, c->status);
   }
 
   // ---- Armijo line search on J(u + t x) ------------------------------------------------
   hipLaunchKernelGGL(k_dot, dim3(nb3), dim3(256), 0, s, n3, c->vg, c->vx, c->blk_node);
-  launch_finish(POST_LS_BEGIN, pa, nullptr, s, src_pairs(c->blk_node, nb3, 1, sc + SC_TMP0));
+  launch_finish(POST_LS_BEGIN, pa, nullptr, s, src_pairs(c->blk_node, nb3, 1, sc + SC_TMP0),
+                src_pairs(c->blk_upd, nbu, 2, sc + SC_TMP1));
   const double *acc = sc + SC_ACCEPT;
   const bool dev_ls = (p->flags & DISCO_FLAG_LS_DEVICE) != 0;
   for (int t = 0; t < p->ls_max; ++t) {

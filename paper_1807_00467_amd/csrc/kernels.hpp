@@ -138,8 +138,6 @@ enum {
   POST_LIN_BRICK,  // linearisation: D, V, K, folds -> sc; J; fold status
   POST_LS_BRICK,   // line-search trial: D, V, K, folds -> sc; Armijo decision
   POST_PCG_START,  // <r,z>, <r,r> of the initial residual
-  POST_PCG_ALPHA,  // p^T H p -> step length or breakdown
-  POST_PCG_BETA,   // <r,z>, <r,r> after the update -> beta, convergence
   POST_LS_BEGIN,   // g^T p -> start of the line search
   POST_STORE       // out values only
 };
@@ -220,25 +218,9 @@ __device__ inline void run_post(int post, const PostArgs &a, const double *r) {
       sc[SC_ITERS] = 0.0;
       sc[SC_BREAK] = 0.0;
       break;
-    case POST_PCG_ALPHA:
-      if (sc[SC_STOP] != 0.0) break;
-      if (!(r[0] > 0.0)) {
-        sc[SC_STOP] = 1.0;
-        sc[SC_BREAK] = 1.0;
-        if (a.status) *a.status |= 2;
-      } else {
-        sc[SC_ALPHA] = sc[SC_RZ] / r[0];
-      }
-      break;
-    case POST_PCG_BETA:
-      if (sc[SC_STOP] != 0.0) break;
-      sc[SC_RR] = r[1];
-      sc[SC_ITERS] += 1.0;
-      sc[SC_BETA] = r[0] / sc[SC_RZ];
-      sc[SC_RZ] = r[0];
-      if (a.tol > 0.0 && sqrt(sc[SC_RR]) <= a.tol * sqrt(sc[SC_BB])) sc[SC_STOP] = 1.0;
-      break;
     case POST_LS_BEGIN:
+      // residual of the last completed CG update (its partials were reduced into SC_TMP1)
+      if (sc[SC_ITERS] > 0.0) sc[SC_RR] = sc[SC_TMP1 + 1];
       sc[SC_GTP] = r[0];
       sc[SC_ACCEPT] = 0.0;
       sc[SC_TACC] = 0.0;
@@ -553,6 +535,86 @@ __device__ __forceinline__ void vcc_cell(const Geo &g, const float u[2][2][2][3]
   }
 }
 
+// GN product of the volume-change term for one cell: out += w C sum_t psi''(d_t)
+// (grad d_t . v) grad d_t over the 64 coefficients d_abc = det[e1_a, e2_b, e3_c] / C.
+// For fixed (b, c) the cross product x = e2_b x e3_c / C is shared by the four a, and
+// grad d . v = de1_a . x + e1_a . y with y = (de2_b x e3_c + e2_b x de3_c) / C.  The
+// derivatives with respect to e2_b and e3_c are (e3_c x e1_a) / C and (e1_a x e2_b) / C,
+// so their sums over a collapse to one cross product with z = sum_a k_a e1_a.
+__device__ __forceinline__ void vcc_cell_hv(const Geo &g, const float u[2][2][2][3], const float v[2][2][2][3],
+                                            float w, float out[2][2][2][3]) {
+  float e1[4][3], e2[4][3], e3[4][3];
+  cell_edges(u, g.Hx, g.Hy, g.Hz, e1, e2, e3);
+  float de1[4][3], de2[4][3], de3[4][3];
+  cell_edges(v, 0.0f, 0.0f, 0.0f, de1, de2, de3);
+  const float iC = frcp(g.C);
+  // k = w C psi''(d) (grad d . v) = 2 w C id^3 jv.  The factor w2 = 2 w C is put into the
+  // v edges and 1/C into the z edges, so that x = e2 x e3' and y = de2' x e3' + e2 x de3'
+  // come out scaled as needed without per-term multiplications.
+  const float w2 = 2.0f * w * g.C;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      de1[a][c] *= w2;
+      de2[a][c] *= w2;
+      de3[a][c] *= w2 * iC;
+      e3[a][c] *= iC;
+    }
+  float G1[4][3] = {}, G2[4][3] = {}, G3[4][3] = {};  // G3 is accumulated times C
+#pragma unroll
+  for (int c3 = 0; c3 < 4; ++c3)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      float x[3], y[3];
+      cross3(e2[b], e3[c3], x);  // e2 x e3 / C
+      // y = w2 (de2 x e3 + e2 x de3) / C, as one fused chain per component
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        float acc = de2[b][c1] * e3[c3][c2];
+        acc = __builtin_fmaf(-de2[b][c2], e3[c3][c1], acc);
+        acc = __builtin_fmaf(e2[b][c1], de3[c3][c2], acc);
+        y[c] = __builtin_fmaf(-e2[b][c2], de3[c3][c1], acc);
+      }
+      float z[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const float d = dot3(e1[a], x);
+        float jv = dot3(de1[a], x);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) jv = __builtin_fmaf(e1[a][c], y[c], jv);
+        const float id = d > 0.0f ? frcp(d) : 0.0f;  // terms with d <= 0 (a fold) do not count
+        const float k = id * id * id * jv;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          G1[a][c] = __builtin_fmaf(k, x[c], G1[a][c]);
+          z[c] = __builtin_fmaf(k, e1[a][c], z[c]);
+        }
+      }
+      // G2 += e3' x z, G3 += z x e2 (fused into the accumulators)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        G2[b][c] = __builtin_fmaf(e3[c3][c1], z[c2], G2[b][c]);
+        G2[b][c] = __builtin_fmaf(-e3[c3][c2], z[c1], G2[b][c]);
+        G3[c3][c] = __builtin_fmaf(z[c1], e2[b][c2], G3[c3][c]);
+        G3[c3][c] = __builtin_fmaf(-z[c2], e2[b][c1], G3[c3][c]);
+      }
+    }
+  // edges -> corners: +G on the far node of the edge, -G on the near node
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          out[k][j][i][c] += (i ? G1[j + 2 * k][c] : -G1[j + 2 * k][c]) + (j ? G2[i + 2 * k][c] : -G2[i + 2 * k][c]) +
+                             (k ? iC * G3[i + 2 * j][c] : -iC * G3[i + 2 * j][c]);
+}
+
 template <int MODE>
 __device__ __forceinline__ void kp_cell(const Geo &g, int ks, int ke, const float *kloc, const float *ktgt,
                                         const float u[2][2][2][3], const float v[2][2][2][3], float w,
@@ -627,8 +689,11 @@ __device__ __forceinline__ void load_corners(const float *fb, const Geo &g, bool
 // ---------------------------------------------------------------------------------
 // The voxel-brick kernel.
 // ---------------------------------------------------------------------------------
+#ifndef DISCO_HV_WAVES
+#define DISCO_HV_WAVES 1
+#endif
 template <class ST, int MODE, bool NGF, bool VCC, bool KP, int ZC>
-__global__ __launch_bounds__(kWG) void k_brick(BrickArgs<ST> A) {
+__global__ __launch_bounds__(kWG, MODE == M_HV ? DISCO_HV_WAVES : 1) void k_brick(BrickArgs<ST> A) {
   constexpr int F = (MODE == M_GRAD) ? 2 : ((MODE == M_HV) ? 1 : 0);
   constexpr int FS = F > 0 ? F : 1;
   constexpr bool CELLT = VCC || KP;
@@ -656,22 +721,6 @@ __global__ __launch_bounds__(kWG) void k_brick(BrickArgs<ST> A) {
   const int64_t pxy = (int64_t)g.px * g.py;
   const int64_t nxy = (int64_t)g.nx * g.ny;
 
-  // NGF: node values of this lane's cell, rolled along z: [k][j][i][c] (u, or v for M_HV)
-  float nc[2][2][2][3];
-  const float *NF = (MODE == M_HV) ? A.v : A.u;
-  const float *NB = NF + (ok ? (int64_t)cy * g.px + cx : 0);
-  if (NGF) {
-    float tmp[2][2][3];
-    load_plane(NB, (int64_t)cz0 * pxy, g, ok, tmp);
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) nc[0][j][i][c] = tmp[j][i][c];
-  }
-
-  float carN[FS][2][3] = {};  // NGF, per lane before the x reduction: [f][jn][c]
   double sD = 0.0, sV = 0.0, sK = 0.0;
   int nfold = 0;
   const float sc_ngf = A.ngf_scale;
@@ -701,187 +750,270 @@ __global__ __launch_bounds__(kWG) void k_brick(BrickArgs<ST> A) {
     }
   };
 
-  for (int czi = cz0; czi < cz1; ++czi) {
-    const int zl = czi - cz0;
-    float accN[FS][2][2][3] = {};  // [f][kn][jn][c]
-    if (NGF) {
-      {
+  // voxel part (NGF): node values rolled along z, layer by layer
+  auto ngf_phase = [&]() {
+    if constexpr (NGF) {
+      // NGF: node values of this lane's cell, rolled along z: [k][j][i][c] (u, or v for M_HV)
+      float nc[2][2][2][3];
+      const float *NF = (MODE == M_HV) ? A.v : A.u;
+      const float *NB = NF + (ok ? (int64_t)cy * g.px + cx : 0);
+      if (NGF) {
         float tmp[2][2][3];
-        load_plane(NB, (int64_t)(czi + 1) * pxy, g, ok, tmp);
-#pragma unroll
+        load_plane(NB, (int64_t)cz0 * pxy, g, ok, tmp);
+    #pragma unroll
         for (int j = 0; j < 2; ++j)
-#pragma unroll
+    #pragma unroll
           for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) nc[1][j][i][c] = tmp[j][i][c];
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) nc[0][j][i][c] = tmp[j][i][c];
       }
-      if (ok) {
-        // node values interpolated along x at this lane's voxel: fx[k][j][c]
-        float fx[2][2][3];
-#pragma unroll
-        for (int k = 0; k < 2; ++k)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) fx[k][j][c] = __builtin_fmaf(xi, nc[k][j][1][c] - nc[k][j][0][c], nc[k][j][0][c]);
-        // first voxel of this lane in the layer; voxel (kv, jv) is vbase + kv*nx*ny + jv*nx,
-        // the offset being the same for the whole wave
-        const int64_t vbase = ((int64_t)(czi * 4) * g.ny + cy * 4) * g.nx + ix;
-        const typename ST::elem *sp = A.sc + vbase * ST::W;
-        const typename ST::elem *rp = A.gR + vbase * ST::W;
-        auto zrow = [&](const int kv) {
-          const float wz = (kv + 0.5f) * 0.25f;
-          const int iz = czi * 4 + kv;
-          float fz[2][3];
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) fz[j][c] = __builtin_fmaf(wz, fx[1][j][c] - fx[0][j][c], fx[0][j][c]);
-          float accY[FS][2][3] = {};
-#pragma unroll
-          for (int jv = 0; jv < 4; ++jv) {
-            const float wy = (jv + 0.5f) * 0.25f;
-            const int iy = cy * 4 + jv;
-            const int64_t voff = (kv * nxy + jv * g.nx) * ST::W;  // wave-uniform
-            float f3[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) f3[c] = __builtin_fmaf(wy, fz[1][c] - fz[0][c], fz[0][c]);
-            if (MODE == M_HV) {
-              float s[3];
-              ST::loadp(sp + voff, A.sS_load, s);
-              const float w = s[0] * f3[0] + s[1] * f3[1] + s[2] * f3[2];
-#pragma unroll
-              for (int c = 0; c < 3; ++c) {
-                const float t = w * s[c];
-                accY[0][0][c] += (1.0f - wy) * t;
-                accY[0][1][c] += wy * t;
-              }
-            } else {
-              // displacement in voxel units: q = index + u/h.  The displacement is interpolated
-              // in a fixed order (x, then z, then y, one fused multiply-add each) so that the
-              // cell holding the sample point is a reproducible FP32 decision.
-              const float uh[3] = {f3[0] * g.ihx, f3[1] * g.ihy, f3[2] * g.ihz};
-              float a[3], JG[3][3], b[3];
-              sample_grad<ST>(A.gT, A.sT, g, ix, iy, iz, uh, a, JG);
-              ST::loadp(rp + voff, A.sR, b);
-              const float e2 = A.eta2;
-              const float Da = e2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
-              const float Db = e2 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-              const float P = e2 + a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-              const float dab[3] = {a[0] - b[0], a[1] - b[1], a[2] - b[2]};
-              float axb[3];
-              cross3(a, b, axb);
-              const float DD = Da * Db;
-              // 1 - r^2 without cancellation (Lagrange's identity)
-              const float cvox = (e2 * dot3(dab, dab) + dot3(axb, axb)) * frcp(DD);
-              sD += (double)cvox;
-              if (MODE == M_GRAD) {
-                const float isq = rsqrtf(DD);
-                const float r = P * isq;
-                const float pda = P * frcp(Da);
-                float dr[3], s[3];
-#pragma unroll
-                for (int c = 0; c < 3; ++c) dr[c] = (b[c] - pda * a[c]) * isq;
-#pragma unroll
-                for (int c = 0; c < 3; ++c) s[c] = JG[0][c] * dr[0] + JG[1][c] * dr[1] + JG[2][c] * dr[2];
-                ST::storep(const_cast<typename ST::elem *>(sp) + voff, A.sS_store, s);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                  const float t = r * s[c];
-                  accY[0][0][c] += (1.0f - wy) * t;
-                  accY[0][1][c] += wy * t;
-                  const float t2 = s[c] * s[c];
-                  accY[FS - 1][0][c] += (1.0f - wy) * (1.0f - wy) * t2;
-                  accY[FS - 1][1][c] += wy * wy * t2;
+
+      float carN[FS][2][3] = {};  // NGF, per lane before the x reduction: [f][jn][c]
+      for (int czi = cz0; czi < cz1; ++czi) {
+        const int zl = czi - cz0;
+        float accN[FS][2][2][3] = {};  // [f][kn][jn][c]
+        if (NGF) {
+          {
+            float tmp[2][2][3];
+            load_plane(NB, (int64_t)(czi + 1) * pxy, g, ok, tmp);
+    #pragma unroll
+            for (int j = 0; j < 2; ++j)
+    #pragma unroll
+              for (int i = 0; i < 2; ++i)
+    #pragma unroll
+                for (int c = 0; c < 3; ++c) nc[1][j][i][c] = tmp[j][i][c];
+          }
+          if (ok) {
+            // node values interpolated along x at this lane's voxel: fx[k][j][c]
+            float fx[2][2][3];
+    #pragma unroll
+            for (int k = 0; k < 2; ++k)
+    #pragma unroll
+              for (int j = 0; j < 2; ++j)
+    #pragma unroll
+                for (int c = 0; c < 3; ++c) fx[k][j][c] = __builtin_fmaf(xi, nc[k][j][1][c] - nc[k][j][0][c], nc[k][j][0][c]);
+            // first voxel of this lane in the layer; voxel (kv, jv) is vbase + kv*nx*ny + jv*nx,
+            // the offset being the same for the whole wave
+            const int64_t vbase = ((int64_t)(czi * 4) * g.ny + cy * 4) * g.nx + ix;
+            const typename ST::elem *sp = A.sc + vbase * ST::W;
+            const typename ST::elem *rp = A.gR + vbase * ST::W;
+            auto zrow = [&](const int kv) {
+              const float wz = (kv + 0.5f) * 0.25f;
+              const int iz = czi * 4 + kv;
+              float fz[2][3];
+    #pragma unroll
+              for (int j = 0; j < 2; ++j)
+    #pragma unroll
+                for (int c = 0; c < 3; ++c) fz[j][c] = __builtin_fmaf(wz, fx[1][j][c] - fx[0][j][c], fx[0][j][c]);
+              float accY[FS][2][3] = {};
+    #pragma unroll
+              for (int jv = 0; jv < 4; ++jv) {
+                const float wy = (jv + 0.5f) * 0.25f;
+                const int iy = cy * 4 + jv;
+                const int64_t voff = (kv * nxy + jv * g.nx) * ST::W;  // wave-uniform
+                float f3[3];
+    #pragma unroll
+                for (int c = 0; c < 3; ++c) f3[c] = __builtin_fmaf(wy, fz[1][c] - fz[0][c], fz[0][c]);
+                if (MODE == M_HV) {
+                  float s[3];
+                  ST::loadp(sp + voff, A.sS_load, s);
+                  const float w = s[0] * f3[0] + s[1] * f3[1] + s[2] * f3[2];
+    #pragma unroll
+                  for (int c = 0; c < 3; ++c) {
+                    const float t = w * s[c];
+                    accY[0][0][c] += (1.0f - wy) * t;
+                    accY[0][1][c] += wy * t;
+                  }
+                } else {
+                  // displacement in voxel units: q = index + u/h.  The displacement is interpolated
+                  // in a fixed order (x, then z, then y, one fused multiply-add each) so that the
+                  // cell holding the sample point is a reproducible FP32 decision.
+                  const float uh[3] = {f3[0] * g.ihx, f3[1] * g.ihy, f3[2] * g.ihz};
+                  float a[3], JG[3][3], b[3];
+                  sample_grad<ST>(A.gT, A.sT, g, ix, iy, iz, uh, a, JG);
+                  ST::loadp(rp + voff, A.sR, b);
+                  const float e2 = A.eta2;
+                  const float Da = e2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+                  const float Db = e2 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+                  const float P = e2 + a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+                  const float dab[3] = {a[0] - b[0], a[1] - b[1], a[2] - b[2]};
+                  float axb[3];
+                  cross3(a, b, axb);
+                  const float DD = Da * Db;
+                  // 1 - r^2 without cancellation (Lagrange's identity)
+                  const float cvox = (e2 * dot3(dab, dab) + dot3(axb, axb)) * frcp(DD);
+                  sD += (double)cvox;
+                  if (MODE == M_GRAD) {
+                    const float isq = rsqrtf(DD);
+                    const float r = P * isq;
+                    const float pda = P * frcp(Da);
+                    float dr[3], s[3];
+    #pragma unroll
+                    for (int c = 0; c < 3; ++c) dr[c] = (b[c] - pda * a[c]) * isq;
+    #pragma unroll
+                    for (int c = 0; c < 3; ++c) s[c] = JG[0][c] * dr[0] + JG[1][c] * dr[1] + JG[2][c] * dr[2];
+                    ST::storep(const_cast<typename ST::elem *>(sp) + voff, A.sS_store, s);
+    #pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                      const float t = r * s[c];
+                      accY[0][0][c] += (1.0f - wy) * t;
+                      accY[0][1][c] += wy * t;
+                      const float t2 = s[c] * s[c];
+                      accY[FS - 1][0][c] += (1.0f - wy) * (1.0f - wy) * t2;
+                      accY[FS - 1][1][c] += wy * wy * t2;
+                    }
+                  }
                 }
               }
+              if (F > 0) {
+    #pragma unroll
+                for (int jn = 0; jn < 2; ++jn)
+    #pragma unroll
+                  for (int c = 0; c < 3; ++c) {
+                    accN[0][0][jn][c] += (1.0f - wz) * accY[0][jn][c];
+                    accN[0][1][jn][c] += wz * accY[0][jn][c];
+                    if (F == 2) {
+                      accN[FS - 1][0][jn][c] += (1.0f - wz) * (1.0f - wz) * accY[FS - 1][jn][c];
+                      accN[FS - 1][1][jn][c] += wz * wz * accY[FS - 1][jn][c];
+                    }
+                  }
+              }
+            };
+            if constexpr (MODE == M_HV) {
+    #pragma unroll
+              for (int kv = 0; kv < 4; ++kv) zrow(kv);
+            } else {
+    #pragma unroll 1
+              for (int kv = 0; kv < 4; ++kv) zrow(kv);
             }
           }
-          if (F > 0) {
-#pragma unroll
+        }
+
+        if (NGF_OUT) {
+          // node plane czi is complete: carried part + this layer's lower plane
+          float nv[FS][2][3];
+    #pragma unroll
+          for (int f = 0; f < FS; ++f)
+    #pragma unroll
             for (int jn = 0; jn < 2; ++jn)
-#pragma unroll
+    #pragma unroll
               for (int c = 0; c < 3; ++c) {
-                accN[0][0][jn][c] += (1.0f - wz) * accY[0][jn][c];
-                accN[0][1][jn][c] += wz * accY[0][jn][c];
-                if (F == 2) {
-                  accN[FS - 1][0][jn][c] += (1.0f - wz) * (1.0f - wz) * accY[FS - 1][jn][c];
-                  accN[FS - 1][1][jn][c] += wz * wz * accY[FS - 1][jn][c];
-                }
+                nv[f][jn][c] = carN[f][jn][c] + accN[f][0][jn][c];
+                carN[f][jn][c] = accN[f][1][jn][c];
               }
-          }
-        };
+          stage(zl, nv);
+        }
+        if (NGF) {
+          // roll the node values
+    #pragma unroll
+          for (int j = 0; j < 2; ++j)
+    #pragma unroll
+            for (int i = 0; i < 2; ++i)
+    #pragma unroll
+              for (int c = 0; c < 3; ++c) nc[0][j][i][c] = nc[1][j][i][c];
+        }
+      }
+
+      // last node plane of the brick: the carried part alone
+      if constexpr (NGF_OUT) stage(cz1 - cz0, carN);
+    }
+  };
+
+  auto cell_phase = [&]() {
+    // cell terms (volume change, keypoints), after the voxel layers so that their registers
+    // do not add to the rolling NGF state: wave w takes cell layers w, w + 4, ..., one cell
+    // per lane
+    if (CELLT) {
+      for (int zl = wave; zl < cz1 - cz0; zl += 4) {
+        const int czi = cz0 + zl;
+        const int lx = lane & 15, ly = lane >> 4;
+        const int ccx = bx * kBXC + lx, ccy = by * kBYC + ly;
+        const bool cok = ccx < g.cx && ccy < g.cy;
+        const int64_t cbase = cok ? (int64_t)czi * pxy + (int64_t)ccy * g.px + ccx : 0;
+        float *cb = &cbuf[0][0] + zl * 64 + lane;  // this cell's column of cbuf (stride 64 * ZC)
+        constexpr int CS = CELL_OUT ? 64 * ZC : 0;
         if constexpr (MODE == M_HV) {
-#pragma unroll
-          for (int kv = 0; kv < 4; ++kv) zrow(kv);
+          // the product: volume change first, written out, then the (rare) keypoint cells
+          // add to it, so that no accumulator is live across the volume-change code
+          {
+            float ct[2][2][2][3] = {};
+            if (VCC) {
+              float ucor[2][2][2][3], vcor[2][2][2][3];
+              load_corners(A.u + cbase, g, cok, ucor);
+              load_corners(A.v + cbase, g, cok, vcor);
+              if (cok) vcc_cell_hv(g, ucor, vcor, A.gamma, ct);
+            }
+  #pragma unroll
+            for (int k = 0; k < 2; ++k)
+  #pragma unroll
+              for (int j = 0; j < 2; ++j)
+  #pragma unroll
+                for (int i = 0; i < 2; ++i)
+  #pragma unroll
+                  for (int c = 0; c < 3; ++c) cb[((i + 2 * j + 4 * k) * 3 + c) * CS] = ct[k][j][i][c];
+          }
         } else {
-#pragma unroll 1
-          for (int kv = 0; kv < 4; ++kv) zrow(kv);
+          float ucor[2][2][2][3], vcor[2][2][2][3];
+          load_corners(A.u + cbase, g, cok, ucor);
+          float ct[FS][2][2][2][3] = {};
+          if (cok) {
+            if (VCC) vcc_cell<MODE>(g, ucor, vcor, A.gamma, ct, sV, nfold);
+            if (KP) {
+              const int64_t cell = ((int64_t)czi * g.cy + ccy) * g.cx + ccx;
+              const int ks = A.kstart[cell], ke = A.kstart[cell + 1];
+              if (ke > ks) kp_cell<MODE>(g, ks, ke, A.kloc, A.ktgt, ucor, vcor, A.delta, ct, sK);
+            }
+          }
+          if constexpr (CELL_OUT) {
+  #pragma unroll
+            for (int f = 0; f < F; ++f)
+  #pragma unroll
+              for (int k = 0; k < 2; ++k)
+  #pragma unroll
+                for (int j = 0; j < 2; ++j)
+  #pragma unroll
+                  for (int i = 0; i < 2; ++i)
+  #pragma unroll
+                    for (int c = 0; c < 3; ++c) cb[(f * 24 + (i + 2 * j + 4 * k) * 3 + c) * CS] = ct[f][k][j][i][c];
+          }
         }
       }
     }
 
-    // cell terms of this layer: wave zl % 4 takes its 64 cells, one per lane
-    if (CELLT && (zl & 3) == wave) {
-      const int lx = lane & 15, ly = lane >> 4;
-      const int ccx = bx * kBXC + lx, ccy = by * kBYC + ly;
-      const bool cok = ccx < g.cx && ccy < g.cy;
-      const int64_t cbase = cok ? (int64_t)czi * pxy + (int64_t)ccy * g.px + ccx : 0;
-      float ucor[2][2][2][3], vcor[2][2][2][3];
-      const bool need_u = (MODE != M_HV) || VCC;
-      if (need_u) load_corners(A.u + cbase, g, cok, ucor);
-      if (MODE == M_HV) load_corners(A.v + cbase, g, cok, vcor);
-      float ct[FS][2][2][2][3] = {};
-      if (cok) {
-        if (VCC) vcc_cell<MODE>(g, ucor, vcor, A.gamma, ct, sV, nfold);
-        if (KP) {
+    // HV keypoint cells (rare) in a pass of their own, adding to the volume-change result
+    if constexpr (MODE == M_HV && KP) {
+      for (int zl = wave; zl < cz1 - cz0; zl += 4) {
+        const int czi = cz0 + zl;
+        const int ccx = bx * kBXC + (lane & 15), ccy = by * kBYC + (lane >> 4);
+        if (ccx < g.cx && ccy < g.cy) {
           const int64_t cell = ((int64_t)czi * g.cy + ccy) * g.cx + ccx;
           const int ks = A.kstart[cell], ke = A.kstart[cell + 1];
-          if (ke > ks) kp_cell<MODE>(g, ks, ke, A.kloc, A.ktgt, ucor, vcor, A.delta, ct, sK);
+          if (ke > ks) {
+            float vcor[2][2][2][3];
+            load_corners(A.v + (int64_t)czi * pxy + (int64_t)ccy * g.px + ccx, g, true, vcor);
+            float kt[1][2][2][2][3] = {};
+            kp_cell<MODE>(g, ks, ke, A.kloc, A.ktgt, vcor, vcor, A.delta, kt, sK);
+            float *cb = &cbuf[0][0] + zl * 64 + lane;
+  #pragma unroll
+            for (int k = 0; k < 2; ++k)
+  #pragma unroll
+              for (int j = 0; j < 2; ++j)
+  #pragma unroll
+                for (int i = 0; i < 2; ++i)
+  #pragma unroll
+                  for (int c = 0; c < 3; ++c) cb[((i + 2 * j + 4 * k) * 3 + c) * 64 * ZC] += kt[0][k][j][i][c];
+          }
         }
-      }
-      if constexpr (CELL_OUT) {
-#pragma unroll
-        for (int f = 0; f < F; ++f)
-#pragma unroll
-          for (int k = 0; k < 2; ++k)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-              for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) cbuf[f * 24 + (i + 2 * j + 4 * k) * 3 + c][zl * 64 + lane] = ct[f][k][j][i][c];
       }
     }
 
-    if (NGF_OUT) {
-      // node plane czi is complete: carried part + this layer's lower plane
-      float nv[FS][2][3];
-#pragma unroll
-      for (int f = 0; f < FS; ++f)
-#pragma unroll
-        for (int jn = 0; jn < 2; ++jn)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            nv[f][jn][c] = carN[f][jn][c] + accN[f][0][jn][c];
-            carN[f][jn][c] = accN[f][1][jn][c];
-          }
-      stage(zl, nv);
-    }
-    if (NGF) {
-      // roll the node values
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) nc[0][j][i][c] = nc[1][j][i][c];
-    }
-  }
+  };
+
+  ngf_phase();
+  cell_phase();
 
   if constexpr (F > 0) {
     const int nl = cz1 - cz0;  // cell layers of this brick
-    if (NGF_OUT) stage(nl, carN);
     __syncthreads();
     // combine in a fixed order and write every node plane of the brick: interior nodes
     // directly, brick-face nodes to the partial buffer

@@ -37,35 +37,42 @@ __device__ inline void block_pair_sum(double x, double y, double *blocks, int64_
   }
 }
 
-// x = 0, r = -g, z = r / M, p = z; per-block <r,z>, <r,r>
-__global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const float *g, const float *diag, const double *sc,
-                                                  float tau, float *x, float *r, float *z, float *p,
-                                                  double *blocks) {
+// x = 0, r = -g, z = r / M, p = z, invM = 1 / M; per-block <r,z>, <r,r>
+__global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const float *__restrict__ g,
+                                                  const float *__restrict__ diag, const double *sc, float tau,
+                                                  float *__restrict__ x, float *__restrict__ r, float *__restrict__ z,
+                                                  float *__restrict__ p, float *__restrict__ invM, double *blocks) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double rz = 0.0, rr = 0.0;
   if (i < n) {
     const float M = diag[i] + tau + (float)(1e-12 * sc[SC_MAXDIAG]);
+    const float iM = 1.0f / M;
     const float ri = -g[i];
-    const float zi = ri / M;
+    const float zi = ri * iM;
     x[i] = 0.0f;
     r[i] = ri;
     z[i] = zi;
     p[i] = zi;
+    invM[i] = iM;
     rz = (double)ri * (double)zi;
     rr = (double)ri * (double)ri;
   }
   block_pair_sum(rz, rr, blocks, blockIdx.x);
 }
 
-// CG iteration, part 1 (grid-stride, few workgroups): every workgroup reduces the
-// per-block <p, H p> of the product pass itself (same fixed order everywhere), so no
-// separate reduction launch is needed.  alpha = <r,z> / <p,Hp>; x += alpha p,
-// r -= alpha q, z = r / M; per-workgroup <r,z>, <r,r>.  <r,z> of this iteration is in
-// slot SC_RZ + (it & 1).
+// elements per thread of the CG vector update (workgroup covers 256 * kUpdK elements)
+constexpr int kUpdK = 16;
+
+// CG iteration, vector part: every workgroup reduces the per-block <p, H p> of the
+// product pass itself (same fixed order everywhere).  alpha = <r,z> / <p,Hp>;
+// x += alpha p, r -= alpha q, z = r / M; per-workgroup <r,z>, <r,r>.  <r,z> of this
+// iteration is in slot SC_RZ + (it & 1).  All loads of a thread are issued before its
+// arithmetic.
 __global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *sc, int it, const double *pq_blocks,
-                                                    int64_t pq_nb, const float *diag, float tau, const float *p,
-                                                    const float *q, float *x, float *r, float *z, double *blocks,
-                                                    int *status) {
+                                                    int64_t pq_nb, const float *__restrict__ invM,
+                                                    const float *__restrict__ p, const float *__restrict__ q,
+                                                    float *__restrict__ x, float *__restrict__ r,
+                                                    float *__restrict__ z, double *blocks, int *status) {
   __shared__ double red[256];
   if (block_stopped(sc)) return;
   const double pq = block_sum_all(pq_blocks, pq_nb, 3, 0, red);
@@ -80,44 +87,87 @@ __global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *sc, int i
   }
   const double alpha = sc[SC_RZ + (it & 1)] / pq;
   const float a = (float)alpha;
-  const float M0 = tau + (float)(1e-12 * sc[SC_MAXDIAG]);
+  const int64_t base = (int64_t)blockIdx.x * (256 * kUpdK) + threadIdx.x;
+  float vp[kUpdK], vq[kUpdK], vx[kUpdK], vr[kUpdK], vm[kUpdK];
+#pragma unroll
+  for (int k = 0; k < kUpdK; ++k) {
+    const int64_t i = base + k * 256;
+    const bool in = i < n;
+    const int64_t j = in ? i : 0;
+    vp[k] = p[j];
+    vq[k] = q[j];
+    vx[k] = x[j];
+    vr[k] = r[j];
+    vm[k] = in ? invM[j] : 0.0f;
+  }
   double rz = 0.0, rr = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const float M = diag[i] + M0;
-    x[i] += a * p[i];
-    const float ri = r[i] - a * q[i];
-    r[i] = ri;
-    const float zi = ri / M;
-    z[i] = zi;
-    rz += (double)ri * (double)zi;
-    rr += (double)ri * (double)ri;
+#pragma unroll
+  for (int k = 0; k < kUpdK; ++k) {
+    const int64_t i = base + k * 256;
+    const float ri = vr[k] - a * vq[k];
+    const float zi = ri * vm[k];
+    if (i < n) {
+      x[i] = vx[k] + a * vp[k];
+      r[i] = ri;
+      z[i] = zi;
+      rz += (double)ri * (double)zi;
+      rr += (double)ri * (double)ri;
+    }
   }
   block_pair_sum(rz, rr, blocks, blockIdx.x);
-  if (blockIdx.x == 0 && threadIdx.x == 0) sc[SC_ALPHA] = alpha;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[SC_ALPHA] = alpha;
+    sc[SC_ITERS] = (double)(it + 1);
+  }
 }
 
-// CG iteration, part 2: every workgroup reduces the <r,z>, <r,r> partials of part 1;
-// beta = <r,z>_new / <r,z>; p = z + beta p unless this was the last iteration or the
-// tolerance is met.  Workgroup 0 records the scalars for the next iteration.
-__global__ __launch_bounds__(256) void k_pcg_p(int64_t n, double *sc, int it, int last, double tol,
-                                               const double *blocks, int64_t nb, const float *z, float *p) {
+// node planes per workgroup of k_curv_Lp
+constexpr int kLpZ = 4;
+
+// Start of CG iteration it >= 1: every workgroup reduces the <r,z>, <r,r> partials of
+// the previous update; beta = <r,z>_new / <r,z>_old; stop when the tolerance is met.
+// Otherwise p_new = z + beta p_old (written to p_new) and L p_new (the curvature
+// operator of the next product) in the same pass: L at node m needs p_new at the
+// 6 neighbours, which are formed from z and p_old there.
+__global__ __launch_bounds__(256) void k_curv_Lp(Geo g, int it, double *sc, double tol, const double *upd_blocks,
+                                                 int64_t upd_nb, const float *__restrict__ z,
+                                                 const float *__restrict__ p_old, float *__restrict__ p_new,
+                                                 float *__restrict__ Lw) {
   __shared__ double red[256];
   if (block_stopped(sc)) return;
-  const double rz_new = block_sum_all(blocks, nb, 2, 0, red);
-  const double rr = block_sum_all(blocks, nb, 2, 1, red);
-  const double beta = rz_new / sc[SC_RZ + (it & 1)];
+  const double rz_new = block_sum_all(upd_blocks, upd_nb, 2, 0, red);
+  const double rr = block_sum_all(upd_blocks, upd_nb, 2, 1, red);
+  const double beta = rz_new / sc[SC_RZ + ((it - 1) & 1)];
   const bool conv = tol > 0.0 && sqrt(rr) <= tol * sqrt(sc[SC_BB]);
-  if (!last && !conv) {
-    const float b = (float)beta;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
-      p[i] = z[i] + b * p[i];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc[SC_RZ + ((it + 1) & 1)] = rz_new;
+  if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
+    sc[SC_RZ + (it & 1)] = rz_new;
     sc[SC_RR] = rr;
     sc[SC_BETA] = beta;
-    sc[SC_ITERS] = (double)(it + 1);
     if (conv) sc[SC_STOP] = 1.0;
+  }
+  if (conv) return;
+  const float b = (float)beta;
+  const int px = blockIdx.x * 64 + (threadIdx.x & 63), py = blockIdx.y * 4 + (threadIdx.x >> 6);
+  if (px >= g.px || py >= g.py) return;
+  const int nn[3] = {g.px, g.py, g.pz};
+  const int64_t st[3] = {1, g.px, (int64_t)g.px * g.py};
+  const float ih2[3] = {g.iHx * g.iHx, g.iHy * g.iHy, g.iHz * g.iHz};
+  const int pz0 = blockIdx.z * kLpZ, pz1 = min(pz0 + kLpZ, g.pz);
+  for (int pz = pz0; pz < pz1; ++pz) {
+    const int pp[3] = {px, py, pz};
+    const int64_t nidx = ((int64_t)pz * g.py + py) * g.px + px;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t off = c * g.nnodes + nidx;
+      auto w = [&](int64_t m) { return z[off + m] + b * p_old[off + m]; };
+      const float w0 = w(0);
+      float acc = 0.0f;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax)
+        if (chi(pp[ax], nn[ax])) acc += (w(-st[ax]) - 2.0f * w0 + w(st[ax])) * ih2[ax];
+      p_new[off] = w0;
+      Lw[off] = acc;
+    }
   }
 }
 
