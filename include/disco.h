@@ -110,7 +110,8 @@ typedef void *disco_stream; /* hipStream_t */
 /* Create a context for one image pair geometry on the current HIP device.  storage is
    DISCO_STORAGE_FP32 or DISCO_STORAGE_FP16.  Allocates the derived volumes (grad R,
    grad T, per-voxel GN vectors: 3 x 12 B per voxel in FP32, 3 x 6 B in FP16) and small
-   workspaces.  *out receives the context (NULL on error). */
+   workspaces.  The volume may hold at most (2^32 - 1) / 3 voxels (DISCO_ERR_SHAPE
+   otherwise).  *out receives the context (NULL on error). */
 int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out);
 
 /* Free a context (synchronises the device first).  NULL is ignored. */

@@ -88,7 +88,7 @@ inline dim3 node_grid(const Geo &g) { return dim3((g.px + 63) / 64, (g.py + 3) /
 inline int64_t node_blocks(const Geo &g) { return (int64_t)((g.px + 63) / 64) * ((g.py + 3) / 4) * g.pz; }
 // workgroups of the CG vector update, and the grid of the fused p update + L p pass
 inline int64_t upd_blocks(const Geo &g) { return (3 * g.nnodes + 256 * kUpdK - 1) / (256 * kUpdK); }
-inline dim3 lp_grid(const Geo &g) { return dim3((g.px + 63) / 64, (g.py + 3) / 4, (g.pz + kLpZ - 1) / kLpZ); }
+inline dim3 lp_grid(const Geo &g) { return node_grid(g); }
 // 3-D grid over the voxels (rows of 256)
 inline dim3 vox_grid(const Geo &g) { return dim3((g.nx + 255) / 256, g.ny, g.nz); }
 
@@ -130,10 +130,25 @@ template <class ST, int MODE>
 void launch_brick_mode(disco_ctx *c, bool ngf, bool vcc, bool kp, const BrickArgs<ST> &a, hipStream_t s) {
   dim3 grid(c->g.nbx, c->g.nby, c->g.nbz);
   const int key = (ngf ? 4 : 0) | (vcc ? 2 : 0) | (kp ? 1 : 0);
+  if (MODE != M_HV && ngf && (vcc || kp)) {
+    // objective and gradient passes: the cell terms (VALU-heavy, many registers) and the
+    // NGF voxel pass (memory-bound) run as two launches with their own occupancy; the
+    // second adds to the outputs of the first
+    launch_brick_mode<ST, MODE>(c, false, vcc, kp, a, s);
+    BrickArgs<ST> b = a;
+    b.acc = 1;
+    hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(kWG), 0, s, b);
+    return;
+  }
+  if constexpr (MODE == M_HV) {
+    switch (key) {
+      case 7: hipLaunchKernelGGL((k_brick<ST, MODE, true, true, true, kZC>), grid, dim3(kWG), 0, s, a); return;
+      case 6: hipLaunchKernelGGL((k_brick<ST, MODE, true, true, false, kZC>), grid, dim3(kWG), 0, s, a); return;
+      case 5: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, true, kZC>), grid, dim3(kWG), 0, s, a); return;
+      default: break;
+    }
+  }
   switch (key) {
-    case 7: hipLaunchKernelGGL((k_brick<ST, MODE, true, true, true, kZC>), grid, dim3(kWG), 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_brick<ST, MODE, true, true, false, kZC>), grid, dim3(kWG), 0, s, a); break;
-    case 5: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, true, kZC>), grid, dim3(kWG), 0, s, a); break;
     case 4: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(kWG), 0, s, a); break;
     case 3: hipLaunchKernelGGL((k_brick<ST, MODE, false, true, true, kZC>), grid, dim3(kWG), 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_brick<ST, MODE, false, true, false, kZC>), grid, dim3(kWG), 0, s, a); break;
@@ -339,9 +354,10 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
     if (geom->n[a] < 4 || geom->n[a] % 4 != 0) return DISCO_ERR_SHAPE;
     if (!std::isfinite(geom->h[a]) || !(geom->h[a] > 0.0)) return DISCO_ERR_NONFINITE;
   }
-  // 32-bit node/voxel coordinates; 64-bit linear indices
+  // 32-bit node/voxel coordinates, 64-bit linear indices; the sampling addresses the
+  // 3-vector volumes with 32-bit element offsets (3 N < 2^32)
   const int64_t nvox = (int64_t)geom->n[0] * geom->n[1] * geom->n[2];
-  if (nvox >= ((int64_t)1 << 31)) return DISCO_ERR_SHAPE;
+  if (3 * nvox >= ((int64_t)1 << 32)) return DISCO_ERR_SHAPE;
 
   disco_ctx *c = new (std::nothrow) disco_ctx();
   if (!c) return DISCO_ERR_NOMEM;

@@ -242,51 +242,140 @@ struct RedSrc {
   double *out;
 };
 
-// Reduce up to three sources in a fixed order (one workgroup of 1024 threads), then run
-// the scalar post-operation.  Deterministic; no inter-workgroup communication.
-__global__ __launch_bounds__(1024) void k_finish(RedSrc s0, RedSrc s1, RedSrc s2, int nsrc, int post, PostArgs pa,
-                                                 const double *stop) {
-  __shared__ double red[1024];
-  if (stop && *stop != 0.0) return;
-  const int t = threadIdx.x;
-  const RedSrc srcs[3] = {s0, s1, s2};
-  for (int q = 0; q < nsrc; ++q) {
-    const RedSrc &S = srcs[q];
-    for (int k = 0; k < S.nvals; ++k) {
-      const bool mx = (S.max_mask >> k) & 1u;
-      double acc = mx ? -INFINITY : 0.0;
-      for (int64_t b = t; b < S.nb; b += 1024) {
-        const double x = S.blocks[b * S.stride + k];
-        acc = mx ? fmax(acc, x) : acc + x;
-      }
-      red[t] = acc;
-      __syncthreads();
-      for (int w = 512; w > 0; w >>= 1) {
-        if (t < w) red[t] = mx ? fmax(red[t], red[t + w]) : red[t] + red[t + w];
-        __syncthreads();
-      }
-      if (t == 0) S.out[k] = red[0];
-      __syncthreads();
-    }
+// butterfly over the 64 lanes of a wave: every lane gets the same sum (or maximum)
+__device__ __forceinline__ double wave_red_d(double v, bool mx) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double w = __shfl_xor(v, o, 64);
+    v = mx ? fmax(v, w) : v + w;
   }
-  if (t == 0) run_post(post, pa, srcs[0].out);
+  return v;
 }
 
-// Sum of n partials, computed identically by every workgroup that calls it (fixed
-// order: per-thread strided sums, then a fixed tree over the 256 threads).
-__device__ inline double block_sum_all(const double *blocks, int64_t n, int stride, int k, double *red) {
-  const int t = threadIdx.x;
-  double acc = 0.0;
-  for (int64_t b = t; b < n; b += 256) acc += blocks[b * stride + k];
-  red[t] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) red[t] += red[t + w];
-    __syncthreads();
+// Reduce up to three sources of at most 4 values each in a fixed order (one workgroup of
+// 1024 threads: per-thread sums over strided partials, a butterfly per wave, then the 16
+// wave results in order), then run the scalar post-operation.  The first 2048 partials
+// of every source are requested together.  Deterministic; no inter-workgroup
+// communication.
+__global__ __launch_bounds__(1024) void k_finish(RedSrc s0, RedSrc s1, RedSrc s2, int nsrc, int post, PostArgs pa,
+                                                 const double *stop) {
+  __shared__ double wred[16][12];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  // sources selected by value (no local array: it would live in scratch memory)
+  auto src = [&](int q) -> const RedSrc & { return q == 0 ? s0 : (q == 1 ? s1 : s2); };
+  const double stopv = stop ? *stop : 0.0;  // no workgroup writes it here: uniform
+  double x[3][2][4];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const RedSrc &S = src(q);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int64_t b = u * 1024 + t;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[q][u][k] = (q < nsrc && b < S.nb && k < S.nvals) ? S.blocks[b * S.stride + k] : 0.0;
+    }
   }
-  const double r = red[0];
+  if (stopv != 0.0) return;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const RedSrc &S = src(q);
+    if (q < nsrc) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool mx = (S.max_mask >> k) & 1u;
+        double acc = mx ? -INFINITY : 0.0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+          if (u * 1024 + t < S.nb) acc = mx ? fmax(acc, x[q][u][k]) : acc + x[q][u][k];
+        for (int64_t b = 2048 + t; b < S.nb; b += 1024) {
+          const double y = k < S.nvals ? S.blocks[b * S.stride + k] : 0.0;
+          acc = mx ? fmax(acc, y) : acc + y;
+        }
+        const double r = wave_red_d(acc, mx);
+        if (lane == 0) wred[w][q * 4 + k] = r;
+      }
+    }
+  }
   __syncthreads();
-  return r;
+  if (t < nsrc * 4) {
+    const int q = t >> 2, k = t & 3;
+    const RedSrc &S = src(q);
+    if (k < S.nvals) {
+      const bool mx = (S.max_mask >> k) & 1u;
+      double r = wred[0][t];
+      for (int i = 1; i < 16; ++i) r = mx ? fmax(r, wred[i][t]) : r + wred[i][t];
+      S.out[k] = r;
+    }
+  }
+  __syncthreads();
+  if (t == 0) run_post(post, pa, s0.out);
+}
+
+// Sums of NV values over n partials, blocks[b * stride + k0 + k], computed identically by
+// every 256-thread workgroup that calls it (fixed order: per-thread sums over b = t,
+// t + 256, ... with sixteen loads in flight, a butterfly per wave, then the four wave
+// sums in order).  Every thread receives the sums.  If flagp is given, thread 0 reads
+// *flagp together with its partials and every thread receives that value in *flag (one
+// read per workgroup, so all its threads take the same branch on it).
+template <int NV>
+__device__ inline void block_sums(const double *blocks, int64_t n, int stride, int k0, double out[NV],
+                                  const double *flagp = nullptr, double *flag = nullptr) {
+  __shared__ double wsum[4][NV];
+  __shared__ double sflag;
+  const int t = threadIdx.x;
+  const double fl = (flagp && t == 0) ? *flagp : 0.0;
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  for (int64_t b0 = 0; b0 < n; b0 += 16 * 256) {
+    double x[16][NV];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int64_t b = b0 + u * 256 + t;
+#pragma unroll
+      for (int k = 0; k < NV; ++k) x[u][k] = b < n ? blocks[b * stride + k0 + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+#pragma unroll
+      for (int k = 0; k < NV; ++k) acc[k] += x[u][k];
+  }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double r = wave_red_d(acc[k], false);
+    if ((t & 63) == 0) wsum[t >> 6][k] = r;
+  }
+  if (t == 0) sflag = fl;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NV; ++k) out[k] = ((wsum[0][k] + wsum[1][k]) + wsum[2][k]) + wsum[3][k];
+  if (flag) *flag = sflag;
+  __syncthreads();
+}
+
+// Per-workgroup sums (or maxima, bit k of max_mask) of NV values over 256 threads in a
+// fixed order (butterfly per wave, then the four waves in order); thread 0 writes them to
+// out[k].  All threads of the workgroup must call it.
+template <int NV>
+__device__ inline void block_write(const double v[NV], double *out, unsigned max_mask = 0u) {
+  __shared__ double wsum[4][NV];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double r = wave_red_d(v[k], (max_mask >> k) & 1u);
+    if ((t & 63) == 0) wsum[t >> 6][k] = r;
+  }
+  __syncthreads();
+  if (t == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const bool mx = (max_mask >> k) & 1u;
+      double r = wsum[0][k];
+#pragma unroll
+      for (int i = 1; i < 4; ++i) r = mx ? fmax(r, wsum[i][k]) : r + wsum[i][k];
+      out[k] = r;
+    }
+  }
 }
 
 template <class ST>
@@ -309,6 +398,8 @@ struct BrickArgs {
   float *part;                  // face partials
   double *blocks;               // BS_N doubles per workgroup
   const double *stop;           // if non-null and *stop != 0 the launch does nothing
+  int acc;                      // add to out0/out1, part and blocks instead of writing them
+                                // (a second pass over the same bricks, fixed order)
 };
 
 // node plane of the 2 x 2 corner nodes of a lane's cell, [j][i][c]: fb points at the
@@ -332,43 +423,12 @@ __device__ __forceinline__ void load_plane(const float *fb, int64_t poff, const 
 // and Jacobian JG[c][a] = dG_c / dy_a.  q is split as (integer voxel index) + (u/h)
 // so that the fraction keeps full precision.
 // ---------------------------------------------------------------------------------
-template <class ST>
-__device__ __forceinline__ void sample_grad(const typename ST::elem *gT, float sT, const Geo &g, int ix, int iy,
-                                            int iz, const float uh[3], float G[3], float JG[3][3]) {
-  const int idx[3] = {ix, iy, iz};
-  const int n[3] = {g.nx, g.ny, g.nz};
-  int i0[3];
-  float t[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    // outside [-2, N+1] every corner is outside the volume: clamp (also avoids overflow)
-    float d = fminf(fmaxf(uh[a], (float)(-2 - idx[a])), (float)(n[a] + 1 - idx[a]));
-    float f = floorf(d);
-    t[a] = d - f;
-    i0[a] = idx[a] + (int)f;
-  }
-  const bool vx0 = (unsigned)i0[0] < (unsigned)g.nx, vx1 = (unsigned)(i0[0] + 1) < (unsigned)g.nx;
-  const bool vy0 = (unsigned)i0[1] < (unsigned)g.ny, vy1 = (unsigned)(i0[1] + 1) < (unsigned)g.ny;
-  const bool vz0 = (unsigned)i0[2] < (unsigned)g.nz, vz1 = (unsigned)(i0[2] + 1) < (unsigned)g.nz;
-  // zero padding: corners outside the volume read a clamped voxel and are discarded
-  const int X[2] = {min(max(i0[0], 0), g.nx - 1), min(max(i0[0] + 1, 0), g.nx - 1)};
-  const int Y[2] = {min(max(i0[1], 0), g.ny - 1) * g.nx, min(max(i0[1] + 1, 0), g.ny - 1) * g.nx};
-  const int Z[2] = {min(max(i0[2], 0), g.nz - 1) * (g.nx * g.ny), min(max(i0[2] + 1, 0), g.nz - 1) * (g.nx * g.ny)};
-  float cv[2][2][2][3];  // [z][y][x][c]
-#pragma unroll
-  for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-    for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-      for (int cx = 0; cx < 2; ++cx) {
-        const bool ok = (cz ? vz1 : vz0) && (cy ? vy1 : vy0) && (cx ? vx1 : vx0);
-        const unsigned vi = (unsigned)(Z[cz] + Y[cy] + X[cx]);
-        float t3[3];
-        ST::loadp(gT + (uint64_t)vi * ST::W, sT, t3);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) cv[cz][cy][cx][c] = ok ? t3[c] : 0.0f;
-      }
-  // x, then y, then z; derivatives from differences of the lower-order interpolants
+// trilinear interpolation of the 8 corner values cv[z][y][x][c] at fractions t: value G
+// and (JGW) the Jacobian JG[c][a] = dG_c / dy_a.  x, then y, then z; derivatives from
+// differences of the lower-order interpolants.
+template <bool JGW>
+__device__ __forceinline__ void interp_corners(const float cv[2][2][2][3], const float t[3], const Geo &g, float G[3],
+                                               float JG[3][3]) {
   float gx[2][2][3], dx[2][2][3];
 #pragma unroll
   for (int cz = 0; cz < 2; ++cz)
@@ -391,10 +451,162 @@ __device__ __forceinline__ void sample_grad(const typename ST::elem *gT, float s
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     G[c] = gxy[0][c] + t[2] * (gxy[1][c] - gxy[0][c]);
-    JG[c][0] = (dxy[0][c] + t[2] * (dxy[1][c] - dxy[0][c])) * g.ihx;
-    JG[c][1] = (dyy[0][c] + t[2] * (dyy[1][c] - dyy[0][c])) * g.ihy;
-    JG[c][2] = (gxy[1][c] - gxy[0][c]) * g.ihz;
+    if (JGW) {
+      JG[c][0] = (dxy[0][c] + t[2] * (dxy[1][c] - dxy[0][c])) * g.ihx;
+      JG[c][1] = (dyy[0][c] + t[2] * (dyy[1][c] - dyy[0][c])) * g.ihy;
+      JG[c][2] = (gxy[1][c] - gxy[0][c]) * g.ihz;
+    }
   }
+}
+
+// ---------------------------------------------------------------------------------
+// trilinear sample of a 3-vector volume at continuous index q (zero padding): value G
+// and (JGW) Jacobian JG[c][a] = dG_c / dy_a.  q is split as (integer voxel index) +
+// (u/h) so that the fraction keeps full precision.  When the 8 corners of every active
+// lane of the wave lie inside the volume, the corners are addressed from one 32-bit
+// element offset and uniform strides without clamping or masking; otherwise corners
+// outside read a clamped voxel and are discarded.
+// ---------------------------------------------------------------------------------
+template <class ST, bool JGW = true>
+__device__ __forceinline__ void sample_grad(const typename ST::elem *gT, float sT, const Geo &g, int ix, int iy,
+                                            int iz, const float uh[3], float G[3], float JG[3][3]) {
+  const int idx[3] = {ix, iy, iz};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  int i0[3];
+  float t[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    // outside [-2, N+1] every corner is outside the volume: clamp (also avoids overflow)
+    float d = fminf(fmaxf(uh[a], (float)(-2 - idx[a])), (float)(n[a] + 1 - idx[a]));
+    float f = floorf(d);
+    t[a] = d - f;
+    i0[a] = idx[a] + (int)f;
+  }
+  float cv[2][2][2][3];  // [z][y][x][c]
+  const bool inside = (unsigned)i0[0] < (unsigned)(g.nx - 1) && (unsigned)i0[1] < (unsigned)(g.ny - 1) &&
+                      (unsigned)i0[2] < (unsigned)(g.nz - 1);
+  if (__all(inside)) {
+    const uint32_t sy = (uint32_t)g.nx * ST::W, sz = (uint32_t)g.nx * (uint32_t)g.ny * ST::W;
+    const uint32_t off = ((uint32_t)i0[2] * (uint32_t)g.ny + (uint32_t)i0[1]) * (uint32_t)g.nx * ST::W +
+                         (uint32_t)i0[0] * ST::W;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx)
+          ST::loadp(gT + (off + (cz ? sz : 0u) + (cy ? sy : 0u) + (cx ? (uint32_t)ST::W : 0u)), sT, cv[cz][cy][cx]);
+  } else {
+    const bool vx0 = (unsigned)i0[0] < (unsigned)g.nx, vx1 = (unsigned)(i0[0] + 1) < (unsigned)g.nx;
+    const bool vy0 = (unsigned)i0[1] < (unsigned)g.ny, vy1 = (unsigned)(i0[1] + 1) < (unsigned)g.ny;
+    const bool vz0 = (unsigned)i0[2] < (unsigned)g.nz, vz1 = (unsigned)(i0[2] + 1) < (unsigned)g.nz;
+    // zero padding: corners outside the volume read a clamped voxel and are discarded
+    const int X[2] = {min(max(i0[0], 0), g.nx - 1), min(max(i0[0] + 1, 0), g.nx - 1)};
+    const int Y[2] = {min(max(i0[1], 0), g.ny - 1) * g.nx, min(max(i0[1] + 1, 0), g.ny - 1) * g.nx};
+    const int Z[2] = {min(max(i0[2], 0), g.nz - 1) * (g.nx * g.ny), min(max(i0[2] + 1, 0), g.nz - 1) * (g.nx * g.ny)};
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+      for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+        for (int cx = 0; cx < 2; ++cx) {
+          const bool ok = (cz ? vz1 : vz0) && (cy ? vy1 : vy0) && (cx ? vx1 : vx0);
+          const unsigned vi = (unsigned)(Z[cz] + Y[cy] + X[cx]);
+          float t3[3];
+          ST::loadp(gT + (uint64_t)vi * ST::W, sT, t3);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) cv[cz][cy][cx][c] = ok ? t3[c] : 0.0f;
+        }
+  }
+  interp_corners<JGW>(cv, t, g, G, JG);
+}
+
+// wave-wide shift: lane i receives the value of lane i + 1; lane 63 and lanes whose
+// source lane is inactive keep `old`
+__device__ __forceinline__ int wave_next(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, 0x130, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float wave_next(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+
+// corners of the previous voxel row of the same lane (rows advance by one voxel in y)
+struct RowCache {
+  int i0[3];
+  float up[2][2][3];  // [z][x][c] at y = i0[1] + 1
+  bool valid;
+};
+
+// trilinear sample for consecutive voxel rows of a lane (same x and z, y increasing):
+// the same FP32 sample-cell decision and interpolation as sample_grad.  On the fast
+// path (all corners of all active lanes inside the volume):
+//  * the lower y row of corners is the previous row's upper one when the lane's cell
+//    moved by exactly one voxel in y;
+//  * lanes sample consecutive x, so lane i+1's corner x is usually lane i's corner x+1:
+//    it is taken from the neighbour when the voxel indices say so.
+// Which corners must be loaded depends on indices only, so every load is issued before
+// any loaded value is used; the neighbour exchange follows.
+template <class ST, bool JGW>
+__device__ __forceinline__ void sample_grad_row(const typename ST::elem *gT, float sT, const Geo &g, int ix, int iy,
+                                                int iz, const float uh[3], RowCache &rc, float G[3], float JG[3][3]) {
+  const int idx[3] = {ix, iy, iz};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  int i0[3];
+  float t[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    float d = fminf(fmaxf(uh[a], (float)(-2 - idx[a])), (float)(n[a] + 1 - idx[a]));
+    float f = floorf(d);
+    t[a] = d - f;
+    i0[a] = idx[a] + (int)f;
+  }
+  const bool inside = (unsigned)i0[0] < (unsigned)(g.nx - 1) && (unsigned)i0[1] < (unsigned)(g.ny - 1) &&
+                      (unsigned)i0[2] < (unsigned)(g.nz - 1);
+  if (!__all(inside)) {
+    rc.valid = false;
+    sample_grad<ST, JGW>(gT, sT, g, ix, iy, iz, uh, G, JG);
+    return;
+  }
+  const uint32_t W = ST::W;
+  const int nxy = g.nx * g.ny;
+  const int vid = (i0[2] * g.ny + i0[1]) * g.nx + i0[0];
+  // corner rows r = y + 2 z: voxel index of corner x
+  const int key[4] = {vid, vid + g.nx, vid + nxy, vid + g.nx + nxy};
+  const bool reuse = rc.valid && i0[0] == rc.i0[0] && i0[1] == rc.i0[1] + 1 && i0[2] == rc.i0[2];
+  bool share[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) share[r] = wave_next(key[r], key[r]) == key[r] + 1;
+  float cx0[4][3], cx1[4][3];  // corners x and x+1 of row r
+  // loads: rows y0 only without reuse; corner x+1 only when the neighbour cannot give it
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const bool need = (r & 1) || !reuse;
+    if (need) ST::loadp(gT + (uint32_t)key[r] * W, sT, cx0[r]);
+    if (need && !share[r]) ST::loadp(gT + ((uint32_t)key[r] * W + W), sT, cx1[r]);
+  }
+  float cv[2][2][2][3];  // [z][y][x][c]
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int y = r & 1, z = r >> 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float x0 = (y == 0 && reuse) ? rc.up[z][0][c] : cx0[r][c];
+      const float nb = wave_next(0.0f, x0);  // neighbour's corner x (its own final value)
+      const float x1 = (y == 0 && reuse) ? rc.up[z][1][c] : (share[r] ? nb : cx1[r][c]);
+      cv[z][y][0][c] = x0;
+      cv[z][y][1][c] = x1;
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < 2; ++z)
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rc.up[z][x][c] = cv[z][1][x][c];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) rc.i0[a] = i0[a];
+  rc.valid = true;
+  interp_corners<JGW>(cv, t, g, G, JG);
 }
 
 // ---------------------------------------------------------------------------------
@@ -806,7 +1018,9 @@ __global__ __launch_bounds__(kWG, MODE == M_HV ? DISCO_HV_WAVES : 1) void k_bric
     #pragma unroll
                 for (int c = 0; c < 3; ++c) fz[j][c] = __builtin_fmaf(wz, fx[1][j][c] - fx[0][j][c], fx[0][j][c]);
               float accY[FS][2][3] = {};
-    #pragma unroll
+              RowCache rc;
+              rc.valid = false;
+    #pragma unroll (MODE == M_HV ? 4 : 1)
               for (int jv = 0; jv < 4; ++jv) {
                 const float wy = (jv + 0.5f) * 0.25f;
                 const int iy = cy * 4 + jv;
@@ -830,7 +1044,12 @@ __global__ __launch_bounds__(kWG, MODE == M_HV ? DISCO_HV_WAVES : 1) void k_bric
                   // cell holding the sample point is a reproducible FP32 decision.
                   const float uh[3] = {f3[0] * g.ihx, f3[1] * g.ihy, f3[2] * g.ihz};
                   float a[3], JG[3][3], b[3];
-                  sample_grad<ST>(A.gT, A.sT, g, ix, iy, iz, uh, a, JG);
+                  // objective pass: row sampler (shared corners); gradient pass: plain sampler,
+                  // which measured faster there
+                  if constexpr (MODE == M_EVAL)
+                    sample_grad_row<ST, false>(A.gT, A.sT, g, ix, iy, iz, uh, rc, a, JG);
+                  else
+                    sample_grad<ST, true>(A.gT, A.sT, g, ix, iy, iz, uh, a, JG);
                   ST::loadp(rp + voff, A.sR, b);
                   const float e2 = A.eta2;
                   const float Da = e2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
@@ -1050,11 +1269,13 @@ __global__ __launch_bounds__(kWG, MODE == M_HV ? DISCO_HV_WAVES : 1) void k_bric
       if (pxn > g.cx || pyn > g.cy) continue;
       const bool face = is_face(zl, bz, g.nbz, ZC) || is_face(xl, bx, g.nbx, kBXC) || is_face(yl, by, g.nby, kBYC);
       if (face) {
-        A.part[((brick * (ZC + 1) + zl) * (F * 3) + fc) * kNBOX + yl * 17 + xl] = val;
+        float *pp = A.part + ((brick * (ZC + 1) + zl) * (F * 3) + fc) * kNBOX + yl * 17 + xl;
+        *pp = A.acc ? *pp + val : val;
       } else {
         const int f = fc / 3, c = fc - 3 * f;
         float *o = f == 0 ? A.out0 : A.out1;
-        o[c * g.nnodes + ((int64_t)pzn * g.py + pyn) * g.px + pxn] = val;
+        float *po = o + c * g.nnodes + ((int64_t)pzn * g.py + pyn) * g.px + pxn;
+        *po = A.acc ? *po + val : val;
       }
     }
   }
@@ -1071,7 +1292,8 @@ __global__ __launch_bounds__(kWG, MODE == M_HV ? DISCO_HV_WAVES : 1) void k_bric
     if (threadIdx.x < BS_N) {
       const int t = threadIdx.x;
       const int64_t wg = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-      A.blocks[wg * BS_N + t] = ((lred[0][t] + lred[1][t]) + lred[2][t]) + lred[3][t];
+      const double v = ((lred[0][t] + lred[1][t]) + lred[2][t]) + lred[3][t];
+      A.blocks[wg * BS_N + t] = A.acc ? A.blocks[wg * BS_N + t] + v : v;
     }
   }
 }
@@ -1117,8 +1339,8 @@ __device__ __forceinline__ int brick_cands(int p, int B, int nb, int b[2], int l
 // CURV: add curvature (field 0, and its diagonal to field 1 when NF = 2)
 template <int ZC, int F, int NF, bool CURV>
 __global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
-  __shared__ double red[3][256];
-  if (A.stop && *A.stop != 0.0) return;
+  // read with the other loads; only the writes wait for it (no workgroup writes it here)
+  const bool stopped = A.stop && *A.stop != 0.0;
   const Geo &g = A.g;
   const float *__restrict__ part = A.part;
   const float *__restrict__ Lw = A.Lw;
@@ -1204,10 +1426,12 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) val[0][c] += A.tau * tauv[c * g.nnodes + n];
     }
+    if (!stopped) {
 #pragma unroll
-    for (int f = 0; f < NF; ++f)
+      for (int f = 0; f < NF; ++f)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) (f == 0 ? out0 : out1)[c * g.nnodes + n] = val[f][c];
+        for (int c = 0; c < 3; ++c) (f == 0 ? out0 : out1)[c * g.nnodes + n] = val[f][c];
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       if (dotv) dsum += (double)dotv[c * g.nnodes + n] * (double)val[0][c];
@@ -1215,61 +1439,54 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
       if (NF == 2) dmax = fmax(dmax, (double)val[NF - 1][c]);
     }
   }
-  if (A.blocks) {
-    // fixed-order tree reductions
-    const int t = threadIdx.x;
-    red[0][t] = dsum;
-    red[1][t] = dmax;
-    red[2][t] = gsq;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (t < s) {
-        red[0][t] += red[0][t + s];
-        red[1][t] = fmax(red[1][t], red[1][t + s]);
-        red[2][t] += red[2][t + s];
-      }
-      __syncthreads();
-    }
-    if (t < 3) A.blocks[bid * 3 + t] = red[t][0];
+  if (A.blocks && !stopped) {
+    const double v[3] = {dsum, dmax, gsq};
+    block_write<3>(v, A.blocks + bid * 3, 2u);
   }
 }
 
-// L w for w = a - b (b nullable), and per-block sum of (L w)^2
-__global__ __launch_bounds__(256) void k_curv_L(Geo g, const float *a, const float *b, float *Lw, double *blocks,
-                                                const double *stop) {
-  __shared__ double red[256];
-  if (stop && *stop != 0.0) return;
+// L w for w = a - b (b nullable), and per-block sum of (L w)^2.  Branch-free: stencil
+// neighbours that L does not use (chi = 0) read the centre with weight zero, so every
+// load is requested before the first wait.
+__global__ __launch_bounds__(256) void k_curv_L(Geo g, const float *__restrict__ a, const float *__restrict__ b,
+                                                float *__restrict__ Lw, double *blocks, const double *stop) {
+  // read with the other loads; only the writes wait for it (no workgroup writes it here)
+  const bool stopped = stop && *stop != 0.0;
   const int px = blockIdx.x * 64 + (threadIdx.x & 63), py = blockIdx.y * 4 + (threadIdx.x >> 6), pz = blockIdx.z;
-  const int64_t n = ((int64_t)pz * g.py + py) * g.px + px;
+  const bool in = px < g.px && py < g.py;
+  const int pp[3] = {in ? px : 0, in ? py : 0, pz};
+  const int64_t n = ((int64_t)pp[2] * g.py + pp[1]) * g.px + pp[0];
   const int64_t bid = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  double e = 0.0;
-  if (px < g.px && py < g.py) {
-    const int pp[3] = {px, py, pz};
-    const int nn[3] = {g.px, g.py, g.pz};
-    const int64_t st[3] = {1, g.px, (int64_t)g.px * g.py};
-    const float ih2[3] = {g.iHx * g.iHx, g.iHy * g.iHy, g.iHz * g.iHz};
-    for (int c = 0; c < 3; ++c) {
-      const float *ac = a + c * g.nnodes;
-      const float *bc = b ? b + c * g.nnodes : nullptr;
-      auto w = [&](int64_t m) { return bc ? ac[m] - bc[m] : ac[m]; };
-      float acc = 0.0f;
+  const int nn[3] = {g.px, g.py, g.pz};
+  const int64_t st[3] = {1, g.px, (int64_t)g.px * g.py};
+  const float ih2[3] = {g.iHx * g.iHx, g.iHy * g.iHy, g.iHz * g.iHz};
+  int64_t om[3], op[3];
+  float wgt[3];
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax)
-        if (chi(pp[ax], nn[ax])) acc += (w(n - st[ax]) - 2.0f * w(n) + w(n + st[ax])) * ih2[ax];
-      Lw[c * g.nnodes + n] = acc;
-      e += (double)acc * (double)acc;
-    }
+  for (int ax = 0; ax < 3; ++ax) {
+    const bool use = chi(pp[ax], nn[ax]);
+    om[ax] = use ? -st[ax] : 0;
+    op[ax] = use ? st[ax] : 0;
+    wgt[ax] = use ? ih2[ax] : 0.0f;
   }
-  if (blocks) {
-    const int t = threadIdx.x;
-    red[t] = e;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (t < s) red[t] += red[t + s];
-      __syncthreads();
-    }
-    if (t == 0) blocks[bid] = red[0];
+  float w[3][7];  // [component][centre, -x, +x, -y, +y, -z, +z]
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t off = c * g.nnodes + n;
+    const int64_t o[7] = {0, om[0], op[0], om[1], op[1], om[2], op[2]};
+#pragma unroll
+    for (int m = 0; m < 7; ++m) w[c][m] = b ? a[off + o[m]] - b[off + o[m]] : a[off + o[m]];
   }
+  double e = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) acc += (w[c][1 + 2 * ax] - 2.0f * w[c][0] + w[c][2 + 2 * ax]) * wgt[ax];
+    if (in && !stopped) Lw[c * g.nnodes + n] = acc;
+    if (in) e += (double)acc * (double)acc;
+  }
+  if (blocks && !stopped) block_write<1>(&e, blocks + bid);
 }
 
 // central-difference image gradient with replicated border, stored as ST

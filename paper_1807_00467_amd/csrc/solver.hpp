@@ -8,33 +8,10 @@
 
 namespace disco {
 
-// the stop flag read once per workgroup (another workgroup of the same launch may set
-// it), so that the whole workgroup takes the same branch before any barrier
-__device__ inline bool block_stopped(const double *sc) {
-  __shared__ int s_stop;
-  if (threadIdx.x == 0) s_stop = sc[SC_STOP] != 0.0;
-  __syncthreads();
-  return s_stop != 0;
-}
-
-// per-block sums of two values over 256 threads (fixed tree)
+// per-block sums of two values over 256 threads (fixed order)
 __device__ inline void block_pair_sum(double x, double y, double *blocks, int64_t bid) {
-  __shared__ double red[2][256];
-  const int t = threadIdx.x;
-  red[0][t] = x;
-  red[1][t] = y;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) {
-      red[0][t] += red[0][t + s];
-      red[1][t] += red[1][t + s];
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    blocks[2 * bid] = red[0][0];
-    blocks[2 * bid + 1] = red[1][0];
-  }
+  const double v[2] = {x, y};
+  block_write<2>(v, blocks + 2 * bid);
 }
 
 // x = 0, r = -g, z = r / M, p = z, invM = 1 / M; per-block <r,z>, <r,r>
@@ -66,27 +43,13 @@ constexpr int kUpdK = 16;
 // CG iteration, vector part: every workgroup reduces the per-block <p, H p> of the
 // product pass itself (same fixed order everywhere).  alpha = <r,z> / <p,Hp>;
 // x += alpha p, r -= alpha q, z = r / M; per-workgroup <r,z>, <r,r>.  <r,z> of this
-// iteration is in slot SC_RZ + (it & 1).  All loads of a thread are issued before its
-// arithmetic.
+// iteration is in slot SC_RZ + (it & 1).  The vector loads, the partials and the stop
+// flag are all requested before the first wait.
 __global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *sc, int it, const double *pq_blocks,
                                                     int64_t pq_nb, const float *__restrict__ invM,
                                                     const float *__restrict__ p, const float *__restrict__ q,
                                                     float *__restrict__ x, float *__restrict__ r,
                                                     float *__restrict__ z, double *blocks, int *status) {
-  __shared__ double red[256];
-  if (block_stopped(sc)) return;
-  const double pq = block_sum_all(pq_blocks, pq_nb, 3, 0, red);
-  if (!(pq > 0.0)) {
-    // breakdown: every workgroup sees the same pq and skips the update
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc[SC_STOP] = 1.0;
-      sc[SC_BREAK] = 1.0;
-      *status |= 2;
-    }
-    return;
-  }
-  const double alpha = sc[SC_RZ + (it & 1)] / pq;
-  const float a = (float)alpha;
   const int64_t base = (int64_t)blockIdx.x * (256 * kUpdK) + threadIdx.x;
   float vp[kUpdK], vq[kUpdK], vx[kUpdK], vr[kUpdK], vm[kUpdK];
 #pragma unroll
@@ -100,6 +63,21 @@ __global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *sc, int i
     vr[k] = r[j];
     vm[k] = in ? invM[j] : 0.0f;
   }
+  const double rz_old = sc[SC_RZ + (it & 1)];
+  double pq, stop;
+  block_sums<1>(pq_blocks, pq_nb, 3, 0, &pq, sc + SC_STOP, &stop);
+  if (stop != 0.0) return;
+  if (!(pq > 0.0)) {
+    // breakdown: every workgroup sees the same pq and skips the update
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc[SC_STOP] = 1.0;
+      sc[SC_BREAK] = 1.0;
+      *status |= 2;
+    }
+    return;
+  }
+  const double alpha = rz_old / pq;
+  const float a = (float)alpha;
   double rz = 0.0, rr = 0.0;
 #pragma unroll
   for (int k = 0; k < kUpdK; ++k) {
@@ -121,23 +99,52 @@ __global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *sc, int i
   }
 }
 
-// node planes per workgroup of k_curv_Lp
-constexpr int kLpZ = 4;
-
 // Start of CG iteration it >= 1: every workgroup reduces the <r,z>, <r,r> partials of
 // the previous update; beta = <r,z>_new / <r,z>_old; stop when the tolerance is met.
 // Otherwise p_new = z + beta p_old (written to p_new) and L p_new (the curvature
 // operator of the next product) in the same pass: L at node m needs p_new at the
-// 6 neighbours, which are formed from z and p_old there.
+// 6 neighbours, which are formed from z and p_old there.  One node plane per workgroup;
+// all loads are requested before the first wait.
 __global__ __launch_bounds__(256) void k_curv_Lp(Geo g, int it, double *sc, double tol, const double *upd_blocks,
                                                  int64_t upd_nb, const float *__restrict__ z,
                                                  const float *__restrict__ p_old, float *__restrict__ p_new,
                                                  float *__restrict__ Lw) {
-  __shared__ double red[256];
-  if (block_stopped(sc)) return;
-  const double rz_new = block_sum_all(upd_blocks, upd_nb, 2, 0, red);
-  const double rr = block_sum_all(upd_blocks, upd_nb, 2, 1, red);
-  const double beta = rz_new / sc[SC_RZ + ((it - 1) & 1)];
+  const int px = blockIdx.x * 64 + (threadIdx.x & 63), py = blockIdx.y * 4 + (threadIdx.x >> 6), pz = blockIdx.z;
+  const bool in = px < g.px && py < g.py;
+  const int pp[3] = {in ? px : 0, in ? py : 0, pz};
+  const int nn[3] = {g.px, g.py, g.pz};
+  const int64_t st[3] = {1, g.px, (int64_t)g.px * g.py};
+  const int64_t nidx = ((int64_t)pp[2] * g.py + pp[1]) * g.px + pp[0];
+  // stencil neighbours that L uses (chi), else the centre (weight zero)
+  int64_t om[3], op[3];
+  float wgt[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const bool use = chi(pp[ax], nn[ax]);
+    om[ax] = use ? -st[ax] : 0;
+    op[ax] = use ? st[ax] : 0;
+    wgt[ax] = use ? 1.0f : 0.0f;
+  }
+  float zc[3][7], pc[3][7];  // [component][centre, -x, +x, -y, +y, -z, +z]
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t off = c * g.nnodes + nidx;
+    zc[c][0] = z[off];
+    pc[c][0] = p_old[off];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      zc[c][1 + 2 * ax] = z[off + om[ax]];
+      pc[c][1 + 2 * ax] = p_old[off + om[ax]];
+      zc[c][2 + 2 * ax] = z[off + op[ax]];
+      pc[c][2 + 2 * ax] = p_old[off + op[ax]];
+    }
+  }
+  const double rz_prev = sc[SC_RZ + ((it - 1) & 1)];
+  double sums[2], stop;
+  block_sums<2>(upd_blocks, upd_nb, 2, 0, sums, sc + SC_STOP, &stop);
+  if (stop != 0.0) return;
+  const double rz_new = sums[0], rr = sums[1];
+  const double beta = rz_new / rz_prev;
   const bool conv = tol > 0.0 && sqrt(rr) <= tol * sqrt(sc[SC_BB]);
   if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
     sc[SC_RZ + (it & 1)] = rz_new;
@@ -145,29 +152,20 @@ __global__ __launch_bounds__(256) void k_curv_Lp(Geo g, int it, double *sc, doub
     sc[SC_BETA] = beta;
     if (conv) sc[SC_STOP] = 1.0;
   }
-  if (conv) return;
+  if (conv || !in) return;
   const float b = (float)beta;
-  const int px = blockIdx.x * 64 + (threadIdx.x & 63), py = blockIdx.y * 4 + (threadIdx.x >> 6);
-  if (px >= g.px || py >= g.py) return;
-  const int nn[3] = {g.px, g.py, g.pz};
-  const int64_t st[3] = {1, g.px, (int64_t)g.px * g.py};
   const float ih2[3] = {g.iHx * g.iHx, g.iHy * g.iHy, g.iHz * g.iHz};
-  const int pz0 = blockIdx.z * kLpZ, pz1 = min(pz0 + kLpZ, g.pz);
-  for (int pz = pz0; pz < pz1; ++pz) {
-    const int pp[3] = {px, py, pz};
-    const int64_t nidx = ((int64_t)pz * g.py + py) * g.px + px;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const int64_t off = c * g.nnodes + nidx;
-      auto w = [&](int64_t m) { return z[off + m] + b * p_old[off + m]; };
-      const float w0 = w(0);
-      float acc = 0.0f;
+  for (int c = 0; c < 3; ++c) {
+    float w[7];
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax)
-        if (chi(pp[ax], nn[ax])) acc += (w(-st[ax]) - 2.0f * w0 + w(st[ax])) * ih2[ax];
-      p_new[off] = w0;
-      Lw[off] = acc;
-    }
+    for (int m = 0; m < 7; ++m) w[m] = zc[c][m] + b * pc[c][m];
+    float acc = 0.0f;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) acc += wgt[ax] * (w[1 + 2 * ax] - 2.0f * w[0] + w[2 + 2 * ax]) * ih2[ax];
+    const int64_t off = c * g.nnodes + nidx;
+    p_new[off] = w[0];
+    Lw[off] = acc;
   }
 }
 
