@@ -202,6 +202,43 @@ int disco_profile_read(disco_ctx *ctx, int32_t kernel, int64_t *launches, double
 /* Human-readable text of a return code. */
 const char *disco_status_string(int code);
 
+/* ---- Batched Gauss-Newton steps over many pairs (uneven sizes) ----------------------
+   A batch groups existing contexts (same device and storage, images and keypoints set)
+   and runs one Gauss-Newton step of eq. 11 for every pair with ONE kernel launch per
+   phase of the step: each launch walks the (pair, block) work items of all pairs, the
+   largest pair first.  Each pair gets the arithmetic of gn_pcg_step with
+   DISCO_FLAG_LS_DEVICE (equal up to the rounding of fused multiply-adds).  The step has no
+   host synchronisation, so it can be captured in a graph (disco_batch_graph_capture) and
+   replayed; replays are bitwise reproducible. */
+typedef struct disco_batch disco_batch;
+
+/* Group npairs contexts (not copied: they must outlive the batch; no context twice). */
+int disco_batch_create(int32_t npairs, disco_ctx *const *ctxs, disco_batch **out);
+void disco_batch_destroy(disco_batch *batch);
+
+/* Fix what the next steps work on: params[i] (HOST array of npairs, each with
+   DISCO_FLAG_LS_DEVICE; the terms present, pcg_iters and ls_max equal for all pairs) and
+   u[i] (HOST array of npairs DEVICE node fields, updated in place by every step).
+   report_dev (device, npairs x DISCO_REP_SIZE doubles, nullable) and status_dev (device,
+   npairs int32, nullable) receive each pair's report and status.  Copies a descriptor
+   table to the device (synchronous); invalidates a captured graph. */
+int disco_batch_prepare(disco_batch *batch, const disco_params *params, float *const *u, double *report_dev,
+                        int32_t *status_dev);
+
+/* One GN step of every pair on `stream`. */
+int disco_batch_gn_step(disco_batch *batch, disco_stream stream);
+
+/* Launch shape of the persistent loops: workgroups per compute unit for the brick passes
+   (pass 0, 1..4 useful), the node passes (1) and the vector passes (2).  Invalidates a
+   captured graph. */
+int disco_batch_set_launch(disco_batch *batch, int32_t pass, int32_t wg_per_cu);
+
+/* Capture nsteps GN steps into a graph owned by the batch (library stream; no host
+   synchronisation inside), and replay it on `stream`.  A replay works on the arrays
+   given to disco_batch_prepare. */
+int disco_batch_graph_capture(disco_batch *batch, int32_t nsteps);
+int disco_batch_graph_launch(disco_batch *batch, disco_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -15,6 +15,7 @@
 #include "kernels.hpp"
 #include "solver.hpp"
 #include "adjoint.hpp"
+#include "batch.hpp"
 
 using namespace disco;
 
@@ -64,6 +65,24 @@ struct disco_ctx {
   // profiling
   bool prof = false;
   std::vector<EventPair> ev[4];
+};
+
+// a group of contexts stepped together (see batch.hpp)
+struct disco_batch {
+  int device = 0;
+  int storage = DISCO_STORAGE_FP32;
+  std::vector<disco_ctx *> ctx;  // in work order (largest pair first)
+  std::vector<int> order;        // order[i] = caller index of ctx[i]
+  void *desc = nullptr;          // PairDesc<ST>[npairs] on the device
+  int *start = nullptr;          // work lists on the device: 4 x (npairs + 1)
+  bool prepared = false;
+  bool vcc = false, kp = false, curv = false;
+  int pcg_iters = 0, ls_max = 0;
+  int ncu = 0;
+  int wpc[3] = {4, 8, 8};        // workgroups per compute unit: brick, node, vector passes
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -308,6 +327,107 @@ int check_field(const void *p) {
 int set_device(disco_ctx *c) {
   HIP_TRY(hipSetDevice(c->device));
   return DISCO_OK;
+}
+
+// ------------------------------------------------------------------------------
+// batched GN step (all pairs, one launch per phase)
+// ------------------------------------------------------------------------------
+template <class ST>
+GatherArgs gather_args(disco_ctx *c, int F, int nf, float *out0, float *out1, const float *Lw, float curv_scale,
+                       int curv_diag, const float *tauv, float tau, const float *dotv, const double *stop) {
+  GatherArgs a{};
+  a.g = c->g;
+  a.F = F;
+  a.nf = nf;
+  a.part = c->part;
+  a.out0 = out0;
+  a.out1 = out1;
+  a.Lw = Lw;
+  a.curv_scale = curv_scale;
+  a.curv_diag = curv_diag;
+  a.tauv = tauv;
+  a.tau = tau;
+  a.dotv = dotv;
+  a.blocks = c->blk_node;
+  a.stop = stop;
+  return a;
+}
+
+FinishArgs finish_args(int post, const PostArgs &pa, const double *stop, RedSrc s0, RedSrc s1 = RedSrc{},
+                       RedSrc s2 = RedSrc{}) {
+  FinishArgs f{};
+  f.s0 = s0;
+  f.s1 = s1;
+  f.s2 = s2;
+  f.nsrc = s2.blocks ? 3 : (s1.blocks ? 2 : 1);
+  f.post = post;
+  f.pa = pa;
+  f.stop = stop;
+  return f;
+}
+
+template <class ST>
+PairDesc<ST> pair_desc(disco_ctx *c, const disco_params *p, float *u, double *report, int32_t *status_out) {
+  PairDesc<ST> d{};
+  const Geo &g = c->g;
+  const bool vcc = p->gamma != 0.0;
+  const bool kp = p->delta != 0.0 && c->nkp > 0;
+  const bool curv = p->alpha != 0.0;
+  const float eta2 = (float)(p->eta * p->eta);
+  const double CH = ch_of(c);
+  set_s_scale(c, p->eta);
+  d.g = g;
+  d.u = u;
+  d.u_ref = c->u_ref;
+  d.u_lin = c->u_lin;
+  d.Lw = c->Lw;
+  d.grad = c->vg;
+  d.diag = c->vdiag;
+  d.x = c->vx;
+  d.r = c->vr;
+  d.z = c->vz;
+  d.p[0] = c->vp;
+  d.p[1] = c->vp2;
+  d.q = c->vq;
+  d.ut = c->vut;
+  d.invM = c->vinvm;
+  d.sc = c->sc;
+  d.blk_node = c->blk_node;
+  d.blk_curv = c->blk_curv;
+  d.blk_upd = c->blk_upd;
+  d.status = c->status;
+  d.report = report;
+  d.status_out = status_out;
+  d.n3 = 3 * g.nnodes;
+  d.nodeblocks = c->nodeblocks;
+  d.tau = (float)p->tau;
+  d.tol = p->pcg_tol;
+  d.CH = CH;
+  PairDesc<ST> &D = d;
+  D.lin = make_args<ST>(c, BrickCall{M_GRAD, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, u, nullptr,
+                                     c->vg, c->vdiag, nullptr});
+  for (int k = 0; k < 2; ++k)
+    D.hv[k] = make_args<ST>(c, BrickCall{M_HV, true, vcc, kp, 0.f, (float)p->gamma, (float)p->delta, c->u_lin,
+                                         D.p[k], c->vq, nullptr, c->sc + SC_STOP});
+  D.eval = make_args<ST>(c, BrickCall{M_EVAL, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, c->vut,
+                                      nullptr, nullptr, nullptr, c->sc + SC_ACCEPT});
+  D.glin = gather_args<ST>(c, 2, 2, c->vg, c->vdiag, curv ? c->Lw : nullptr, (float)(p->alpha * CH), curv ? 1 : 0,
+                           nullptr, 0.f, nullptr, nullptr);
+  for (int k = 0; k < 2; ++k)
+    D.ghv[k] = gather_args<ST>(c, 1, 1, c->vq, nullptr, curv ? c->Lw : nullptr, (float)(p->alpha * CH), 0,
+                               p->tau != 0.0 ? D.p[k] : nullptr, (float)p->tau, D.p[k], c->sc + SC_STOP);
+  PostArgs pa = post_args(c, p->alpha, p->gamma, p->delta);
+  pa.c1 = p->armijo_c1;
+  pa.tol = p->pcg_tol;
+  double *sc = c->sc;
+  const int64_t nb3 = nblk(3 * g.nnodes);
+  D.fin_lin = finish_args(POST_LIN_BRICK, pa, nullptr, src_brick(c, sc + SC_TMP0), src_curv(c, sc + SC_SRAW),
+                          src_gather(c, sc + SC_DOT));
+  D.fin_pcg = finish_args(POST_PCG_START, pa, nullptr, src_pairs(c->blk_node, nb3, 2, sc + SC_TMP0));
+  D.fin_lsb = finish_args(POST_LS_BEGIN, pa, nullptr, src_pairs(c->blk_node, nb3, 1, sc + SC_TMP0),
+                          src_pairs(c->blk_upd, upd_blocks(g), 2, sc + SC_TMP1));
+  D.fin_trial = finish_args(POST_LS_BRICK, pa, sc + SC_ACCEPT, src_brick(c, sc + SC_TMP0), src_curv(c, sc + SC_TSRAW));
+  return d;
 }
 
 }  // namespace
@@ -909,6 +1029,295 @@ int disco_profile_read(disco_ctx *c, int32_t kernel, int64_t *launches, double *
   }
   *launches = (int64_t)c->ev[kernel].size();
   *ms_total = tot;
+  return DISCO_OK;
+}
+
+// ------------------------------------------------------------------------------
+// batched GN step
+// ------------------------------------------------------------------------------
+enum { WL_BRICK = 0, WL_NODE = 1, WL_VEC = 2, WL_UPD = 3 };
+
+static void batch_free_graph(disco_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+int disco_batch_create(int32_t npairs, disco_ctx *const *ctxs, disco_batch **out) {
+  if (!out) return DISCO_ERR_ARG;
+  *out = nullptr;
+  if (npairs < 1 || !ctxs) return DISCO_ERR_ARG;
+  for (int i = 0; i < npairs; ++i) {
+    if (!ctxs[i]) return DISCO_ERR_ARG;
+    if (ctxs[i]->device != ctxs[0]->device || ctxs[i]->storage != ctxs[0]->storage) return DISCO_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return DISCO_ERR_ARG;
+  }
+  disco_batch *b = new (std::nothrow) disco_batch();
+  if (!b) return DISCO_ERR_NOMEM;
+  b->device = ctxs[0]->device;
+  b->storage = ctxs[0]->storage;
+  // work order: largest pair first (balances the persistent loops)
+  b->order.resize(npairs);
+  std::iota(b->order.begin(), b->order.end(), 0);
+  std::stable_sort(b->order.begin(), b->order.end(),
+                   [&](int a, int c) { return ctxs[a]->g.nvox > ctxs[c]->g.nvox; });
+  for (int i = 0; i < npairs; ++i) b->ctx.push_back(ctxs[b->order[i]]);
+  if (hipSetDevice(b->device) != hipSuccess) {
+    delete b;
+    return DISCO_ERR_ARG;
+  }
+  hipDeviceProp_t prop;
+  b->ncu = hipGetDeviceProperties(&prop, b->device) == hipSuccess ? prop.multiProcessorCount : 256;
+  const size_t dsz = b->storage == DISCO_STORAGE_FP16 ? sizeof(PairDesc<F16x3>) : sizeof(PairDesc<F32x3>);
+  if (hipMalloc(&b->desc, dsz * (size_t)npairs) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&b->start), sizeof(int) * 4 * (size_t)(npairs + 1)) != hipSuccess) {
+    (void)hipFree(b->desc);
+    delete b;
+    return DISCO_ERR_NOMEM;
+  }
+  // work lists: bricks, node blocks, 256-element vector blocks, CG update blocks
+  std::vector<int> st(4 * (size_t)(npairs + 1), 0);
+  int64_t acc[4] = {0, 0, 0, 0};
+  for (int i = 0; i < npairs; ++i) {
+    const disco_ctx *c = b->ctx[i];
+    const int64_t cnt[4] = {c->nwg, c->nodeblocks, (int64_t)nblk(3 * c->g.nnodes), upd_blocks(c->g)};
+    for (int w = 0; w < 4; ++w) {
+      st[w * (npairs + 1) + i] = (int)acc[w];
+      acc[w] += cnt[w];
+    }
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (acc[w] >= ((int64_t)1 << 31)) {
+      (void)hipFree(b->desc);
+      (void)hipFree(b->start);
+      delete b;
+      return DISCO_ERR_SHAPE;
+    }
+    st[w * (npairs + 1) + npairs] = (int)acc[w];
+  }
+  if (hipMemcpy(b->start, st.data(), sizeof(int) * st.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(b->desc);
+    (void)hipFree(b->start);
+    delete b;
+    return DISCO_ERR_NOMEM;
+  }
+  *out = b;
+  return DISCO_OK;
+}
+
+void disco_batch_destroy(disco_batch *b) {
+  if (!b) return;
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  batch_free_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  (void)hipFree(b->desc);
+  (void)hipFree(b->start);
+  delete b;
+}
+
+extern "C++" {
+template <class ST>
+static int batch_prepare_t(disco_batch *b, const disco_params *params, float *const *u, double *report_dev,
+                           int32_t *status_dev) {
+  const int n = (int)b->ctx.size();
+  std::vector<PairDesc<ST>> d(n);
+  for (int i = 0; i < n; ++i) {
+    const int ci = b->order[i];
+    d[i] = pair_desc<ST>(b->ctx[i], &params[ci], u[ci], report_dev ? report_dev + 16 * (size_t)ci : nullptr,
+                         status_dev ? status_dev + ci : nullptr);
+  }
+  HIP_TRY(hipMemcpy(b->desc, d.data(), sizeof(PairDesc<ST>) * (size_t)n, hipMemcpyHostToDevice));
+  return DISCO_OK;
+}
+
+}  // extern "C++"
+
+int disco_batch_prepare(disco_batch *b, const disco_params *params, float *const *u, double *report_dev,
+                        int32_t *status_dev) {
+  if (!b || !params || !u) return DISCO_ERR_ARG;
+  const int n = (int)b->ctx.size();
+  int e;
+  for (int i = 0; i < n; ++i) {
+    if ((e = check_params(&params[i]))) return e;
+    if ((e = check_field(u[i]))) return e;
+    if (!(params[i].flags & DISCO_FLAG_LS_DEVICE)) return DISCO_ERR_ARG;  // no host round trips in a batch
+  }
+  if ((report_dev && ((reinterpret_cast<uintptr_t>(report_dev) & 7u) != 0)) || (status_dev && !aligned4(status_dev)))
+    return DISCO_ERR_SHAPE;
+  // the terms present, the CG iteration count and the trial count are shared by the batch
+  const disco_params &p0 = params[0];
+  const bool vcc = p0.gamma != 0.0, curv = p0.alpha != 0.0;
+  const bool kp = p0.delta != 0.0 && b->ctx[0]->nkp > 0;
+  for (int i = 0; i < n; ++i) {
+    const disco_ctx *c = b->ctx[i];
+    const disco_params &pi = params[b->order[i]];
+    if (!c->images) return DISCO_ERR_STATE;
+    if ((pi.gamma != 0.0) != vcc || (pi.alpha != 0.0) != curv || ((pi.delta != 0.0 && c->nkp > 0) != kp) ||
+        pi.pcg_iters != p0.pcg_iters || pi.ls_max != p0.ls_max)
+      return DISCO_ERR_ARG;
+  }
+  if ((e = set_device(b->ctx[0]))) return e;
+  batch_free_graph(b);
+  b->prepared = false;
+  b->vcc = vcc;
+  b->kp = kp;
+  b->curv = curv;
+  b->pcg_iters = p0.pcg_iters;
+  b->ls_max = p0.ls_max;
+  e = b->storage == DISCO_STORAGE_FP16 ? batch_prepare_t<F16x3>(b, params, u, report_dev, status_dev)
+                                       : batch_prepare_t<F32x3>(b, params, u, report_dev, status_dev);
+  if (e) return e;
+  b->prepared = true;
+  return DISCO_OK;
+}
+
+int disco_batch_set_launch(disco_batch *b, int32_t pass, int32_t wg_per_cu) {
+  if (!b || pass < 0 || pass > 2 || wg_per_cu < 1 || wg_per_cu > 64) return DISCO_ERR_ARG;
+  b->wpc[pass] = wg_per_cu;
+  batch_free_graph(b);  // a captured graph keeps the old launch shape
+  return DISCO_OK;
+}
+
+extern "C++" {
+template <class ST, int MODE, bool NGF>
+static void launch_b_brick(disco_batch *b, unsigned grid, const int *st, int n, int sel, int acc, hipStream_t s) {
+  const PairDesc<ST> *D = reinterpret_cast<const PairDesc<ST> *>(b->desc);
+  const int key = (b->vcc ? 2 : 0) | (b->kp ? 1 : 0);
+  if constexpr (NGF && MODE != M_HV) {
+    hipLaunchKernelGGL((k_b_brick<ST, MODE, true, false, false>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc);
+  } else if constexpr (NGF) {
+    switch (key) {
+      case 3: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, true, true>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
+      case 2: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, true, false>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
+      case 1: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, false, true>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
+      default: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, false, false>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
+    }
+  } else {
+    switch (key) {
+      case 3: hipLaunchKernelGGL((k_b_brick<ST, MODE, false, true, true>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
+      case 2: hipLaunchKernelGGL((k_b_brick<ST, MODE, false, true, false>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
+      case 1: hipLaunchKernelGGL((k_b_brick<ST, MODE, false, false, true>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
+      default: break;
+    }
+  }
+}
+
+template <class ST>
+static void batch_step_t(disco_batch *b, hipStream_t s) {
+  const int n = (int)b->ctx.size();
+  const PairDesc<ST> *D = reinterpret_cast<const PairDesc<ST> *>(b->desc);
+  const int *wl[4];
+  int tot[4];
+  for (int w = 0; w < 4; ++w) wl[w] = b->start + w * (n + 1);
+  for (int w = 0; w < 4; ++w) {
+    int64_t t = 0;
+    for (auto *c : b->ctx)
+      t += w == WL_BRICK ? c->nwg : (w == WL_NODE ? c->nodeblocks : (w == WL_VEC ? (int64_t)nblk(3 * c->g.nnodes) : upd_blocks(c->g)));
+    tot[w] = (int)t;
+  }
+  auto grid = [&](int w, int pass) { return (unsigned)std::max(1, std::min(tot[w], b->ncu * b->wpc[pass])); };
+  const unsigned gb = grid(WL_BRICK, 0), gn = grid(WL_NODE, 1), gv = grid(WL_VEC, 2), gu = grid(WL_UPD, 2);
+  const bool cells = b->vcc || b->kp;
+  const unsigned pairs_grid = (unsigned)std::min(n, b->ncu * 4);
+
+  hipLaunchKernelGGL(k_b_status<ST>, dim3((n + 63) / 64), dim3(64), 0, s, D, n, 0);
+  // linearisation: objective, gradient, GN diagonal, s cache
+  if (b->curv) hipLaunchKernelGGL(k_b_curv_L<ST>, dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 0);
+  if (cells) launch_b_brick<ST, M_GRAD, false>(b, gb, wl[WL_BRICK], n, 0, 0, s);
+  launch_b_brick<ST, M_GRAD, true>(b, gb, wl[WL_BRICK], n, 0, cells ? 1 : 0, s);
+  if (b->curv)
+    hipLaunchKernelGGL((k_b_gather<ST, 2, 2, true>), dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 0);
+  else
+    hipLaunchKernelGGL((k_b_gather<ST, 2, 2, false>), dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 0);
+  hipLaunchKernelGGL(k_b_finish<ST>, dim3(pairs_grid), dim3(1024), 0, s, D, n, 0);
+  hipLaunchKernelGGL(k_b_vec<ST>, dim3(gv), dim3(256), 0, s, D, wl[WL_VEC], n, 0, 0);  // u_lin = u
+  // Jacobi-PCG
+  hipLaunchKernelGGL(k_b_vec<ST>, dim3(gv), dim3(256), 0, s, D, wl[WL_VEC], n, 1, 0);
+  hipLaunchKernelGGL(k_b_finish<ST>, dim3(pairs_grid), dim3(1024), 0, s, D, n, 1);
+  for (int it = 0; it < b->pcg_iters; ++it) {
+    if (it == 0) {
+      if (b->curv) hipLaunchKernelGGL(k_b_curv_L<ST>, dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 1);
+    } else {
+      hipLaunchKernelGGL(k_b_curv_Lp<ST>, dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, it);
+    }
+    launch_b_brick<ST, M_HV, true>(b, gb, wl[WL_BRICK], n, 1 + (it & 1), 0, s);
+    if (b->curv)
+      hipLaunchKernelGGL((k_b_gather<ST, 1, 1, true>), dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 1 + (it & 1));
+    else
+      hipLaunchKernelGGL((k_b_gather<ST, 1, 1, false>), dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 1 + (it & 1));
+    hipLaunchKernelGGL(k_b_pcg_update<ST>, dim3(gu), dim3(256), 0, s, D, wl[WL_UPD], n, it);
+  }
+  // Armijo line search on the device (ls_max trials, skipped once accepted)
+  hipLaunchKernelGGL(k_b_vec<ST>, dim3(gv), dim3(256), 0, s, D, wl[WL_VEC], n, 2, 0);
+  hipLaunchKernelGGL(k_b_finish<ST>, dim3(pairs_grid), dim3(1024), 0, s, D, n, 2);
+  for (int t = 0; t < b->ls_max; ++t) {
+    hipLaunchKernelGGL(k_b_vec<ST>, dim3(gv), dim3(256), 0, s, D, wl[WL_VEC], n, 3, t);
+    hipLaunchKernelGGL(k_b_curv_L<ST>, dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 2);
+    if (cells) launch_b_brick<ST, M_EVAL, false>(b, gb, wl[WL_BRICK], n, 3, 0, s);
+    launch_b_brick<ST, M_EVAL, true>(b, gb, wl[WL_BRICK], n, 3, cells ? 1 : 0, s);
+    hipLaunchKernelGGL(k_b_finish<ST>, dim3(pairs_grid), dim3(1024), 0, s, D, n, 3);
+  }
+  hipLaunchKernelGGL(k_b_vec<ST>, dim3(gv), dim3(256), 0, s, D, wl[WL_VEC], n, 4, 0);
+  hipLaunchKernelGGL(k_b_status<ST>, dim3((n + 63) / 64), dim3(64), 0, s, D, n, 1);
+}
+
+}  // extern "C++"
+
+static int batch_step(disco_batch *b, hipStream_t s) {
+  if (b->storage == DISCO_STORAGE_FP16)
+    batch_step_t<F16x3>(b, s);
+  else
+    batch_step_t<F32x3>(b, s);
+  for (auto *c : b->ctx) {
+    c->lin = true;
+  }
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+int disco_batch_gn_step(disco_batch *b, disco_stream stream) {
+  if (!b) return DISCO_ERR_ARG;
+  if (!b->prepared) return DISCO_ERR_STATE;
+  int e;
+  if ((e = set_device(b->ctx[0]))) return e;
+  return batch_step(b, S(stream));
+}
+
+int disco_batch_graph_capture(disco_batch *b, int32_t nsteps) {
+  if (!b || nsteps < 1) return DISCO_ERR_ARG;
+  if (!b->prepared) return DISCO_ERR_STATE;
+  int e;
+  if ((e = set_device(b->ctx[0]))) return e;
+  batch_free_graph(b);
+  if (!b->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  int err = DISCO_OK;
+  for (int k = 0; k < nsteps && !err; ++k) err = batch_step(b, b->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t ce = hipStreamEndCapture(b->cap_stream, &graph);
+  if (err) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return err;
+  }
+  if (ce != hipSuccess) return hip_err(ce);
+  b->graph = graph;
+  const hipError_t ie = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    batch_free_graph(b);
+    return hip_err(ie);
+  }
+  return DISCO_OK;
+}
+
+int disco_batch_graph_launch(disco_batch *b, disco_stream stream) {
+  if (!b) return DISCO_ERR_ARG;
+  if (!b->exec) return DISCO_ERR_STATE;
+  int e;
+  if ((e = set_device(b->ctx[0]))) return e;
+  HIP_TRY(hipGraphLaunch(b->exec, S(stream)));
   return DISCO_OK;
 }
 

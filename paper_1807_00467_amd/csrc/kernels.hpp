@@ -29,6 +29,18 @@ constexpr int kNBOX = (kBXC + 1) * (kBYC + 1);  // nodes of one brick plane (17 
 
 enum { M_EVAL = 0, M_GRAD = 1, M_HV = 2 };
 
+// Block coordinates of a work item: the hardware block index for single-pair launches,
+// or a (pair, block) item of a batched launch.  lin is the linear block index within the
+// pair's grid (x fastest), which also indexes the pair's per-block partials.
+struct Blk {
+  int x, y, z;
+  int64_t lin;
+};
+__device__ __forceinline__ Blk hw_blk() {
+  return Blk{(int)blockIdx.x, (int)blockIdx.y, (int)blockIdx.z,
+             ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x};
+}
+
 // block scalar slots written by k_brick (doubles per workgroup)
 enum { BS_D = 0, BS_V = 1, BS_K = 2, BS_FOLD = 3, BS_N = 4 };
 
@@ -257,17 +269,17 @@ __device__ __forceinline__ double wave_red_d(double v, bool mx) {
 // wave results in order), then run the scalar post-operation.  The first 2048 partials
 // of every source are requested together.  Deterministic; no inter-workgroup
 // communication.
-__global__ __launch_bounds__(1024) void k_finish(RedSrc s0, RedSrc s1, RedSrc s2, int nsrc, int post, PostArgs pa,
-                                                 const double *stop) {
+__device__ __forceinline__ void finish_body(const RedSrc s0, const RedSrc s1, const RedSrc s2, int nsrc, int post,
+                                            const PostArgs &pa, const double *stop) {
   __shared__ double wred[16][12];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  // sources selected by value (no local array: it would live in scratch memory)
-  auto src = [&](int q) -> const RedSrc & { return q == 0 ? s0 : (q == 1 ? s1 : s2); };
+  // sources selected by value (no addressable local array: it would live in scratch memory)
+  auto src = [&](int q) -> RedSrc { return q == 0 ? s0 : (q == 1 ? s1 : s2); };
   const double stopv = stop ? *stop : 0.0;  // no workgroup writes it here: uniform
   double x[3][2][4];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const RedSrc &S = src(q);
+    const RedSrc S = src(q);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int64_t b = u * 1024 + t;
@@ -278,7 +290,7 @@ __global__ __launch_bounds__(1024) void k_finish(RedSrc s0, RedSrc s1, RedSrc s2
   if (stopv != 0.0) return;
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const RedSrc &S = src(q);
+    const RedSrc S = src(q);
     if (q < nsrc) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -297,10 +309,12 @@ __global__ __launch_bounds__(1024) void k_finish(RedSrc s0, RedSrc s1, RedSrc s2
     }
   }
   __syncthreads();
-  if (t < nsrc * 4) {
-    const int q = t >> 2, k = t & 3;
-    const RedSrc &S = src(q);
-    if (k < S.nvals) {
+  // thread 4 q + k finishes value k of source q (q static in each unrolled pass)
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const RedSrc S = src(q);
+    const int k = t - 4 * q;
+    if (q < nsrc && k >= 0 && k < 4 && k < S.nvals) {
       const bool mx = (S.max_mask >> k) & 1u;
       double r = wred[0][t];
       for (int i = 1; i < 16; ++i) r = mx ? fmax(r, wred[i][t]) : r + wred[i][t];
@@ -309,6 +323,11 @@ __global__ __launch_bounds__(1024) void k_finish(RedSrc s0, RedSrc s1, RedSrc s2
   }
   __syncthreads();
   if (t == 0) run_post(post, pa, s0.out);
+}
+
+__global__ __launch_bounds__(1024) void k_finish(RedSrc s0, RedSrc s1, RedSrc s2, int nsrc, int post, PostArgs pa,
+                                                 const double *stop) {
+  finish_body(s0, s1, s2, nsrc, post, pa, stop);
 }
 
 // Sums of NV values over n partials, blocks[b * stride + k0 + k], computed identically by
@@ -905,7 +924,7 @@ __device__ __forceinline__ void load_corners(const float *fb, const Geo &g, bool
 #define DISCO_HV_WAVES 1
 #endif
 template <class ST, int MODE, bool NGF, bool VCC, bool KP, int ZC>
-__global__ __launch_bounds__(kWG, MODE == M_HV ? DISCO_HV_WAVES : 1) void k_brick(BrickArgs<ST> A) {
+__device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B, int acc) {
   constexpr int F = (MODE == M_GRAD) ? 2 : ((MODE == M_HV) ? 1 : 0);
   constexpr int FS = F > 0 ? F : 1;
   constexpr bool CELLT = VCC || KP;
@@ -921,7 +940,7 @@ __global__ __launch_bounds__(kWG, MODE == M_HV ? DISCO_HV_WAVES : 1) void k_bric
   const Geo &g = A.g;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q = lane & 3, xq = lane >> 2;
-  const int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  const int bx = B.x, by = B.y, bz = B.z;
   const int ix = bx * 64 + lane;
   const int cx = ix >> 2;
   const int cy = by * kBYC + wave;
@@ -1270,12 +1289,12 @@ __global__ __launch_bounds__(kWG, MODE == M_HV ? DISCO_HV_WAVES : 1) void k_bric
       const bool face = is_face(zl, bz, g.nbz, ZC) || is_face(xl, bx, g.nbx, kBXC) || is_face(yl, by, g.nby, kBYC);
       if (face) {
         float *pp = A.part + ((brick * (ZC + 1) + zl) * (F * 3) + fc) * kNBOX + yl * 17 + xl;
-        *pp = A.acc ? *pp + val : val;
+        *pp = acc ? *pp + val : val;
       } else {
         const int f = fc / 3, c = fc - 3 * f;
         float *o = f == 0 ? A.out0 : A.out1;
         float *po = o + c * g.nnodes + ((int64_t)pzn * g.py + pyn) * g.px + pxn;
-        *po = A.acc ? *po + val : val;
+        *po = acc ? *po + val : val;
       }
     }
   }
@@ -1291,11 +1310,16 @@ __global__ __launch_bounds__(kWG, MODE == M_HV ? DISCO_HV_WAVES : 1) void k_bric
     __syncthreads();
     if (threadIdx.x < BS_N) {
       const int t = threadIdx.x;
-      const int64_t wg = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+      const int64_t wg = B.lin;
       const double v = ((lred[0][t] + lred[1][t]) + lred[2][t]) + lred[3][t];
-      A.blocks[wg * BS_N + t] = A.acc ? A.blocks[wg * BS_N + t] + v : v;
+      A.blocks[wg * BS_N + t] = acc ? A.blocks[wg * BS_N + t] + v : v;
     }
   }
+}
+
+template <class ST, int MODE, bool NGF, bool VCC, bool KP, int ZC>
+__global__ __launch_bounds__(kWG, MODE == M_HV ? DISCO_HV_WAVES : 1) void k_brick(BrickArgs<ST> A) {
+  brick_body<ST, MODE, NGF, VCC, KP, ZC>(A, hw_blk(), A.acc);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1321,24 +1345,11 @@ struct GatherArgs {
 
 __device__ __forceinline__ int chi(int p, int n) { return (p >= 1 && p <= n - 2) ? 1 : 0; }
 
-__device__ __forceinline__ int brick_cands(int p, int B, int nb, int b[2], int l[2]) {
-  int n = 0;
-  const int b0 = p / B;
-  for (int bb = b0 - 1; bb <= b0; ++bb) {
-    if (bb < 0 || bb >= nb) continue;
-    const int ll = p - bb * B;
-    if (ll < 0 || ll > B) continue;
-    b[n] = bb;
-    l[n] = ll;
-    ++n;
-  }
-  return n;
-}
 
 // F: fields the brick kernel wrote (0: none ran), NF: fields produced (1 or 2),
 // CURV: add curvature (field 0, and its diagonal to field 1 when NF = 2)
 template <int ZC, int F, int NF, bool CURV>
-__global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
+__device__ __forceinline__ void gather_body(const GatherArgs &A, const Blk &B) {
   // read with the other loads; only the writes wait for it (no workgroup writes it here)
   const bool stopped = A.stop && *A.stop != 0.0;
   const Geo &g = A.g;
@@ -1349,28 +1360,46 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
   float *__restrict__ out0 = A.out0;
   float *__restrict__ out1 = A.out1;
   // block (64 x 4 threads) covers nodes x in [64 bx, 64 bx + 64), y in [4 by, 4 by + 4), plane bz
-  const int px = blockIdx.x * 64 + (threadIdx.x & 63), py = blockIdx.y * 4 + (threadIdx.x >> 6), pz = blockIdx.z;
-  const int64_t bid = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int px = B.x * 64 + (threadIdx.x & 63), py = B.y * 4 + (threadIdx.x >> 6), pz = B.z;
+  const int64_t bid = B.lin;
   double dsum = 0.0, dmax = 0.0, gsq = 0.0;
   if (px < g.px && py < g.py) {
     const int64_t n = ((int64_t)pz * g.py + py) * g.px + px;
     float val[NF][3];
     // brick kernel part: interior nodes were written directly, face nodes are summed here
     if (F > 0) {
-      int bxs[2], lxs[2], bys[2], lys[2], bzs[2], lzs[2];
-      const int nbx = brick_cands(px, kBXC, g.nbx, bxs, lxs);
-      const int nby = brick_cands(py, kBYC, g.nby, bys, lys);
-      const int nbz = brick_cands(pz, ZC, g.nbz, bzs, lzs);
-      if (nbx > 1 || nby > 1 || nbz > 1) {
+      // the (at most two) bricks per axis whose box holds this node, in increasing order;
+      // fixed-size candidate lists so that nothing is indexed dynamically
+      const int pcoord[3] = {px, py, pz};
+      const int BB[3] = {kBXC, kBYC, ZC};
+      const int NB[3] = {g.nbx, g.nby, g.nbz};
+      int cb[3][2], cl[3][2];
+      bool cok[3][2];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int bb = pcoord[a] / BB[a] - 1 + k;
+          const int ll = pcoord[a] - bb * BB[a];
+          cb[a][k] = bb;
+          cl[a][k] = ll;
+          cok[a][k] = bb >= 0 && bb < NB[a] && ll >= 0 && ll <= BB[a];
+        }
+      const bool face = (cok[0][0] && cok[0][1]) || (cok[1][0] && cok[1][1]) || (cok[2][0] && cok[2][1]);
+      if (face) {
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
           for (int c = 0; c < 3; ++c) val[f][c] = 0.0f;
-        for (int iz = 0; iz < nbz; ++iz)
-          for (int iy = 0; iy < nby; ++iy)
-            for (int ixx = 0; ixx < nbx; ++ixx) {
-              const int64_t brick = ((int64_t)bzs[iz] * g.nby + bys[iy]) * g.nbx + bxs[ixx];
-              const float *pp = part + (brick * (ZC + 1) + lzs[iz]) * (F * 3) * kNBOX + lys[iy] * 17 + lxs[ixx];
+#pragma unroll
+        for (int iz = 0; iz < 2; ++iz)
+#pragma unroll
+          for (int iy = 0; iy < 2; ++iy)
+#pragma unroll
+            for (int ixx = 0; ixx < 2; ++ixx) {
+              if (!(cok[2][iz] && cok[1][iy] && cok[0][ixx])) continue;
+              const int64_t brick = ((int64_t)cb[2][iz] * g.nby + cb[1][iy]) * g.nbx + cb[0][ixx];
+              const float *pp = part + (brick * (ZC + 1) + cl[2][iz]) * (F * 3) * kNBOX + cl[1][iy] * 17 + cl[0][ixx];
 #pragma unroll
               for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -1445,18 +1474,23 @@ __global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
   }
 }
 
+template <int ZC, int F, int NF, bool CURV>
+__global__ __launch_bounds__(256) void k_gather(GatherArgs A) {
+  gather_body<ZC, F, NF, CURV>(A, hw_blk());
+}
+
 // L w for w = a - b (b nullable), and per-block sum of (L w)^2.  Branch-free: stencil
 // neighbours that L does not use (chi = 0) read the centre with weight zero, so every
 // load is requested before the first wait.
-__global__ __launch_bounds__(256) void k_curv_L(Geo g, const float *__restrict__ a, const float *__restrict__ b,
-                                                float *__restrict__ Lw, double *blocks, const double *stop) {
+__device__ __forceinline__ void curv_L_body(const Geo &g, const float *__restrict__ a, const float *__restrict__ b,
+                                            float *__restrict__ Lw, double *blocks, const double *stop, const Blk &B) {
   // read with the other loads; only the writes wait for it (no workgroup writes it here)
   const bool stopped = stop && *stop != 0.0;
-  const int px = blockIdx.x * 64 + (threadIdx.x & 63), py = blockIdx.y * 4 + (threadIdx.x >> 6), pz = blockIdx.z;
+  const int px = B.x * 64 + (threadIdx.x & 63), py = B.y * 4 + (threadIdx.x >> 6), pz = B.z;
   const bool in = px < g.px && py < g.py;
   const int pp[3] = {in ? px : 0, in ? py : 0, pz};
   const int64_t n = ((int64_t)pp[2] * g.py + pp[1]) * g.px + pp[0];
-  const int64_t bid = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  const int64_t bid = B.lin;
   const int nn[3] = {g.px, g.py, g.pz};
   const int64_t st[3] = {1, g.px, (int64_t)g.px * g.py};
   const float ih2[3] = {g.iHx * g.iHx, g.iHy * g.iHy, g.iHz * g.iHz};
@@ -1487,6 +1521,11 @@ __global__ __launch_bounds__(256) void k_curv_L(Geo g, const float *__restrict__
     if (in) e += (double)acc * (double)acc;
   }
   if (blocks && !stopped) block_write<1>(&e, blocks + bid);
+}
+
+__global__ __launch_bounds__(256) void k_curv_L(Geo g, const float *__restrict__ a, const float *__restrict__ b,
+                                                float *__restrict__ Lw, double *blocks, const double *stop) {
+  curv_L_body(g, a, b, Lw, blocks, stop, hw_blk());
 }
 
 // central-difference image gradient with replicated border, stored as ST

@@ -15,11 +15,11 @@ __device__ inline void block_pair_sum(double x, double y, double *blocks, int64_
 }
 
 // x = 0, r = -g, z = r / M, p = z, invM = 1 / M; per-block <r,z>, <r,r>
-__global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const float *__restrict__ g,
-                                                  const float *__restrict__ diag, const double *sc, float tau,
-                                                  float *__restrict__ x, float *__restrict__ r, float *__restrict__ z,
-                                                  float *__restrict__ p, float *__restrict__ invM, double *blocks) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void pcg_init_body(int64_t n, const float *__restrict__ g, const float *__restrict__ diag,
+                                              const double *sc, float tau, float *__restrict__ x,
+                                              float *__restrict__ r, float *__restrict__ z, float *__restrict__ p,
+                                              float *__restrict__ invM, double *blocks, int64_t bid) {
+  const int64_t i = bid * 256 + threadIdx.x;
   double rz = 0.0, rr = 0.0;
   if (i < n) {
     const float M = diag[i] + tau + (float)(1e-12 * sc[SC_MAXDIAG]);
@@ -34,7 +34,13 @@ __global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const float *__rest
     rz = (double)ri * (double)zi;
     rr = (double)ri * (double)ri;
   }
-  block_pair_sum(rz, rr, blocks, blockIdx.x);
+  block_pair_sum(rz, rr, blocks, bid);
+}
+__global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const float *__restrict__ g,
+                                                  const float *__restrict__ diag, const double *sc, float tau,
+                                                  float *__restrict__ x, float *__restrict__ r, float *__restrict__ z,
+                                                  float *__restrict__ p, float *__restrict__ invM, double *blocks) {
+  pcg_init_body(n, g, diag, sc, tau, x, r, z, p, invM, blocks, blockIdx.x);
 }
 
 // elements per thread of the CG vector update (workgroup covers 256 * kUpdK elements)
@@ -45,12 +51,12 @@ constexpr int kUpdK = 16;
 // x += alpha p, r -= alpha q, z = r / M; per-workgroup <r,z>, <r,r>.  <r,z> of this
 // iteration is in slot SC_RZ + (it & 1).  The vector loads, the partials and the stop
 // flag are all requested before the first wait.
-__global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *sc, int it, const double *pq_blocks,
-                                                    int64_t pq_nb, const float *__restrict__ invM,
-                                                    const float *__restrict__ p, const float *__restrict__ q,
-                                                    float *__restrict__ x, float *__restrict__ r,
-                                                    float *__restrict__ z, double *blocks, int *status) {
-  const int64_t base = (int64_t)blockIdx.x * (256 * kUpdK) + threadIdx.x;
+__device__ __forceinline__ void pcg_update_body(int64_t n, double *sc, int it, const double *pq_blocks, int64_t pq_nb,
+                                                const float *__restrict__ invM, const float *__restrict__ p,
+                                                const float *__restrict__ q, float *__restrict__ x,
+                                                float *__restrict__ r, float *__restrict__ z, double *blocks,
+                                                int *status, int64_t bid) {
+  const int64_t base = bid * (256 * kUpdK) + threadIdx.x;
   float vp[kUpdK], vq[kUpdK], vx[kUpdK], vr[kUpdK], vm[kUpdK];
 #pragma unroll
   for (int k = 0; k < kUpdK; ++k) {
@@ -69,7 +75,7 @@ __global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *sc, int i
   if (stop != 0.0) return;
   if (!(pq > 0.0)) {
     // breakdown: every workgroup sees the same pq and skips the update
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
       sc[SC_STOP] = 1.0;
       sc[SC_BREAK] = 1.0;
       *status |= 2;
@@ -92,11 +98,18 @@ __global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *sc, int i
       rr += (double)ri * (double)ri;
     }
   }
-  block_pair_sum(rz, rr, blocks, blockIdx.x);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  block_pair_sum(rz, rr, blocks, bid);
+  if (bid == 0 && threadIdx.x == 0) {
     sc[SC_ALPHA] = alpha;
     sc[SC_ITERS] = (double)(it + 1);
   }
+}
+__global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *sc, int it, const double *pq_blocks,
+                                                    int64_t pq_nb, const float *__restrict__ invM,
+                                                    const float *__restrict__ p, const float *__restrict__ q,
+                                                    float *__restrict__ x, float *__restrict__ r,
+                                                    float *__restrict__ z, double *blocks, int *status) {
+  pcg_update_body(n, sc, it, pq_blocks, pq_nb, invM, p, q, x, r, z, blocks, status, blockIdx.x);
 }
 
 // Start of CG iteration it >= 1: every workgroup reduces the <r,z>, <r,r> partials of
@@ -105,11 +118,11 @@ __global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *sc, int i
 // operator of the next product) in the same pass: L at node m needs p_new at the
 // 6 neighbours, which are formed from z and p_old there.  One node plane per workgroup;
 // all loads are requested before the first wait.
-__global__ __launch_bounds__(256) void k_curv_Lp(Geo g, int it, double *sc, double tol, const double *upd_blocks,
-                                                 int64_t upd_nb, const float *__restrict__ z,
-                                                 const float *__restrict__ p_old, float *__restrict__ p_new,
-                                                 float *__restrict__ Lw) {
-  const int px = blockIdx.x * 64 + (threadIdx.x & 63), py = blockIdx.y * 4 + (threadIdx.x >> 6), pz = blockIdx.z;
+__device__ __forceinline__ void curv_Lp_body(const Geo &g, int it, double *sc, double tol, const double *upd_blocks,
+                                             int64_t upd_nb, const float *__restrict__ z,
+                                             const float *__restrict__ p_old, float *__restrict__ p_new,
+                                             float *__restrict__ Lw, const Blk &B) {
+  const int px = B.x * 64 + (threadIdx.x & 63), py = B.y * 4 + (threadIdx.x >> 6), pz = B.z;
   const bool in = px < g.px && py < g.py;
   const int pp[3] = {in ? px : 0, in ? py : 0, pz};
   const int nn[3] = {g.px, g.py, g.pz};
@@ -146,7 +159,7 @@ __global__ __launch_bounds__(256) void k_curv_Lp(Geo g, int it, double *sc, doub
   const double rz_new = sums[0], rr = sums[1];
   const double beta = rz_new / rz_prev;
   const bool conv = tol > 0.0 && sqrt(rr) <= tol * sqrt(sc[SC_BB]);
-  if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) {
+  if (B.lin == 0 && threadIdx.x == 0) {
     sc[SC_RZ + (it & 1)] = rz_new;
     sc[SC_RR] = rr;
     sc[SC_BETA] = beta;
@@ -168,32 +181,54 @@ __global__ __launch_bounds__(256) void k_curv_Lp(Geo g, int it, double *sc, doub
     Lw[off] = acc;
   }
 }
+__global__ __launch_bounds__(256) void k_curv_Lp(Geo g, int it, double *sc, double tol, const double *upd_blocks,
+                                                 int64_t upd_nb, const float *__restrict__ z,
+                                                 const float *__restrict__ p_old, float *__restrict__ p_new,
+                                                 float *__restrict__ Lw) {
+  curv_Lp_body(g, it, sc, tol, upd_blocks, upd_nb, z, p_old, p_new, Lw, hw_blk());
+}
 
 // per-block <a, b>
-__global__ __launch_bounds__(256) void k_dot(int64_t n, const float *a, const float *b, double *blocks) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void dot_body(int64_t n, const float *a, const float *b, double *blocks, int64_t bid) {
+  const int64_t i = bid * 256 + threadIdx.x;
   const double x = i < n ? (double)a[i] * (double)b[i] : 0.0;
-  block_pair_sum(x, 0.0, blocks, blockIdx.x);
+  block_pair_sum(x, 0.0, blocks, bid);
+}
+__global__ __launch_bounds__(256) void k_dot(int64_t n, const float *a, const float *b, double *blocks) {
+  dot_body(n, a, b, blocks, blockIdx.x);
 }
 
 // trial point ut = u + t x with t = 2^-trial
-__global__ __launch_bounds__(256) void k_ls_point(int64_t n, double *sc, int trial, const float *u, const float *x,
-                                                  float *ut) {
+__device__ __forceinline__ void ls_point_body(int64_t n, double *sc, int trial, const float *u, const float *x,
+                                              float *ut, int64_t bid) {
   if (sc[SC_ACCEPT] != 0.0) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = bid * 256 + threadIdx.x;
   const float t = ldexpf(1.0f, -trial);
   if (i < n) ut[i] = u[i] + t * x[i];
   if (i == 0) sc[SC_TTRY] = (double)t;
 }
-
-// accept: u = ut
-__global__ __launch_bounds__(256) void k_ls_finish(int64_t n, const double *sc, const float *ut, float *u) {
-  if (sc[SC_ACCEPT] == 0.0) return;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i < n) u[i] = ut[i];
+__global__ __launch_bounds__(256) void k_ls_point(int64_t n, double *sc, int trial, const float *u, const float *x,
+                                                  float *ut) {
+  ls_point_body(n, sc, trial, u, x, ut, blockIdx.x);
 }
 
-__global__ void k_report(const double *sc, double CH, double *rep, int *status, int *status_out) {
+// accept: u = ut
+__device__ __forceinline__ void ls_finish_body(int64_t n, const double *sc, const float *ut, float *u, int64_t bid) {
+  if (sc[SC_ACCEPT] == 0.0) return;
+  const int64_t i = bid * 256 + threadIdx.x;
+  if (i < n) u[i] = ut[i];
+}
+__global__ __launch_bounds__(256) void k_ls_finish(int64_t n, const double *sc, const float *ut, float *u) {
+  ls_finish_body(n, sc, ut, u, blockIdx.x);
+}
+
+// copy of a node field (the linearisation point)
+__device__ __forceinline__ void copy_body(int64_t n, const float *src, float *dst, int64_t bid) {
+  const int64_t i = bid * 256 + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__device__ __forceinline__ void report_body(const double *sc, double CH, double *rep, int *status, int *status_out) {
   if (rep) {
     rep[0] = sc[SC_J];
     rep[1] = sc[SC_D];
@@ -214,6 +249,9 @@ __global__ void k_report(const double *sc, double CH, double *rep, int *status, 
   }
   if (sc[SC_ACCEPT] == 0.0) *status |= 4;
   if (status_out) *status_out = *status;
+}
+__global__ void k_report(const double *sc, double CH, double *rep, int *status, int *status_out) {
+  report_body(sc, CH, rep, status, status_out);
 }
 
 __global__ void k_clear_status(int *status) { *status = 0; }

@@ -69,6 +69,13 @@ _SIGS = {
     "disco_profile": ([_P, _I], ctypes.c_int),
     "disco_profile_read": ([_P, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D)], ctypes.c_int),
     "disco_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "disco_batch_create": ([_I, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "disco_batch_destroy": ([_P], None),
+    "disco_batch_prepare": ([_P, _P, _P, _P, _P], ctypes.c_int),
+    "disco_batch_gn_step": ([_P, _P], ctypes.c_int),
+    "disco_batch_set_launch": ([_P, _I, _I], ctypes.c_int),
+    "disco_batch_graph_capture": ([_P, _I], ctypes.c_int),
+    "disco_batch_graph_launch": ([_P, _P], ctypes.c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -280,6 +287,65 @@ class Disco:
         ms = ctypes.c_double()
         _check(_lib.disco_profile_read(self._h, kernel, ctypes.byref(n), ctypes.byref(ms)), "disco_profile_read")
         return n.value, ms.value
+
+
+class Batch:
+    """Several contexts stepped together: one launch per phase of the GN step for all
+    pairs (see disco_batch_* in include/disco.h)."""
+
+    PASS_BRICK, PASS_NODE, PASS_VEC = 0, 1, 2
+
+    def __init__(self, ctxs: Sequence[Disco]):
+        self.ctxs = list(ctxs)
+        self.device = self.ctxs[0].device
+        arr = (_P * len(self.ctxs))(*[c._h for c in self.ctxs])
+        h = ctypes.c_void_p()
+        _check(_lib.disco_batch_create(len(self.ctxs), arr, ctypes.byref(h)), "disco_batch_create")
+        self._h = h
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.disco_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def prepare(self, params: Sequence[Params], us: Sequence[torch.Tensor]):
+        """Fix the per-pair parameters and displacement fields (updated in place by every
+        step).  Returns (report [npairs][16] float64, status [npairs] int32) tensors that
+        every step rewrites."""
+        n = len(self.ctxs)
+        if len(params) != n or len(us) != n:
+            raise ValueError("one Params and one u per pair")
+        for c, u in zip(self.ctxs, us):
+            c._field(u, "u")
+        pa = (_Params * n)(*[p.c() for p in params])
+        ua = (_P * n)(*[u.data_ptr() for u in us])
+        rep = torch.zeros((n, 16), dtype=torch.float64, device=self.device)
+        st = torch.zeros(n, dtype=torch.int32, device=self.device)
+        _check(_lib.disco_batch_prepare(self._h, pa, ua, _ptr(rep), _ptr(st)), "disco_batch_prepare")
+        self._keep = (list(us), rep, st)
+        return rep, st
+
+    def gn_step(self):
+        _check(_lib.disco_batch_gn_step(self._h, self._stream()), "disco_batch_gn_step")
+
+    def set_launch(self, pass_: int, wg_per_cu: int):
+        _check(_lib.disco_batch_set_launch(self._h, pass_, wg_per_cu), "disco_batch_set_launch")
+
+    def graph_capture(self, nsteps: int):
+        _check(_lib.disco_batch_graph_capture(self._h, nsteps), "disco_batch_graph_capture")
+
+    def graph_launch(self):
+        _check(_lib.disco_batch_graph_launch(self._h, self._stream()), "disco_batch_graph_launch")
 
 
 def status_string(code: int) -> str:
