@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--print-source-hash", action="store_true")
+    ap.add_argument("--batched", action="store_true",
+                    help="batched form instead: 24 uneven pyramid-shape pairs, 5 GN iterations (15 PCG each), "
+                         "one launch per phase and one graph, against the same steps pair by pair")
     args = ap.parse_args()
     if args.print_source_hash:
         print(kernel_source_hash())
@@ -114,6 +117,9 @@ def main():
     import torch
     import synth
     from paper_1807_00467_amd import disco
+
+    if args.batched:
+        return bench_batched(args)
 
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -225,6 +231,118 @@ def main():
         out["cpu_baseline"] = cpu_baseline(d, params)
     print(json.dumps(out), flush=True)
     ctx.close()
+
+
+def bench_batched(args):
+    """24 uneven pairs (pyramid shapes 64^2x32 ... 512^2x128 at a fixed field of view),
+    5 GN iterations with 15 PCG products and a device line search (6 trials) each.
+    Timed three ways on the same inputs: pair by pair (gn_pcg_step), batched eager (one
+    launch per phase for all pairs) and one captured graph of all 5 iterations."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1807_00467_amd import autotune, disco
+
+    dev = torch.device("cuda:0")
+    iters, pcg, ls_max = 5, 15, 6
+    cfgs = synth.batch_configs(24)
+    t0 = time.perf_counter()
+    pairs = []
+    for i, c in enumerate(cfgs):
+        pairs.append(synth.make_pair(c))
+        log(f"[bench-batched] pair {i}: {c.shape} ({time.perf_counter() - t0:.1f} s)")
+    log(f"[bench-batched] generated {len(pairs)} pairs in {time.perf_counter() - t0:.1f} s; "
+        f"{sum(int(np.prod(p['shape'])) for p in pairs) / 1e6:.1f} M voxels")
+
+    def contexts():
+        cs = []
+        for d in pairs:
+            c = disco.Disco(d["shape"], d["spacing"], device=dev)
+            c.set_images(torch.from_numpy(d["R"]).to(dev), torch.from_numpy(d["T"]).to(dev))
+            c.set_keypoints(d["kp_x"], d["kp_t"])
+            cs.append(c)
+        return cs
+
+    ctxs = contexts()
+    params = []
+    for c, d in zip(ctxs, pairs):
+        z = torch.zeros((3,) + tuple(c.nodes[::-1]), device=dev)
+        D0 = c.ngf_eval(z, 10.0).item()
+        K0 = c.keypoint_penalty(1.0, z, grad=False, diag=False)["K"].item()
+        params.append(disco.Params(eta=10.0, alpha=1.0, gamma=0.1, delta=D0 / K0, pcg_iters=pcg, ls_max=ls_max,
+                                   flags=disco.FLAG_LS_DEVICE))
+    u0 = [torch.from_numpy(d["u_true"]).to(dev) for d in pairs]
+    us = [u.clone() for u in u0]
+
+    def reset():
+        for u, a in zip(us, u0):
+            u.copy_(a)
+        torch.cuda.synchronize()
+
+    def timed(fn):
+        reset()
+        fn()  # warm-up run
+        reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    def pair_by_pair():
+        for c, p, u in zip(ctxs, params, us):
+            for _ in range(iters):
+                c.gn_pcg_step(p, u)
+
+    ms_seq = timed(pair_by_pair)
+    log(f"[bench-batched] pair by pair: {ms_seq:.2f} ms")
+    cache = os.path.join(os.path.expanduser("~"), ".cache", "paper_1807_00467_amd", "autotune.json")
+    launch = autotune.tune(ctxs, params, u0, cache=cache, log=log)
+    log(f"[bench-batched] launch shape (workgroups per CU: brick, node, vector): {launch}")
+    batch = disco.Batch(ctxs)
+    rep, st = batch.prepare(params, us)
+    autotune.apply(batch, launch)
+
+    def eager():
+        for _ in range(iters):
+            batch.gn_step()
+
+    ms_eager = timed(eager)
+    log(f"[bench-batched] batched eager: {ms_eager:.2f} ms")
+    batch.graph_capture(iters)
+    ms_graph = timed(batch.graph_launch)
+    log(f"[bench-batched] batched graph: {ms_graph:.2f} ms; status {st.cpu().tolist()}")
+    nvox = sum(int(np.prod(d["shape"])) for d in pairs)
+    n_hv = len(pairs) * iters * pcg
+    out = {
+        "metric": "GN Hv products/s, batched form (24 uneven pairs)",
+        "value": n_hv / (ms_graph / 1e3),
+        "unit": "Hv/s",
+        "n_gpus": 1,
+        "steps": iters,
+        "warmup": 1,
+        "ms_per_step": ms_graph / iters,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"24 pairs drawn from 64x64x32, 128x128x64, 256x256x96, 512x512x128 at a "
+                               f"358.4x358.4x320 mm field of view ({nvox / 1e6:.1f} M voxels); per pair "
+                               f"{iters} GN iterations x ({pcg} PCG GN products + device line search, "
+                               f"{ls_max} trials)", "launch": {str(k): v for k, v in launch.items()}},
+        "ms_pair_by_pair": ms_seq,
+        "ms_batched_eager": ms_eager,
+        "ms_batched_graph": ms_graph,
+        "speedup_graph_vs_pair_by_pair": ms_seq / ms_graph,
+        "speedup_eager_vs_pair_by_pair": ms_seq / ms_eager,
+        "gvoxel_steps_per_s": nvox * iters / (ms_graph / 1e3) / 1e9,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    batch.close()
 
 
 if __name__ == "__main__":
