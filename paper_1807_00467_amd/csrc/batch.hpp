@@ -66,7 +66,7 @@ __device__ __forceinline__ int node_gy(const Geo &g) { return (g.py + 3) / 4; }
 // ---- brick passes -------------------------------------------------------------------
 // sel: 0 = linearisation, 1/2 = GN product with p[0]/p[1], 3 = line-search trial
 template <class ST, int MODE, bool NGF, bool VCC, bool KP>
-__global__ __launch_bounds__(kWG, MODE == M_HV ? DISCO_HV_WAVES : 1) void k_b_brick(const PairDesc<ST> *D,
+__global__ __launch_bounds__((brick_threads<MODE, NGF, VCC || KP>()), MODE == M_HV ? DISCO_HV_WAVES : 1) void k_b_brick(const PairDesc<ST> *D,
                                                                                    const int *start, int npairs,
                                                                                    int sel, int acc) {
   const int total = start[npairs];

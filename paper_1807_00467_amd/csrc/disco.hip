@@ -156,22 +156,22 @@ void launch_brick_mode(disco_ctx *c, bool ngf, bool vcc, bool kp, const BrickArg
     launch_brick_mode<ST, MODE>(c, false, vcc, kp, a, s);
     BrickArgs<ST> b = a;
     b.acc = 1;
-    hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(kWG), 0, s, b);
+    hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(brick_threads<MODE, true, false || false>()), 0, s, b);
     return;
   }
   if constexpr (MODE == M_HV) {
     switch (key) {
-      case 7: hipLaunchKernelGGL((k_brick<ST, MODE, true, true, true, kZC>), grid, dim3(kWG), 0, s, a); return;
-      case 6: hipLaunchKernelGGL((k_brick<ST, MODE, true, true, false, kZC>), grid, dim3(kWG), 0, s, a); return;
-      case 5: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, true, kZC>), grid, dim3(kWG), 0, s, a); return;
+      case 7: hipLaunchKernelGGL((k_brick<ST, MODE, true, true, true, kZC>), grid, dim3(brick_threads<MODE, true, true || true>()), 0, s, a); return;
+      case 6: hipLaunchKernelGGL((k_brick<ST, MODE, true, true, false, kZC>), grid, dim3(brick_threads<MODE, true, true || false>()), 0, s, a); return;
+      case 5: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, true, kZC>), grid, dim3(brick_threads<MODE, true, false || true>()), 0, s, a); return;
       default: break;
     }
   }
   switch (key) {
-    case 4: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(kWG), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_brick<ST, MODE, false, true, true, kZC>), grid, dim3(kWG), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_brick<ST, MODE, false, true, false, kZC>), grid, dim3(kWG), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_brick<ST, MODE, false, false, true, kZC>), grid, dim3(kWG), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(brick_threads<MODE, true, false || false>()), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_brick<ST, MODE, false, true, true, kZC>), grid, dim3(brick_threads<MODE, false, true || true>()), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_brick<ST, MODE, false, true, false, kZC>), grid, dim3(brick_threads<MODE, false, true || false>()), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_brick<ST, MODE, false, false, true, kZC>), grid, dim3(brick_threads<MODE, false, false || true>()), 0, s, a); break;
     default: break;
   }
 }
@@ -1187,19 +1187,19 @@ static void launch_b_brick(disco_batch *b, unsigned grid, const int *st, int n, 
   const PairDesc<ST> *D = reinterpret_cast<const PairDesc<ST> *>(b->desc);
   const int key = (b->vcc ? 2 : 0) | (b->kp ? 1 : 0);
   if constexpr (NGF && MODE != M_HV) {
-    hipLaunchKernelGGL((k_b_brick<ST, MODE, true, false, false>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc);
+    hipLaunchKernelGGL((k_b_brick<ST, MODE, true, false, false>), dim3(grid), dim3(brick_threads<MODE, true, false || false>()), 0, s, D, st, n, sel, acc);
   } else if constexpr (NGF) {
     switch (key) {
-      case 3: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, true, true>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
-      case 2: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, true, false>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
-      case 1: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, false, true>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
-      default: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, false, false>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
+      case 3: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, true, true>), dim3(grid), dim3(brick_threads<MODE, true, true || true>()), 0, s, D, st, n, sel, acc); break;
+      case 2: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, true, false>), dim3(grid), dim3(brick_threads<MODE, true, true || false>()), 0, s, D, st, n, sel, acc); break;
+      case 1: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, false, true>), dim3(grid), dim3(brick_threads<MODE, true, false || true>()), 0, s, D, st, n, sel, acc); break;
+      default: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, false, false>), dim3(grid), dim3(brick_threads<MODE, true, false || false>()), 0, s, D, st, n, sel, acc); break;
     }
   } else {
     switch (key) {
-      case 3: hipLaunchKernelGGL((k_b_brick<ST, MODE, false, true, true>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
-      case 2: hipLaunchKernelGGL((k_b_brick<ST, MODE, false, true, false>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
-      case 1: hipLaunchKernelGGL((k_b_brick<ST, MODE, false, false, true>), dim3(grid), dim3(kWG), 0, s, D, st, n, sel, acc); break;
+      case 3: hipLaunchKernelGGL((k_b_brick<ST, MODE, false, true, true>), dim3(grid), dim3(brick_threads<MODE, false, true || true>()), 0, s, D, st, n, sel, acc); break;
+      case 2: hipLaunchKernelGGL((k_b_brick<ST, MODE, false, true, false>), dim3(grid), dim3(brick_threads<MODE, false, true || false>()), 0, s, D, st, n, sel, acc); break;
+      case 1: hipLaunchKernelGGL((k_b_brick<ST, MODE, false, false, true>), dim3(grid), dim3(brick_threads<MODE, false, false || true>()), 0, s, D, st, n, sel, acc); break;
       default: break;
     }
   }

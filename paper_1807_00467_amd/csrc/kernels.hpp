@@ -23,6 +23,19 @@
 namespace disco {
 
 constexpr int kWG = 256;   // threads of a brick workgroup (4 waves)
+
+// The GN product pass with cell terms runs workgroups of 4 + kCellWaves waves: waves 0-3
+// stream the voxels (NGF, memory-bound), the others compute the cell terms of the brick's
+// layers (volume change, keypoints; VALU-bound), so that the SIMDs hold waves of both
+// kinds and the two overlap.  All other passes use 4 waves that do both in turn.
+#ifndef DISCO_CELL_WAVES
+#define DISCO_CELL_WAVES 4
+#endif
+constexpr int kCellWaves = DISCO_CELL_WAVES;  // cell-term waves per GN product workgroup
+template <int MODE, bool NGF, bool CELLT>
+__host__ __device__ constexpr int brick_threads() {
+  return (MODE == 2 && NGF && CELLT) ? 64 * (4 + kCellWaves) : 256;
+}
 constexpr int kBXC = 16;   // cells per brick along x (64 voxels = one wave)
 constexpr int kBYC = 4;    // cells per brick along y (one wave per cell row)
 constexpr int kNBOX = (kBXC + 1) * (kBYC + 1);  // nodes of one brick plane (17 x 5)
@@ -938,7 +951,11 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
 
   if (A.stop && *A.stop != 0.0) return;
   const Geo &g = A.g;
+  constexpr int WGS = brick_threads<MODE, NGF, CELLT>();
+  constexpr bool SPLIT = WGS != 256;
+  constexpr int NCW = SPLIT ? kCellWaves : 4;  // waves that take cell layers
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cw = SPLIT ? wave - 4 : wave;  // index among the waves that compute cell terms
   const int q = lane & 3, xq = lane >> 2;
   const int bx = B.x, by = B.y, bz = B.z;
   const int ix = bx * 64 + lane;
@@ -1162,7 +1179,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
     // do not add to the rolling NGF state: wave w takes cell layers w, w + 4, ..., one cell
     // per lane
     if (CELLT) {
-      for (int zl = wave; zl < cz1 - cz0; zl += 4) {
+      for (int zl = cw; zl < cz1 - cz0; zl += NCW) {
         const int czi = cz0 + zl;
         const int lx = lane & 15, ly = lane >> 4;
         const int ccx = bx * kBXC + lx, ccy = by * kBYC + ly;
@@ -1220,7 +1237,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
 
     // HV keypoint cells (rare) in a pass of their own, adding to the volume-change result
     if constexpr (MODE == M_HV && KP) {
-      for (int zl = wave; zl < cz1 - cz0; zl += 4) {
+      for (int zl = cw; zl < cz1 - cz0; zl += NCW) {
         const int czi = cz0 + zl;
         const int ccx = bx * kBXC + (lane & 15), ccy = by * kBYC + (lane >> 4);
         if (ccx < g.cx && ccy < g.cy) {
@@ -1247,8 +1264,15 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
 
   };
 
-  ngf_phase();
-  cell_phase();
+  if constexpr (SPLIT) {
+    if (wave < 4)
+      ngf_phase();
+    else
+      cell_phase();
+  } else {
+    ngf_phase();
+    cell_phase();
+  }
 
   if constexpr (F > 0) {
     const int nl = cz1 - cz0;  // cell layers of this brick
@@ -1256,7 +1280,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
     // combine in a fixed order and write every node plane of the brick: interior nodes
     // directly, brick-face nodes to the partial buffer
     const int total = (nl + 1) * F * 3 * kNBOX;
-    for (int e = threadIdx.x; e < total; e += kWG) {
+    for (int e = threadIdx.x; e < total; e += WGS) {
       const int xl = e % 17, yl = (e / 17) % 5, fc = (e / kNBOX) % (F * 3), zl = e / (kNBOX * F * 3);
       float val = 0.0f;
       if (NGF_OUT) {
@@ -1318,7 +1342,8 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
 }
 
 template <class ST, int MODE, bool NGF, bool VCC, bool KP, int ZC>
-__global__ __launch_bounds__(kWG, MODE == M_HV ? DISCO_HV_WAVES : 1) void k_brick(BrickArgs<ST> A) {
+__global__ __launch_bounds__((brick_threads<MODE, NGF, VCC || KP>()), MODE == M_HV ? DISCO_HV_WAVES : 1) void k_brick(
+    BrickArgs<ST> A) {
   brick_body<ST, MODE, NGF, VCC, KP, ZC>(A, hw_blk(), A.acc);
 }
 
