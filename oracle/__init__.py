@@ -404,3 +404,102 @@ def gn_pcg_step(prob: Problem, u, params: StepParams = StepParams()):
                gnorm=float(np.sqrt(np.sum(g * g))), t=t if accepted else 0.0, accepted=accepted,
                p=p, gtp=gtp, pcg=info, trial=trial, g=g, diag=lin["diag"])
     return u_new, rep
+
+
+# ------------------------------------------------------------------------------------
+# L-BFGS (Sec. II-D3): limited memory m, initial inverse Hessian H0^-1 with
+# H0 = alpha C_H L^T L + tau I (the Hessian of the curvature term plus tau I)
+# ------------------------------------------------------------------------------------
+
+def h0_apply(prob: Problem, v, tau: float):
+    """H0 v = alpha C_H L^T L v + tau v (node field)."""
+    v = _f64(v)
+    return prob.w.alpha * curvature(v, prob.H)["g"] + tau * v
+
+
+def h0_solve(prob: Problem, q, tau: float, rtol: float = 1e-12):
+    """H0^-1 q for the symmetric positive definite H0 (tau > 0), by conjugate gradients
+    (scipy) run to a relative residual of rtol, i.e. exactly up to rounding."""
+    from scipy.sparse.linalg import LinearOperator, cg
+    q = _f64(q)
+    n = q.size
+    A = LinearOperator((n, n), matvec=lambda x: h0_apply(prob, x.reshape(q.shape), tau).ravel(), dtype=np.float64)
+    x, info = cg(A, q.ravel(), rtol=rtol, atol=0.0, maxiter=20 * n)
+    if info != 0:
+        raise RuntimeError("H0 solve did not converge")
+    return x.reshape(q.shape)
+
+
+def lbfgs_direction(g, S, Y, h0inv):
+    """Two-loop recursion: returns -H_k g, where H_k is the inverse Hessian approximation
+    obtained from h0inv (a function applying H0^-1) by BFGS updates with the pairs (S[i],
+    Y[i]), oldest first.  Pairs with s.y <= 0 carry rho = 0 and change nothing."""
+    q = _f64(g).copy()
+    rho = [1.0 / float(np.sum(s * y)) if float(np.sum(s * y)) > 0.0 else 0.0 for s, y in zip(S, Y)]
+    alpha = [0.0] * len(S)
+    for i in reversed(range(len(S))):
+        alpha[i] = rho[i] * float(np.sum(S[i] * q))
+        q = q - alpha[i] * Y[i]
+    r = h0inv(q)
+    for i in range(len(S)):
+        beta = rho[i] * float(np.sum(Y[i] * r))
+        r = r + (alpha[i] - beta) * S[i]
+    return -r
+
+
+@dataclasses.dataclass
+class LbfgsParams:
+    m: int = 5                # history length
+    tau: float = 10.0         # H0 = alpha C_H L^T L + tau I
+    ls_max: int = 10
+    armijo_c1: float = 1e-4
+    curv_eps: float = 1e-10   # pair stored only if s.y > curv_eps |s| |y|
+
+
+def lbfgs_run(prob, u0, iters: int, params: LbfgsParams = LbfgsParams(), fg=None, f=None, h0inv=None):
+    """L-BFGS iterations from u0 with Armijo backtracking on t in {1, 1/2, ...} (trial
+    points with J = +inf rejected).  fg(u) -> (J, g), f(u) -> J and h0inv(q) default to the
+    registration objective of eq. 11 of `prob` and the exact H0 solve.  A pair (s, y) with
+    s.y <= curv_eps |s||y| is stored as zeros (rho = 0), so the history still advances.
+    Returns (u, per-iteration reports)."""
+    if fg is None:
+        def fg(u):
+            lin = prob.linearise(u)
+            return lin["J"], lin["g"]
+    if f is None:
+        def f(u):
+            return prob.objective(u)["J"]
+    if h0inv is None:
+        def h0inv(q):
+            return h0_solve(prob, q, params.tau)
+    u = _f64(u0).copy()
+    J, g = fg(u)
+    S, Y = [], []
+    reps = []
+    for _ in range(iters):
+        p = lbfgs_direction(g, S, Y, h0inv)
+        gtp = float(np.sum(g * p))
+        t, accepted, Jt = 1.0, False, np.inf
+        for _ in range(params.ls_max):
+            Jt = f(u + t * p)
+            if np.isfinite(Jt) and Jt <= J + params.armijo_c1 * t * gtp:
+                accepted = True
+                break
+            t *= 0.5
+        reps.append(dict(J=J, gnorm=float(np.sqrt(np.sum(g * g))), gtp=gtp, t=t if accepted else 0.0,
+                         accepted=accepted, J_new=Jt, p=p))
+        if not accepted:
+            break
+        u_new = u + t * p
+        J_new, g_new = fg(u_new)
+        s, y = u_new - u, g_new - g
+        sy = float(np.sum(s * y))
+        if sy <= params.curv_eps * float(np.linalg.norm(s) * np.linalg.norm(y)):
+            s, y = s * 0.0, y * 0.0
+        S.append(s)
+        Y.append(y)
+        if len(S) > params.m:
+            S.pop(0)
+            Y.pop(0)
+        u, J, g = u_new, J_new, g_new
+    return u, reps

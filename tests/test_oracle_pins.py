@@ -597,3 +597,89 @@ def test_ngf_grad_T_matches_finite_differences_in_T():
             fd = (D_of(Tp) - D_of(Tm)) / (2 * eps)
             best = min(best, abs(fd - dT[idx]) / max(abs(dT[idx]), 1e-3 * scale))
         assert best < 1e-5, (idx, best)
+
+
+# ---------------------------------------------------------------------------------
+# L-BFGS (Sec. II-D3)
+# ---------------------------------------------------------------------------------
+
+def _spd(r, n, lo=0.5):
+    Q, _ = np.linalg.qr(r.standard_normal((n, n)))
+    return Q @ np.diag(lo + r.random(n) * 3.0) @ Q.T
+
+
+def test_lbfgs_two_loop_equals_dense_bfgs_update():
+    """The two-loop recursion applies the inverse BFGS matrix built by the explicit
+    update H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T from H0^-1, oldest pair first."""
+    r = rng(40)
+    n = 12
+    H0 = _spd(r, n)
+    B = _spd(r, n)
+    S = [r.standard_normal(n) for _ in range(4)]
+    Y = [B @ s + 0.05 * r.standard_normal(n) for s in S]
+    assert all(float(s @ y) > 0 for s, y in zip(S, Y))
+    Hinv = np.linalg.inv(H0)
+    for s, y in zip(S, Y):
+        rho = 1.0 / float(s @ y)
+        V = np.eye(n) - rho * np.outer(y, s)
+        Hinv = V.T @ Hinv @ V + rho * np.outer(s, s)
+    g = r.standard_normal(n)
+    p = oracle.lbfgs_direction(g, S, Y, lambda q: np.linalg.solve(H0, q))
+    assert np.allclose(p, -Hinv @ g, rtol=1e-10, atol=1e-12)
+    # the secant condition of the newest pair: H_k y = s
+    p_y = oracle.lbfgs_direction(-Y[-1], S, Y, lambda q: np.linalg.solve(H0, q))
+    assert np.allclose(p_y, S[-1], rtol=1e-9, atol=1e-11)
+
+
+def test_lbfgs_without_history_is_preconditioned_gradient():
+    r = rng(41)
+    H0 = _spd(r, 9)
+    g = r.standard_normal(9)
+    p = oracle.lbfgs_direction(g, [], [], lambda q: np.linalg.solve(H0, q))
+    assert np.allclose(p, -np.linalg.solve(H0, g), rtol=1e-12)
+
+
+def test_lbfgs_minimises_a_quadratic():
+    r = rng(42)
+    n = 30
+    A = _spd(r, n, lo=0.2)
+    b = r.standard_normal(n)
+    x_star = np.linalg.solve(A, b)
+    fg = lambda u: (0.5 * u @ A @ u - b @ u, A @ u - b)
+    f = lambda u: 0.5 * u @ A @ u - b @ u
+    u, reps = oracle.lbfgs_run(None, np.zeros(n), 80, oracle.LbfgsParams(m=5, ls_max=30), fg=fg, f=f,
+                               h0inv=lambda q: q)
+    assert np.linalg.norm(u - x_star) <= 1e-8 * np.linalg.norm(x_star)
+    Js = [rep["J"] for rep in reps]
+    assert all(b_ <= a_ + 1e-14 for a_, b_ in zip(Js, Js[1:]))
+
+
+def test_h0_solve_matches_dense_solve():
+    """H0 = alpha C_H L^T L + tau I on a small node grid: symmetric, eigenvalues >= tau,
+    and the solve equals numpy's dense solve."""
+    d = small_case(9, shape=(12, 8, 8))
+    P = oracle.Problem(d["R"], d["T"], d["spacing"], weights=oracle.Weights(alpha=1.7))
+    shape = (3,) + tuple(P.nodes[::-1])
+    n = int(np.prod(shape))
+    cols = []
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = 1.0
+        cols.append(oracle.h0_apply(P, e.reshape(shape), 10.0).ravel())
+    A = np.array(cols).T
+    assert np.allclose(A, A.T, atol=1e-9 * np.abs(A).max())
+    assert np.linalg.eigvalsh(A).min() >= 10.0 - 1e-8
+    q = rng(43).standard_normal(shape)
+    x = oracle.h0_solve(P, q, 10.0)
+    assert np.allclose(x.ravel(), np.linalg.solve(A, q.ravel()), rtol=1e-9, atol=1e-12)
+
+
+def test_lbfgs_registration_decreases_objective():
+    d = small_case(10, shape=(16, 12, 12))
+    P = oracle.Problem(d["R"], d["T"], d["spacing"], d["kp_x"], d["kp_t"], oracle.Weights(eta=10.0, alpha=1.0,
+                                                                                           gamma=0.1))
+    P.w.delta = P.adaptive_delta(np.zeros_like(d["u_true"], np.float64))
+    u, reps = oracle.lbfgs_run(P, np.zeros_like(d["u_true"], np.float64), 4)
+    assert len(reps) == 4 and all(rep["accepted"] for rep in reps)
+    Js = [rep["J"] for rep in reps] + [reps[-1]["J_new"]]
+    assert all(b_ < a_ for a_, b_ in zip(Js, Js[1:]))
