@@ -104,6 +104,15 @@ typedef struct {
     int32_t flags;     /* DISCO_FLAG_* */
 } disco_params;
 
+/* L-BFGS settings (Sec. II-D3) */
+typedef struct {
+    double tau;       /* H0 = alpha C_H L^T L + tau I, > 0 */
+    double curv_eps;  /* a pair (s, y) is used only if s^T y > curv_eps |s| |y|, >= 0 */
+    double h0_tol;    /* stop the H0 solve at |r| <= h0_tol |q| (0: run h0_iters), >= 0 */
+    int32_t m;        /* history length, 1..8 */
+    int32_t h0_iters; /* CG iterations of the H0 solve, >= 1 */
+} disco_lbfgs;
+
 typedef struct disco_ctx disco_ctx;
 typedef void *disco_stream; /* hipStream_t */
 
@@ -187,6 +196,27 @@ int gn_hessvec(disco_ctx *ctx, const disco_params *p, const float *v, float *Hv,
    trial; with it the call never synchronises and can be graph captured. */
 int gn_pcg_step(disco_ctx *ctx, const disco_params *p, float *u_inout, double *report_dev, int32_t *status_dev,
                 disco_stream stream);
+
+/* One L-BFGS iteration on J of eq. 11 from u (updated in place), Sec. II-D3: J and
+   grad J at u; if the previous call of this context made a step, the pair
+   s = u - u_old, y = grad J(u) - grad J(u_old) joins a history of the last lb->m pairs
+   (a pair failing s^T y > curv_eps |s||y| is kept with rho = 0, i.e. it changes nothing);
+   the two-loop recursion gives p = -H g, with the initial inverse H0^{-1} applied by
+   Jacobi-PCG on H0 = alpha C_H L^T L + tau I (x0 = 0, h0_iters iterations or
+   |r| <= h0_tol |q|); then the Armijo line search of gn_pcg_step along p.  The report
+   has the layout of gn_pcg_step's, with the H0 solve in the CG slots.  Only the
+   weights, eta, armijo_c1, ls_max and flags of p are used.  The history buffers
+   (2 m vectors of 3 (Nx/4+1)(Ny/4+1)(Nz/4+1) floats) are allocated on the first call and
+   when m changes (which also clears the history; the call then synchronises the
+   stream).  u must be the field returned by the previous call for the history to
+   describe the iteration; lbfgs_reset starts a new one.  The history position is host
+   state, so a graph-captured call would replay one fixed position: capture is not
+   supported. */
+int lbfgs_step(disco_ctx *ctx, const disco_params *p, const disco_lbfgs *lb, float *u_inout, double *report_dev,
+               int32_t *status_dev, disco_stream stream);
+
+/* Forget the L-BFGS history of the context (the next lbfgs_step starts from H0). */
+int lbfgs_reset(disco_ctx *ctx);
 
 /* Copy a derived buffer (DISCO_BUF_*) to dst, converted to float32 [Nz][Ny][Nx][3]. */
 int disco_copy_buffer(disco_ctx *ctx, int32_t which, float *dst, disco_stream stream);

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_b_vec(const PairDesc<ST> *D, const int 
     if (op == 0)
       copy_body(P.n3, P.u, P.u_lin, bid);
     else if (op == 1)
-      pcg_init_body(P.n3, P.grad, P.diag, P.sc, P.tau, P.x, P.r, P.z, P.p[0], P.invM, P.blk_node, bid);
+      pcg_init_body(P.n3, P.grad, P.diag, P.sc, P.tau, -1.0f, P.x, P.r, P.z, P.p[0], P.invM, P.blk_node, bid);
     else if (op == 2)
       dot_body(P.n3, P.grad, P.x, P.blk_node, bid);
     else if (op == 3)

@@ -56,6 +56,12 @@ struct disco_ctx {
   double *blk_brick = nullptr, *blk_node = nullptr, *sc = nullptr;
   double *blk_curv = nullptr, *blk_upd = nullptr;
   float *adjW = nullptr;  // dD/d(grad T) accumulator of ngf_grad_T, [N][3] (allocated on first use)
+  // L-BFGS history (allocated on first use): a ring of lb_m pairs (s, y)
+  float *lbS = nullptr, *lbY = nullptr;  // [lb_m][3][nodes]
+  int lb_m = 0;
+  int lb_count = 0;      // complete pairs in the ring
+  int lb_next = 0;       // slot of the next pair
+  bool lb_pending = false;  // the last step started a pair in slot lb_next
   int *status = nullptr;
   double *host_sc = nullptr;  // pinned
   // keypoints
@@ -458,7 +464,8 @@ void disco_destroy(disco_ctx *c) {
   clear_profile(c);
   void *ptrs[] = {c->gR,  c->gT,  c->scache, c->u_lin, c->u_ref, c->Lw,   c->vg,   c->vdiag, c->vx,   c->vr,
                   c->vz,  c->vp,  c->vq,     c->vut,   c->tmp0,  c->tmp1, c->part, c->blk_brick, c->blk_node,
-                  c->sc,  c->status, c->kloc, c->ktgt, c->kstart, c->blk_curv, c->blk_upd, c->adjW, c->vp2, c->vinvm};
+                  c->sc,  c->status, c->kloc, c->ktgt, c->kstart, c->blk_curv, c->blk_upd, c->adjW, c->vp2, c->vinvm,
+                  c->lbS, c->lbY};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->host_sc) (void)hipHostFree(c->host_sc);
@@ -535,8 +542,9 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
   for (float **p : nodebufs) alloc(reinterpret_cast<void **>(p), nf);
   alloc(reinterpret_cast<void **>(&c->part), sizeof(float) * (size_t)c->nwg * (kZC + 1) * 6 * kNBOX);
   alloc(reinterpret_cast<void **>(&c->blk_brick), sizeof(double) * (size_t)c->nwg * BS_N);
-  // node-parallel reductions: 3 values per block over nnodes, or 2 per block over 3 nnodes
-  alloc(reinterpret_cast<void **>(&c->blk_node), sizeof(double) * ((size_t)c->nodeblocks * 6 + 16));
+  // node-parallel reductions: 3 values per block over nnodes, or 3 per 256 elements of 3 nnodes
+  alloc(reinterpret_cast<void **>(&c->blk_node),
+        sizeof(double) * ((size_t)std::max<int64_t>(c->nodeblocks * 6, 3 * (int64_t)nblk(3 * g.nnodes)) + 16));
   alloc(reinterpret_cast<void **>(&c->sc), sizeof(double) * SC_COUNT);
   alloc(reinterpret_cast<void **>(&c->status), sizeof(int));
   alloc(reinterpret_cast<void **>(&c->blk_curv), sizeof(double) * (size_t)c->nodeblocks);
@@ -868,6 +876,208 @@ int gn_hessvec(disco_ctx *c, const disco_params *p, const float *v, float *Hv, d
   return DISCO_OK;
 }
 
+// linearisation of a step at u: J and its parts (device scalars), grad J (vg), diag of
+// the GN matrix (vdiag), s cache; u_lin = u
+static int linearise(disco_ctx *c, const disco_params *p, const float *u, const PostArgs &pa, hipStream_t s) {
+  const bool vcc = p->gamma != 0.0;
+  const bool kp = p->delta != 0.0 && c->nkp > 0;
+  const bool curv = p->alpha != 0.0;
+  const float eta2 = (float)(p->eta * p->eta);
+  double *sc = c->sc;
+  set_s_scale(c, p->eta);
+  launch_curv_L(c, u, c->u_ref, c->Lw, true, nullptr, s);
+  BrickCall b{M_GRAD, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, u, nullptr, c->vg, c->vdiag, nullptr};
+  launch_brick(c, b, s);
+  launch_gather(c, 2, 2, c->vg, c->vdiag, curv ? c->Lw : nullptr, (float)(p->alpha * ch_of(c)), curv ? 1 : 0, nullptr,
+                0.f, nullptr, true, nullptr, s);
+  // D, V, K, folds; sum (L(u - uhat))^2; max diag, |g|^2 -> J
+  launch_finish(POST_LIN_BRICK, pa, nullptr, s, src_brick(c, sc + SC_TMP0), src_curv(c, sc + SC_SRAW),
+                src_gather(c, sc + SC_DOT));
+  HIP_TRY(hipMemcpyAsync(c->u_lin, u, sizeof(float) * 3 * c->g.nnodes, hipMemcpyDeviceToDevice, s));
+  c->lin = true;
+  c->lin_eta = p->eta;
+  return DISCO_OK;
+}
+
+// Armijo backtracking along vx from u (t = 1, 1/2, ...); before u is replaced, `pre`
+// runs (it may read u, vut and the acceptance flag); then the report
+extern "C++" {
+template <class Pre>
+static int line_search(disco_ctx *c, const disco_params *p, float *u, const PostArgs &pa, double *report_dev,
+                       int32_t *status_dev, hipStream_t s, Pre pre) {
+  const Geo &g = c->g;
+  const int64_t n3 = 3 * g.nnodes;
+  const unsigned nb3 = nblk(n3);
+  double *sc = c->sc;
+  const bool vcc = p->gamma != 0.0;
+  const bool kp = p->delta != 0.0 && c->nkp > 0;
+  const float eta2 = (float)(p->eta * p->eta);
+  hipLaunchKernelGGL(k_dot, dim3(nb3), dim3(256), 0, s, n3, c->vg, c->vx, c->blk_node);
+  launch_finish(POST_LS_BEGIN, pa, nullptr, s, src_pairs(c->blk_node, nb3, 1, sc + SC_TMP0),
+                src_pairs(c->blk_upd, upd_blocks(g), 2, sc + SC_TMP1));
+  const double *acc = sc + SC_ACCEPT;
+  const bool dev_ls = (p->flags & DISCO_FLAG_LS_DEVICE) != 0;
+  for (int t = 0; t < p->ls_max; ++t) {
+    hipLaunchKernelGGL(k_ls_point, dim3(nb3), dim3(256), 0, s, n3, sc, t, u, c->vx, c->vut);
+    launch_curv_L(c, c->vut, c->u_ref, c->Lw, true, acc, s);
+    BrickCall b{M_EVAL, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, c->vut, nullptr, nullptr, nullptr, acc};
+    launch_brick(c, b, s);
+    launch_finish(POST_LS_BRICK, pa, acc, s, src_brick(c, sc + SC_TMP0), src_curv(c, sc + SC_TSRAW));
+    if (!dev_ls) {
+      HIP_TRY(hipMemcpyAsync(c->host_sc, sc + SC_ACCEPT, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (c->host_sc[0] != 0.0) break;
+    }
+  }
+  pre();
+  hipLaunchKernelGGL(k_ls_finish, dim3(nb3), dim3(256), 0, s, n3, sc, c->vut, u);
+  hipLaunchKernelGGL(k_report, dim3(1), dim3(1), 0, s, sc, ch_of(c), report_dev, c->status, status_dev);
+  return DISCO_OK;
+}
+}  // extern "C++"
+
+static int check_lbfgs(const disco_lbfgs *lb) {
+  if (!lb) return DISCO_ERR_ARG;
+  if (lb->m < 1 || lb->m > kLbfgsMax || lb->h0_iters < 1) return DISCO_ERR_ARG;
+  if (!std::isfinite(lb->tau) || !(lb->tau > 0.0) || !finite_nonneg(lb->curv_eps) || !finite_nonneg(lb->h0_tol))
+    return DISCO_ERR_NONFINITE;
+  return DISCO_OK;
+}
+
+int lbfgs_reset(disco_ctx *c) {
+  if (!c) return DISCO_ERR_ARG;
+  c->lb_count = 0;
+  c->lb_next = 0;
+  c->lb_pending = false;
+  return DISCO_OK;
+}
+
+int lbfgs_step(disco_ctx *c, const disco_params *p, const disco_lbfgs *lb, float *u, double *report_dev,
+               int32_t *status_dev, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_params(p)) || (e = check_lbfgs(lb))) return e;
+  if ((e = check_field(u))) return e;
+  if ((report_dev && ((reinterpret_cast<uintptr_t>(report_dev) & 7u) != 0)) ||
+      (status_dev && !aligned4(status_dev)))
+    return DISCO_ERR_SHAPE;
+  if (!c->images) return DISCO_ERR_STATE;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  const Geo &g = c->g;
+  const int64_t n3 = 3 * g.nnodes;
+  const unsigned nb3 = nblk(n3);
+  double *sc = c->sc;
+  if (c->lb_m != lb->m) {
+    // new history length: fresh history in new buffers
+    HIP_TRY(hipStreamSynchronize(s));
+    if (c->lbS) (void)hipFree(c->lbS);
+    if (c->lbY) (void)hipFree(c->lbY);
+    c->lbS = c->lbY = nullptr;
+    c->lb_m = 0;
+    lbfgs_reset(c);
+    const size_t bytes = sizeof(float) * (size_t)lb->m * (size_t)n3;
+    if (hipMalloc(reinterpret_cast<void **>(&c->lbS), bytes) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&c->lbY), bytes) != hipSuccess) {
+      if (c->lbS) (void)hipFree(c->lbS);
+      c->lbS = c->lbY = nullptr;
+      return DISCO_ERR_NOMEM;
+    }
+    c->lb_m = lb->m;
+  }
+  const int m = c->lb_m;
+  auto Sv = [&](int k) { return c->lbS + (size_t)k * n3; };
+  auto Yv = [&](int k) { return c->lbY + (size_t)k * n3; };
+  const bool curv = p->alpha != 0.0;
+  PostArgs pa = post_args(c, p->alpha, p->gamma, p->delta);
+  pa.c1 = p->armijo_c1;
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, c->status);
+
+  // ---- J and grad J at u --------------------------------------------------------------
+  if ((e = linearise(c, p, u, pa, s))) return e;
+
+  // ---- complete the pair of the previous step: y = g - g_old, rho ---------------------
+  if (c->lb_pending) {
+    const int k = c->lb_next;
+    hipLaunchKernelGGL(k_lb_pair, dim3(nb3), dim3(256), 0, s, n3, Sv(k), Yv(k), c->vg, c->blk_node);
+    PostArgs pp = pa;
+    pp.idx = k;
+    pp.tol = lb->curv_eps;
+    launch_finish(POST_LB_PAIR, pp, nullptr, s, RedSrc{c->blk_node, (int64_t)nb3, 3, 3, 0u, sc + SC_TMP0});
+    c->lb_count = std::min(c->lb_count + 1, m);
+    c->lb_next = (k + 1) % m;
+    c->lb_pending = false;
+  }
+  const int cnt = c->lb_count;
+  auto slot = [&](int age) { return ((c->lb_next - 1 - age) % m + m) % m; };  // age 0 = newest
+
+  // ---- first loop, newest to oldest: alpha_i = rho_i s_i.q, q -= alpha_i y_i ---------
+  const float *q = c->vg;
+  if (cnt > 0) {
+    hipLaunchKernelGGL(k_dot, dim3(nb3), dim3(256), 0, s, n3, Sv(slot(0)), c->vg, c->blk_node);
+    for (int age = 0; age < cnt; ++age) {
+      const int k = slot(age);
+      PostArgs pp = pa;
+      pp.idx = k;
+      launch_finish(POST_LB_ALPHA, pp, nullptr, s, src_pairs(c->blk_node, nb3, 1, sc + SC_TMP0));
+      const bool more = age + 1 < cnt;
+      hipLaunchKernelGGL(k_lb_axpy, dim3(nb3), dim3(256), 0, s, n3, 1.0f, q, Yv(k), c->tmp1, sc, 0.0,
+                         SC_LB_ALPHA + k, -1.0, -1, 0, 0.0, more ? Sv(slot(age + 1)) : nullptr,
+                         more ? c->blk_node : nullptr);
+      q = c->tmp1;
+    }
+  }
+
+  // ---- x = -H0^{-1} q by Jacobi-PCG, H0 = alpha C_H L^T L + tau I -----------------------
+  // diagonal of alpha C_H L^T L (the tau part is added by the CG start)
+  launch_gather(c, 0, 2, c->tmp0, c->vdiag, curv ? c->Lw : nullptr, (float)(p->alpha * ch_of(c)), curv ? 1 : 0,
+                nullptr, 0.f, nullptr, false, nullptr, s);
+  hipLaunchKernelGGL(k_pcg_init, dim3(nb3), dim3(256), 0, s, n3, q, c->vdiag, sc, (float)lb->tau, -1.0f, c->vx, c->vr,
+                     c->vz, c->vp, c->vinvm, c->blk_node);
+  launch_finish(POST_PCG_START, pa, nullptr, s, src_pairs(c->blk_node, nb3, 2, sc + SC_TMP0));
+  {
+    const double *stop = sc + SC_STOP;
+    const int64_t nbu = upd_blocks(g);
+    float *P[2] = {c->vp, c->vp2};
+    for (int it = 0; it < lb->h0_iters; ++it) {
+      float *pv = P[it & 1];
+      if (it == 0) {
+        if (curv) launch_curv_L(c, pv, nullptr, c->Lw, false, stop, s);
+      } else {
+        hipLaunchKernelGGL(k_curv_Lp, lp_grid(g), dim3(256), 0, s, g, it, sc, lb->h0_tol, c->blk_upd, nbu, c->vz,
+                           P[(it - 1) & 1], pv, c->Lw);
+      }
+      launch_gather(c, 0, 1, c->vq, nullptr, curv ? c->Lw : nullptr, (float)(p->alpha * ch_of(c)), 0, pv,
+                    (float)lb->tau, pv, true, stop, s);
+      hipLaunchKernelGGL(k_pcg_update, dim3((unsigned)nbu), dim3(256), 0, s, n3, sc, it, c->blk_node, c->nodeblocks,
+                         c->vinvm, pv, c->vq, c->vx, c->vr, c->vz, c->blk_upd, c->status);
+    }
+  }
+
+  // ---- second loop, oldest to newest on x = -r: x += (-alpha_i - rho_i y_i.x) s_i -------
+  if (cnt > 0) {
+    hipLaunchKernelGGL(k_dot, dim3(nb3), dim3(256), 0, s, n3, Yv(slot(cnt - 1)), c->vx, c->blk_node);
+    for (int age = cnt - 1; age >= 0; --age) {
+      const int k = slot(age);
+      launch_finish(POST_STORE, pa, nullptr, s, src_pairs(c->blk_node, nb3, 1, sc + SC_LB_DOT));
+      const bool more = age > 0;
+      hipLaunchKernelGGL(k_lb_axpy, dim3(nb3), dim3(256), 0, s, n3, 1.0f, c->vx, Sv(k), c->vx, sc, 0.0,
+                         SC_LB_ALPHA + k, -1.0, SC_LB_RHO + k, SC_LB_DOT, -1.0, more ? Yv(slot(age - 1)) : nullptr,
+                         more ? c->blk_node : nullptr);
+    }
+  }
+
+  // ---- Armijo line search along x; the accepted step starts the next pair --------------
+  float *Snext = Sv(c->lb_next), *Ynext = Yv(c->lb_next);
+  if ((e = line_search(c, p, u, pa, report_dev, status_dev, s, [&] {
+         hipLaunchKernelGGL(k_lb_save, dim3(nb3), dim3(256), 0, s, n3, sc, u, c->vut, c->vg, Snext, Ynext);
+       })))
+    return e;
+  c->lb_pending = true;
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
 int gn_pcg_step(disco_ctx *c, const disco_params *p, float *u, double *report_dev, int32_t *status_dev,
                 disco_stream stream) {
   if (!c) return DISCO_ERR_ARG;
@@ -884,35 +1094,18 @@ int gn_pcg_step(disco_ctx *c, const disco_params *p, float *u, double *report_de
   const int64_t n3 = 3 * g.nnodes;
   const unsigned nb3 = nblk(n3);
   double *sc = c->sc;
-  const double CH = ch_of(c);
-  const bool vcc = p->gamma != 0.0;
-  const bool kp = p->delta != 0.0 && c->nkp > 0;
   const bool curv = p->alpha != 0.0;
-  const float eta2 = (float)(p->eta * p->eta);
   PostArgs pa = post_args(c, p->alpha, p->gamma, p->delta);
   pa.c1 = p->armijo_c1;
   pa.tol = p->pcg_tol;
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, c->status);
 
   // ---- linearise at u: J, grad J, diag of the GN matrix, s cache --------------------
-  set_s_scale(c, p->eta);
-  launch_curv_L(c, u, c->u_ref, c->Lw, true, nullptr, s);
-  {
-    BrickCall b{M_GRAD, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, u, nullptr, c->vg, c->vdiag, nullptr};
-    launch_brick(c, b, s);
-  }
-  launch_gather(c, 2, 2, c->vg, c->vdiag, curv ? c->Lw : nullptr, (float)(p->alpha * CH), curv ? 1 : 0, nullptr, 0.f,
-                nullptr, true, nullptr, s);
-  // D, V, K, folds; sum (L(u - uhat))^2; max diag, |g|^2 -> J
-  launch_finish(POST_LIN_BRICK, pa, nullptr, s, src_brick(c, sc + SC_TMP0), src_curv(c, sc + SC_SRAW),
-                src_gather(c, sc + SC_DOT));
-  HIP_TRY(hipMemcpyAsync(c->u_lin, u, sizeof(float) * n3, hipMemcpyDeviceToDevice, s));
-  c->lin = true;
-  c->lin_eta = p->eta;
+  if ((e = linearise(c, p, u, pa, s))) return e;
 
   // ---- Jacobi-PCG on (H + tau I) x = -g ----------------------------------------------
-  hipLaunchKernelGGL(k_pcg_init, dim3(nb3), dim3(256), 0, s, n3, c->vg, c->vdiag, sc, (float)p->tau, c->vx, c->vr,
-                     c->vz, c->vp, c->vinvm, c->blk_node);
+  hipLaunchKernelGGL(k_pcg_init, dim3(nb3), dim3(256), 0, s, n3, c->vg, c->vdiag, sc, (float)p->tau, -1.0f, c->vx,
+                     c->vr, c->vz, c->vp, c->vinvm, c->blk_node);
   launch_finish(POST_PCG_START, pa, nullptr, s, src_pairs(c->blk_node, nb3, 2, sc + SC_TMP0));
   const double *stop = sc + SC_STOP;
   const int64_t nbu = upd_blocks(g);
@@ -932,25 +1125,7 @@ int gn_pcg_step(disco_ctx *c, const disco_params *p, float *u, double *report_de
   }
 
   // ---- Armijo line search on J(u + t x) ------------------------------------------------
-  hipLaunchKernelGGL(k_dot, dim3(nb3), dim3(256), 0, s, n3, c->vg, c->vx, c->blk_node);
-  launch_finish(POST_LS_BEGIN, pa, nullptr, s, src_pairs(c->blk_node, nb3, 1, sc + SC_TMP0),
-                src_pairs(c->blk_upd, nbu, 2, sc + SC_TMP1));
-  const double *acc = sc + SC_ACCEPT;
-  const bool dev_ls = (p->flags & DISCO_FLAG_LS_DEVICE) != 0;
-  for (int t = 0; t < p->ls_max; ++t) {
-    hipLaunchKernelGGL(k_ls_point, dim3(nb3), dim3(256), 0, s, n3, sc, t, u, c->vx, c->vut);
-    launch_curv_L(c, c->vut, c->u_ref, c->Lw, true, acc, s);
-    BrickCall b{M_EVAL, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, c->vut, nullptr, nullptr, nullptr, acc};
-    launch_brick(c, b, s);
-    launch_finish(POST_LS_BRICK, pa, acc, s, src_brick(c, sc + SC_TMP0), src_curv(c, sc + SC_TSRAW));
-    if (!dev_ls) {
-      HIP_TRY(hipMemcpyAsync(c->host_sc, sc + SC_ACCEPT, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      if (c->host_sc[0] != 0.0) break;
-    }
-  }
-  hipLaunchKernelGGL(k_ls_finish, dim3(nb3), dim3(256), 0, s, n3, sc, c->vut, u);
-  hipLaunchKernelGGL(k_report, dim3(1), dim3(1), 0, s, sc, CH, report_dev, c->status, status_dev);
+  if ((e = line_search(c, p, u, pa, report_dev, status_dev, s, [] {}))) return e;
   HIP_TRY(hipGetLastError());
   // the s cache and u_lin now describe the linearisation point of this step
   return DISCO_OK;

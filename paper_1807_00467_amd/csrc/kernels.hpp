@@ -164,7 +164,9 @@ enum {
   POST_LS_BRICK,   // line-search trial: D, V, K, folds -> sc; Armijo decision
   POST_PCG_START,  // <r,z>, <r,r> of the initial residual
   POST_LS_BEGIN,   // g^T p -> start of the line search
-  POST_STORE       // out values only
+  POST_STORE,      // out values only
+  POST_LB_PAIR,    // s.y, s.s, y.y of a new L-BFGS pair -> rho (0 if s.y <= eps |s||y|)
+  POST_LB_ALPHA    // alpha_idx = rho_idx * (s_idx . q)
 };
 
 struct PostArgs {
@@ -194,8 +196,15 @@ enum {
   SC_TD, SC_TSRAW, SC_TV, SC_TK, SC_TNFOLD,    // trial point reductions
   SC_JT, SC_DT, SC_ST, SC_VT, SC_KT,           // accepted (or last) trial values
   SC_TMP0, SC_TMP1, SC_TMP2, SC_TMP3, SC_TMP4,
-  SC_COUNT = 48
+  SC_LB_RHO = 48,     // L-BFGS: rho_i = 1 / s_i.y_i of the stored pairs (0: pair skipped)
+  SC_LB_ALPHA = 56,   // L-BFGS: alpha_i of the first loop
+  SC_LB_DOT = 64,     // L-BFGS: dot product scratch
+  SC_COUNT = 72
 };
+constexpr int kLbfgsMax = 8;  // longest L-BFGS history
+static_assert(SC_TMP4 < SC_LB_RHO && SC_LB_RHO + kLbfgsMax <= SC_LB_ALPHA && SC_LB_ALPHA + kLbfgsMax <= SC_LB_DOT &&
+                  SC_LB_DOT < SC_COUNT,
+              "scalar slots overlap");
 
 __device__ inline void run_post(int post, const PostArgs &a, const double *r) {
   double *sc = a.sc;
@@ -242,6 +251,14 @@ __device__ inline void run_post(int post, const PostArgs &a, const double *r) {
       sc[SC_STOP] = 0.0;
       sc[SC_ITERS] = 0.0;
       sc[SC_BREAK] = 0.0;
+      break;
+    case POST_LB_PAIR: {
+      const double sy = r[0], ss = r[1], yy = r[2];
+      sc[SC_LB_RHO + a.idx] = (sy > a.tol * sqrt(ss * yy) && sy > 0.0) ? 1.0 / sy : 0.0;
+      break;
+    }
+    case POST_LB_ALPHA:
+      sc[SC_LB_ALPHA + a.idx] = sc[SC_LB_RHO + a.idx] * r[0];
       break;
     case POST_LS_BEGIN:
       // residual of the last completed CG update (its partials were reduced into SC_TMP1)

@@ -14,9 +14,10 @@ __device__ inline void block_pair_sum(double x, double y, double *blocks, int64_
   block_write<2>(v, blocks + 2 * bid);
 }
 
-// x = 0, r = -g, z = r / M, p = z, invM = 1 / M; per-block <r,z>, <r,r>
+// x = 0, r = sgn g (sgn = -1: the GN system H x = -g; +1: a system A x = g), z = r / M,
+// p = z, invM = 1 / M; per-block <r,z>, <r,r>
 __device__ __forceinline__ void pcg_init_body(int64_t n, const float *__restrict__ g, const float *__restrict__ diag,
-                                              const double *sc, float tau, float *__restrict__ x,
+                                              const double *sc, float tau, float sgn, float *__restrict__ x,
                                               float *__restrict__ r, float *__restrict__ z, float *__restrict__ p,
                                               float *__restrict__ invM, double *blocks, int64_t bid) {
   const int64_t i = bid * 256 + threadIdx.x;
@@ -24,7 +25,7 @@ __device__ __forceinline__ void pcg_init_body(int64_t n, const float *__restrict
   if (i < n) {
     const float M = diag[i] + tau + (float)(1e-12 * sc[SC_MAXDIAG]);
     const float iM = 1.0f / M;
-    const float ri = -g[i];
+    const float ri = sgn * g[i];
     const float zi = ri * iM;
     x[i] = 0.0f;
     r[i] = ri;
@@ -38,9 +39,10 @@ __device__ __forceinline__ void pcg_init_body(int64_t n, const float *__restrict
 }
 __global__ __launch_bounds__(256) void k_pcg_init(int64_t n, const float *__restrict__ g,
                                                   const float *__restrict__ diag, const double *sc, float tau,
-                                                  float *__restrict__ x, float *__restrict__ r, float *__restrict__ z,
-                                                  float *__restrict__ p, float *__restrict__ invM, double *blocks) {
-  pcg_init_body(n, g, diag, sc, tau, x, r, z, p, invM, blocks, blockIdx.x);
+                                                  float sgn, float *__restrict__ x, float *__restrict__ r,
+                                                  float *__restrict__ z, float *__restrict__ p, float *__restrict__ invM,
+                                                  double *blocks) {
+  pcg_init_body(n, g, diag, sc, tau, sgn, x, r, z, p, invM, blocks, blockIdx.x);
 }
 
 // elements per thread of the CG vector update (workgroup covers 256 * kUpdK elements)
@@ -255,5 +257,54 @@ __global__ void k_report(const double *sc, double CH, double *rep, int *status, 
 }
 
 __global__ void k_clear_status(int *status) { *status = 0; }
+
+// ---- L-BFGS vector operations (node fields) ----------------------------------------
+// out = sa a + c b with c = f0 + fa sc[ka] + fb sc[kb] sc[kc] (a term whose first slot
+// index is negative vanishes; b nullable); out may alias a.  With `blocks`, per-block
+// <d, out> (stride 2, second value 0).
+__global__ __launch_bounds__(256) void k_lb_axpy(int64_t n, float sa, const float *a, const float *b, float *out,
+                                                 const double *sc, double f0, int ka, double fa, int kb, int kc,
+                                                 double fb, const float *d, double *blocks) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double dot = 0.0;
+  if (i < n) {
+    double c = f0;
+    if (ka >= 0) c += fa * sc[ka];
+    if (kb >= 0) c += fb * sc[kb] * sc[kc];
+    float v = sa * a[i];
+    if (b) v += (float)c * b[i];
+    out[i] = v;
+    if (blocks) dot = (double)d[i] * (double)v;
+  }
+  if (blocks) block_pair_sum(dot, 0.0, blocks, blockIdx.x);
+}
+
+// completes a stored pair: y = Y + g (Y held -g_old), written back; per-block s.y, s.s,
+// y.y (stride 3)
+__global__ __launch_bounds__(256) void k_lb_pair(int64_t n, const float *S, float *Y, const float *g,
+                                                 double *blocks) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (i < n) {
+    const float y = Y[i] + g[i];
+    Y[i] = y;
+    const double s = S[i];
+    v[0] = s * (double)y;
+    v[1] = s * s;
+    v[2] = (double)y * (double)y;
+  }
+  block_write<3>(v, blocks + 3 * (int64_t)blockIdx.x);
+}
+
+// starts a pair at the end of a step: S = ut - u if the line search accepted ut, else 0;
+// Y = -g (the next linearisation adds its gradient)
+__global__ __launch_bounds__(256) void k_lb_save(int64_t n, const double *sc, const float *u, const float *ut,
+                                                 const float *g, float *S, float *Y) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const bool acc = sc[SC_ACCEPT] != 0.0;
+  S[i] = acc ? ut[i] - u[i] : 0.0f;
+  Y[i] = -g[i];
+}
 
 }  // namespace disco

@@ -46,6 +46,11 @@ class _Params(ctypes.Structure):
                 ("flags", ctypes.c_int32)]
 
 
+class _Lbfgs(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("curv_eps", ctypes.c_double), ("h0_tol", ctypes.c_double),
+                ("m", ctypes.c_int32), ("h0_iters", ctypes.c_int32)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I = ctypes.c_int32
@@ -65,6 +70,8 @@ _SIGS = {
     "keypoint_penalty": ([_P, _D, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "gn_hessvec": ([_P, ctypes.POINTER(_Params), _P, _P, _P], ctypes.c_int),
     "gn_pcg_step": ([_P, ctypes.POINTER(_Params), _P, _P, _P, _P], ctypes.c_int),
+    "lbfgs_step": ([_P, ctypes.POINTER(_Params), ctypes.POINTER(_Lbfgs), _P, _P, _P, _P], ctypes.c_int),
+    "lbfgs_reset": ([_P], ctypes.c_int),
     "disco_copy_buffer": ([_P, _I, _P, _P], ctypes.c_int),
     "disco_profile": ([_P, _I], ctypes.c_int),
     "disco_profile_read": ([_P, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D)], ctypes.c_int),
@@ -112,6 +119,21 @@ class Params:
     def c(self) -> _Params:
         return _Params(self.eta, self.alpha, self.gamma, self.delta, self.tau, self.armijo_c1, self.pcg_tol,
                        self.pcg_iters, self.ls_max, self.flags)
+
+
+@dataclasses.dataclass
+class Lbfgs:
+    """L-BFGS settings (Sec. II-D3): history m, H0 = alpha C_H L^T L + tau I solved by
+    h0_iters Jacobi-PCG iterations (or to |r| <= h0_tol |q|), pairs used only when
+    s.y > curv_eps |s||y|."""
+    m: int = 5
+    tau: float = 10.0
+    curv_eps: float = 1e-10
+    h0_iters: int = 30
+    h0_tol: float = 1e-6
+
+    def c(self) -> _Lbfgs:
+        return _Lbfgs(self.tau, self.curv_eps, self.h0_tol, self.m, self.h0_iters)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -266,6 +288,22 @@ class Disco:
         _check(_lib.gn_pcg_step(self._h, ctypes.byref(p), _ptr(self._field(u, "u")), _ptr(rep), _ptr(st),
                                 self._stream()), "gn_pcg_step")
         return rep, st
+
+    def lbfgs_step(self, params: Params, lb: Lbfgs, u: torch.Tensor, report: Optional[torch.Tensor] = None,
+                   status: Optional[torch.Tensor] = None):
+        """One L-BFGS iteration in place on u (the history of this context advances).
+        Returns (report tensor [16] float64, status int32 tensor); the CG slots describe
+        the H0 solve."""
+        rep = torch.zeros(16, dtype=torch.float64, device=self.device) if report is None else report
+        st = torch.zeros(1, dtype=torch.int32, device=self.device) if status is None else status
+        p = params.c()
+        q = lb.c()
+        _check(_lib.lbfgs_step(self._h, ctypes.byref(p), ctypes.byref(q), _ptr(self._field(u, "u")), _ptr(rep),
+                               _ptr(st), self._stream()), "lbfgs_step")
+        return rep, st
+
+    def lbfgs_reset(self):
+        _check(_lib.lbfgs_reset(self._h), "lbfgs_reset")
 
     @staticmethod
     def report_dict(rep: torch.Tensor) -> dict:

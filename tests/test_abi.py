@@ -32,7 +32,7 @@ def test_header_declares_the_path_entry_points():
     for n in ("ngf_eval", "ngf_grad", "ngf_hessvec", "curvature_apply", "volchange_eval", "keypoint_penalty",
               "gn_pcg_step", "gn_hessvec", "disco_create", "disco_destroy", "disco_set_images",
               "disco_set_keypoints", "disco_set_reference", "disco_copy_buffer", "disco_profile",
-              "disco_profile_read", "disco_status_string"):
+              "disco_profile_read", "disco_status_string", "lbfgs_step", "lbfgs_reset"):
         assert n in names, n
 
 
@@ -76,6 +76,10 @@ def test_host_validation_codes_without_device(lib):
     assert lib.ngf_hessvec(None, None, None, None) == -1
     lib.gn_pcg_step.argtypes = [V, V, V, V, V, V]
     assert lib.gn_pcg_step(None, None, None, None, None, None) == -1
+    lib.lbfgs_step.argtypes = [V, V, V, V, V, V, V]
+    assert lib.lbfgs_step(None, None, None, None, None, None, None) == -1
+    lib.lbfgs_reset.argtypes = [V]
+    assert lib.lbfgs_reset(None) == -1
     lib.disco_destroy.argtypes = [V]
     lib.disco_destroy(None)
     for code in (0, -1, -2, -3, -4, -5):
