@@ -104,6 +104,9 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="batched form instead: 24 uneven pyramid-shape pairs, 5 GN iterations (15 PCG each), "
                          "one launch per phase and one graph, against the same steps pair by pair")
+    ap.add_argument("--lbfgs", action="store_true",
+                    help="L-BFGS iterations (m = 5, H0 = alpha C_H L^T L + tau I) on the same workload instead")
+    ap.add_argument("--tau", type=float, default=10.0, help="tau of the L-BFGS initial Hessian")
     args = ap.parse_args()
     if args.print_source_hash:
         print(kernel_source_hash())
@@ -120,6 +123,8 @@ def main():
 
     if args.batched:
         return bench_batched(args)
+    if args.lbfgs:
+        return bench_lbfgs(args)
 
     if args.calib_copy_mib > 0:
         n = args.calib_copy_mib * (1 << 20) // 4
@@ -229,6 +234,93 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(d, params)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_lbfgs(args):
+    """L-BFGS on the full-size workload: the first K iterations of a run from u = 0
+    (timed after W untimed runs of the same iterations; the history is reset before each
+    run).  One iteration = J and grad J at u, two-loop recursion over the stored pairs
+    (full from the sixth iteration on), H0 solve (Jacobi-PCG, 30 iterations at most,
+    relative residual 1e-6), Armijo trials."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1807_00467_amd import disco
+
+    log(f"[bench] generating {args.config} ...")
+    d = synth.make_pair(args.config)
+    dev = torch.device("cuda:0")
+    ctx = disco.Disco(d["shape"], d["spacing"], storage=args.storage, device=dev)
+    ctx.set_images(torch.from_numpy(d["R"]).to(dev), torch.from_numpy(d["T"]).to(dev))
+    ctx.set_keypoints(d["kp_x"], d["kp_t"])
+    zero = torch.zeros((3,) + tuple(ctx.nodes[::-1]), device=dev)
+    D0 = ctx.ngf_eval(zero, 10.0).item()
+    K0 = ctx.keypoint_penalty(1.0, zero, grad=False, diag=False)["K"].item()
+    params = disco.Params(eta=10.0, alpha=1.0, gamma=0.1, delta=D0 / K0 if K0 > 0 else 0.0, ls_max=10,
+                          flags=disco.FLAG_LS_DEVICE)
+    lb = disco.Lbfgs(m=5, tau=args.tau, h0_iters=30, h0_tol=1e-6)
+    u = zero.clone()
+    rep = torch.zeros(16, dtype=torch.float64, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    for _ in range(args.warmup):
+        ctx.lbfgs_reset()
+        u.zero_()
+        for _ in range(args.steps):
+            ctx.lbfgs_step(params, lb, u, rep, st)
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+    ctx.lbfgs_reset()
+    u.zero_()
+    reps = []
+    ctx.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.lbfgs_step(params, lb, u, rep, st)
+        reps.append(rep.clone())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ctx.profile(False)
+    n_gr, ms_gr = ctx.profile_read(disco.PROF_GRAD)
+    n_ev, ms_ev = ctx.profile_read(disco.PROF_EVAL)
+    rs = [disco.Disco.report_dict(r) for r in reps]
+    trials = sum(int(r["ls_trials"]) for r in rs)
+    h0 = [int(r["pcg_iters"]) for r in rs]
+    for k, r in enumerate(rs):
+        log(f"[bench]   it {k}: J {r['J']:.6e} |g| {r['gnorm']:.3e} g.p {r['gtp']:.3e} t {r['t']} "
+            f"trials {int(r['ls_trials'])} J_new {r['J_new']:.6e} V_new {r['V_new']:.3e}")
+    log(f"[bench] J {rs[0]['J']:.6e} -> {rs[-1]['J_new']:.6e}; trials {trials}; H0 CG iterations {h0}; "
+        f"status {int(st.item())}")
+    nx, ny, nz = ctx.nodes
+    out = {
+        "metric": "L-BFGS iterations/s",
+        "value": args.steps / elapsed,
+        "unit": "iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage == "fp32" else "f16-storage/f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.config}: R,T {d['shape'][0]}x{d['shape'][1]}x{d['shape'][2]}, node grid "
+                        f"{nx}x{ny}x{nz}; step = one L-BFGS iteration (m 5, H0 tau {args.tau:g}, <= 30 H0 CG "
+                        f"iterations, Armijo on the device, 10 trials at most); the first {args.steps} "
+                        f"iterations from u = 0",
+            "storage": args.storage,
+        },
+        "grad_kernel_us": 1e3 * ms_gr / max(n_gr, 1),
+        "eval_kernel_us": 1e3 * ms_ev / max(n_ev, 1),
+        "ls_trials_per_iter": trials / args.steps,
+        "h0_cg_iters": h0,
+        "J_first": rs[0]["J"],
+        "J_last": rs[-1]["J_new"],
+    }
     print(json.dumps(out), flush=True)
     ctx.close()
 
