@@ -503,3 +503,161 @@ def lbfgs_run(prob, u0, iters: int, params: LbfgsParams = LbfgsParams(), fg=None
             Y.pop(0)
         u, J, g = u_new, J_new, g_new
     return u, reps
+
+
+# ------------------------------------------------------------------------------------
+# multilevel scheme (Sec. II-D3): image pyramid by Gaussian smoothing and downsampling
+# toward isotropic voxels, control grid halved with the voxels, coarse-to-fine
+# optimisation with the displacement prolonged by trilinear interpolation
+# ------------------------------------------------------------------------------------
+
+PYR_SIGMA = 1.0   # Gaussian sigma in voxels of the finer level, along halved axes
+PYR_RADIUS = 3    # taps at -3 .. 3 (truncated at 3 sigma), renormalised
+
+
+def pyramid_halving(shape, spacing):
+    """Axes halved to go one level coarser, (hx, hy, hz) in {0, 1}: among the non-empty
+    subsets whose axes have a size divisible by 8 (so the coarse size stays a multiple
+    of 4) and a coarse size of at least 8 voxels, the one whose coarse spacing is most
+    nearly isotropic (smallest max h / min h); ties go to more halved axes, then to the
+    subset that halves x before y before z.  None if no subset qualifies."""
+    best = None
+    for mask in range(1, 8):
+        S = tuple((mask >> a) & 1 for a in range(3))
+        if any(S[a] and (shape[a] % 8 != 0 or shape[a] // 2 < 8) for a in range(3)):
+            continue
+        h = [float(spacing[a]) * (2.0 if S[a] else 1.0) for a in range(3)]
+        key = (max(h) / min(h), -sum(S), mask)
+        if best is None or key < best[0]:
+            best = (key, S)
+    return None if best is None else best[1]
+
+
+def pyramid_plan(shape, spacing, levels):
+    """Levels finest first, at most `levels`: dicts with shape (Nx, Ny, Nz), spacing and
+    the axes halved from the next finer level ((0, 0, 0) on the finest)."""
+    plan = [dict(shape=tuple(int(n) for n in shape), spacing=tuple(float(h) for h in spacing), halve=(0, 0, 0))]
+    while len(plan) < levels:
+        last = plan[-1]
+        S = pyramid_halving(last["shape"], last["spacing"])
+        if S is None:
+            break
+        plan.append(dict(shape=tuple(n // 2 if s else n for n, s in zip(last["shape"], S)),
+                         spacing=tuple(h * 2.0 if s else h for h, s in zip(last["spacing"], S)), halve=S))
+    return plan
+
+
+def gaussian_taps(sigma: float = PYR_SIGMA, radius: int = PYR_RADIUS):
+    k = np.arange(-radius, radius + 1, dtype=np.float64)
+    w = np.exp(-0.5 * (k / sigma) ** 2)
+    return w / np.sum(w)
+
+
+def smooth_axis(img, axis: int, sigma: float = PYR_SIGMA, radius: int = PYR_RADIUS):
+    """Gaussian smoothing of a volume [Nz][Ny][Nx] along image axis `axis` (0 = x), with
+    the border value replicated: out(i) = sum_k w_k img(clamp(i + k))."""
+    img = _f64(img)
+    ax = 2 - axis
+    n = img.shape[ax]
+    w = gaussian_taps(sigma, radius)
+    out = np.zeros_like(img)
+    for j, k in enumerate(range(-radius, radius + 1)):
+        idx = np.clip(np.arange(n) + k, 0, n - 1)
+        out += w[j] * np.take(img, idx, axis=ax)
+    return out
+
+
+def downsample(img, halve):
+    """One pyramid step: Gaussian smoothing along every halved axis, then each coarse
+    voxel is the mean of the two finer voxels it covers along each halved axis (the
+    smoothed image at the coarse voxel centre, which lies midway between them)."""
+    out = _f64(img)
+    for a in range(3):
+        if halve[a]:
+            out = smooth_axis(out, a)
+    for a in range(3):
+        if halve[a]:
+            ax = 2 - a
+            n = out.shape[ax]
+            even = np.take(out, np.arange(0, n, 2), axis=ax)
+            odd = np.take(out, np.arange(1, n, 2), axis=ax)
+            out = 0.5 * (even + odd)
+    return out
+
+
+def prolong(uc, halve):
+    """Coarse node field [3][nz][ny][nx] to the next finer level: along a halved axis the
+    fine node q sits at coarse coordinate q/2, so even nodes copy a coarse node and odd
+    nodes average the two coarse nodes beside it.  This is the coarse trilinear field
+    evaluated at the fine nodes, and it represents that field exactly (the coarse cells
+    are unions of fine cells).  Displacements are in mm and are not rescaled."""
+    u = _f64(uc)
+    for a in range(3):
+        if halve[a]:
+            ax = 3 - a
+            n = u.shape[ax]
+            shp = list(u.shape)
+            shp[ax] = 2 * (n - 1) + 1
+            out = np.empty(shp)
+            sl = [slice(None)] * 4
+            sl[ax] = slice(0, None, 2)
+            out[tuple(sl)] = u
+            sl[ax] = slice(1, None, 2)
+            lo = np.take(u, np.arange(0, n - 1), axis=ax)
+            hi = np.take(u, np.arange(1, n), axis=ax)
+            out[tuple(sl)] = 0.5 * (lo + hi)
+            u = out
+    return u
+
+
+@dataclasses.dataclass
+class MultilevelParams:
+    levels: int = 4
+    iters: tuple = (10, 10, 10, 10)   # iterations per level, coarsest first
+    optimizer: str = "lbfgs"          # "lbfgs" or "gn"
+    lbfgs: LbfgsParams = dataclasses.field(default_factory=LbfgsParams)
+    step: StepParams = dataclasses.field(default_factory=StepParams)
+
+
+def multilevel_run(R, T, spacing, kp_x, kp_t, weights: Weights, params: MultilevelParams = MultilevelParams()):
+    """Coarse-to-fine registration: the pyramid of pyramid_plan; on the coarsest level
+    u = 0, on each finer level u = prolong(u of the coarser level); `iters` iterations of
+    the optimiser per level (a fresh L-BFGS history per level; GN steps stop early when
+    the line search fails).  With weights.delta < 0 the keypoint weight is set once on
+    the coarsest level at u = 0 so that D = delta K (Sec. II-D2).  Level images are
+    computed in FP64 and stored as float32 (the precision of the input volumes).
+    Returns (u on the finest level, per-level dicts with shape, delta and reports)."""
+    plan = pyramid_plan((R.shape[2], R.shape[1], R.shape[0]), spacing, params.levels)
+    Rs, Ts = [np.asarray(R, np.float32)], [np.asarray(T, np.float32)]
+    for lv in plan[1:]:
+        Rs.append(downsample(Rs[-1], lv["halve"]).astype(np.float32))
+        Ts.append(downsample(Ts[-1], lv["halve"]).astype(np.float32))
+    L = len(plan)
+    delta = weights.delta
+    u = None
+    out = []
+    for li in range(L - 1, -1, -1):
+        lv = plan[li]
+        w = dataclasses.replace(weights, delta=0.0 if delta < 0 else delta)
+        P = Problem(Rs[li], Ts[li], lv["spacing"], kp_x, kp_t, w)
+        nn = P.nodes
+        if u is None:
+            u = np.zeros((3, nn[2], nn[1], nn[0]))
+            if delta < 0:
+                delta = P.adaptive_delta(u)
+                P.w.delta = delta
+        else:
+            u = prolong(u, plan[li + 1]["halve"])
+        iters = params.iters[L - 1 - li]
+        if params.optimizer == "lbfgs":
+            u, reps = lbfgs_run(P, u, iters, params.lbfgs)
+        else:
+            reps = []
+            for _ in range(iters):
+                u, rep = gn_pcg_step(P, u, params.step)
+                reps.append(rep)
+                if not rep["accepted"]:
+                    break
+        out.append(dict(shape=lv["shape"], spacing=lv["spacing"], delta=delta, reports=reps,
+                        J_final=P.objective(u)["J"]))
+    return u, out

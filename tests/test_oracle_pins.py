@@ -683,3 +683,108 @@ def test_lbfgs_registration_decreases_objective():
     assert len(reps) == 4 and all(rep["accepted"] for rep in reps)
     Js = [rep["J"] for rep in reps] + [reps[-1]["J_new"]]
     assert all(b_ < a_ for a_, b_ in zip(Js, Js[1:]))
+
+
+# ---- multilevel scheme (Sec. II-D3) ----------------------------------------------------
+
+def test_pyramid_plan_examples():
+    """Coarse levels approach isotropic voxels: worked by hand from the halving rule."""
+    plan = oracle.pyramid_plan((512, 512, 128), (0.7, 0.7, 2.5), 4)
+    assert [l["shape"] for l in plan] == [(512, 512, 128), (256, 256, 128), (128, 128, 128), (64, 64, 64)]
+    assert [l["halve"] for l in plan] == [(0, 0, 0), (1, 1, 0), (1, 1, 0), (1, 1, 1)]
+    np.testing.assert_allclose(plan[-1]["spacing"], (5.6, 5.6, 5.0))
+    plan = oracle.pyramid_plan((64, 64, 48), (1.5, 1.5, 1.5), 4)
+    assert [l["shape"] for l in plan] == [(64, 64, 48), (32, 32, 24), (16, 16, 12), (8, 8, 12)]
+    # 12 is not divisible by 8 and 8 // 2 < 8: the pyramid stops early
+    plan = oracle.pyramid_plan((48, 32, 24), (1.2, 1.4, 2.2), 4)
+    assert [l["shape"] for l in plan] == [(48, 32, 24), (24, 16, 24), (12, 8, 12)]
+    assert oracle.pyramid_halving((12, 8, 12), (4.8, 5.6, 4.4)) is None
+
+
+def test_pyramid_halving_is_the_most_isotropic_choice():
+    """Brute force over all subsets on random shapes and spacings: no valid subset gives a
+    smaller anisotropy than the chosen one."""
+    rng = np.random.default_rng(5)
+    for _ in range(200):
+        shape = tuple(int(x) for x in rng.choice([8, 12, 16, 24, 32, 40, 64], 3))
+        spacing = tuple(float(x) for x in rng.uniform(0.5, 3.0, 3))
+        S = oracle.pyramid_halving(shape, spacing)
+        ratios = []
+        for mask in range(1, 8):
+            T = [(mask >> a) & 1 for a in range(3)]
+            if any(T[a] and (shape[a] % 8 or shape[a] < 16) for a in range(3)):
+                continue
+            h = [spacing[a] * (1 + T[a]) for a in range(3)]
+            ratios.append(max(h) / min(h))
+        if not ratios:
+            assert S is None
+            continue
+        h = [spacing[a] * (1 + S[a]) for a in range(3)]
+        assert max(h) / min(h) <= min(ratios) + 1e-15
+
+
+def test_smooth_axis_matches_scipy_gaussian_filter():
+    from scipy.ndimage import gaussian_filter1d
+    rng = np.random.default_rng(6)
+    img = rng.normal(size=(10, 12, 14))
+    for a in range(3):
+        ref = gaussian_filter1d(img, sigma=1.0, axis=2 - a, mode="nearest", truncate=3.0)
+        np.testing.assert_allclose(oracle.smooth_axis(img, a), ref, rtol=0, atol=1e-13)
+
+
+def test_downsample_constant_and_linear_ramp():
+    """A constant stays constant; a linear function of position is reproduced exactly at
+    the coarse voxel centres wherever the smoothing stencil stays inside the volume (the
+    symmetric kernel preserves linear functions; the pair mean is the midpoint value)."""
+    Nz, Ny, Nx = 16, 24, 32
+    c = oracle.downsample(np.full((Nz, Ny, Nx), 3.25), (1, 1, 1))
+    assert c.shape == (8, 12, 16)
+    np.testing.assert_allclose(c, 3.25, rtol=0, atol=1e-13)
+    h = (0.7, 0.9, 2.0)
+    z, y, x = np.meshgrid(*[(np.arange(n) + 0.5) * hh for n, hh in zip((Nz, Ny, Nx), h[::-1])], indexing="ij")
+    f = 1.0 + 0.3 * x - 0.2 * y + 0.05 * z
+    for halve in ((1, 0, 0), (1, 1, 0), (1, 1, 1), (0, 0, 1)):
+        d = oracle.downsample(f, halve)
+        hc = [hh * (1 + s) for hh, s in zip(h, halve)]
+        shp = d.shape
+        zc, yc, xc = np.meshgrid(*[(np.arange(n) + 0.5) * hh for n, hh in zip(shp, hc[::-1])], indexing="ij")
+        ref = 1.0 + 0.3 * xc - 0.2 * yc + 0.05 * zc
+        # interior: coarse index i with fine stencil 2i - 3 .. 2i + 4 inside along halved axes
+        sl = []
+        for ax, a in zip(range(3), (2, 1, 0)):
+            n = shp[ax]
+            sl.append(slice(2, n - 2) if halve[a] else slice(None))
+        np.testing.assert_allclose(d[tuple(sl)], ref[tuple(sl)], rtol=0, atol=1e-12)
+
+
+def test_prolong_represents_the_coarse_trilinear_field():
+    """The prolonged node field and the coarse field define the same trilinear function
+    (scipy RegularGridInterpolator on both grids at random points)."""
+    from scipy.interpolate import RegularGridInterpolator
+    rng = np.random.default_rng(7)
+    Hc = (4.0, 3.0, 5.0)
+    nc = (5, 4, 6)  # nodes x, y, z
+    uc = rng.normal(size=(3, nc[2], nc[1], nc[0]))
+    for halve in ((1, 1, 1), (1, 0, 1), (0, 1, 0)):
+        uf = oracle.prolong(uc, halve)
+        Hf = tuple(H / (1 + s) for H, s in zip(Hc, halve))
+        nf = (uf.shape[3], uf.shape[2], uf.shape[1])
+        assert nf == tuple(2 * (n - 1) + 1 if s else n for n, s in zip(nc, halve))
+        pts = rng.uniform(0, 1, size=(200, 3)) * np.array([(n - 1) * H for n, H in zip(nc, Hc)])[::-1]
+        for c in range(3):
+            gc = RegularGridInterpolator([np.arange(n) * H for n, H in zip(nc[::-1], Hc[::-1])], uc[c])
+            gf = RegularGridInterpolator([np.arange(n) * H for n, H in zip(nf[::-1], Hf[::-1])], uf[c])
+            np.testing.assert_allclose(gf(pts), gc(pts), rtol=0, atol=1e-12)
+
+
+def test_multilevel_run_decreases_objective_on_every_level():
+    d = synth.small_pair(shape=(32, 32, 24), spacing=(1.5, 1.5, 2.0), seed=8, n_tubes=6, n_kp=20, field_max=3.0)
+    w = oracle.Weights(eta=10.0, alpha=1.0, gamma=0.1, delta=-1.0)
+    prm = oracle.MultilevelParams(levels=3, iters=(4, 3, 2), optimizer="lbfgs")
+    u, levels = oracle.multilevel_run(d["R"], d["T"], d["spacing"], d["kp_x"], d["kp_t"], w, prm)
+    assert [l["shape"] for l in levels] == [(8, 8, 12), (16, 16, 12), (32, 32, 24)]
+    for lv in levels:
+        assert lv["delta"] > 0
+        r = lv["reports"]
+        assert r[-1]["J_new"] < r[0]["J"]
+    assert u.shape == (3, 7, 9, 9)
