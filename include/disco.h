@@ -218,6 +218,65 @@ int lbfgs_step(disco_ctx *ctx, const disco_params *p, const disco_lbfgs *lb, flo
 /* Forget the L-BFGS history of the context (the next lbfgs_step starts from H0). */
 int lbfgs_reset(disco_ctx *ctx);
 
+/* ---- multilevel scheme (Sec. II-D3) ------------------------------------------------- */
+
+#define DISCO_MAX_LEVELS 8
+#define DISCO_OPT_GN 0    /* gn_pcg_step per iteration */
+#define DISCO_OPT_LBFGS 1 /* lbfgs_step per iteration (fresh history on every level) */
+
+/* The pyramid of a volume of n voxels at spacing h (host only, no device call): level 0
+   is the input; each coarser level halves the axes of the valid non-empty subset (sizes
+   divisible by 8, coarse size >= 8) whose coarse spacing is most nearly isotropic
+   (smallest max h / min h; ties: more axes, then x before y before z), so the voxels
+   approach isotropy as the paper asks.  Stops early when no subset is valid.  Writes
+   *levels_out <= levels, and per level (finest first) n_out[3 l + a], h_out[3 l + a] and
+   halve_out[3 l + a] (1 if axis a was halved from level l - 1; 0 on level 0).  The
+   control grid follows the voxels (4 voxels per cell), so it halves with them.
+   Arrays hold 3 * levels entries; levels in 1..DISCO_MAX_LEVELS; n multiples of 4. */
+int pyramid_plan(const int32_t n[3], const double h[3], int32_t levels, int32_t *levels_out, int32_t *n_out,
+                 double *h_out, int32_t *halve_out);
+
+/* One pyramid step of a volume (device float32 [Nz][Ny][Nx], n = {Nx, Ny, Nz}): along
+   each halved axis Gaussian smoothing (sigma = 1 voxel of the finer level, taps -3..3
+   renormalised, border replicated), then each coarse voxel is the mean of the two finer
+   voxels it covers (the smoothed value at the coarse voxel centre).  dst has the halved
+   size.  Halved sizes must be even.  With two or more halved axes, work (device) holds
+   N/2 + N/4 floats, N = Nx Ny Nz (NULL otherwise); axes are processed x, y, z. */
+int pyramid_downsample(const float *src, const int32_t n[3], const int32_t halve[3], float *dst, float *work,
+                       disco_stream stream);
+
+/* Prolongation of a node field (device float32 [3][nz][ny][nx], nodes = {nx, ny, nz}) to
+   the next finer level: along a halved axis the fine grid has 2 (n - 1) + 1 nodes, even
+   ones copy a coarse node and odd ones average the two beside it, which is the coarse
+   trilinear displacement evaluated at the fine nodes (the coarse field is represented
+   exactly).  Values are displacements in mm and are not rescaled. */
+int pyramid_prolong(const float *uc, const int32_t nodes[3], const int32_t halve[3], float *uf, disco_stream stream);
+
+typedef struct {
+    disco_params params;    /* weights, eta, line search, CG (GN); delta is ignored with adaptive_delta */
+    disco_lbfgs lbfgs;      /* L-BFGS settings (optimizer DISCO_OPT_LBFGS) */
+    int32_t levels;         /* requested levels, 1..DISCO_MAX_LEVELS (fewer if the pyramid stops) */
+    int32_t optimizer;      /* DISCO_OPT_GN or DISCO_OPT_LBFGS */
+    int32_t adaptive_delta; /* 1: delta with D = delta K at u = 0 on the coarsest level (Sec. II-D2) */
+    int32_t storage;        /* DISCO_STORAGE_* of every level */
+    int32_t iters[DISCO_MAX_LEVELS]; /* iterations per level, coarsest built level first */
+} disco_multilevel;
+
+/* Coarse-to-fine registration (Sec. II-D3) of R and T (device float32 [Nz][Ny][Nx] of
+   geometry geom) with nkp keypoints (HOST float32 [nkp][3], mm): builds the pyramid
+   (pyramid_plan, pyramid_downsample), starts from u = 0 on the coarsest level, runs
+   iters[k] iterations of the optimiser on each level (a level ends early when a line
+   search accepts no step) and prolongs u to the next level (pyramid_prolong).  u_out
+   (device node field of the finest level) receives the result.  report_dev (nullable,
+   device doubles [sum of iters over the built levels][DISCO_REP_SIZE]) receives one
+   report per iteration in execution order; rows of iterations not run are NaN.
+   *levels_out and *delta_out (host, nullable) receive the number of levels and the
+   keypoint weight used.  Allocates every level's context and images for the duration of
+   the call and synchronises the stream after each iteration (to stop a level early). */
+int multilevel_register(const disco_geom *geom, const float *R, const float *T, int32_t nkp, const float *kp_x,
+                        const float *kp_t, const disco_multilevel *cfg, float *u_out, double *report_dev,
+                        int32_t *levels_out, double *delta_out, disco_stream stream);
+
 /* Copy a derived buffer (DISCO_BUF_*) to dst, converted to float32 [Nz][Ny][Nx][3]. */
 int disco_copy_buffer(disco_ctx *ctx, int32_t which, float *dst, disco_stream stream);
 

@@ -16,6 +16,7 @@
 #include "solver.hpp"
 #include "adjoint.hpp"
 #include "batch.hpp"
+#include "pyramid.hpp"
 
 using namespace disco;
 
@@ -1493,6 +1494,283 @@ int disco_batch_graph_launch(disco_batch *b, disco_stream stream) {
   int e;
   if ((e = set_device(b->ctx[0]))) return e;
   HIP_TRY(hipGraphLaunch(b->exec, S(stream)));
+  return DISCO_OK;
+}
+
+// ---- multilevel scheme (Sec. II-D3) ----------------------------------------------------
+
+// the axes halved to go one level coarser: the valid non-empty subset (halved sizes
+// divisible by 8, coarse size >= 8) with the most nearly isotropic coarse spacing; ties:
+// more axes, then x before y before z.  false if none is valid.
+static bool pyr_halving(const int32_t n[3], const double h[3], int32_t S[3]) {
+  bool found = false;
+  double best_ratio = 0.0;
+  int best_cnt = 0;
+  for (int mask = 1; mask < 8; ++mask) {
+    bool ok = true;
+    double hh[3];
+    int cnt = 0;
+    for (int a = 0; a < 3; ++a) {
+      const bool s = (mask >> a) & 1;
+      if (s && (n[a] % 8 != 0 || n[a] / 2 < 8)) ok = false;
+      hh[a] = s ? h[a] * 2.0 : h[a];
+      cnt += s;
+    }
+    if (!ok) continue;
+    const double ratio = std::max(hh[0], std::max(hh[1], hh[2])) / std::min(hh[0], std::min(hh[1], hh[2]));
+    if (!found || ratio < best_ratio || (ratio == best_ratio && cnt > best_cnt)) {
+      found = true;
+      best_ratio = ratio;
+      best_cnt = cnt;
+      for (int a = 0; a < 3; ++a) S[a] = (mask >> a) & 1;
+    }
+  }
+  return found;
+}
+
+int pyramid_plan(const int32_t n[3], const double h[3], int32_t levels, int32_t *levels_out, int32_t *n_out,
+                 double *h_out, int32_t *halve_out) {
+  if (!n || !h || !levels_out || !n_out || !h_out || !halve_out) return DISCO_ERR_ARG;
+  if (levels < 1 || levels > DISCO_MAX_LEVELS) return DISCO_ERR_ARG;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 4 || n[a] % 4 != 0) return DISCO_ERR_SHAPE;
+    if (!std::isfinite(h[a]) || !(h[a] > 0.0)) return DISCO_ERR_NONFINITE;
+  }
+  int L = 1;
+  for (int a = 0; a < 3; ++a) {
+    n_out[a] = n[a];
+    h_out[a] = h[a];
+    halve_out[a] = 0;
+  }
+  while (L < levels) {
+    int32_t S[3];
+    if (!pyr_halving(n_out + 3 * (L - 1), h_out + 3 * (L - 1), S)) break;
+    for (int a = 0; a < 3; ++a) {
+      n_out[3 * L + a] = S[a] ? n_out[3 * (L - 1) + a] / 2 : n_out[3 * (L - 1) + a];
+      h_out[3 * L + a] = S[a] ? h_out[3 * (L - 1) + a] * 2.0 : h_out[3 * (L - 1) + a];
+      halve_out[3 * L + a] = S[a];
+    }
+    ++L;
+  }
+  *levels_out = L;
+  return DISCO_OK;
+}
+
+// combined taps of one downsampling pass: Gaussian (sigma = 1 finer voxel, taps -3..3,
+// renormalised), then the mean of the two finer voxels a coarse voxel covers
+static DownTaps down_taps() {
+  double w[7], sum = 0.0;
+  for (int k = -3; k <= 3; ++k) {
+    w[k + 3] = std::exp(-0.5 * (double)(k * k));
+    sum += w[k + 3];
+  }
+  DownTaps t;
+  for (int m = -3; m <= 4; ++m) {
+    const double a = (m <= 3) ? w[m + 3] / sum : 0.0;
+    const double b = (m - 1 >= -3) ? w[m - 1 + 3] / sum : 0.0;
+    t.c[m + 3] = (float)(0.5 * (a + b));
+  }
+  return t;
+}
+
+int pyramid_downsample(const float *src, const int32_t n[3], const int32_t halve[3], float *dst, float *work,
+                       disco_stream stream) {
+  if (!src || !n || !halve || !dst) return DISCO_ERR_ARG;
+  int nh = 0;
+  for (int a = 0; a < 3; ++a) {
+    if (halve[a] != 0 && halve[a] != 1) return DISCO_ERR_ARG;
+    if (n[a] < 1 || (halve[a] && (n[a] < 2 || n[a] % 2 != 0))) return DISCO_ERR_SHAPE;
+    nh += halve[a];
+  }
+  if (nh == 0) return DISCO_ERR_ARG;
+  if (nh >= 2 && !work) return DISCO_ERR_ARG;
+  if (!aligned4(src) || !aligned4(dst) || (work && !aligned4(work))) return DISCO_ERR_SHAPE;
+  hipStream_t s = S(stream);
+  const DownTaps t = down_taps();
+  int dims[3] = {n[0], n[1], n[2]};
+  const int64_t N = (int64_t)n[0] * n[1] * n[2];
+  // pass outputs: work[0, N/2), then work[N/2, 3N/4), the last pass into dst
+  float *outs[2] = {work, work ? work + N / 2 : nullptr};
+  const float *in = src;
+  int done = 0;
+  for (int a = 0; a < 3; ++a) {
+    if (!halve[a]) continue;
+    float *out = (done == nh - 1) ? dst : outs[done];
+    int od[3] = {dims[0], dims[1], dims[2]};
+    od[a] /= 2;
+    const dim3 grid((unsigned)((od[0] + 255) / 256), (unsigned)od[1], (unsigned)od[2]);
+    if (a == 0)
+      hipLaunchKernelGGL(k_down_axis<0>, grid, dim3(256), 0, s, in, dims[0], dims[1], dims[2], out, t);
+    else if (a == 1)
+      hipLaunchKernelGGL(k_down_axis<1>, grid, dim3(256), 0, s, in, dims[0], dims[1], dims[2], out, t);
+    else
+      hipLaunchKernelGGL(k_down_axis<2>, grid, dim3(256), 0, s, in, dims[0], dims[1], dims[2], out, t);
+    dims[a] = od[a];
+    in = out;
+    ++done;
+  }
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+int pyramid_prolong(const float *uc, const int32_t nodes[3], const int32_t halve[3], float *uf, disco_stream stream) {
+  if (!uc || !nodes || !halve || !uf) return DISCO_ERR_ARG;
+  int f[3];
+  for (int a = 0; a < 3; ++a) {
+    if (halve[a] != 0 && halve[a] != 1) return DISCO_ERR_ARG;
+    if (nodes[a] < 2) return DISCO_ERR_SHAPE;
+    f[a] = halve[a] ? 2 * (nodes[a] - 1) + 1 : nodes[a];
+  }
+  if (!aligned4(uc) || !aligned4(uf)) return DISCO_ERR_SHAPE;
+  const dim3 grid((unsigned)((f[0] + 255) / 256), (unsigned)f[1], (unsigned)f[2]);
+  hipLaunchKernelGGL(k_prolong, grid, dim3(256), 0, S(stream), uc, nodes[0], nodes[1], nodes[2], halve[0], halve[1],
+                     halve[2], uf, f[0], f[1], f[2]);
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+// device buffers of a multilevel run, freed together
+extern "C++" {
+struct MlBuffers {
+  std::vector<void *> p;
+  ~MlBuffers() {
+    for (void *q : p)
+      if (q) (void)hipFree(q);
+  }
+  template <class T>
+  bool alloc(T **out, size_t count) {
+    void *q = nullptr;
+    if (hipMalloc(&q, count * sizeof(T)) != hipSuccess) return false;
+    p.push_back(q);
+    *out = static_cast<T *>(q);
+    return true;
+  }
+};
+}  // extern "C++"
+
+int multilevel_register(const disco_geom *geom, const float *R, const float *T, int32_t nkp, const float *kp_x,
+                        const float *kp_t, const disco_multilevel *cfg, float *u_out, double *report_dev,
+                        int32_t *levels_out, double *delta_out, disco_stream stream) {
+  if (!geom || !R || !T || !cfg || !u_out) return DISCO_ERR_ARG;
+  if (nkp < 0 || (nkp > 0 && (!kp_x || !kp_t))) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_params(&cfg->params))) {
+    // a negative delta is allowed when it is replaced by the adaptive one
+    disco_params q = cfg->params;
+    if (cfg->adaptive_delta) q.delta = 0.0;
+    if ((e = check_params(&q))) return e;
+  }
+  if (cfg->optimizer != DISCO_OPT_GN && cfg->optimizer != DISCO_OPT_LBFGS) return DISCO_ERR_ARG;
+  if (cfg->optimizer == DISCO_OPT_LBFGS && (e = check_lbfgs(&cfg->lbfgs))) return e;
+  if (cfg->storage != DISCO_STORAGE_FP32 && cfg->storage != DISCO_STORAGE_FP16) return DISCO_ERR_ARG;
+  if (!aligned4(R) || !aligned4(T) || !aligned4(u_out) ||
+      (report_dev && (reinterpret_cast<uintptr_t>(report_dev) & 7u) != 0))
+    return DISCO_ERR_SHAPE;
+  int32_t L = 0, ns[3 * DISCO_MAX_LEVELS], hv[3 * DISCO_MAX_LEVELS];
+  double hs[3 * DISCO_MAX_LEVELS];
+  if ((e = pyramid_plan(geom->n, geom->h, cfg->levels, &L, ns, hs, hv))) return e;
+  for (int l = 0; l < L; ++l)
+    if (cfg->iters[L - 1 - l] < 0) return DISCO_ERR_ARG;
+  int64_t rows = 0;
+  for (int l = 0; l < L; ++l) rows += cfg->iters[l];
+  hipStream_t s = S(stream);
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  MlBuffers B;
+  // level images (level 0 is the caller's), one work buffer for the downsampling passes
+  std::vector<const float *> Rl(L), Tl(L);
+  std::vector<float *> ul(L);
+  Rl[0] = R;
+  Tl[0] = T;
+  const int64_t N0 = (int64_t)ns[0] * ns[1] * ns[2];
+  float *work = nullptr;
+  if (L > 1 && !B.alloc(&work, (size_t)(N0 / 2 + N0 / 4 + 1))) return DISCO_ERR_NOMEM;
+  for (int l = 1; l < L; ++l) {
+    const int64_t Nl = (int64_t)ns[3 * l] * ns[3 * l + 1] * ns[3 * l + 2];
+    float *r = nullptr, *t = nullptr;
+    if (!B.alloc(&r, (size_t)Nl) || !B.alloc(&t, (size_t)Nl)) return DISCO_ERR_NOMEM;
+    if ((e = pyramid_downsample(Rl[l - 1], ns + 3 * (l - 1), hv + 3 * l, r, work, stream)) ||
+        (e = pyramid_downsample(Tl[l - 1], ns + 3 * (l - 1), hv + 3 * l, t, work, stream)))
+      return e;
+    Rl[l] = r;
+    Tl[l] = t;
+  }
+  for (int l = 0; l < L; ++l) {
+    const int64_t nn = 3LL * (ns[3 * l] / 4 + 1) * (ns[3 * l + 1] / 4 + 1) * (ns[3 * l + 2] / 4 + 1);
+    if (l == 0)
+      ul[0] = u_out;
+    else if (!B.alloc(&ul[l], (size_t)nn))
+      return DISCO_ERR_NOMEM;
+  }
+  double *scal = nullptr;  // D(0), K(0) of the adaptive keypoint weight
+  int32_t *st_dev = nullptr;
+  if (!B.alloc(&scal, 2) || !B.alloc(&st_dev, 1)) return DISCO_ERR_NOMEM;
+  // rows of iterations that are not run read as NaN
+  if (report_dev && rows > 0) HIP_TRY(hipMemsetAsync(report_dev, 0xFF, sizeof(double) * 16 * (size_t)rows, s));
+
+  disco_params prm = cfg->params;
+  double delta = cfg->adaptive_delta ? 0.0 : prm.delta;
+  int64_t row = 0;
+  disco_ctx *prev = nullptr;
+  for (int l = L - 1; l >= 0; --l) {
+    disco_geom gl;
+    for (int a = 0; a < 3; ++a) {
+      gl.n[a] = ns[3 * l + a];
+      gl.h[a] = hs[3 * l + a];
+    }
+    disco_ctx *c = nullptr;
+    HIP_TRY(hipSetDevice(dev));
+    if ((e = disco_create(&gl, cfg->storage, &c))) {
+      disco_destroy(prev);
+      return e;
+    }
+    auto fail = [&](int code) {
+      disco_destroy(c);
+      disco_destroy(prev);
+      return code;
+    };
+    const int64_t n3 = 3 * c->g.nnodes;
+    if ((e = disco_set_images(c, Rl[l], Tl[l], stream)) || (e = disco_set_keypoints(c, nkp, kp_x, kp_t, stream)))
+      return fail(e);
+    if (l == L - 1) {
+      hipLaunchKernelGGL(k_fill, dim3(nblk(n3)), dim3(256), 0, s, n3, ul[l], 0.0f);
+      if (cfg->adaptive_delta) {
+        // delta with D = delta K at the start of the registration (Sec. II-D2)
+        if ((e = ngf_eval(c, prm.eta, ul[l], scal, stream))) return fail(e);
+        if (nkp > 0 && (e = keypoint_penalty(c, 1.0, ul[l], scal + 1, nullptr, nullptr, nullptr, nullptr, stream)))
+          return fail(e);
+        double hsc[2] = {0.0, 0.0};
+        if (hipMemcpyAsync(hsc, scal, sizeof(double) * (nkp > 0 ? 2 : 1), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          return fail(DISCO_ERR_HIP);
+        delta = (nkp > 0 && hsc[1] > 0.0) ? hsc[0] / hsc[1] : 0.0;
+      }
+    } else {
+      const int32_t nc[3] = {prev->g.px, prev->g.py, prev->g.pz};
+      if ((e = pyramid_prolong(ul[l + 1], nc, hv + 3 * (l + 1), ul[l], stream))) return fail(e);
+    }
+    disco_destroy(prev);
+    prev = nullptr;
+    prm.delta = delta;
+    const int iters = cfg->iters[L - 1 - l];
+    for (int it = 0; it < iters; ++it) {
+      double *rep = report_dev ? report_dev + 16 * (row + it) : nullptr;
+      e = cfg->optimizer == DISCO_OPT_GN ? gn_pcg_step(c, &prm, ul[l], rep, st_dev, stream)
+                                         : lbfgs_step(c, &prm, &cfg->lbfgs, ul[l], rep, st_dev, stream);
+      if (e) return fail(e);
+      int32_t st = 0;
+      if (hipMemcpyAsync(&st, st_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return fail(DISCO_ERR_HIP);
+      if (st & DISCO_STATUS_LS_FAIL) break;  // no descent along this direction: next level
+    }
+    row += iters;
+    prev = c;
+  }
+  disco_destroy(prev);
+  if (levels_out) *levels_out = L;
+  if (delta_out) *delta_out = delta;
+  HIP_TRY(hipStreamSynchronize(s));
   return DISCO_OK;
 }
 

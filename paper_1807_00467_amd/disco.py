@@ -51,6 +51,16 @@ class _Lbfgs(ctypes.Structure):
                 ("m", ctypes.c_int32), ("h0_iters", ctypes.c_int32)]
 
 
+MAX_LEVELS = 8
+OPT_GN, OPT_LBFGS = 0, 1
+
+
+class _Multilevel(ctypes.Structure):
+    _fields_ = [("params", _Params), ("lbfgs", _Lbfgs), ("levels", ctypes.c_int32), ("optimizer", ctypes.c_int32),
+                ("adaptive_delta", ctypes.c_int32), ("storage", ctypes.c_int32),
+                ("iters", ctypes.c_int32 * MAX_LEVELS)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I = ctypes.c_int32
@@ -72,6 +82,11 @@ _SIGS = {
     "gn_pcg_step": ([_P, ctypes.POINTER(_Params), _P, _P, _P, _P], ctypes.c_int),
     "lbfgs_step": ([_P, ctypes.POINTER(_Params), ctypes.POINTER(_Lbfgs), _P, _P, _P, _P], ctypes.c_int),
     "lbfgs_reset": ([_P], ctypes.c_int),
+    "pyramid_plan": ([_P, _P, _I, _P, _P, _P, _P], ctypes.c_int),
+    "pyramid_downsample": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
+    "pyramid_prolong": ([_P, _P, _P, _P, _P], ctypes.c_int),
+    "multilevel_register": ([ctypes.POINTER(_Geom), _P, _P, _I, _P, _P, ctypes.POINTER(_Multilevel), _P, _P, _P,
+                             _P, _P], ctypes.c_int),
     "disco_copy_buffer": ([_P, _I, _P, _P], ctypes.c_int),
     "disco_profile": ([_P, _I], ctypes.c_int),
     "disco_profile_read": ([_P, _I, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_D)], ctypes.c_int),
@@ -388,3 +403,96 @@ class Batch:
 
 def status_string(code: int) -> str:
     return _lib.disco_status_string(code).decode()
+
+
+# ---- multilevel scheme (Sec. II-D3) ----------------------------------------------------
+
+def _i3(v):
+    return (ctypes.c_int32 * 3)(*[int(x) for x in v])
+
+
+def pyramid_plan(shape: Sequence[int], spacing: Sequence[float], levels: int):
+    """Host-only: list of (shape (Nx, Ny, Nz), spacing, halve) per level, finest first."""
+    n_out = (ctypes.c_int32 * (3 * levels))()
+    h_out = (ctypes.c_double * (3 * levels))()
+    hv_out = (ctypes.c_int32 * (3 * levels))()
+    L = ctypes.c_int32()
+    _check(_lib.pyramid_plan(_i3(shape), (ctypes.c_double * 3)(*[float(h) for h in spacing]), levels,
+                             ctypes.byref(L), n_out, h_out, hv_out), "pyramid_plan")
+    return [(tuple(n_out[3 * l:3 * l + 3]), tuple(h_out[3 * l:3 * l + 3]), tuple(hv_out[3 * l:3 * l + 3]))
+            for l in range(L.value)]
+
+
+def _stream_of(t: torch.Tensor):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def pyramid_downsample(img: torch.Tensor, halve: Sequence[int]) -> torch.Tensor:
+    """One pyramid step of a float32 CUDA volume [Nz][Ny][Nx]."""
+    if img.dtype != torch.float32 or not img.is_cuda or not img.is_contiguous() or img.dim() != 3:
+        raise ValueError("img must be a contiguous float32 CUDA tensor [Nz][Ny][Nx]")
+    nz, ny, nx = img.shape
+    out_shape = tuple(n // 2 if h else n for n, h in zip((nz, ny, nx), tuple(halve)[::-1]))
+    out = torch.empty(out_shape, dtype=torch.float32, device=img.device)
+    work = None
+    if sum(int(h) for h in halve) >= 2:
+        work = torch.empty(img.numel() // 2 + img.numel() // 4 + 1, dtype=torch.float32, device=img.device)
+    _check(_lib.pyramid_downsample(_ptr(img), _i3((nx, ny, nz)), _i3(halve), _ptr(out), _ptr(work),
+                                   _stream_of(img)), "pyramid_downsample")
+    return out
+
+
+def pyramid_prolong(uc: torch.Tensor, halve: Sequence[int]) -> torch.Tensor:
+    """Node field [3][nz][ny][nx] of a coarse level to the next finer level."""
+    if uc.dtype != torch.float32 or not uc.is_cuda or not uc.is_contiguous() or uc.dim() != 4 or uc.shape[0] != 3:
+        raise ValueError("uc must be a contiguous float32 CUDA tensor [3][nz][ny][nx]")
+    _, nz, ny, nx = uc.shape
+    f = tuple(2 * (n - 1) + 1 if h else n for n, h in zip((nx, ny, nz), halve))
+    out = torch.empty((3, f[2], f[1], f[0]), dtype=torch.float32, device=uc.device)
+    _check(_lib.pyramid_prolong(_ptr(uc), _i3((nx, ny, nz)), _i3(halve), _ptr(out), _stream_of(uc)),
+           "pyramid_prolong")
+    return out
+
+
+@dataclasses.dataclass
+class Multilevel:
+    """Coarse-to-fine settings: levels requested, optimiser ("lbfgs" or "gn"), iterations
+    per level (coarsest built level first), adaptive keypoint weight, storage."""
+    levels: int = 4
+    optimizer: str = "lbfgs"
+    iters: Sequence[int] = (10, 10, 10, 10)
+    adaptive_delta: bool = True
+    storage: str = "fp32"
+
+
+def multilevel_register(R: torch.Tensor, T: torch.Tensor, spacing: Sequence[float], kp_x, kp_t, params: Params,
+                        ml: Multilevel, lbfgs: Optional[Lbfgs] = None):
+    """Whole coarse-to-fine registration on the device.  Returns (u on the finest level,
+    reports [rows][16] float64 with NaN rows for iterations not run, levels, delta)."""
+    import numpy as np
+    for t in (R, T):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 3:
+            raise ValueError("R and T must be contiguous float32 CUDA tensors [Nz][Ny][Nx]")
+    if R.shape != T.shape:
+        raise ValueError("R and T differ in shape")
+    nz, ny, nx = R.shape
+    g = _Geom((ctypes.c_int32 * 3)(nx, ny, nz), (ctypes.c_double * 3)(*[float(h) for h in spacing]))
+    if len(ml.iters) > MAX_LEVELS:
+        raise ValueError("too many levels")
+    its = (ctypes.c_int32 * MAX_LEVELS)(*([int(i) for i in ml.iters] + [0] * (MAX_LEVELS - len(ml.iters))))
+    cfg = _Multilevel(params.c(), (lbfgs or Lbfgs()).c(), ml.levels, OPT_LBFGS if ml.optimizer == "lbfgs" else OPT_GN,
+                      1 if ml.adaptive_delta else 0, STORAGE_FP16 if ml.storage == "fp16" else STORAGE_FP32, its)
+    x = np.ascontiguousarray(np.asarray(kp_x, dtype=np.float32).reshape(-1, 3))
+    t = np.ascontiguousarray(np.asarray(kp_t, dtype=np.float32).reshape(-1, 3))
+    if x.shape != t.shape:
+        raise ValueError("keypoints and targets differ in shape")
+    u = torch.empty((3, nz // 4 + 1, ny // 4 + 1, nx // 4 + 1), dtype=torch.float32, device=R.device)
+    rows = sum(int(i) for i in ml.iters[:ml.levels])
+    rep = torch.empty((max(rows, 1), 16), dtype=torch.float64, device=R.device)
+    L = ctypes.c_int32()
+    delta = ctypes.c_double()
+    with torch.cuda.device(R.device):
+        _check(_lib.multilevel_register(ctypes.byref(g), _ptr(R), _ptr(T), len(x), x.ctypes.data_as(_P),
+                                        t.ctypes.data_as(_P), ctypes.byref(cfg), _ptr(u), _ptr(rep), ctypes.byref(L),
+                                        ctypes.byref(delta), _stream_of(R)), "multilevel_register")
+    return u, rep[:rows], L.value, delta.value
