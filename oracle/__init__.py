@@ -5,10 +5,11 @@ import this package.  It never imports the GPU library and the GPU library never
 imports it; both receive the same seeded inputs from ``synth``.
 
 The element-wise work is in ``disco_oracle.c`` (plain loops, double precision).
-This module composes the joint objective (eq. 11 with beta = 0)
+This module composes the joint objective of eq. 11
 
-    J(u) = D(u) + alpha S(u) + gamma Vhat(u) + delta K(u)
+    J(u) = D(u) + alpha S(u) + beta B(u) + gamma Vhat(u) + delta K(u)
 
+(the lung-boundary term B only when masks are given and beta != 0)
 its gradient, the Gauss-Newton matrix-vector product, the adaptive keypoint weight
 (Sec. II-D2: delta such that D = delta K at the start), and one Gauss-Newton step
 with a Jacobi-preconditioned CG solve and Armijo backtracking.
@@ -72,6 +73,8 @@ def _load():
         lib.or_det_voxels.restype = None
         lib.or_ngf_grad_T.argtypes = [P, P, P, D, P, P, P, P]
         lib.or_ngf_grad_T.restype = None
+        lib.or_mask.argtypes = [P, P, P, P, P, P, P, P, P, P]
+        lib.or_mask.restype = D
         lib.or_num_threads.argtypes = []
         lib.or_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -171,6 +174,32 @@ def ngf_hv(s, spacing, v, m=(4, 4, 4)):
     return out
 
 
+def mask_term(bF, bM, spacing, u, m=(4, 4, 4), want=("g", "diag", "sb", "res")):
+    """Lung-boundary term of eq. 6 and its derivatives: B, and the requested arrays
+    (g, diag: node fields; sb: [N][3] gradient of the interpolated moving mask at the
+    warped voxel; res: [N] residual b_M(y) - b_F)."""
+    bF = _f64(bF)
+    bM = _f64(bM)
+    nz, ny, nx = bF.shape
+    nn = [nx // m[0] + 1, ny // m[1] + 1, nz // m[2] + 1]
+    u = _f64(u)
+    assert u.shape == (3, nn[2], nn[1], nn[0]), (u.shape, nn)
+    g = np.empty((3, nn[2], nn[1], nn[0])) if "g" in want else None
+    diag = np.empty((3, nn[2], nn[1], nn[0])) if "diag" in want else None
+    sb = np.empty((nz, ny, nx, 3)) if "sb" in want else None
+    res = np.empty((nz, ny, nx)) if "res" in want else None
+    B = _load().or_mask(_p(_i64([nx, ny, nz])), _p(_f64(spacing)), _p(_i64(m)), _p(bF), _p(bM), _p(u), _p(g),
+                        _p(diag), _p(sb), _p(res))
+    return dict(B=B, g=g, diag=diag, sb=sb, res=res)
+
+
+def mask_hv(sb, spacing, v, m=(4, 4, 4)):
+    """Gauss-Newton product of the lung-boundary term, h^3 sum_v phi_v sb_v (sb_v . Pv):
+    the NGF product routine computes 2 h^3 sum_v phi_v s_v (s_v . Pv), so it is called
+    with s = sb / sqrt(2)."""
+    return ngf_hv(_f64(sb) * np.sqrt(0.5), spacing, v, m)
+
+
 def curvature(w, H):
     """S(w) (eq. 5 on the node grid), C_H L^T L w, C_H diag(L^T L)."""
     w = _f64(w)
@@ -241,13 +270,14 @@ class Weights:
     alpha: float = 1.0
     gamma: float = 0.1
     delta: float = 0.0
+    beta: float = 0.0     # lung-boundary weight (eq. 6, eq. 11); needs masks
 
 
 class Problem:
     """One registration pair: J(u) = D + alpha S + gamma Vhat + delta K."""
 
     def __init__(self, R, T, spacing, kp_x=None, kp_t=None, weights: Weights = Weights(),
-                 u_ref=None, m=(4, 4, 4)):
+                 u_ref=None, m=(4, 4, 4), bF=None, bM=None):
         self.spacing = tuple(float(s) for s in spacing)
         self.m = tuple(int(a) for a in m)
         self.shape = (R.shape[2], R.shape[1], R.shape[0])
@@ -260,7 +290,10 @@ class Problem:
         nn = node_shape(self.shape)
         self.nodes = nn
         self.u_ref = np.zeros((3, nn[2], nn[1], nn[0])) if u_ref is None else _f64(u_ref)
+        self.bF = None if bF is None else _f64(bF)
+        self.bM = None if bM is None else _f64(bM)
         self._s = None
+        self._sb = None
 
     # individual terms ---------------------------------------------------------------
     def ngf(self, u, want=("g", "diag", "s", "r", "c")):
@@ -278,6 +311,18 @@ class Problem:
             return dict(K=0.0, g=z, diag=z.copy(), Hv=None if v is None else z.copy())
         return keypoints(u, self.H, self.kp_x, self.kp_t, v)
 
+    def mask(self, u, want=("g", "diag", "sb", "res")):
+        if self.bF is None:
+            z = np.zeros_like(_f64(u))
+            return dict(B=0.0, g=z, diag=z.copy(), sb=None, res=None)
+        return mask_term(self.bF, self.bM, self.spacing, u, self.m, want)
+
+    def adaptive_beta(self, u0):
+        """beta such that D = 100 beta B at the start of the registration (Sec. II-D2)."""
+        D = self.ngf(u0, want=())["D"]
+        B = self.mask(u0, want=())["B"]
+        return D / (100.0 * B) if B > 0 else 0.0
+
     def adaptive_delta(self, u0):
         """delta such that D = delta K at the start of the registration (Sec. II-D2)."""
         D = self.ngf(u0, want=())["D"]
@@ -292,11 +337,12 @@ class Problem:
         S = self.curvature(u)["S"]
         vc = self.vcc(u)
         K = self.keypoints(u)["K"]
+        B = self.mask(u, want=())["B"] if w.beta != 0.0 else 0.0
         # Vhat = +inf on a fold (eq. 9); the term only exists when gamma > 0
         folded = vc["nfold"] > 0 and w.gamma != 0.0
         vterm = w.gamma * vc["V"] if w.gamma != 0.0 else 0.0
-        J = np.inf if folded else D + w.alpha * S + vterm + w.delta * K
-        return dict(J=J, D=D, S=S, V=vc["V"], K=K, nfold=vc["nfold"])
+        J = np.inf if folded else D + w.alpha * S + w.beta * B + vterm + w.delta * K
+        return dict(J=J, D=D, S=S, V=vc["V"], K=K, B=B, nfold=vc["nfold"])
 
     def linearise(self, u):
         """Objective, gradient and GN diagonal at u; keeps s for gn_hv."""
@@ -309,15 +355,22 @@ class Problem:
         self._u = _f64(u).copy()
         g = nd["g"] + w.alpha * cv["g"] + w.delta * kp["g"]
         diag = nd["diag"] + w.alpha * cv["diag"] + w.delta * kp["diag"]
+        B = 0.0
+        if w.beta != 0.0:
+            mk = self.mask(u)
+            self._sb = mk["sb"]
+            B = mk["B"]
+            g = g + w.beta * mk["g"]
+            diag = diag + w.beta * mk["diag"]
         if w.gamma != 0.0:
             g = g + w.gamma * vc["g"]
             diag = diag + w.gamma * vc["diag"]
         folded = vc["nfold"] > 0 and w.gamma != 0.0
         vterm = w.gamma * vc["V"] if w.gamma != 0.0 else 0.0
-        J = np.inf if folded else nd["D"] + w.alpha * cv["S"] + vterm + w.delta * kp["K"]
-        return dict(J=J, D=nd["D"], S=cv["S"], V=vc["V"], K=kp["K"], nfold=vc["nfold"], g=g, diag=diag)
+        J = np.inf if folded else nd["D"] + w.alpha * cv["S"] + w.beta * B + vterm + w.delta * kp["K"]
+        return dict(J=J, D=nd["D"], S=cv["S"], V=vc["V"], K=kp["K"], B=B, nfold=vc["nfold"], g=g, diag=diag)
 
-    def gn_hv(self, v, terms=("D", "S", "V", "K")):
+    def gn_hv(self, v, terms=("D", "S", "V", "K", "B")):
         """Gauss-Newton matrix of eq. 11 times v, at the last linearisation point."""
         assert self._s is not None, "call linearise first"
         w = self.w
@@ -331,6 +384,8 @@ class Problem:
             out += w.gamma * vcc(self._u, self.H, v)["Hv"]
         if "K" in terms and w.delta != 0.0:
             out += w.delta * self.keypoints(self._u, v)["Hv"]
+        if "B" in terms and w.beta != 0.0:
+            out += w.beta * mask_hv(self._sb, self.spacing, v, self.m)
         return out
 
 
@@ -400,7 +455,7 @@ def gn_pcg_step(prob: Problem, u, params: StepParams = StepParams()):
             break
         t *= 0.5
     u_new = _f64(u) + t * p if accepted else _f64(u).copy()
-    rep = dict(J=lin["J"], D=lin["D"], S=lin["S"], V=lin["V"], K=lin["K"],
+    rep = dict(J=lin["J"], D=lin["D"], S=lin["S"], V=lin["V"], K=lin["K"], B=lin["B"],
                gnorm=float(np.sqrt(np.sum(g * g))), t=t if accepted else 0.0, accepted=accepted,
                p=p, gtp=gtp, pcg=info, trial=trial, g=g, diag=lin["diag"])
     return u_new, rep

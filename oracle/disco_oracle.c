@@ -838,3 +838,94 @@ void or_ngf_grad_T(const int64_t *n, const double *h, const int64_t *m, double e
     free(cell);
     free(qq);
 }
+
+/* ------------------------------------------------------------------------------ */
+/* Lung-boundary term, eq. 6: B = 1/2 int (b_M(y(x)) - b_F(x))^2 dx with the binary  */
+/* masks b_F (fixed, at the voxel centres) and b_M (moving, sampled at y(x_v) by      */
+/* trilinear interpolation with zero outside the volume, like grad T in eq. 1, in the  */
+/* cell decided by decide_cells_f32):                                                 */
+/*   res_v = b_M(y_v) - b_F(x_v),   B = 1/2 h^3 sum_v res_v^2.                        */
+/* With sb_v = grad b_M(y_v) (the gradient of the trilinear interpolant in mm,        */
+/* inside the decided cell):                                                          */
+/*   grad B = h^3 sum_v phi_v res_v sb_v,                                             */
+/*   Gauss-Newton matrix h^3 J^T J with J_v = phi_v sb_v^T (exact form of the SSD     */
+/*   Gauss-Newton matrix), diagonal h^3 sum_v phi_v^2 sb_v^2.                          */
+/* bF, bM are [N] volumes; u a node field; g, diag, sb ([N][3]), res ([N]) optional.  */
+/* Returns B.                                                                          */
+/* ------------------------------------------------------------------------------ */
+static void sample_scalar_at(const int64_t *n, const double *h, const double *f, const double q[3],
+                             const int64_t i0[3], double *val, double grad[3])
+{
+    double t[3];
+    for (int a = 0; a < 3; ++a) t[a] = q[a] - (double)i0[a];
+    *val = 0.0;
+    grad[0] = grad[1] = grad[2] = 0.0;
+    for (int cz = 0; cz < 2; ++cz)
+        for (int cy = 0; cy < 2; ++cy)
+            for (int cx = 0; cx < 2; ++cx) {
+                int64_t ii = i0[0] + cx, jj = i0[1] + cy, kk = i0[2] + cz;
+                if (ii < 0 || ii >= n[0] || jj < 0 || jj >= n[1] || kk < 0 || kk >= n[2]) continue;
+                const double fv = f[IDX3(ii, jj, kk, n[0], n[1])];
+                double wx = cx ? t[0] : 1.0 - t[0], dwx = cx ? 1.0 : -1.0;
+                double wy = cy ? t[1] : 1.0 - t[1], dwy = cy ? 1.0 : -1.0;
+                double wz = cz ? t[2] : 1.0 - t[2], dwz = cz ? 1.0 : -1.0;
+                *val += wx * wy * wz * fv;
+                grad[0] += dwx * wy * wz * fv / h[0];
+                grad[1] += wx * dwy * wz * fv / h[1];
+                grad[2] += wx * wy * dwz * fv / h[2];
+            }
+}
+
+double or_mask(const int64_t *n, const double *h, const int64_t *m, const double *bF, const double *bM,
+               const double *u, double *g, double *diag, double *sb_out, double *res_out)
+{
+    const int64_t nx = n[0], ny = n[1], nz = n[2];
+    const int64_t nvox = nx * ny * nz;
+    int64_t nn[3];
+    node_counts(n, m, nn);
+    const int64_t nnodes = nn[0] * nn[1] * nn[2];
+    const double h3 = h[0] * h[1] * h[2];
+    double *res = (double *)malloc(sizeof(double) * nvox);
+    double *sb = (double *)malloc(sizeof(double) * 3 * nvox);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                const int64_t v = IDX3(i, j, k, nx, ny);
+                double uv[3], q[3], val;
+                interp_voxel(nn, m, u, i, j, k, uv);
+                q[0] = (double)i + uv[0] / h[0];
+                q[1] = (double)j + uv[1] / h[1];
+                q[2] = (double)k + uv[2] / h[2];
+                int64_t i0[3];
+                decide_cells_f32(nn, m, n, h, u, i, j, k, i0);
+                sample_scalar_at(n, h, bM, q, i0, &val, sb + 3 * v);
+                res[v] = val - bF[v];
+            }
+    double B = 0.0;
+    for (int64_t v = 0; v < nvox; ++v) B += res[v] * res[v];
+    B *= 0.5 * h3;
+    if (g) memset(g, 0, sizeof(double) * 3 * nnodes);
+    if (diag) memset(diag, 0, sizeof(double) * 3 * nnodes);
+    if (g || diag) {
+        for (int64_t k = 0; k < nz; ++k)
+            for (int64_t j = 0; j < ny; ++j)
+                for (int64_t i = 0; i < nx; ++i) {
+                    const int64_t v = IDX3(i, j, k, nx, ny);
+                    double val[3];
+                    if (g) {
+                        for (int t = 0; t < 3; ++t) val[t] = h3 * res[v] * sb[3 * v + t];
+                        scatter_voxel(nn, m, g, i, j, k, val, 0);
+                    }
+                    if (diag) {
+                        for (int t = 0; t < 3; ++t) val[t] = h3 * sb[3 * v + t] * sb[3 * v + t];
+                        scatter_voxel(nn, m, diag, i, j, k, val, 1);
+                    }
+                }
+    }
+    if (sb_out) memcpy(sb_out, sb, sizeof(double) * 3 * nvox);
+    if (res_out) memcpy(res_out, res, sizeof(double) * nvox);
+    free(res);
+    free(sb);
+    return B;
+}

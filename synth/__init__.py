@@ -367,12 +367,16 @@ def _phantom(cfg: PairConfig, rng: np.random.Generator) -> Tuple[np.ndarray, np.
     return vol, lung
 
 
-def _warp_moving(R: np.ndarray, field: Field, cfg: PairConfig) -> np.ndarray:
-    """T(z) = (R(psi(z)) + 1000) det(grad psi(z)) - 1000, evaluated slab by slab."""
+def _warp_moving(R: np.ndarray, field: Field, cfg: PairConfig, lung: Optional[np.ndarray] = None):
+    """T(z) = (R(psi(z)) + 1000) det(grad psi(z)) - 1000, evaluated slab by slab; with the
+    fixed lung mask given, also the moving lung mask (lung(psi(z)) by linear interpolation,
+    thresholded at 1/2) as uint8."""
     nx, ny, nz = cfg.shape
     h = np.asarray(cfg.spacing)
     xs, ys, zs = _axes_mm(cfg.shape, cfg.spacing)
     T = np.empty_like(R)
+    mT = None if lung is None else np.empty(R.shape, np.uint8)
+    lf = None if lung is None else lung.astype(np.float32)
     slab = max(1, int(4_000_000 // (nx * ny)))
     for k0 in range(0, nz, slab):
         k1 = min(nz, k0 + slab)
@@ -384,7 +388,10 @@ def _warp_moving(R: np.ndarray, field: Field, cfg: PairConfig) -> np.ndarray:
         coords = np.stack([qz.ravel(), qy.ravel(), qx.ravel()], axis=0).astype(np.float32)
         Rw = ndimage.map_coordinates(R, coords, order=1, mode="nearest").reshape(w[0].shape)
         T[k0:k1] = ((Rw + 1000.0) * det - 1000.0).astype(np.float32)
-    return T
+        if lf is not None:
+            mw = ndimage.map_coordinates(lf, coords, order=1, mode="nearest").reshape(w[0].shape)
+            mT[k0:k1] = (mw >= 0.5).astype(np.uint8)
+    return T if lung is None else (T, mT)
 
 
 def random_direction(nodes: Tuple[int, int, int], seed: int) -> np.ndarray:
@@ -399,7 +406,8 @@ def make_pair(cfg: PairConfig | str, seed: Optional[int] = None) -> dict:
 
     Returns a dict with R, T (float32 [Nz][Ny][Nx]), shape, spacing, nodes,
     u_true (float32 [3][nz][ny][nx]), kp_x, kp_t (float32 [n][3], mm),
-    v (float32 node field for Hessian-vector tests), min_det of grad psi.
+    v (float32 node field for Hessian-vector tests), min_det of grad psi, and the binary
+    lung masks mask_R, mask_T (uint8 [Nz][Ny][Nx]) of the fixed and moving images.
     """
     if isinstance(cfg, str):
         cfg = CONFIGS[cfg]
@@ -411,7 +419,7 @@ def make_pair(cfg: PairConfig | str, seed: Optional[int] = None) -> dict:
     rng = np.random.default_rng(cfg.seed)
     R, lung = _phantom(cfg, rng)
     field = Field(cfg, rng)
-    T = _warp_moving(R, field, cfg)
+    T, mask_T = _warp_moving(R, field, cfg, lung)
     nodes = node_shape(cfg.shape)
     H = np.asarray(cfg.spacing) * CELL
     pz, py, px = np.meshgrid(np.arange(nodes[2]), np.arange(nodes[1]), np.arange(nodes[0]), indexing="ij")
@@ -434,7 +442,7 @@ def make_pair(cfg: PairConfig | str, seed: Optional[int] = None) -> dict:
     v = random_direction(nodes, cfg.seed + 1000)
     return dict(R=R, T=T, shape=cfg.shape, spacing=cfg.spacing, nodes=nodes,
                 u_true=u_true, kp_x=kp_x.astype(np.float32), kp_t=kp_t.astype(np.float32),
-                v=v, lung=lung, min_det=field.min_det, cfg=cfg)
+                v=v, lung=lung, mask_R=lung.astype(np.uint8), mask_T=mask_T, min_det=field.min_det, cfg=cfg)
 
 
 def small_pair(shape=(16, 16, 12), spacing=(1.5, 1.5, 1.5), seed=0, n_tubes=6, n_kp=20,

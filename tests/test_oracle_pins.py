@@ -788,3 +788,116 @@ def test_multilevel_run_decreases_objective_on_every_level():
         r = lv["reports"]
         assert r[-1]["J_new"] < r[0]["J"]
     assert u.shape == (3, 7, 9, 9)
+
+
+# ---- lung-boundary term (eq. 6) ---------------------------------------------------------
+
+def mask_case(seed=12, shape=(16, 16, 12), spacing=(1.5, 1.5, 2.0)):
+    d = synth.small_pair(shape=shape, spacing=spacing, seed=seed, n_tubes=4, n_kp=10, field_max=4.0)
+    return d, d["mask_R"].astype(np.float64), d["mask_T"].astype(np.float64)
+
+
+def test_mask_term_zero_for_identical_masks():
+    d, bF, _ = mask_case()
+    u = np.zeros_like(d["u_true"], np.float64)
+    res = oracle.mask_term(bF, bF, d["spacing"], u)
+    assert res["B"] == 0.0 and np.all(res["g"] == 0.0) and np.all(res["res"] == 0.0)
+
+
+def test_mask_term_integer_translation_brute_force():
+    """b_M(z) = b_F(z - k h_x e_x) and u = k h_x e_x: inside, b_M(y(x)) = b_F(x); the last
+    k voxel columns sample beyond the volume (zero), so B = 1/2 h^3 sum of b_F there."""
+    d, _, _ = mask_case(13)
+    bF = (rng(13).random(d["mask_R"].shape) > 0.5).astype(np.float64)  # reaches every border
+    h = d["spacing"]
+    k = 2
+    bM = np.zeros_like(bF)
+    bM[:, :, k:] = bF[:, :, :-k]
+    u = np.zeros_like(d["u_true"], np.float64)
+    u[0] = k * h[0]
+    res = oracle.mask_term(bF, bM, h, u)
+    expect = 0.5 * np.prod(h) * np.sum(bF[:, :, -k:] ** 2)
+    assert expect > 0
+    assert abs(res["B"] - expect) <= 1e-12 * expect
+    np.testing.assert_array_equal(res["res"][:, :, :-k], 0.0)
+
+
+def test_mask_sampling_matches_grid_sample():
+    d, bF, bM = mask_case(14)
+    h = d["spacing"]
+    u = d["u_true"].astype(np.float64) * 0.8 + 0.031
+    res = oracle.mask_term(bF, bM, h, u)
+    nx, ny, nz = d["shape"]
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    vox = np.stack([(i + 0.5) * h[0], (j + 0.5) * h[1], (k + 0.5) * h[2]], -1).reshape(-1, 3)
+    uv = trilinear_nodes(u, [4 * s for s in h], vox)
+    q = (vox + uv) / np.array(h) - 0.5
+    ref = grid_sample_vec(np.repeat(bM[..., None], 3, axis=-1), q)[:, 0]
+    np.testing.assert_allclose(res["res"].ravel() + bF.ravel(), ref, rtol=0, atol=1e-12)
+    # the interpolant's gradient: central differences of the library sampler in mm
+    eps = 1e-6
+    for a in range(3):
+        dq = np.zeros(3)
+        dq[a] = eps / h[a]
+        fd = (grid_sample_vec(np.repeat(bM[..., None], 3, -1), q + dq)[:, 0]
+              - grid_sample_vec(np.repeat(bM[..., None], 3, -1), q - dq)[:, 0]) / (2 * eps)
+        # points within eps of a cell face have a one-sided derivative: skip them
+        frac = q[:, a] - np.floor(q[:, a])
+        okp = (frac > 1e-4) & (frac < 1 - 1e-4)
+        np.testing.assert_allclose(res["sb"].reshape(-1, 3)[okp, a], fd[okp], rtol=0, atol=1e-7)
+
+
+def test_mask_gradient_matches_finite_differences():
+    d, bF, bM = mask_case(15)
+    h = d["spacing"]
+    u = d["u_true"].astype(np.float64) * 0.7 + 0.023
+    g = oracle.mask_term(bF, bM, h, u)["g"]
+    err = _fd_check(lambda x: oracle.mask_term(bF, bM, h, x, want=())["B"], g, u, random_coords(u.shape, 25, 3))
+    assert err < 1e-5
+
+
+def test_mask_gauss_newton_matrix_dense_brute_force_8cubed():
+    """h^3 J^T J with J from finite differences of the residual equals the oracle's GN
+    product (columns) and diagonal; symmetric positive semi-definite."""
+    d = synth.small_pair(shape=(8, 8, 8), spacing=(2.0, 2.0, 2.0), seed=16, n_tubes=3, n_kp=4, field_max=3.0)
+    bF = d["mask_R"].astype(np.float64)
+    bM = d["mask_T"].astype(np.float64)
+    if bF.sum() == 0:
+        bF[2:6, 2:6, 2:6] = 1.0
+        bM[3:7, 2:6, 1:5] = 1.0
+    h = d["spacing"]
+    u = d["u_true"].astype(np.float64) * 0.6 + 0.017
+    res = oracle.mask_term(bF, bM, h, u)
+    n = u.size
+    Jm = np.empty((bF.size, n))
+    eps = 1e-6
+    for col in range(n):
+        e = np.zeros(n)
+        e[col] = eps
+        e = e.reshape(u.shape)
+        rp = oracle.mask_term(bF, bM, h, u + e, want=("res",))["res"].ravel()
+        rm = oracle.mask_term(bF, bM, h, u - e, want=("res",))["res"].ravel()
+        Jm[:, col] = (rp - rm) / (2 * eps)
+    Hd = np.prod(h) * Jm.T @ Jm
+    Ho = np.stack([oracle.mask_hv(res["sb"], h, np.eye(n)[c].reshape(u.shape)).ravel() for c in range(n)], 1)
+    assert np.linalg.norm(Hd) > 0
+    assert np.linalg.norm(Ho - Hd) / np.linalg.norm(Hd) < 1e-6
+    np.testing.assert_allclose(res["diag"].ravel(), np.diag(Ho), rtol=1e-12, atol=1e-12 * np.max(np.diag(Ho)))
+    assert np.linalg.eigvalsh(0.5 * (Ho + Ho.T)).min() > -1e-10 * np.abs(Ho).max()
+
+
+def test_problem_with_boundary_term_and_adaptive_beta():
+    """J includes beta B; the adaptive beta gives D = 100 beta B at u = 0 (Sec. II-D2); the
+    GN step with the term decreases J."""
+    d, bF, bM = mask_case(17, shape=(24, 24, 16))
+    P = oracle.Problem(d["R"], d["T"], d["spacing"], d["kp_x"], d["kp_t"], oracle.Weights(eta=10.0, alpha=1.0,
+                       gamma=0.1, delta=0.0), bF=bF, bM=bM)
+    u0 = np.zeros_like(d["u_true"], np.float64)
+    beta = P.adaptive_beta(u0)
+    P.w.beta = beta
+    o = P.objective(u0)
+    assert abs(o["D"] - 100.0 * beta * o["B"]) <= 1e-12 * o["D"]
+    P0 = oracle.Problem(d["R"], d["T"], d["spacing"], weights=oracle.Weights(eta=10.0, alpha=1.0, gamma=0.1))
+    assert abs(o["J"] - (P0.objective(u0)["J"] + beta * o["B"])) <= 1e-12 * o["J"]
+    u1, rep = oracle.gn_pcg_step(P, u0, oracle.StepParams(pcg_iters=10))
+    assert rep["accepted"] and rep["trial"]["J"] < rep["J"]
