@@ -162,7 +162,7 @@ def main():
                           pcg_iters=PCG_ITERS, pcg_tol=0.0, ls_max=10)
     log(f"[bench] delta = {params.delta:.4g}")
     u = torch.empty_like(u_true)
-    rep = torch.zeros(16, dtype=torch.float64, device=dev)
+    rep = torch.zeros(disco.REP_SIZE, dtype=torch.float64, device=dev)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def step():
@@ -269,7 +269,7 @@ def bench_lbfgs(args):
                           flags=disco.FLAG_LS_DEVICE)
     lb = disco.Lbfgs(m=5, tau=args.tau, h0_iters=30, h0_tol=1e-6)
     u = zero.clone()
-    rep = torch.zeros(16, dtype=torch.float64, device=dev)
+    rep = torch.zeros(disco.REP_SIZE, dtype=torch.float64, device=dev)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
     for _ in range(args.warmup):
         ctx.lbfgs_reset()

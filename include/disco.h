@@ -84,7 +84,9 @@ extern "C" {
 #define DISCO_REP_V_NEW 13
 #define DISCO_REP_K_NEW 14
 #define DISCO_REP_LS_TRIALS 15
-#define DISCO_REP_SIZE 16
+#define DISCO_REP_B 16       /* lung-boundary term B(u) (eq. 6; 0 without masks) */
+#define DISCO_REP_B_NEW 17
+#define DISCO_REP_SIZE 18
 
 typedef struct {
     int32_t n[3]; /* voxels Nx, Ny, Nz (multiples of 4) */
@@ -102,6 +104,7 @@ typedef struct {
     int32_t pcg_iters; /* CG iterations, >= 1 */
     int32_t ls_max;    /* maximum number of line-search trials (t = 1, 1/2, ...), >= 1 */
     int32_t flags;     /* DISCO_FLAG_* */
+    double beta;       /* lung-boundary weight (eq. 6, eq. 11), >= 0; used only with masks set */
 } disco_params;
 
 /* L-BFGS settings (Sec. II-D3) */
@@ -153,6 +156,23 @@ int ngf_grad(disco_ctx *ctx, double eta, const float *u, double *D_dev, float *g
    gn_pcg_step); DISCO_ERR_STATE if there is none. */
 int ngf_hessvec(disco_ctx *ctx, const float *v, float *Hv, disco_stream stream);
 
+/* Set the binary lung masks b_F of R and b_M of T (device uint8 [Nz][Ny][Nx], values 0
+   or 1) of the lung-boundary term of eq. 6, copied into the context; both NULL clears
+   them.  With masks set and params->beta != 0, the objective, gradient and GN products
+   of gn_pcg_step, gn_hessvec, lbfgs_step and objective_linearise include
+   beta B = beta/2 h^3 sum_v (b_M(y(x_v)) - b_F(x_v))^2, b_M sampled trilinearly at the
+   warped voxel (zero outside the volume), with the exact-form Gauss-Newton matrix
+   beta h^3 sum_v P_v^T grad b_M grad b_M^T P_v.  Allocates 14 bytes per voxel on the
+   first call (masks and the per-voxel GN vectors of the term). */
+int disco_set_masks(disco_ctx *ctx, const uint8_t *bF, const uint8_t *bM, disco_stream stream);
+
+/* Linearise the joint objective of eq. 11 at u: terms_dev (nullable, device doubles [8])
+   receives J, D, S, V (+inf on a fold), K, B, the fold count and |grad J|; g and diag
+   (nullable) receive grad J and the diagonal of the GN matrix.  Sets the linearisation
+   used by gn_hessvec. */
+int objective_linearise(disco_ctx *ctx, const disco_params *p, const float *u, double *terms_dev, float *g,
+                        float *diag, disco_stream stream);
+
 /* Derivative of the NGF distance of eq. 1 with respect to the moving image values at
    displacement u: dT (device float32 [Nz][Ny][Nx]) = dD/dT, through the trilinear
    sampling of grad T and its central-difference stencil.  The scatter to warped
@@ -183,7 +203,9 @@ int keypoint_penalty(disco_ctx *ctx, double delta, const float *u, double *K_dev
                      const float *v, float *Hv, disco_stream stream);
 
 /* Full Gauss-Newton product of eq. 11 at the last linearisation:
-   Hv = H_D v + alpha C_H L^T L v + gamma H_V v + delta 2 P^T P v + tau v. */
+   Hv = H_D v + alpha C_H L^T L v + beta H_B v + gamma H_V v + delta 2 P^T P v + tau v
+   (H_B only with masks set; then the linearisation must have had beta != 0 too, else
+   DISCO_ERR_STATE). */
 int gn_hessvec(disco_ctx *ctx, const disco_params *p, const float *v, float *Hv, disco_stream stream);
 
 /* One Gauss-Newton step of eq. 11 from u (updated in place on success):

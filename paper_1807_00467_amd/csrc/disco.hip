@@ -57,6 +57,11 @@ struct disco_ctx {
   double *blk_brick = nullptr, *blk_node = nullptr, *sc = nullptr;
   double *blk_curv = nullptr, *blk_upd = nullptr;
   float *adjW = nullptr;  // dD/d(grad T) accumulator of ngf_grad_T, [N][3] (allocated on first use)
+  // lung masks and the boundary term's GN vectors (allocated by disco_set_masks)
+  uint8_t *mF = nullptr, *mM = nullptr, *rflag = nullptr;
+  float *sbc = nullptr;
+  bool masks = false;
+  bool lin_mask = false;  // the last linearisation wrote the boundary term's GN vectors
   // L-BFGS history (allocated on first use): a ring of lb_m pairs (s, y)
   float *lbS = nullptr, *lbY = nullptr;  // [lb_m][3][nodes]
   int lb_m = 0;
@@ -153,18 +158,32 @@ void clear_profile(disco_ctx *c) {
 // brick kernel dispatch
 // ------------------------------------------------------------------------------
 template <class ST, int MODE>
-void launch_brick_mode(disco_ctx *c, bool ngf, bool vcc, bool kp, const BrickArgs<ST> &a, hipStream_t s) {
+void launch_brick_mode(disco_ctx *c, bool ngf, bool vcc, bool kp, bool mask, const BrickArgs<ST> &a,
+                       hipStream_t s) {
   dim3 grid(c->g.nbx, c->g.nby, c->g.nbz);
   const int key = (ngf ? 4 : 0) | (vcc ? 2 : 0) | (kp ? 1 : 0);
   if (MODE != M_HV && ngf && (vcc || kp)) {
     // objective and gradient passes: the cell terms (VALU-heavy, many registers) and the
     // NGF voxel pass (memory-bound) run as two launches with their own occupancy; the
     // second adds to the outputs of the first
-    launch_brick_mode<ST, MODE>(c, false, vcc, kp, a, s);
+    launch_brick_mode<ST, MODE>(c, false, vcc, kp, false, a, s);
     BrickArgs<ST> b = a;
     b.acc = 1;
-    hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(brick_threads<MODE, true, false || false>()), 0, s, b);
+    if (mask)
+      hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC, true>), grid, dim3(brick_threads<MODE, true, false>()), 0, s, b);
+    else
+      hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(brick_threads<MODE, true, false>()), 0, s, b);
     return;
+  }
+  if (mask && ngf) {
+    // the lung-boundary term rides on the voxel pass
+    switch (key) {
+      case 7: if constexpr (MODE == M_HV) { hipLaunchKernelGGL((k_brick<ST, MODE, true, true, true, kZC, true>), grid, dim3(brick_threads<MODE, true, true>()), 0, s, a); return; } break;
+      case 6: if constexpr (MODE == M_HV) { hipLaunchKernelGGL((k_brick<ST, MODE, true, true, false, kZC, true>), grid, dim3(brick_threads<MODE, true, true>()), 0, s, a); return; } break;
+      case 5: if constexpr (MODE == M_HV) { hipLaunchKernelGGL((k_brick<ST, MODE, true, false, true, kZC, true>), grid, dim3(brick_threads<MODE, true, true>()), 0, s, a); return; } break;
+      case 4: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC, true>), grid, dim3(brick_threads<MODE, true, false>()), 0, s, a); return;
+      default: break;
+    }
   }
   if constexpr (MODE == M_HV) {
     switch (key) {
@@ -191,6 +210,7 @@ struct BrickCall {
   const float *u, *v;
   float *out0, *out1;
   const double *stop;
+  double beta = 0.0;  // lung-boundary weight (needs masks; rides on the NGF voxel pass)
 };
 
 template <class ST>
@@ -218,22 +238,29 @@ BrickArgs<ST> make_args(disco_ctx *c, const BrickCall &b) {
   a.part = c->part;
   a.blocks = c->blk_brick;
   a.stop = b.stop;
+  a.mF = c->mF;
+  a.mM = c->mM;
+  a.sbc = c->sbc;
+  a.rflag = c->rflag;
+  a.mscale = (float)(0.5 * b.beta);
+  a.mroot = (float)std::sqrt(0.5 * b.beta);
   return a;
 }
 
 void launch_brick(disco_ctx *c, const BrickCall &b, hipStream_t s) {
   const int pk = b.mode == M_HV ? 0 : (b.mode == M_GRAD ? 1 : 2);
   ProfScope ps(c, pk, s);
+  const bool mask = b.ngf && b.beta != 0.0 && c->masks;
   if (c->storage == DISCO_STORAGE_FP16) {
     auto a = make_args<F16x3>(c, b);
-    if (b.mode == M_EVAL) launch_brick_mode<F16x3, M_EVAL>(c, b.ngf, b.vcc, b.kp, a, s);
-    if (b.mode == M_GRAD) launch_brick_mode<F16x3, M_GRAD>(c, b.ngf, b.vcc, b.kp, a, s);
-    if (b.mode == M_HV) launch_brick_mode<F16x3, M_HV>(c, b.ngf, b.vcc, b.kp, a, s);
+    if (b.mode == M_EVAL) launch_brick_mode<F16x3, M_EVAL>(c, b.ngf, b.vcc, b.kp, mask, a, s);
+    if (b.mode == M_GRAD) launch_brick_mode<F16x3, M_GRAD>(c, b.ngf, b.vcc, b.kp, mask, a, s);
+    if (b.mode == M_HV) launch_brick_mode<F16x3, M_HV>(c, b.ngf, b.vcc, b.kp, mask, a, s);
   } else {
     auto a = make_args<F32x3>(c, b);
-    if (b.mode == M_EVAL) launch_brick_mode<F32x3, M_EVAL>(c, b.ngf, b.vcc, b.kp, a, s);
-    if (b.mode == M_GRAD) launch_brick_mode<F32x3, M_GRAD>(c, b.ngf, b.vcc, b.kp, a, s);
-    if (b.mode == M_HV) launch_brick_mode<F32x3, M_HV>(c, b.ngf, b.vcc, b.kp, a, s);
+    if (b.mode == M_EVAL) launch_brick_mode<F32x3, M_EVAL>(c, b.ngf, b.vcc, b.kp, mask, a, s);
+    if (b.mode == M_GRAD) launch_brick_mode<F32x3, M_GRAD>(c, b.ngf, b.vcc, b.kp, mask, a, s);
+    if (b.mode == M_HV) launch_brick_mode<F32x3, M_HV>(c, b.ngf, b.vcc, b.kp, mask, a, s);
   }
 }
 
@@ -249,6 +276,7 @@ PostArgs post_args(disco_ctx *c, double alpha = 0.0, double gamma = 0.0, double 
   a.delta = delta;
   a.CH = ch_of(c);
   a.h3 = h3_of(c);
+  a.beta = 0.0;
   return a;
 }
 
@@ -466,7 +494,7 @@ void disco_destroy(disco_ctx *c) {
   void *ptrs[] = {c->gR,  c->gT,  c->scache, c->u_lin, c->u_ref, c->Lw,   c->vg,   c->vdiag, c->vx,   c->vr,
                   c->vz,  c->vp,  c->vq,     c->vut,   c->tmp0,  c->tmp1, c->part, c->blk_brick, c->blk_node,
                   c->sc,  c->status, c->kloc, c->ktgt, c->kstart, c->blk_curv, c->blk_upd, c->adjW, c->vp2, c->vinvm,
-                  c->lbS, c->lbY};
+                  c->lbS, c->lbY, c->mF, c->mM, c->rflag, c->sbc};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->host_sc) (void)hipHostFree(c->host_sc);
@@ -700,6 +728,41 @@ int disco_set_reference(disco_ctx *c, const float *u_ref, disco_stream stream) {
   return DISCO_OK;
 }
 
+int disco_set_masks(disco_ctx *c, const uint8_t *bF, const uint8_t *bM, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  if ((bF == nullptr) != (bM == nullptr)) return DISCO_ERR_ARG;
+  int e;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  const Geo &g = c->g;
+  if (!bF) {
+    c->masks = false;
+    c->lin_mask = false;
+    return DISCO_OK;
+  }
+  if (!c->mF) {
+    HIP_TRY(hipStreamSynchronize(s));
+    const size_t nrow = (size_t)g.nz * g.ny * g.nbx;
+    bool okm = hipMalloc(reinterpret_cast<void **>(&c->mF), (size_t)g.nvox) == hipSuccess &&
+               hipMalloc(reinterpret_cast<void **>(&c->mM), (size_t)g.nvox) == hipSuccess &&
+               hipMalloc(reinterpret_cast<void **>(&c->rflag), nrow) == hipSuccess &&
+               hipMalloc(reinterpret_cast<void **>(&c->sbc), sizeof(float) * 3 * (size_t)g.nvox) == hipSuccess;
+    if (!okm) {
+      void *ps[] = {c->mF, c->mM, c->rflag, c->sbc};
+      for (void *q : ps)
+        if (q) (void)hipFree(q);
+      c->mF = c->mM = c->rflag = nullptr;
+      c->sbc = nullptr;
+      return DISCO_ERR_NOMEM;
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(c->mF, bF, (size_t)g.nvox, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(c->mM, bM, (size_t)g.nvox, hipMemcpyDeviceToDevice, s));
+  c->masks = true;
+  c->lin_mask = false;
+  return DISCO_OK;
+}
+
 int ngf_eval(disco_ctx *c, double eta, const float *u, double *D_dev, disco_stream stream) {
   if (!c || !D_dev) return DISCO_ERR_ARG;
   int e;
@@ -742,6 +805,7 @@ int ngf_grad(disco_ctx *c, double eta, const float *u, double *D_dev, float *g, 
   HIP_TRY(hipGetLastError());
   c->lin = true;
   c->lin_eta = eta;
+  c->lin_mask = false;
   return DISCO_OK;
 }
 
@@ -837,7 +901,7 @@ static int check_params(const disco_params *p) {
   if (!p) return DISCO_ERR_ARG;
   if (!std::isfinite(p->eta) || !(p->eta > 0.0)) return DISCO_ERR_NONFINITE;
   if (!finite_nonneg(p->alpha) || !finite_nonneg(p->gamma) || !finite_nonneg(p->delta) || !finite_nonneg(p->tau) ||
-      !finite_nonneg(p->pcg_tol))
+      !finite_nonneg(p->pcg_tol) || !finite_nonneg(p->beta))
     return DISCO_ERR_NONFINITE;
   if (!std::isfinite(p->armijo_c1) || !(p->armijo_c1 > 0.0 && p->armijo_c1 < 1.0)) return DISCO_ERR_NONFINITE;
   if (p->pcg_iters < 1 || p->ls_max < 1 || p->ls_max > 60) return DISCO_ERR_ARG;
@@ -854,6 +918,7 @@ static void gn_hv_body(disco_ctx *c, const disco_params *p, const float *v, floa
   const bool kp = p->delta != 0.0 && c->nkp > 0;
   const bool curv = p->alpha != 0.0;
   BrickCall b{M_HV, true, vcc, kp, 0.f, (float)p->gamma, (float)p->delta, c->u_lin, v, Hv, nullptr, stop};
+  b.beta = p->beta;
   launch_brick(c, b, s);
   launch_gather(c, 1, 1, Hv, nullptr, curv ? c->Lw : nullptr, (float)(p->alpha * ch_of(c)), 0,
                 p->tau != 0.0 ? v : nullptr, (float)p->tau, dot ? v : nullptr, dot, stop, s);
@@ -871,6 +936,8 @@ int gn_hessvec(disco_ctx *c, const disco_params *p, const float *v, float *Hv, d
   if ((e = check_params(p))) return e;
   if ((e = check_field(v)) || (e = check_field(Hv))) return e;
   if (!c->lin) return DISCO_ERR_STATE;
+  // the boundary term's GN vectors come from a linearisation with the term
+  if (p->beta != 0.0 && c->masks && !c->lin_mask) return DISCO_ERR_STATE;
   if ((e = set_device(c))) return e;
   gn_hv_launch(c, p, v, Hv, false, nullptr, S(stream));
   HIP_TRY(hipGetLastError());
@@ -888,6 +955,7 @@ static int linearise(disco_ctx *c, const disco_params *p, const float *u, const 
   set_s_scale(c, p->eta);
   launch_curv_L(c, u, c->u_ref, c->Lw, true, nullptr, s);
   BrickCall b{M_GRAD, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, u, nullptr, c->vg, c->vdiag, nullptr};
+  b.beta = p->beta;
   launch_brick(c, b, s);
   launch_gather(c, 2, 2, c->vg, c->vdiag, curv ? c->Lw : nullptr, (float)(p->alpha * ch_of(c)), curv ? 1 : 0, nullptr,
                 0.f, nullptr, true, nullptr, s);
@@ -897,6 +965,7 @@ static int linearise(disco_ctx *c, const disco_params *p, const float *u, const 
   HIP_TRY(hipMemcpyAsync(c->u_lin, u, sizeof(float) * 3 * c->g.nnodes, hipMemcpyDeviceToDevice, s));
   c->lin = true;
   c->lin_eta = p->eta;
+  c->lin_mask = p->beta != 0.0 && c->masks;
   return DISCO_OK;
 }
 
@@ -922,6 +991,7 @@ static int line_search(disco_ctx *c, const disco_params *p, float *u, const Post
     hipLaunchKernelGGL(k_ls_point, dim3(nb3), dim3(256), 0, s, n3, sc, t, u, c->vx, c->vut);
     launch_curv_L(c, c->vut, c->u_ref, c->Lw, true, acc, s);
     BrickCall b{M_EVAL, true, vcc, kp, eta2, (float)p->gamma, (float)p->delta, c->vut, nullptr, nullptr, nullptr, acc};
+    b.beta = p->beta;
     launch_brick(c, b, s);
     launch_finish(POST_LS_BRICK, pa, acc, s, src_brick(c, sc + SC_TMP0), src_curv(c, sc + SC_TSRAW));
     if (!dev_ls) {
@@ -991,6 +1061,7 @@ int lbfgs_step(disco_ctx *c, const disco_params *p, const disco_lbfgs *lb, float
   auto Yv = [&](int k) { return c->lbY + (size_t)k * n3; };
   const bool curv = p->alpha != 0.0;
   PostArgs pa = post_args(c, p->alpha, p->gamma, p->delta);
+  pa.beta = c->masks ? p->beta : 0.0;
   pa.c1 = p->armijo_c1;
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, c->status);
 
@@ -1097,6 +1168,7 @@ int gn_pcg_step(disco_ctx *c, const disco_params *p, float *u, double *report_de
   double *sc = c->sc;
   const bool curv = p->alpha != 0.0;
   PostArgs pa = post_args(c, p->alpha, p->gamma, p->delta);
+  pa.beta = c->masks ? p->beta : 0.0;
   pa.c1 = p->armijo_c1;
   pa.tol = p->pcg_tol;
   hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, c->status);
@@ -1129,6 +1201,30 @@ int gn_pcg_step(disco_ctx *c, const disco_params *p, float *u, double *report_de
   if ((e = line_search(c, p, u, pa, report_dev, status_dev, s, [] {}))) return e;
   HIP_TRY(hipGetLastError());
   // the s cache and u_lin now describe the linearisation point of this step
+  return DISCO_OK;
+}
+
+int objective_linearise(disco_ctx *c, const disco_params *p, const float *u, double *terms_dev, float *g,
+                        float *diag, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_params(p))) return e;
+  if ((e = check_field(u))) return e;
+  if ((g && !aligned4(g)) || (diag && !aligned4(diag)) ||
+      (terms_dev && (reinterpret_cast<uintptr_t>(terms_dev) & 7u) != 0))
+    return DISCO_ERR_SHAPE;
+  if (!c->images) return DISCO_ERR_STATE;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  PostArgs pa = post_args(c, p->alpha, p->gamma, p->delta);
+  pa.beta = c->masks ? p->beta : 0.0;
+  hipLaunchKernelGGL(k_clear_status, dim3(1), dim3(1), 0, s, c->status);
+  if ((e = linearise(c, p, u, pa, s))) return e;
+  const size_t nf = sizeof(float) * 3 * (size_t)c->g.nnodes;
+  if (g) HIP_TRY(hipMemcpyAsync(g, c->vg, nf, hipMemcpyDeviceToDevice, s));
+  if (diag) HIP_TRY(hipMemcpyAsync(diag, c->vdiag, nf, hipMemcpyDeviceToDevice, s));
+  if (terms_dev) hipLaunchKernelGGL(k_terms, dim3(1), dim3(1), 0, s, c->sc, ch_of(c), terms_dev);
+  HIP_TRY(hipGetLastError());
   return DISCO_OK;
 }
 
@@ -1302,7 +1398,7 @@ static int batch_prepare_t(disco_batch *b, const disco_params *params, float *co
   std::vector<PairDesc<ST>> d(n);
   for (int i = 0; i < n; ++i) {
     const int ci = b->order[i];
-    d[i] = pair_desc<ST>(b->ctx[i], &params[ci], u[ci], report_dev ? report_dev + 16 * (size_t)ci : nullptr,
+    d[i] = pair_desc<ST>(b->ctx[i], &params[ci], u[ci], report_dev ? report_dev + DISCO_REP_SIZE * (size_t)ci : nullptr,
                          status_dev ? status_dev + ci : nullptr);
   }
   HIP_TRY(hipMemcpy(b->desc, d.data(), sizeof(PairDesc<ST>) * (size_t)n, hipMemcpyHostToDevice));
@@ -1320,6 +1416,7 @@ int disco_batch_prepare(disco_batch *b, const disco_params *params, float *const
     if ((e = check_params(&params[i]))) return e;
     if ((e = check_field(u[i]))) return e;
     if (!(params[i].flags & DISCO_FLAG_LS_DEVICE)) return DISCO_ERR_ARG;  // no host round trips in a batch
+    if (params[i].beta != 0.0) return DISCO_ERR_ARG;  // the batched passes have no boundary term
   }
   if ((report_dev && ((reinterpret_cast<uintptr_t>(report_dev) & 7u) != 0)) || (status_dev && !aligned4(status_dev)))
     return DISCO_ERR_SHAPE;
@@ -1449,6 +1546,7 @@ static int batch_step(disco_batch *b, hipStream_t s) {
     batch_step_t<F32x3>(b, s);
   for (auto *c : b->ctx) {
     c->lin = true;
+    c->lin_mask = false;
   }
   HIP_TRY(hipGetLastError());
   return DISCO_OK;
@@ -1706,7 +1804,7 @@ int multilevel_register(const disco_geom *geom, const float *R, const float *T, 
   int32_t *st_dev = nullptr;
   if (!B.alloc(&scal, 2) || !B.alloc(&st_dev, 1)) return DISCO_ERR_NOMEM;
   // rows of iterations that are not run read as NaN
-  if (report_dev && rows > 0) HIP_TRY(hipMemsetAsync(report_dev, 0xFF, sizeof(double) * 16 * (size_t)rows, s));
+  if (report_dev && rows > 0) HIP_TRY(hipMemsetAsync(report_dev, 0xFF, sizeof(double) * DISCO_REP_SIZE * (size_t)rows, s));
 
   disco_params prm = cfg->params;
   double delta = cfg->adaptive_delta ? 0.0 : prm.delta;
@@ -1754,7 +1852,7 @@ int multilevel_register(const disco_geom *geom, const float *R, const float *T, 
     prm.delta = delta;
     const int iters = cfg->iters[L - 1 - l];
     for (int it = 0; it < iters; ++it) {
-      double *rep = report_dev ? report_dev + 16 * (row + it) : nullptr;
+      double *rep = report_dev ? report_dev + DISCO_REP_SIZE * (row + it) : nullptr;
       e = cfg->optimizer == DISCO_OPT_GN ? gn_pcg_step(c, &prm, ul[l], rep, st_dev, stream)
                                          : lbfgs_step(c, &prm, &cfg->lbfgs, ul[l], rep, st_dev, stream);
       if (e) return fail(e);

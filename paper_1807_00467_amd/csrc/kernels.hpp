@@ -55,7 +55,8 @@ __device__ __forceinline__ Blk hw_blk() {
 }
 
 // block scalar slots written by k_brick (doubles per workgroup)
-enum { BS_D = 0, BS_V = 1, BS_K = 2, BS_FOLD = 3, BS_N = 4 };
+enum { BS_D = 0, BS_V = 1, BS_K = 2, BS_FOLD = 3, BS_B = 4, BS_N = 5 };
+constexpr int kRedVals = 5;  // values per source of the single-workgroup reduction (>= BS_N)
 
 struct Geo {
   int nx, ny, nz;        // voxels
@@ -173,6 +174,7 @@ struct PostArgs {
   double *sc;         // device scalar slots (solver state)
   int *status;        // device status word
   double alpha, gamma, delta, CH, h3;  // objective weights, C_H, voxel volume
+  double beta;                        // lung-boundary weight
   double c1, tol;     // Armijo constant, CG tolerance
   double *dst;        // POST_WRITE destination (nullable)
   int32_t *idst;      // POST_WRITE fold-count destination (nullable)
@@ -182,9 +184,10 @@ struct PostArgs {
 
 
 // the objective from reduced terms; a fold counts only when gamma > 0 (then J = +inf)
-__device__ inline double total_J(const PostArgs &w, double D, double Sraw, double V, double K, double nfold) {
+__device__ inline double total_J(const PostArgs &w, double D, double Sraw, double V, double K, double nfold,
+                                 double B) {
   if (w.gamma != 0.0 && nfold > 0.0) return INFINITY;
-  return D + w.alpha * 0.5 * w.CH * Sraw + (w.gamma != 0.0 ? w.gamma * V : 0.0) + w.delta * K;
+  return D + w.alpha * 0.5 * w.CH * Sraw + w.beta * B + (w.gamma != 0.0 ? w.gamma * V : 0.0) + w.delta * K;
 }
 
 // slots of the device scalar array used by the Gauss-Newton step
@@ -196,13 +199,14 @@ enum {
   SC_TD, SC_TSRAW, SC_TV, SC_TK, SC_TNFOLD,    // trial point reductions
   SC_JT, SC_DT, SC_ST, SC_VT, SC_KT,           // accepted (or last) trial values
   SC_TMP0, SC_TMP1, SC_TMP2, SC_TMP3, SC_TMP4,
+  SC_B, SC_TB,                                 // lung-boundary term B at the linearisation / trial point
   SC_LB_RHO = 48,     // L-BFGS: rho_i = 1 / s_i.y_i of the stored pairs (0: pair skipped)
   SC_LB_ALPHA = 56,   // L-BFGS: alpha_i of the first loop
   SC_LB_DOT = 64,     // L-BFGS: dot product scratch
   SC_COUNT = 72
 };
 constexpr int kLbfgsMax = 8;  // longest L-BFGS history
-static_assert(SC_TMP4 < SC_LB_RHO && SC_LB_RHO + kLbfgsMax <= SC_LB_ALPHA && SC_LB_ALPHA + kLbfgsMax <= SC_LB_DOT &&
+static_assert(SC_TB < SC_LB_RHO && SC_TMP0 + kRedVals - 1 == SC_TMP4 && SC_LB_RHO + kLbfgsMax <= SC_LB_ALPHA && SC_LB_ALPHA + kLbfgsMax <= SC_LB_DOT &&
                   SC_LB_DOT < SC_COUNT,
               "scalar slots overlap");
 
@@ -221,7 +225,8 @@ __device__ inline void run_post(int post, const PostArgs &a, const double *r) {
       sc[SC_V] = r[1];
       sc[SC_K] = r[2];
       sc[SC_NFOLD] = r[3];
-      sc[SC_J] = total_J(a, sc[SC_D], sc[SC_SRAW], sc[SC_V], sc[SC_K], sc[SC_NFOLD]);
+      sc[SC_B] = 0.5 * a.h3 * r[4];
+      sc[SC_J] = total_J(a, sc[SC_D], sc[SC_SRAW], sc[SC_V], sc[SC_K], sc[SC_NFOLD], sc[SC_B]);
       if (a.status && a.gamma != 0.0 && sc[SC_NFOLD] > 0.0) *a.status |= 1;
       break;
     case POST_LS_BRICK: {
@@ -230,8 +235,9 @@ __device__ inline void run_post(int post, const PostArgs &a, const double *r) {
       sc[SC_TV] = r[1];
       sc[SC_TK] = r[2];
       sc[SC_TNFOLD] = r[3];
+      sc[SC_TB] = 0.5 * a.h3 * r[4];
       const double t = sc[SC_TTRY];
-      const double Jt = total_J(a, sc[SC_TD], sc[SC_TSRAW], sc[SC_TV], sc[SC_TK], sc[SC_TNFOLD]);
+      const double Jt = total_J(a, sc[SC_TD], sc[SC_TSRAW], sc[SC_TV], sc[SC_TK], sc[SC_TNFOLD], sc[SC_TB]);
       sc[SC_TRIALS] += 1.0;
       sc[SC_JT] = Jt;
       sc[SC_DT] = sc[SC_TD];
@@ -275,7 +281,7 @@ __device__ inline void run_post(int post, const PostArgs &a, const double *r) {
 }
 
 // One source of a single-workgroup reduction: out[k] = sum (or max) over b of
-// blocks[b * stride + k], k < nvals.
+// blocks[b * stride + k], k < nvals <= kRedVals.
 struct RedSrc {
   const double *blocks;
   int64_t nb;
@@ -294,19 +300,19 @@ __device__ __forceinline__ double wave_red_d(double v, bool mx) {
   return v;
 }
 
-// Reduce up to three sources of at most 4 values each in a fixed order (one workgroup of
+// Reduce up to three sources of at most kRedVals values each in a fixed order (one workgroup of
 // 1024 threads: per-thread sums over strided partials, a butterfly per wave, then the 16
 // wave results in order), then run the scalar post-operation.  The first 2048 partials
 // of every source are requested together.  Deterministic; no inter-workgroup
 // communication.
 __device__ __forceinline__ void finish_body(const RedSrc s0, const RedSrc s1, const RedSrc s2, int nsrc, int post,
                                             const PostArgs &pa, const double *stop) {
-  __shared__ double wred[16][12];
+  __shared__ double wred[16][3 * kRedVals];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   // sources selected by value (no addressable local array: it would live in scratch memory)
   auto src = [&](int q) -> RedSrc { return q == 0 ? s0 : (q == 1 ? s1 : s2); };
   const double stopv = stop ? *stop : 0.0;  // no workgroup writes it here: uniform
-  double x[3][2][4];
+  double x[3][2][kRedVals];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const RedSrc S = src(q);
@@ -314,7 +320,7 @@ __device__ __forceinline__ void finish_body(const RedSrc s0, const RedSrc s1, co
     for (int u = 0; u < 2; ++u) {
       const int64_t b = u * 1024 + t;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) x[q][u][k] = (q < nsrc && b < S.nb && k < S.nvals) ? S.blocks[b * S.stride + k] : 0.0;
+      for (int k = 0; k < kRedVals; ++k) x[q][u][k] = (q < nsrc && b < S.nb && k < S.nvals) ? S.blocks[b * S.stride + k] : 0.0;
     }
   }
   if (stopv != 0.0) return;
@@ -323,7 +329,7 @@ __device__ __forceinline__ void finish_body(const RedSrc s0, const RedSrc s1, co
     const RedSrc S = src(q);
     if (q < nsrc) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < kRedVals; ++k) {
         const bool mx = (S.max_mask >> k) & 1u;
         double acc = mx ? -INFINITY : 0.0;
 #pragma unroll
@@ -334,17 +340,17 @@ __device__ __forceinline__ void finish_body(const RedSrc s0, const RedSrc s1, co
           acc = mx ? fmax(acc, y) : acc + y;
         }
         const double r = wave_red_d(acc, mx);
-        if (lane == 0) wred[w][q * 4 + k] = r;
+        if (lane == 0) wred[w][q * kRedVals + k] = r;
       }
     }
   }
   __syncthreads();
-  // thread 4 q + k finishes value k of source q (q static in each unrolled pass)
+  // thread kRedVals q + k finishes value k of source q (q static in each unrolled pass)
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const RedSrc S = src(q);
-    const int k = t - 4 * q;
-    if (q < nsrc && k >= 0 && k < 4 && k < S.nvals) {
+    const int k = t - kRedVals * q;
+    if (q < nsrc && k >= 0 && k < kRedVals && k < S.nvals) {
       const bool mx = (S.max_mask >> k) & 1u;
       double r = wred[0][t];
       for (int i = 1; i < 16; ++i) r = mx ? fmax(r, wred[i][t]) : r + wred[i][t];
@@ -446,6 +452,10 @@ struct BrickArgs {
   float *out0, *out1;           // node fields: field 0 (g or Hv), field 1 (GN diagonal)
   float *part;                  // face partials
   double *blocks;               // BS_N doubles per workgroup
+  const uint8_t *mF, *mM;       // lung masks b_F, b_M [N] (lung-boundary term)
+  float *sbc;                   // boundary-term GN vectors sqrt(beta/2) grad b_M(y) [N][3], rows with rflag set
+  uint8_t *rflag;               // per 64-voxel row (z, y, brick x): 1 if its boundary-term vectors are not all 0
+  float mscale, mroot;          // beta / 2, sqrt(beta / 2)
   const double *stop;           // if non-null and *stop != 0 the launch does nothing
   int acc;                      // add to out0/out1, part and blocks instead of writing them
                                 // (a second pass over the same bricks, fixed order)
@@ -953,8 +963,62 @@ __device__ __forceinline__ void load_corners(const float *fb, const Geo &g, bool
 #ifndef DISCO_HV_WAVES
 #define DISCO_HV_WAVES 1
 #endif
-template <class ST, int MODE, bool NGF, bool VCC, bool KP, int ZC>
+// Trilinear sample of the moving lung mask (uint8 0/1, zero outside the volume) at the
+// warped voxel, in the same cell as the gradient sample (same FP32 decision), and the
+// gradient of the interpolant in mm.
+__device__ __forceinline__ void sample_mask(const uint8_t *__restrict__ mM, const Geo &g, int ix, int iy, int iz,
+                                            const float uh[3], float &val, float grad[3]) {
+  const int idx[3] = {ix, iy, iz};
+  const int n[3] = {g.nx, g.ny, g.nz};
+  int i0[3];
+  float t[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float d = fminf(fmaxf(uh[a], (float)(-2 - idx[a])), (float)(n[a] + 1 - idx[a]));
+    const float f = floorf(d);
+    t[a] = d - f;
+    i0[a] = idx[a] + (int)f;
+  }
+  float m[2][2][2];  // [z][y][x]
+#pragma unroll
+  for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int cx = 0; cx < 2; ++cx) {
+        const int ii = i0[0] + cx, jj = i0[1] + cy, kk = i0[2] + cz;
+        const bool in = (unsigned)ii < (unsigned)g.nx && (unsigned)jj < (unsigned)g.ny && (unsigned)kk < (unsigned)g.nz;
+        const int64_t off = in ? ((int64_t)kk * g.ny + jj) * g.nx + ii : 0;
+        const uint8_t b = mM[off];
+        m[cz][cy][cx] = in ? (float)b : 0.0f;
+      }
+  // along x, then y, then z
+  float ax[2][2], dx[2][2];
+#pragma unroll
+  for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy) {
+      dx[cz][cy] = m[cz][cy][1] - m[cz][cy][0];
+      ax[cz][cy] = m[cz][cy][0] + t[0] * dx[cz][cy];
+    }
+  float ay[2], dyv[2], dxy[2];
+#pragma unroll
+  for (int cz = 0; cz < 2; ++cz) {
+    dyv[cz] = ax[cz][1] - ax[cz][0];
+    ay[cz] = ax[cz][0] + t[1] * dyv[cz];
+    dxy[cz] = dx[cz][0] + t[1] * (dx[cz][1] - dx[cz][0]);
+  }
+  val = ay[0] + t[2] * (ay[1] - ay[0]);
+  grad[0] = (dxy[0] + t[2] * (dxy[1] - dxy[0])) * g.ihx;
+  grad[1] = (dyv[0] + t[2] * (dyv[1] - dyv[0])) * g.ihy;
+  grad[2] = (ay[1] - ay[0]) * g.ihz;
+}
+
+// MASK adds the lung-boundary term (eq. 6) to the voxel pass: it needs NGF (the voxel
+// pass of the data terms)
+template <class ST, int MODE, bool NGF, bool VCC, bool KP, int ZC, bool MASK = false>
 __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B, int acc) {
+  static_assert(!MASK || NGF, "the boundary term rides on the voxel pass");
   constexpr int F = (MODE == M_GRAD) ? 2 : ((MODE == M_HV) ? 1 : 0);
   constexpr int FS = F > 0 ? F : 1;
   constexpr bool CELLT = VCC || KP;
@@ -986,7 +1050,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
   const int64_t pxy = (int64_t)g.px * g.py;
   const int64_t nxy = (int64_t)g.nx * g.ny;
 
-  double sD = 0.0, sV = 0.0, sK = 0.0;
+  double sD = 0.0, sV = 0.0, sK = 0.0, sB = 0.0;
   int nfold = 0;
   const float sc_ngf = A.ngf_scale;
   const float sg0 = (MODE == M_GRAD) ? -sc_ngf : sc_ngf;  // field 0: -2h^3 r s (gradient) or 2h^3 (GN)
@@ -1091,6 +1155,20 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
                     accY[0][0][c] += (1.0f - wy) * t;
                     accY[0][1][c] += wy * t;
                   }
+                  if constexpr (MASK) {
+                    // boundary term: only rows that touch the mask boundary carry vectors
+                    if (A.rflag[((int64_t)iz * g.ny + iy) * g.nbx + bx]) {
+                      const float *bp = A.sbc + (vbase + kv * nxy + jv * g.nx) * 3;
+                      const float sb[3] = {bp[0], bp[1], bp[2]};
+                      const float wb = sb[0] * f3[0] + sb[1] * f3[1] + sb[2] * f3[2];
+    #pragma unroll
+                      for (int c = 0; c < 3; ++c) {
+                        const float t = wb * sb[c];
+                        accY[0][0][c] += (1.0f - wy) * t;
+                        accY[0][1][c] += wy * t;
+                      }
+                    }
+                  }
                 } else {
                   // displacement in voxel units: q = index + u/h.  The displacement is interpolated
                   // in a fixed order (x, then z, then y, one fused multiply-add each) so that the
@@ -1133,6 +1211,35 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
                       const float t2 = s[c] * s[c];
                       accY[FS - 1][0][c] += (1.0f - wy) * (1.0f - wy) * t2;
                       accY[FS - 1][1][c] += wy * wy * t2;
+                    }
+                  }
+                  if constexpr (MASK) {
+                    // lung-boundary term: res = b_M(y) - b_F(x), B += res^2 (times h^3 / 2 later)
+                    float bm, gb[3];
+                    sample_mask(A.mM, g, ix, iy, iz, uh, bm, gb);
+                    const int64_t vi = vbase + kv * nxy + jv * g.nx;
+                    const float res = bm - (float)A.mF[vi];
+                    sB += (double)(res * res);
+                    if (MODE == M_GRAD) {
+                      // in units of the NGF fields: gradient -2h^3 (-(beta/2) res grad b),
+                      // diagonal 2h^3 (beta/2) grad b^2, GN vector sqrt(beta/2) grad b
+                      const bool nz = gb[0] != 0.0f || gb[1] != 0.0f || gb[2] != 0.0f;
+                      const bool row = __any(nz);
+                      if (row) {
+                        float *bp = A.sbc + vi * 3;
+    #pragma unroll
+                        for (int c = 0; c < 3; ++c) bp[c] = A.mroot * gb[c];
+                      }
+                      if (lane == 0) A.rflag[((int64_t)iz * g.ny + iy) * g.nbx + bx] = row ? 1 : 0;
+    #pragma unroll
+                      for (int c = 0; c < 3; ++c) {
+                        const float t = -A.mscale * res * gb[c];
+                        accY[0][0][c] += (1.0f - wy) * t;
+                        accY[0][1][c] += wy * t;
+                        const float t2 = A.mscale * gb[c] * gb[c];
+                        accY[FS - 1][0][c] += (1.0f - wy) * (1.0f - wy) * t2;
+                        accY[FS - 1][1][c] += wy * wy * t2;
+                      }
                     }
                   }
                 }
@@ -1342,7 +1449,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
 
   // workgroup scalars in a fixed order
   if (MODE != M_HV) {
-    double vals[BS_N] = {sD, sV * (double)g.C, sK, (double)nfold};
+    double vals[BS_N] = {sD, sV * (double)g.C, sK, (double)nfold, sB};
 #pragma unroll
     for (int t = 0; t < BS_N; ++t) {
       const double s = wave_sum_d(vals[t]);
@@ -1358,10 +1465,10 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
   }
 }
 
-template <class ST, int MODE, bool NGF, bool VCC, bool KP, int ZC>
+template <class ST, int MODE, bool NGF, bool VCC, bool KP, int ZC, bool MASK = false>
 __global__ __launch_bounds__((brick_threads<MODE, NGF, VCC || KP>()), MODE == M_HV ? DISCO_HV_WAVES : 1) void k_brick(
     BrickArgs<ST> A) {
-  brick_body<ST, MODE, NGF, VCC, KP, ZC>(A, hw_blk(), A.acc);
+  brick_body<ST, MODE, NGF, VCC, KP, ZC, MASK>(A, hw_blk(), A.acc);
 }
 
 // ---------------------------------------------------------------------------------

@@ -248,6 +248,8 @@ __device__ __forceinline__ void report_body(const double *sc, double CH, double 
     rep[13] = sc[SC_TNFOLD] > 0.0 ? INFINITY : sc[SC_VT];
     rep[14] = sc[SC_KT];
     rep[15] = sc[SC_TRIALS];
+    rep[16] = sc[SC_B];
+    rep[17] = sc[SC_TB];
   }
   if (sc[SC_ACCEPT] == 0.0) *status |= 4;
   if (status_out) *status_out = *status;
@@ -257,6 +259,18 @@ __global__ void k_report(const double *sc, double CH, double *rep, int *status, 
 }
 
 __global__ void k_clear_status(int *status) { *status = 0; }
+
+// the terms of the last linearisation: J, D, S, V (+inf on a fold), K, B, folds, |grad J|
+__global__ void k_terms(const double *sc, double CH, double *out) {
+  out[0] = sc[SC_J];
+  out[1] = sc[SC_D];
+  out[2] = 0.5 * CH * sc[SC_SRAW];
+  out[3] = sc[SC_NFOLD] > 0.0 ? INFINITY : sc[SC_V];
+  out[4] = sc[SC_K];
+  out[5] = sc[SC_B];
+  out[6] = sc[SC_NFOLD];
+  out[7] = sqrt(sc[SC_GG]);
+}
 
 // ---- L-BFGS vector operations (node fields) ----------------------------------------
 // out = sa a + c b with c = f0 + fa sc[ka] + fb sc[kb] sc[kc] (a term whose first slot

@@ -31,7 +31,9 @@ STORAGE_FP32, STORAGE_FP16 = 0, 1
 FLAG_LS_DEVICE = 1
 BUF_GRAD_R, BUF_GRAD_T, BUF_SCACHE = 0, 1, 2
 REPORT_FIELDS = ["J", "D", "S", "V", "K", "gnorm", "t", "pcg_iters", "pcg_res", "gtp",
-                 "J_new", "D_new", "S_new", "V_new", "K_new", "ls_trials"]
+                 "J_new", "D_new", "S_new", "V_new", "K_new", "ls_trials", "B", "B_new"]
+REP_SIZE = len(REPORT_FIELDS)
+TERM_FIELDS = ["J", "D", "S", "V", "K", "B", "nfold", "gnorm"]
 PROF_HV, PROF_GRAD, PROF_EVAL, PROF_IMGRAD = 0, 1, 2, 3
 
 
@@ -43,7 +45,7 @@ class _Params(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_double), ("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("delta", ctypes.c_double), ("tau", ctypes.c_double), ("armijo_c1", ctypes.c_double),
                 ("pcg_tol", ctypes.c_double), ("pcg_iters", ctypes.c_int32), ("ls_max", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("beta", ctypes.c_double)]
 
 
 class _Lbfgs(ctypes.Structure):
@@ -82,6 +84,8 @@ _SIGS = {
     "gn_pcg_step": ([_P, ctypes.POINTER(_Params), _P, _P, _P, _P], ctypes.c_int),
     "lbfgs_step": ([_P, ctypes.POINTER(_Params), ctypes.POINTER(_Lbfgs), _P, _P, _P, _P], ctypes.c_int),
     "lbfgs_reset": ([_P], ctypes.c_int),
+    "disco_set_masks": ([_P, _P, _P, _P], ctypes.c_int),
+    "objective_linearise": ([_P, ctypes.POINTER(_Params), _P, _P, _P, _P, _P], ctypes.c_int),
     "pyramid_plan": ([_P, _P, _I, _P, _P, _P, _P], ctypes.c_int),
     "pyramid_downsample": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
     "pyramid_prolong": ([_P, _P, _P, _P, _P], ctypes.c_int),
@@ -130,10 +134,11 @@ class Params:
     pcg_iters: int = 20
     ls_max: int = 10
     flags: int = 0
+    beta: float = 0.0
 
     def c(self) -> _Params:
         return _Params(self.eta, self.alpha, self.gamma, self.delta, self.tau, self.armijo_c1, self.pcg_tol,
-                       self.pcg_iters, self.ls_max, self.flags)
+                       self.pcg_iters, self.ls_max, self.flags, self.beta)
 
 
 @dataclasses.dataclass
@@ -223,6 +228,32 @@ class Disco:
         _check(_lib.disco_set_keypoints(self._h, len(x), x.ctypes.data_as(_P), t.ctypes.data_as(_P),
                                         self._stream()), "disco_set_keypoints")
 
+    def set_masks(self, bF: Optional[torch.Tensor], bM: Optional[torch.Tensor]):
+        """Binary lung masks (uint8 CUDA tensors [Nz][Ny][Nx]) of the lung-boundary term;
+        None, None clears them."""
+        if bF is None and bM is None:
+            _check(_lib.disco_set_masks(self._h, None, None, self._stream()), "disco_set_masks")
+            return
+        nx, ny, nz = self.shape
+        for t in (bF, bM):
+            if t.dtype != torch.uint8 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (nz, ny, nx):
+                raise ValueError("masks must be contiguous uint8 CUDA tensors [Nz][Ny][Nx]")
+        _check(_lib.disco_set_masks(self._h, _ptr(bF), _ptr(bM), self._stream()), "disco_set_masks")
+
+    def objective_linearise(self, params: Params, u: torch.Tensor, grad: bool = True, diag: bool = True):
+        """J and its terms (dict of TERM_FIELDS), grad J and the GN diagonal at u (sets the
+        linearisation used by gn_hessvec)."""
+        terms = torch.zeros(8, dtype=torch.float64, device=self.device)
+        g = torch.empty_like(u) if grad else None
+        d = torch.empty_like(u) if diag else None
+        p = params.c()
+        _check(_lib.objective_linearise(self._h, ctypes.byref(p), _ptr(self._field(u, "u")), _ptr(terms), _ptr(g),
+                                        _ptr(d), self._stream()), "objective_linearise")
+        out = dict(zip(TERM_FIELDS, terms.cpu().tolist()))
+        out["g"] = g
+        out["diag"] = d
+        return out
+
     def set_reference(self, u_ref: Optional[torch.Tensor]):
         _check(_lib.disco_set_reference(self._h, _ptr(None if u_ref is None else self._field(u_ref, "u_ref")),
                                         self._stream()), "disco_set_reference")
@@ -296,8 +327,8 @@ class Disco:
 
     def gn_pcg_step(self, params: Params, u: torch.Tensor, report: Optional[torch.Tensor] = None,
                     status: Optional[torch.Tensor] = None):
-        """One GN step in place on u.  Returns (report tensor [16] float64, status int32 tensor)."""
-        rep = torch.zeros(16, dtype=torch.float64, device=self.device) if report is None else report
+        """One GN step in place on u.  Returns (report tensor [REP_SIZE] float64, status int32 tensor)."""
+        rep = torch.zeros(REP_SIZE, dtype=torch.float64, device=self.device) if report is None else report
         st = torch.zeros(1, dtype=torch.int32, device=self.device) if status is None else status
         p = params.c()
         _check(_lib.gn_pcg_step(self._h, ctypes.byref(p), _ptr(self._field(u, "u")), _ptr(rep), _ptr(st),
@@ -307,9 +338,9 @@ class Disco:
     def lbfgs_step(self, params: Params, lb: Lbfgs, u: torch.Tensor, report: Optional[torch.Tensor] = None,
                    status: Optional[torch.Tensor] = None):
         """One L-BFGS iteration in place on u (the history of this context advances).
-        Returns (report tensor [16] float64, status int32 tensor); the CG slots describe
+        Returns (report tensor [REP_SIZE] float64, status int32 tensor); the CG slots describe
         the H0 solve."""
-        rep = torch.zeros(16, dtype=torch.float64, device=self.device) if report is None else report
+        rep = torch.zeros(REP_SIZE, dtype=torch.float64, device=self.device) if report is None else report
         st = torch.zeros(1, dtype=torch.int32, device=self.device) if status is None else status
         p = params.c()
         q = lb.c()
@@ -373,7 +404,7 @@ class Batch:
 
     def prepare(self, params: Sequence[Params], us: Sequence[torch.Tensor]):
         """Fix the per-pair parameters and displacement fields (updated in place by every
-        step).  Returns (report [npairs][16] float64, status [npairs] int32) tensors that
+        step).  Returns (report [npairs][REP_SIZE] float64, status [npairs] int32) tensors that
         every step rewrites."""
         n = len(self.ctxs)
         if len(params) != n or len(us) != n:
@@ -382,7 +413,7 @@ class Batch:
             c._field(u, "u")
         pa = (_Params * n)(*[p.c() for p in params])
         ua = (_P * n)(*[u.data_ptr() for u in us])
-        rep = torch.zeros((n, 16), dtype=torch.float64, device=self.device)
+        rep = torch.zeros((n, REP_SIZE), dtype=torch.float64, device=self.device)
         st = torch.zeros(n, dtype=torch.int32, device=self.device)
         _check(_lib.disco_batch_prepare(self._h, pa, ua, _ptr(rep), _ptr(st)), "disco_batch_prepare")
         self._keep = (list(us), rep, st)
@@ -468,7 +499,7 @@ class Multilevel:
 def multilevel_register(R: torch.Tensor, T: torch.Tensor, spacing: Sequence[float], kp_x, kp_t, params: Params,
                         ml: Multilevel, lbfgs: Optional[Lbfgs] = None):
     """Whole coarse-to-fine registration on the device.  Returns (u on the finest level,
-    reports [rows][16] float64 with NaN rows for iterations not run, levels, delta)."""
+    reports [rows][REP_SIZE] float64 with NaN rows for iterations not run, levels, delta)."""
     import numpy as np
     for t in (R, T):
         if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != 3:
@@ -488,7 +519,7 @@ def multilevel_register(R: torch.Tensor, T: torch.Tensor, spacing: Sequence[floa
         raise ValueError("keypoints and targets differ in shape")
     u = torch.empty((3, nz // 4 + 1, ny // 4 + 1, nx // 4 + 1), dtype=torch.float32, device=R.device)
     rows = sum(int(i) for i in ml.iters[:ml.levels])
-    rep = torch.empty((max(rows, 1), 16), dtype=torch.float64, device=R.device)
+    rep = torch.empty((max(rows, 1), REP_SIZE), dtype=torch.float64, device=R.device)
     L = ctypes.c_int32()
     delta = ctypes.c_double()
     with torch.cuda.device(R.device):

@@ -1,0 +1,179 @@
+"""Lung-boundary term of eq. 6 on the device against the FP64 oracle.
+
+Isolated: with R = T = 0 every NGF quantity vanishes exactly (both image gradients are
+zero), so with alpha = gamma = delta = 0 the joint entry points return beta B, its
+gradient, GN diagonal and GN product alone; checked on ragged small volumes and at
+512 x 512 x 128.  Joint: with real images, all terms of eq. 11 and the adaptive beta
+(D = 100 beta B at u = 0), the linearisation, GN product, one GN step and L-BFGS
+iterations against the oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+ETA, ALPHA, GAMMA = 10.0, 1.0, 0.1
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    a = a.detach().cpu().numpy().astype(np.float64) if torch.is_tensor(a) else np.asarray(a, np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def disco():
+    from paper_1807_00467_amd import disco as d
+    return d
+
+
+def make_ctx(disco, d, zero_images=False):
+    ctx = disco.Disco(d["shape"], d["spacing"], device=DEV)
+    if zero_images:
+        z = torch.zeros(d["R"].shape, dtype=torch.float32, device=DEV)
+        ctx.set_images(z, z)
+    else:
+        ctx.set_images(torch.from_numpy(d["R"]).to(DEV), torch.from_numpy(d["T"]).to(DEV))
+        ctx.set_keypoints(d["kp_x"], d["kp_t"])
+    ctx.set_masks(torch.from_numpy(d["mask_R"]).to(DEV), torch.from_numpy(d["mask_T"]).to(DEV))
+    return ctx
+
+
+def isolated_check(disco, d, u, v, beta=1.7):
+    ctx = make_ctx(disco, d, zero_images=True)
+    p = disco.Params(eta=ETA, alpha=0.0, gamma=0.0, delta=0.0, beta=beta)
+    ut = torch.from_numpy(u.astype(np.float32)).to(DEV)
+    out = ctx.objective_linearise(p, ut)
+    Hv = ctx.gn_hessvec(p, torch.from_numpy(v).to(DEV))
+    torch.cuda.synchronize()
+    ref = oracle.mask_term(d["mask_R"], d["mask_T"], d["spacing"], ut.cpu().numpy())
+    hv_ref = beta * oracle.mask_hv(ref["sb"], d["spacing"], v)
+    eB = abs(out["B"] - ref["B"]) / ref["B"]
+    eJ = abs(out["J"] - beta * ref["B"]) / (beta * ref["B"])
+    eg = rel_l2(out["g"], beta * ref["g"])
+    ed = rel_l2(out["diag"], beta * ref["diag"])
+    eh = rel_l2(Hv, hv_ref)
+    say(f"  B {out['B']:.8e} / {ref['B']:.8e} ({eB:.1e}); g {eg:.1e}; diag {ed:.1e}; Hv {eh:.1e}; D {out['D']}")
+    assert out["D"] == 0.0
+    assert eB < 1e-5 and eJ < 1e-5
+    assert eg < 1e-4 and ed < 1e-4 and eh < 1e-4
+
+
+@pytest.mark.parametrize("shape,spacing,seed", [((48, 40, 28), (1.2, 1.4, 2.2), 21), ((68, 36, 20), (1.5, 1.5, 2.0), 22)])
+def test_boundary_term_isolated(disco, shape, spacing, seed):
+    say(f"[boundary] isolated shape={shape} seed={seed}")
+    d = synth.small_pair(shape=shape, spacing=spacing, seed=seed, n_tubes=6, n_kp=10, field_max=4.0)
+    assert d["mask_R"].sum() > 0 and (d["mask_R"] != d["mask_T"]).sum() > 0
+    u = d["u_true"].astype(np.float64) * 0.6
+    isolated_check(disco, d, u, d["v"])
+
+
+def test_boundary_term_isolated_fullsize(disco):
+    say("[boundary] isolated 512x512x128")
+    d = synth.make_pair("cfg1")
+    isolated_check(disco, d, d["u_true"].astype(np.float64) * 0.8, d["v"])
+
+
+@pytest.fixture(scope="module")
+def joint(disco):
+    d = synth.small_pair(shape=(48, 40, 28), spacing=(1.2, 1.4, 2.2), seed=23, n_tubes=8, n_kp=30, field_max=4.0)
+    P = oracle.Problem(d["R"], d["T"], d["spacing"], d["kp_x"], d["kp_t"],
+                       oracle.Weights(eta=ETA, alpha=ALPHA, gamma=GAMMA), bF=d["mask_R"], bM=d["mask_T"])
+    z = np.zeros(d["u_true"].shape)
+    P.w.delta = P.adaptive_delta(z)
+    P.w.beta = P.adaptive_beta(z)
+    return d, P
+
+
+def joint_params(disco, P, **kw):
+    return disco.Params(eta=ETA, alpha=ALPHA, gamma=GAMMA, delta=P.w.delta, beta=P.w.beta, **kw)
+
+
+def test_joint_linearisation_and_product(disco, joint):
+    d, P = joint
+    say(f"[boundary] joint linearisation, beta={P.w.beta:.4g} delta={P.w.delta:.4g}")
+    ctx = make_ctx(disco, d)
+    p = joint_params(disco, P)
+    u = d["u_true"].astype(np.float64) * 0.5
+    out = ctx.objective_linearise(p, torch.from_numpy(u.astype(np.float32)).to(DEV))
+    Hv = ctx.gn_hessvec(p, torch.from_numpy(d["v"]).to(DEV))
+    torch.cuda.synchronize()
+    lin = P.linearise(u.astype(np.float32).astype(np.float64))
+    hv = P.gn_hv(d["v"])
+    for k in ("J", "D", "B", "K"):
+        assert abs(out[k] - lin[k]) <= 1e-5 * abs(lin[k]), k
+    assert rel_l2(out["g"], lin["g"]) < 1e-4
+    assert rel_l2(out["diag"], lin["diag"]) < 1e-4
+    assert rel_l2(Hv, hv) < 1e-4
+    # the term is not negligible in what is compared
+    Pb = oracle.Problem(d["R"], d["T"], d["spacing"], d["kp_x"], d["kp_t"], dataclass_copy(P.w, beta=0.0))
+    lin0 = Pb.linearise(u)
+    assert np.linalg.norm(lin["g"] - lin0["g"]) > 1e-3 * np.linalg.norm(lin["g"])
+
+
+def dataclass_copy(w, **kw):
+    import dataclasses
+    return dataclasses.replace(w, **kw)
+
+
+def test_joint_gn_step_and_lbfgs(disco, joint):
+    d, P = joint
+    say("[boundary] joint GN step and L-BFGS")
+    ctx = make_ctx(disco, d)
+    p = joint_params(disco, P, pcg_iters=8, ls_max=10, flags=disco.FLAG_LS_DEVICE)
+    u0 = d["u_true"].astype(np.float32) * 0.5
+    u = torch.from_numpy(u0.copy()).to(DEV)
+    rep, st = ctx.gn_pcg_step(p, u)
+    torch.cuda.synchronize()
+    r = disco.Disco.report_dict(rep)
+    u1, ref = oracle.gn_pcg_step(P, u0.astype(np.float64), oracle.StepParams(pcg_iters=8, ls_max=10))
+    say(f"  GN: J {r['J']:.8e} / {ref['J']:.8e}, B {r['B']:.6e} / {ref['B']:.6e}, t {r['t']} / {ref['t']}")
+    for k in ("J", "D", "B"):
+        assert abs(r[k] - ref[k]) <= 1e-5 * abs(ref[k]), k
+    assert r["t"] == ref["t"] and int(st.item()) == 0
+    assert abs(r["B_new"] - ref["trial"]["B"]) <= 1e-5 * abs(ref["trial"]["B"])
+    assert rel_l2(u.cpu().numpy() - u0, u1 - u0) < 1e-3
+    # L-BFGS with the term
+    ctx2 = make_ctx(disco, d)
+    lb = disco.Lbfgs(m=3, tau=10.0, h0_iters=60, h0_tol=1e-7)
+    ul = torch.zeros_like(u)
+    reps = []
+    for _ in range(4):
+        rp, _ = ctx2.lbfgs_step(p, lb, ul)
+        reps.append(disco.Disco.report_dict(rp))
+    torch.cuda.synchronize()
+    uo, oreps = oracle.lbfgs_run(P, np.zeros(u0.shape), 4, oracle.LbfgsParams(m=3, tau=10.0, ls_max=10))
+    for k, (a, b) in enumerate(zip(reps, oreps)):
+        say(f"  L-BFGS it {k}: J {a['J']:.8e} / {b['J']:.8e} t {a['t']} / {b['t']}")
+        assert abs(a["J"] - b["J"]) <= 1e-5 * abs(b["J"]) and a["t"] == b["t"], k
+    assert rel_l2(ul.cpu().numpy(), uo) < 2e-3
+
+
+def test_masks_argument_errors(disco):
+    d = synth.small_pair(shape=(16, 16, 12), spacing=(1.5, 1.5, 1.5), seed=24)
+    ctx = make_ctx(disco, d)
+    with pytest.raises(ValueError):
+        ctx.set_masks(torch.zeros((12, 16, 15), dtype=torch.uint8, device=DEV), torch.zeros((12, 16, 15),
+                      dtype=torch.uint8, device=DEV))
+    p = disco.Params(eta=ETA, beta=1.0)
+    u = torch.zeros((3,) + tuple(ctx.nodes[::-1]), device=DEV)
+    ctx.ngf_grad(u, ETA)  # a linearisation without the boundary term
+    with pytest.raises(disco.DiscoError) as e:
+        ctx.gn_hessvec(p, u)
+    assert e.value.code == disco.ERR_STATE
+    with pytest.raises(disco.DiscoError) as e:
+        ctx.objective_linearise(disco.Params(eta=ETA, beta=-1.0), u)
+    assert e.value.code == disco.ERR_NONFINITE
+    ctx.set_masks(None, None)
+    ctx.gn_hessvec(p, u)  # without masks beta is ignored
+    torch.cuda.synchronize()
