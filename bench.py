@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="batched form instead: 24 uneven pyramid-shape pairs, 5 GN iterations (15 PCG each), "
                          "one launch per phase and one graph, against the same steps pair by pair")
+    ap.add_argument("--boundary", action="store_true",
+                    help="add the lung-boundary term (eq. 6) with the adaptive beta (D = 100 beta B at u = 0)")
     ap.add_argument("--lbfgs", action="store_true",
                     help="L-BFGS iterations (m = 5, H0 = alpha C_H L^T L + tau I) on the same workload instead")
     ap.add_argument("--tau", type=float, default=10.0, help="tau of the L-BFGS initial Hessian")
@@ -161,6 +163,12 @@ def main():
     params = disco.Params(eta=10.0, alpha=1.0, gamma=0.1, delta=D0 / K0 if K0 > 0 else 0.0,
                           pcg_iters=PCG_ITERS, pcg_tol=0.0, ls_max=10)
     log(f"[bench] delta = {params.delta:.4g}")
+    if args.boundary:
+        ctx.set_masks(torch.from_numpy(d["mask_R"]).to(dev), torch.from_numpy(d["mask_T"]).to(dev))
+        B0 = ctx.objective_linearise(disco.Params(eta=10.0, alpha=0.0, gamma=0.0, delta=0.0, beta=1.0), zero,
+                                     grad=False, diag=False)["B"]
+        params.beta = D0 / (100.0 * B0) if B0 > 0 else 0.0
+        log(f"[bench] beta = {params.beta:.4g}")
     u = torch.empty_like(u_true)
     rep = torch.zeros(disco.REP_SIZE, dtype=torch.float64, device=dev)
     st = torch.zeros(1, dtype=torch.int32, device=dev)
@@ -199,6 +207,8 @@ def main():
     hv_total = PCG_ITERS * args.steps
     value = hv_total / elapsed
     kernel_tag = f"brick_hv_{d['shape'][0]}x{d['shape'][1]}x{d['shape'][2]}_{args.storage}"
+    if args.boundary:
+        kernel_tag += "_boundary"
     out = {
         "metric": METRIC,
         "value": value,
@@ -216,9 +226,10 @@ def main():
             "workload": f"{args.config}: R,T {d['shape'][0]}x{d['shape'][1]}x{d['shape'][2]} at "
                         f"{d['spacing'][0]}x{d['spacing'][1]}x{d['spacing'][2]} mm, node grid {nx}x{ny}x{nz}, "
                         f"{len(d['kp_x'])} keypoints; step = image gradients + GN step "
-                        f"(linearise + {PCG_ITERS} PCG GN products + Armijo)",
+                        f"(linearise + {PCG_ITERS} PCG GN products + Armijo)"
+                        + ("; with the lung-boundary term" if args.boundary else ""),
             "eta": params.eta, "alpha": params.alpha, "gamma": params.gamma, "delta": params.delta,
-            "storage": args.storage,
+            "beta": params.beta, "storage": args.storage,
         },
         "gvoxel_per_s_hv_kernel": nvox / hv_s / 1e9,
         "hv_kernel_us": hv_s * 1e6,

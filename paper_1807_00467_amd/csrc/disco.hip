@@ -59,7 +59,7 @@ struct disco_ctx {
   float *adjW = nullptr;  // dD/d(grad T) accumulator of ngf_grad_T, [N][3] (allocated on first use)
   // lung masks and the boundary term's GN vectors (allocated by disco_set_masks)
   uint8_t *mF = nullptr, *mM = nullptr, *rflag = nullptr;
-  float *sbc = nullptr;
+  float *sbc = nullptr, *zb = nullptr;
   bool masks = false;
   bool lin_mask = false;  // the last linearisation wrote the boundary term's GN vectors
   // L-BFGS history (allocated on first use): a ring of lb_m pairs (s, y)
@@ -242,6 +242,7 @@ BrickArgs<ST> make_args(disco_ctx *c, const BrickCall &b) {
   a.mM = c->mM;
   a.sbc = c->sbc;
   a.rflag = c->rflag;
+  a.zb = c->zb;
   a.mscale = (float)(0.5 * b.beta);
   a.mroot = (float)std::sqrt(0.5 * b.beta);
   return a;
@@ -494,7 +495,7 @@ void disco_destroy(disco_ctx *c) {
   void *ptrs[] = {c->gR,  c->gT,  c->scache, c->u_lin, c->u_ref, c->Lw,   c->vg,   c->vdiag, c->vx,   c->vr,
                   c->vz,  c->vp,  c->vq,     c->vut,   c->tmp0,  c->tmp1, c->part, c->blk_brick, c->blk_node,
                   c->sc,  c->status, c->kloc, c->ktgt, c->kstart, c->blk_curv, c->blk_upd, c->adjW, c->vp2, c->vinvm,
-                  c->lbS, c->lbY, c->mF, c->mM, c->rflag, c->sbc};
+                  c->lbS, c->lbY, c->mF, c->mM, c->rflag, c->sbc, c->zb};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->host_sc) (void)hipHostFree(c->host_sc);
@@ -746,13 +747,16 @@ int disco_set_masks(disco_ctx *c, const uint8_t *bF, const uint8_t *bM, disco_st
     bool okm = hipMalloc(reinterpret_cast<void **>(&c->mF), (size_t)g.nvox) == hipSuccess &&
                hipMalloc(reinterpret_cast<void **>(&c->mM), (size_t)g.nvox) == hipSuccess &&
                hipMalloc(reinterpret_cast<void **>(&c->rflag), nrow) == hipSuccess &&
-               hipMalloc(reinterpret_cast<void **>(&c->sbc), sizeof(float) * 3 * (size_t)g.nvox) == hipSuccess;
+               hipMalloc(reinterpret_cast<void **>(&c->sbc), sizeof(float) * 3 * (size_t)g.nvox) == hipSuccess &&
+               hipMalloc(reinterpret_cast<void **>(&c->zb), sizeof(float) * 3 * 64) == hipSuccess &&
+               hipMemset(c->zb, 0, sizeof(float) * 3 * 64) == hipSuccess &&
+               hipMemset(c->rflag, 0, nrow) == hipSuccess && hipDeviceSynchronize() == hipSuccess;
     if (!okm) {
-      void *ps[] = {c->mF, c->mM, c->rflag, c->sbc};
+      void *ps[] = {c->mF, c->mM, c->rflag, c->sbc, c->zb};
       for (void *q : ps)
         if (q) (void)hipFree(q);
       c->mF = c->mM = c->rflag = nullptr;
-      c->sbc = nullptr;
+      c->sbc = c->zb = nullptr;
       return DISCO_ERR_NOMEM;
     }
   }

@@ -454,7 +454,10 @@ struct BrickArgs {
   double *blocks;               // BS_N doubles per workgroup
   const uint8_t *mF, *mM;       // lung masks b_F, b_M [N] (lung-boundary term)
   float *sbc;                   // boundary-term GN vectors sqrt(beta/2) grad b_M(y) [N][3], rows with rflag set
-  uint8_t *rflag;               // per 64-voxel row (z, y, brick x): 1 if its boundary-term vectors are not all 0
+  uint8_t *rflag;               // per 64-voxel row: 1 if its boundary-term vectors are not all 0; 16 rows
+                                // (4 z x 4 y voxel rows) of a wave's cell row per cell layer, together:
+                                // [cz][brick x][cy][kv * 4 + jv]
+  const float *zb;              // 64 x 3 zeros: read instead of sbc for rows without vectors
   float mscale, mroot;          // beta / 2, sqrt(beta / 2)
   const double *stop;           // if non-null and *stop != 0 the launch does nothing
   int acc;                      // add to out0/out1, part and blocks instead of writing them
@@ -1124,6 +1127,15 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
             // first voxel of this lane in the layer; voxel (kv, jv) is vbase + kv*nx*ny + jv*nx,
             // the offset being the same for the whole wave
             const int64_t vbase = ((int64_t)(czi * 4) * g.ny + cy * 4) * g.nx + ix;
+            // boundary-term row flags of this layer (16 bytes, one load)
+            uint32_t mflags[4] = {0u, 0u, 0u, 0u};
+            if constexpr (MASK && MODE == M_HV) {
+              const uint4 f4 = *reinterpret_cast<const uint4 *>(A.rflag + (((int64_t)czi * g.nbx + bx) * g.cy + cy) * 16);
+              mflags[0] = f4.x;
+              mflags[1] = f4.y;
+              mflags[2] = f4.z;
+              mflags[3] = f4.w;
+            }
             const typename ST::elem *sp = A.sc + vbase * ST::W;
             const typename ST::elem *rp = A.gR + vbase * ST::W;
             auto zrow = [&](const int kv) {
@@ -1156,17 +1168,18 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
                     accY[0][1][c] += wy * t;
                   }
                   if constexpr (MASK) {
-                    // boundary term: only rows that touch the mask boundary carry vectors
-                    if (A.rflag[((int64_t)iz * g.ny + iy) * g.nbx + bx]) {
-                      const float *bp = A.sbc + (vbase + kv * nxy + jv * g.nx) * 3;
-                      const float sb[3] = {bp[0], bp[1], bp[2]};
-                      const float wb = sb[0] * f3[0] + sb[1] * f3[1] + sb[2] * f3[2];
+                    // boundary term: only rows that touch the mask boundary carry vectors; the
+                    // others read a small zero buffer (cache hits), so that the loads need no
+                    // branch and issue with the s loads
+                    const bool fl = ((mflags[kv] >> (8 * jv)) & 0xffu) != 0u;
+                    const float *bp = fl ? A.sbc + (vbase + kv * nxy + jv * g.nx) * 3 : A.zb + lane * 3;
+                    const float sb[3] = {bp[0], bp[1], bp[2]};
+                    const float wb = sb[0] * f3[0] + sb[1] * f3[1] + sb[2] * f3[2];
     #pragma unroll
-                      for (int c = 0; c < 3; ++c) {
-                        const float t = wb * sb[c];
-                        accY[0][0][c] += (1.0f - wy) * t;
-                        accY[0][1][c] += wy * t;
-                      }
+                    for (int c = 0; c < 3; ++c) {
+                      const float t = wb * sb[c];
+                      accY[0][0][c] += (1.0f - wy) * t;
+                      accY[0][1][c] += wy * t;
                     }
                   }
                 } else {
@@ -1230,7 +1243,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
     #pragma unroll
                         for (int c = 0; c < 3; ++c) bp[c] = A.mroot * gb[c];
                       }
-                      if (lane == 0) A.rflag[((int64_t)iz * g.ny + iy) * g.nbx + bx] = row ? 1 : 0;
+                      if (lane == 0) A.rflag[(((int64_t)czi * g.nbx + bx) * g.cy + cy) * 16 + kv * 4 + jv] = row ? 1 : 0;
     #pragma unroll
                       for (int c = 0; c < 3; ++c) {
                         const float t = -A.mscale * res * gb[c];
