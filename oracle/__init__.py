@@ -75,6 +75,8 @@ def _load():
         lib.or_ngf_grad_T.restype = None
         lib.or_mask.argtypes = [P, P, P, P, P, P, P, P, P, P]
         lib.or_mask.restype = D
+        lib.or_kp_cost.argtypes = [P, P, P, I64, P, D, I64, I64, P]
+        lib.or_kp_cost.restype = None
         lib.or_num_threads.argtypes = []
         lib.or_num_threads.restype = ctypes.c_int
         _lib = lib
@@ -716,3 +718,122 @@ def multilevel_run(R, T, spacing, kp_x, kp_t, weights: Weights, params: Multilev
         out.append(dict(shape=lv["shape"], spacing=lv["spacing"], delta=delta, reports=reps,
                         J_final=P.objective(u)["J"]))
     return u, out
+
+
+# ------------------------------------------------------------------------------------
+# keypoint stage (Sec. II-C2, II-C3): NGF matching cost over a displacement grid, a
+# minimum spanning tree over the keypoints, min-sum belief propagation on the tree
+# ------------------------------------------------------------------------------------
+
+KP_PATCH = (-3, -1, 1, 3)   # patch offsets per axis: a 7^3 patch with stride 2 (64 voxels)
+
+
+def kp_labels(R: int = 16, step: int = 2):
+    """Label displacements in voxels, [(2R+1)^3][3] (x, y, z), ordered [iz][iy][ix]."""
+    i = np.arange(2 * R + 1) - R
+    dz, dy, dx = np.meshgrid(i, i, i, indexing="ij")
+    return step * np.stack([dx.ravel(), dy.ravel(), dz.ravel()], axis=1)
+
+
+def kp_cost_volume(F, M, spacing, kps, eta, R: int = 16, step: int = 2):
+    """D_KP(k, d) of eq. 2 for keypoints kps (integer voxel indices [n][3], x, y, z) and
+    labels d = step (i - R) voxels, i = 0..2R per axis: [n][(2R+1)^3] (label order of
+    kp_labels).  Gradients by central differences (HU/mm), zero outside the volume."""
+    gF = image_gradient(F, spacing)
+    gM = image_gradient(M, spacing)
+    nz, ny, nx = np.asarray(F).shape
+    kps = _i64(np.asarray(kps).reshape(-1, 3))
+    nl = 2 * R + 1
+    out = np.empty((len(kps), nl ** 3))
+    _load().or_kp_cost(_p(_i64([nx, ny, nz])), _p(gF), _p(gM), len(kps), _p(kps), float(eta), int(R), int(step),
+                       _p(out))
+    return out
+
+
+def kp_edge_weight(x, inten, k, q, sigma_I: float = 150.0):
+    """Spatial-plus-intensity distance of two keypoints (the denominator of eq. 3)."""
+    return float(np.linalg.norm(x[k] - x[q]) + abs(float(inten[k]) - float(inten[q])) / sigma_I)
+
+
+def kp_mst(x, inten, sigma_I: float = 150.0):
+    """Minimum spanning tree over all keypoint pairs with the edge cost of eq. 3's
+    denominator (Prim's algorithm from keypoint 0; ties to the lowest index).  Returns
+    (parent [n] with parent[0] = -1, visit order)."""
+    x = _f64(x).reshape(-1, 3)
+    inten = _f64(inten).ravel()
+    n = len(x)
+    key = np.full(n, np.inf)
+    parent = np.full(n, -1, np.int64)
+    done = np.zeros(n, bool)
+    key[0] = 0.0
+    order = []
+    for _ in range(n):
+        cand = np.where(done, np.inf, key)
+        k = int(np.argmin(cand))
+        done[k] = True
+        order.append(k)
+        w = np.sqrt(np.sum((x - x[k]) ** 2, axis=1)) + np.abs(inten - inten[k]) / sigma_I
+        upd = (~done) & (w < key)
+        key[upd] = w[upd]
+        parent[upd] = k
+    return parent, np.asarray(order, np.int64)
+
+
+def kp_mincon_bruteforce(f, c, R: int = 16, step: int = 2):
+    """out(d_q) = min over d_k of f(d_k) + c |d_k - d_q|^2 (labels of kp_labels, |.| in
+    voxels): the plain definition, O(L^2)."""
+    lab = kp_labels(R, step).astype(np.float64)
+    f = _f64(f).ravel()
+    out = np.empty_like(f)
+    for qi in range(len(f)):
+        out[qi] = np.min(f + c * np.sum((lab - lab[qi]) ** 2, axis=1))
+    return out
+
+
+def kp_mincon(f, c, R: int = 16, step: int = 2):
+    """The same minimum by separability of |.|^2: a 1-D minimum along x, then y, then z
+    (each over the 2R+1 labels of its line)."""
+    nl = 2 * R + 1
+    g = _f64(f).reshape(nl, nl, nl)
+    i = np.arange(nl)
+    pen = c * (step * (i[:, None] - i[None, :])) ** 2   # [out][in]
+    for ax in (2, 1, 0):
+        gm = np.moveaxis(g, ax, -1)                          # [..., in]
+        g = np.moveaxis(np.min(gm[..., None, :] + pen, axis=-1), -1, ax)
+    return g.ravel()
+
+
+def kp_belief_propagation(D, parent, order, x, inten, alpha_kp: float, sigma_I: float = 150.0, R: int = 16,
+                          step: int = 2, mincon=None):
+    """Min-sum belief propagation on the tree (eq. 4 with the regulariser of eq. 3):
+    inward pass from the leaves, m_kq(d_q) = min_{d_k} h_k(d_k) + R_KP(d_k, d_q) with
+    h_k = D(k, .) + sum of the messages of k's children; outward pass from the root,
+    m_qk(d_k) = min_{d_q} (M_q(d_q) - m_kq(d_q)) + R_KP(d_q, d_k), and min-marginals
+    M_k = h_k + m_qk (M_root = h_root).  R_KP = alpha_kp |d_k - d_q|^2 / w_kq with the
+    label displacement in mm (voxel size 1 mm at the keypoint stage).  Returns
+    (min-marginals [n][L], inward messages [n][L])."""
+    mincon = mincon or kp_mincon
+    D = _f64(D)
+    n, L = D.shape
+    x = _f64(x).reshape(-1, 3)
+    h = D.copy()
+    msg = np.zeros_like(D)
+    cw = np.zeros(n)
+    for k in range(n):
+        if parent[k] >= 0:
+            cw[k] = alpha_kp / kp_edge_weight(x, inten, k, parent[k], sigma_I)
+    for k in order[::-1]:
+        if parent[k] >= 0:
+            msg[k] = mincon(h[k], cw[k], R, step)
+            h[parent[k]] += msg[k]
+    marg = np.empty_like(D)
+    marg[order[0]] = h[order[0]]
+    for k in order[1:]:
+        q = parent[k]
+        marg[k] = h[k] + mincon(marg[q] - msg[k], cw[k], R, step)
+    return marg, msg
+
+
+def kp_argmin(marg):
+    """Label of smallest min-marginal per keypoint (lowest index on ties)."""
+    return np.argmin(_f64(marg), axis=1)

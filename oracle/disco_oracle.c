@@ -929,3 +929,54 @@ double or_mask(const int64_t *n, const double *h, const int64_t *m, const double
     free(sb);
     return B;
 }
+
+/* ------------------------------------------------------------------------------ */
+/* Keypoint matching cost, eq. 2 (Sec. II-C2), on images at isotropic resolution:   */
+/*   D_KP(k, d) = 1/|P| sum_{p in P_k} [1 - <grad M(p+d), grad F(p)>_eta^2 /         */
+/*                                    (|grad M(p+d)|_eta^2 |grad F(p)|_eta^2)]        */
+/* with <f,g>_eta = eta^2 + f.g as in eq. 1 (cancellation-free form of 1 - r^2).     */
+/* Keypoints k are voxel indices; P_k = k + {-3,-1,1,3}^3 (a 7^3 patch, stride 2,    */
+/* 64 voxels); labels d = step (i - R) voxels per axis, i = 0..2R, ordered           */
+/* [iz][iy][ix].  Gradients outside the volume are zero (zero padding).              */
+/* gF, gM: [N][3] gradient images.  out: [nkp][(2R+1)^3].                             */
+/* ------------------------------------------------------------------------------ */
+void or_kp_cost(const int64_t *n, const double *gF, const double *gM, int64_t nkp, const int64_t *kp,
+                double eta, int64_t R, int64_t step, double *out)
+{
+    const int64_t nl = 2 * R + 1, L = nl * nl * nl;
+    const double e2 = eta * eta;
+    static const int off[4] = {-3, -1, 1, 3};
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nkp * nl; ++q) {
+        const int64_t k = q / nl, iz = q % nl;
+        const int64_t *kv = kp + 3 * k;
+        for (int64_t iy = 0; iy < nl; ++iy)
+            for (int64_t ix = 0; ix < nl; ++ix) {
+                const int64_t d[3] = {step * (ix - R), step * (iy - R), step * (iz - R)};
+                double sum = 0.0;
+                for (int oz = 0; oz < 4; ++oz)
+                    for (int oy = 0; oy < 4; ++oy)
+                        for (int ox = 0; ox < 4; ++ox) {
+                            const int64_t p[3] = {kv[0] + off[ox], kv[1] + off[oy], kv[2] + off[oz]};
+                            double a[3] = {0.0, 0.0, 0.0}, b[3] = {0.0, 0.0, 0.0};
+                            const int64_t pd[3] = {p[0] + d[0], p[1] + d[1], p[2] + d[2]};
+                            if (p[0] >= 0 && p[0] < n[0] && p[1] >= 0 && p[1] < n[1] && p[2] >= 0 && p[2] < n[2]) {
+                                const double *g = gF + 3 * IDX3(p[0], p[1], p[2], n[0], n[1]);
+                                b[0] = g[0]; b[1] = g[1]; b[2] = g[2];
+                            }
+                            if (pd[0] >= 0 && pd[0] < n[0] && pd[1] >= 0 && pd[1] < n[1] && pd[2] >= 0 && pd[2] < n[2]) {
+                                const double *g = gM + 3 * IDX3(pd[0], pd[1], pd[2], n[0], n[1]);
+                                a[0] = g[0]; a[1] = g[1]; a[2] = g[2];
+                            }
+                            const double Da = e2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+                            const double Db = e2 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+                            const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+                            const double cx = a[1] * b[2] - a[2] * b[1];
+                            const double cy = a[2] * b[0] - a[0] * b[2];
+                            const double cz = a[0] * b[1] - a[1] * b[0];
+                            sum += (e2 * (dx * dx + dy * dy + dz * dz) + cx * cx + cy * cy + cz * cz) / (Da * Db);
+                        }
+                out[k * L + (iz * nl + iy) * nl + ix] = sum / 64.0;
+            }
+    }
+}

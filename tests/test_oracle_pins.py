@@ -901,3 +901,120 @@ def test_problem_with_boundary_term_and_adaptive_beta():
     assert abs(o["J"] - (P0.objective(u0)["J"] + beta * o["B"])) <= 1e-12 * o["J"]
     u1, rep = oracle.gn_pcg_step(P, u0, oracle.StepParams(pcg_iters=10))
     assert rep["accepted"] and rep["trial"]["J"] < rep["J"]
+
+
+# ---- keypoint stage (Sec. II-C2, II-C3) ------------------------------------------------
+
+def kp_images(seed=31, shape=(40, 36, 32)):
+    d = synth.small_pair(shape=shape, spacing=(1.0, 1.0, 1.0), seed=seed, n_tubes=8, n_kp=12, field_max=3.0)
+    return d
+
+
+def test_kp_cost_zero_for_identical_images_at_zero_displacement():
+    d = kp_images()
+    kps = np.array([[5, 6, 7], [20, 18, 16], [1, 34, 30], [39, 0, 0]])  # incl. border keypoints
+    D = oracle.kp_cost_volume(d["R"], d["R"], (1.0, 1.0, 1.0), kps, 12.0, R=3, step=2)
+    zero = (3 * 7 + 3) * 7 + 3  # label d = 0
+    np.testing.assert_array_equal(D[:, zero], 0.0)
+    assert np.all(D >= 0.0) and np.all(D <= 1.0)
+
+
+def test_kp_cost_translation_has_zero_at_the_shift():
+    """M(z) = F(z - t) with t = (2, -4, 6): D(k, t) = 0 where patch and gradient
+    stencils stay inside the volume, and t is the arg-min."""
+    d = kp_images(32, shape=(48, 48, 48))
+    F = d["R"]
+    t = (2, -4, 6)
+    M = np.roll(F, shift=(t[2], t[1], t[0]), axis=(0, 1, 2))
+    kps = np.array([[20, 22, 18], [24, 26, 20], [18, 24, 22]])
+    D = oracle.kp_cost_volume(F, M, (1.0, 1.0, 1.0), kps, 12.0, R=4, step=2)
+    lab = oracle.kp_labels(4, 2)
+    it = int(np.where((lab == np.array(t)).all(axis=1))[0][0])
+    assert np.all(D[:, it] < 1e-15)
+    assert np.all(np.argmin(D, axis=1) == it)
+
+
+def test_kp_cost_matches_library_gradients_and_plain_formula():
+    """Eq. 2 evaluated with torch central differences and numpy at sampled labels; and the
+    eta -> infinity limit eta^2 D -> mean |a - b|^2."""
+    d = kp_images(33)
+    F, M = d["R"], d["T"]
+    gF = conv_gradient(F, (1.0, 1.0, 1.0))
+    gM = conv_gradient(M, (1.0, 1.0, 1.0))
+    nz, ny, nx = F.shape
+    kps = np.array([[10, 12, 9], [30, 20, 25], [2, 33, 3]])
+    R, step = 3, 2
+    lab = oracle.kp_labels(R, step)
+    off = np.array(np.meshgrid(*[oracle.KP_PATCH] * 3, indexing="ij")).reshape(3, -1).T[:, ::-1]
+
+    def grad_at(g, pts):
+        out = np.zeros((len(pts), 3))
+        ok = (pts[:, 0] >= 0) & (pts[:, 0] < nx) & (pts[:, 1] >= 0) & (pts[:, 1] < ny) & (pts[:, 2] >= 0) & (pts[:, 2] < nz)
+        out[ok] = g[pts[ok, 2], pts[ok, 1], pts[ok, 0]]
+        return out
+
+    for eta, tol in ((12.0, 1e-12), (1e7, 1e-6)):
+        D = oracle.kp_cost_volume(F, M, (1.0, 1.0, 1.0), kps, eta, R=R, step=step)
+        for k in range(len(kps)):
+            for li in rng(k).integers(0, len(lab), 12):
+                p = kps[k] + off
+                b = grad_at(gF, p)
+                a = grad_at(gM, p + lab[li])
+                if eta < 1e6:
+                    r2 = (eta ** 2 + np.sum(a * b, 1)) ** 2 / ((eta ** 2 + np.sum(a * a, 1)) * (eta ** 2 + np.sum(b * b, 1)))
+                    ref = np.mean(1.0 - r2)
+                    assert abs(D[k, li] - ref) <= tol, (k, li)
+                else:
+                    ref = np.mean(np.sum((a - b) ** 2, 1))
+                    assert abs(eta ** 2 * D[k, li] - ref) <= tol * max(ref, 1.0), (k, li)
+
+
+def test_kp_mst_is_a_minimum_spanning_tree():
+    from scipy.sparse.csgraph import minimum_spanning_tree
+    r = rng(34)
+    x = r.uniform(0, 100, (60, 3))
+    inten = r.normal(-800, 100, 60)
+    parent, order = oracle.kp_mst(x, inten)
+    W = np.sqrt(((x[:, None] - x[None]) ** 2).sum(-1)) + np.abs(inten[:, None] - inten[None]) / 150.0
+    ref = minimum_spanning_tree(W).sum()
+    ours = sum(W[k, parent[k]] for k in range(60) if parent[k] >= 0)
+    assert abs(ours - ref) <= 1e-9 * ref
+    assert parent[0] == -1 and np.sum(parent >= 0) == 59 and order[0] == 0
+    pos = {int(k): i for i, k in enumerate(order)}
+    assert all(pos[int(parent[k])] < pos[k] for k in range(1, 60))  # parents come first: a tree
+
+
+def test_kp_mincon_separable_equals_brute_force():
+    r = rng(35)
+    for R, step, c in ((2, 2, 0.37), (1, 2, 5.0), (3, 1, 0.01)):
+        f = r.normal(size=(2 * R + 1) ** 3)
+        np.testing.assert_allclose(oracle.kp_mincon(f, c, R, step), oracle.kp_mincon_bruteforce(f, c, R, step),
+                                   rtol=0, atol=1e-12)
+
+
+def test_kp_belief_propagation_gives_exact_min_marginals():
+    """On a 4-node tree with 27 labels the min-marginals equal brute-force minimisation of
+    sum_k D(k, d_k) + sum_edges R_KP over all 27^4 joint labelings with d_k fixed."""
+    r = rng(36)
+    n, R, step = 4, 1, 2
+    L = (2 * R + 1) ** 3
+    x = r.uniform(0, 20, (n, 3))
+    inten = r.normal(-800, 80, n)
+    D = r.uniform(0, 1, (n, L))
+    parent, order = oracle.kp_mst(x, inten)
+    alpha = 0.8
+    marg, _ = oracle.kp_belief_propagation(D, parent, order, x, inten, alpha, R=R, step=step,
+                                           mincon=oracle.kp_mincon_bruteforce)
+    lab = oracle.kp_labels(R, step).astype(np.float64)
+    idx = np.array(np.meshgrid(*[np.arange(L)] * n, indexing="ij")).reshape(n, -1)
+    E = sum(D[k][idx[k]] for k in range(n))
+    for k in range(n):
+        if parent[k] >= 0:
+            w = oracle.kp_edge_weight(x, inten, k, parent[k])
+            E = E + alpha / w * np.sum((lab[idx[k]] - lab[idx[parent[k]]]) ** 2, axis=1)
+    for k in range(n):
+        ref = np.full(L, np.inf)
+        np.minimum.at(ref, idx[k], E)
+        np.testing.assert_allclose(marg[k], ref, rtol=1e-12, atol=1e-12)
+    marg2, _ = oracle.kp_belief_propagation(D, parent, order, x, inten, alpha, R=R, step=step)
+    np.testing.assert_allclose(marg2, marg, rtol=1e-12, atol=1e-12)
