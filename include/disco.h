@@ -299,6 +299,46 @@ int multilevel_register(const disco_geom *geom, const float *R, const float *T, 
                         const float *kp_t, const disco_multilevel *cfg, float *u_out, double *report_dev,
                         int32_t *levels_out, double *delta_out, disco_stream stream);
 
+/* ---- keypoint stage (Sec. II-C2, II-C3) ---------------------------------------------- */
+
+typedef struct disco_kp disco_kp;
+
+/* A keypoint-matching context for images of n = {Nx, Ny, Nz} voxels at spacing h (mm; the
+   paper resamples both scans to 1 mm isotropic for this stage, so that displacements in
+   voxels are displacements in mm), on the current device.  Allocates 2 x 16 bytes per
+   voxel. */
+int disco_kp_create(const int32_t n[3], const double h[3], disco_kp **out);
+void disco_kp_destroy(disco_kp *kp);
+
+/* Fixed image F and moving image M (device float32 [Nz][Ny][Nx]): central-difference
+   gradients (replicated border, HU/mm) normalised with eta as in eq. 1, stored as the
+   4-vectors (eta, grad I) / |(eta, grad I)|; outside the volume the gradient is zero. */
+int disco_kp_set_images(disco_kp *kp, const float *F, const float *M, double eta, disco_stream stream);
+
+/* The matching cost of eq. 2 for nkp keypoints (device int32 [nkp][3], voxel indices
+   x, y, z): cost (device float32 [nkp][(2R+1)^3], labels [iz][iy][ix]) receives
+   D_KP(k, d) = 1/64 sum_{p in P_k} (1 - r(p, p + d)^2) with P_k = k + {-3,-1,1,3}^3 (a
+   7^3 patch of stride 2), d = 2 (i - R) voxels per axis (step 2, the paper's
+   {0, +-2, ..., +-32} mm for R = 16), r the eta-normalised gradient cosine of eq. 1.
+   1 <= R <= 16. */
+int disco_kp_cost(disco_kp *kp, int32_t nkp, const int32_t *kp_vox, int32_t R, float *cost, disco_stream stream);
+
+/* Regularised correspondences (Sec. II-C3): minimum spanning tree over all keypoint pairs
+   with edge cost w_kq = |x_k - x_q| + |I_k - I_q| / sigma_I (Prim's algorithm on the host
+   from keypoint 0, ties to the lowest index), then two-pass min-sum belief propagation on
+   the tree with the data cost `cost` (as written by disco_kp_cost) and the regulariser of
+   eq. 3, alpha_kp |d_k - d_q|^2 / w_kq (|.| in mm), each message a min-convolution done as
+   three exact 1-D minimisations (x, y, z), one tree level per launch.  x_mm (HOST
+   float32 [nkp][3]) and inten (HOST float32 [nkp], F at the keypoint) define w.  Writes
+   the min-marginal energies to marg (device float32 [nkp][(2R+1)^3], nullable), the label
+   of the smallest one per keypoint (lowest index on ties) to labels (device int32 [nkp])
+   and the tree to parent_out (HOST int32 [nkp], nullable; -1 at the root).  Allocates
+   4 x nkp x (2R+1)^3 floats of work memory for the call and waits for the stream before
+   returning. */
+int disco_kp_regularise(disco_kp *kp, int32_t nkp, const float *x_mm, const float *inten, int32_t R,
+                        const float *cost, double alpha_kp, double sigma_I, float *marg, int32_t *labels,
+                        int32_t *parent_out, disco_stream stream);
+
 /* Copy a derived buffer (DISCO_BUF_*) to dst, converted to float32 [Nz][Ny][Nx][3]. */
 int disco_copy_buffer(disco_ctx *ctx, int32_t which, float *dst, disco_stream stream);
 

@@ -17,6 +17,7 @@
 #include "adjoint.hpp"
 #include "batch.hpp"
 #include "pyramid.hpp"
+#include "keypoint.hpp"
 
 using namespace disco;
 
@@ -77,6 +78,15 @@ struct disco_ctx {
   // profiling
   bool prof = false;
   std::vector<EventPair> ev[4];
+};
+
+// keypoint stage: normalised gradient 4-vectors of F and M, split by voxel parity
+struct disco_kp {
+  int device = 0;
+  KpGeo g{};
+  double h[3] = {1.0, 1.0, 1.0};
+  float4 *nF = nullptr, *nM = nullptr;
+  bool images = false;
 };
 
 // a group of contexts stepped together (see batch.hpp)
@@ -1872,6 +1882,201 @@ int multilevel_register(const disco_geom *geom, const float *R, const float *T, 
   disco_destroy(prev);
   if (levels_out) *levels_out = L;
   if (delta_out) *delta_out = delta;
+  HIP_TRY(hipStreamSynchronize(s));
+  return DISCO_OK;
+}
+
+// ---- keypoint stage (Sec. II-C2, II-C3) ---------------------------------------------------
+
+int disco_kp_create(const int32_t n[3], const double h[3], disco_kp **out) {
+  if (!out) return DISCO_ERR_ARG;
+  *out = nullptr;
+  if (!n || !h) return DISCO_ERR_ARG;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 1) return DISCO_ERR_SHAPE;
+    if (!std::isfinite(h[a]) || !(h[a] > 0.0)) return DISCO_ERR_NONFINITE;
+  }
+  const int64_t nvox = (int64_t)n[0] * n[1] * n[2];
+  if (nvox >= ((int64_t)1 << 31)) return DISCO_ERR_SHAPE;
+  disco_kp *k = new (std::nothrow) disco_kp();
+  if (!k) return DISCO_ERR_NOMEM;
+  (void)hipGetDevice(&k->device);
+  KpGeo &g = k->g;
+  g.nx = n[0];
+  g.ny = n[1];
+  g.nz = n[2];
+  g.hx = (n[0] + 1) / 2;
+  g.hy = (n[1] + 1) / 2;
+  g.hz = (n[2] + 1) / 2;
+  g.ihx2 = (float)(0.5 / h[0]);
+  g.ihy2 = (float)(0.5 / h[1]);
+  g.ihz2 = (float)(0.5 / h[2]);
+  for (int a = 0; a < 3; ++a) k->h[a] = h[a];
+  const size_t entries = (size_t)8 * g.hx * g.hy * g.hz;
+  if (hipMalloc(reinterpret_cast<void **>(&k->nF), sizeof(float4) * entries) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void **>(&k->nM), sizeof(float4) * entries) != hipSuccess) {
+    if (k->nF) (void)hipFree(k->nF);
+    delete k;
+    return DISCO_ERR_NOMEM;
+  }
+  *out = k;
+  return DISCO_OK;
+}
+
+void disco_kp_destroy(disco_kp *k) {
+  if (!k) return;
+  (void)hipSetDevice(k->device);
+  (void)hipDeviceSynchronize();
+  if (k->nF) (void)hipFree(k->nF);
+  if (k->nM) (void)hipFree(k->nM);
+  delete k;
+}
+
+int disco_kp_set_images(disco_kp *k, const float *F, const float *M, double eta, disco_stream stream) {
+  if (!k || !F || !M) return DISCO_ERR_ARG;
+  if (!aligned4(F) || !aligned4(M)) return DISCO_ERR_SHAPE;
+  if (!std::isfinite(eta) || !(eta > 0.0)) return DISCO_ERR_NONFINITE;
+  HIP_TRY(hipSetDevice(k->device));
+  const KpGeo &g = k->g;
+  const dim3 grid((unsigned)((g.hx + 255) / 256), (unsigned)g.hy, (unsigned)(8 * g.hz));
+  hipLaunchKernelGGL(k_kp_normalize, grid, dim3(256), 0, S(stream), g, F, (float)eta, k->nF);
+  hipLaunchKernelGGL(k_kp_normalize, grid, dim3(256), 0, S(stream), g, M, (float)eta, k->nM);
+  HIP_TRY(hipGetLastError());
+  k->images = true;
+  return DISCO_OK;
+}
+
+int disco_kp_cost(disco_kp *k, int32_t nkp, const int32_t *kp_vox, int32_t R, float *cost, disco_stream stream) {
+  if (!k || nkp < 0 || (nkp > 0 && (!kp_vox || !cost))) return DISCO_ERR_ARG;
+  if (R < 1 || R > kKpRmax) return DISCO_ERR_ARG;
+  if (!k->images) return DISCO_ERR_STATE;
+  if (nkp == 0) return DISCO_OK;
+  if (!aligned4(kp_vox) || !aligned4(cost)) return DISCO_ERR_SHAPE;
+  HIP_TRY(hipSetDevice(k->device));
+  const int nl = 2 * R + 1;
+  const dim3 grid((unsigned)nkp, (unsigned)nl, (unsigned)((nl + kKpRows - 1) / kKpRows));
+  hipLaunchKernelGGL(k_kp_cost, grid, dim3(kKpThreads), 0, S(stream), k->g, k->nF, k->nM, nkp, kp_vox, R, cost);
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+// minimum spanning tree over all keypoint pairs (Prim from keypoint 0, ties to the lowest
+// index) with the cost |x_k - x_q| + |I_k - I_q| / sigma_I; parent[0] = -1
+static void kp_mst(int n, const float *x, const float *inten, double sigma_I, std::vector<int> &parent,
+                   std::vector<int> &order) {
+  std::vector<double> key(n, INFINITY);
+  std::vector<char> done(n, 0);
+  parent.assign(n, -1);
+  order.clear();
+  key[0] = 0.0;
+  for (int it = 0; it < n; ++it) {
+    int k = -1;
+    double best = INFINITY;
+    for (int q = 0; q < n; ++q)
+      if (!done[q] && (k < 0 || key[q] < best)) {
+        best = key[q];
+        k = q;
+      }
+    done[k] = 1;
+    order.push_back(k);
+    const double xk = x[3 * k], yk = x[3 * k + 1], zk = x[3 * k + 2], ik = inten[k];
+    for (int q = 0; q < n; ++q) {
+      if (done[q]) continue;
+      const double dx = x[3 * q] - xk, dy = x[3 * q + 1] - yk, dz = x[3 * q + 2] - zk;
+      const double w = std::sqrt(dx * dx + dy * dy + dz * dz) + std::fabs((double)inten[q] - ik) / sigma_I;
+      if (w < key[q]) {
+        key[q] = w;
+        parent[q] = k;
+      }
+    }
+  }
+}
+
+int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float *inten, int32_t R,
+                        const float *cost, double alpha_kp, double sigma_I, float *marg, int32_t *labels,
+                        int32_t *parent_out, disco_stream stream) {
+  if (!k || nkp < 1 || !x_mm || !inten || !cost || !labels) return DISCO_ERR_ARG;
+  if (R < 1 || R > kKpRmax) return DISCO_ERR_ARG;
+  if (!finite_nonneg(alpha_kp) || !std::isfinite(sigma_I) || !(sigma_I > 0.0)) return DISCO_ERR_NONFINITE;
+  if (!aligned4(cost) || !aligned4(labels) || (marg && !aligned4(marg))) return DISCO_ERR_SHAPE;
+  HIP_TRY(hipSetDevice(k->device));
+  hipStream_t s = S(stream);
+  const int n = nkp, nl = 2 * R + 1;
+  const int64_t L = (int64_t)nl * nl * nl;
+  // tree, levels (depth from the root), children lists, per-edge weights (host)
+  std::vector<int> parent, order;
+  kp_mst(n, x_mm, inten, sigma_I, parent, order);
+  std::vector<int> depth(n, 0);
+  int maxd = 0;
+  for (size_t i = 1; i < order.size(); ++i) {
+    const int q = order[i];
+    depth[q] = depth[parent[q]] + 1;
+    maxd = std::max(maxd, depth[q]);
+  }
+  std::vector<int> lstart(maxd + 2, 0), lnodes(n), cstart(n + 1, 0), cidx(std::max(n - 1, 1));
+  for (int q = 0; q < n; ++q) ++lstart[depth[q] + 1];
+  for (int d = 0; d <= maxd; ++d) lstart[d + 1] += lstart[d];
+  {
+    std::vector<int> fill(lstart.begin(), lstart.end() - 1);
+    for (int q : order) lnodes[fill[depth[q]]++] = q;
+  }
+  for (int q = 0; q < n; ++q)
+    if (parent[q] >= 0) ++cstart[parent[q] + 1];
+  for (int q = 0; q < n; ++q) cstart[q + 1] += cstart[q];
+  {
+    std::vector<int> fill(cstart.begin(), cstart.end() - 1);
+    for (int q : order)
+      if (parent[q] >= 0) cidx[fill[parent[q]]++] = q;
+  }
+  std::vector<float> cw(n, 0.0f);
+  for (int q = 0; q < n; ++q) {
+    if (parent[q] < 0) continue;
+    const int p = parent[q];
+    const double dx = (double)x_mm[3 * q] - x_mm[3 * p], dy = (double)x_mm[3 * q + 1] - x_mm[3 * p + 1],
+                 dz = (double)x_mm[3 * q + 2] - x_mm[3 * p + 2];
+    const double w = std::sqrt(dx * dx + dy * dy + dz * dz) + std::fabs((double)inten[q] - inten[p]) / sigma_I;
+    cw[q] = (float)(alpha_kp / w);
+  }
+  MlBuffers B;
+  int *d_lnodes = nullptr, *d_cstart = nullptr, *d_cidx = nullptr, *d_parent = nullptr;
+  float *d_cw = nullptr, *h = nullptr, *msg = nullptr, *t1 = nullptr, *t2 = nullptr, *mg = marg;
+  if (!B.alloc(&d_lnodes, n) || !B.alloc(&d_cstart, n + 1) || !B.alloc(&d_cidx, cidx.size()) ||
+      !B.alloc(&d_parent, n) || !B.alloc(&d_cw, n) || !B.alloc(&h, (size_t)n * L) || !B.alloc(&msg, (size_t)n * L) ||
+      !B.alloc(&t1, (size_t)n * L) || !B.alloc(&t2, (size_t)n * L) || (!mg && !B.alloc(&mg, (size_t)n * L)))
+    return DISCO_ERR_NOMEM;
+  HIP_TRY(hipMemcpyAsync(d_lnodes, lnodes.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_cstart, cstart.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_cidx, cidx.data(), sizeof(int) * cidx.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_parent, parent.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_cw, cw.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));
+  const float sx = (float)(2.0 * k->h[0]), sy = (float)(2.0 * k->h[1]), sz = (float)(2.0 * k->h[2]);
+  auto grid_of = [&](int cnt) { return dim3((unsigned)(((int64_t)cnt * L + 255) / 256)); };
+  // inward pass, deepest level first: h_k, then m_k = min-convolution of h_k (x, y, z)
+  for (int d = maxd; d >= 0; --d) {
+    const int cnt = lstart[d + 1] - lstart[d];
+    const int *nodes = d_lnodes + lstart[d];
+    hipLaunchKernelGGL(k_kp_gather_h, grid_of(cnt), dim3(256), 0, s, cnt, nodes, L, cost, msg, d_cstart, d_cidx, h);
+    if (d == 0) break;
+    hipLaunchKernelGGL(k_kp_mincon_axis<0>, grid_of(cnt), dim3(256), 0, s, cnt, nodes, nl, h, d_cw, sx, nullptr, t1);
+    hipLaunchKernelGGL(k_kp_mincon_axis<1>, grid_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t1, d_cw, sy, nullptr, t2);
+    hipLaunchKernelGGL(k_kp_mincon_axis<2>, grid_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t2, d_cw, sz, nullptr, msg);
+  }
+  // outward pass: M_root = h_root; M_k = h_k + min-convolution of (M_parent - m_k)
+  HIP_TRY(hipMemcpyAsync(mg + (int64_t)order[0] * L, h + (int64_t)order[0] * L, sizeof(float) * L,
+                         hipMemcpyDeviceToDevice, s));
+  for (int d = 1; d <= maxd; ++d) {
+    const int cnt = lstart[d + 1] - lstart[d];
+    const int *nodes = d_lnodes + lstart[d];
+    hipLaunchKernelGGL(k_kp_outward_in, grid_of(cnt), dim3(256), 0, s, cnt, nodes, L, mg, msg, d_parent, t1);
+    hipLaunchKernelGGL(k_kp_mincon_axis<0>, grid_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t1, d_cw, sx, nullptr, t2);
+    hipLaunchKernelGGL(k_kp_mincon_axis<1>, grid_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t2, d_cw, sy, nullptr, t1);
+    hipLaunchKernelGGL(k_kp_mincon_axis<2>, grid_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t1, d_cw, sz, h, mg);
+  }
+  hipLaunchKernelGGL(k_kp_argmin, dim3((unsigned)n), dim3(256), 0, s, L, mg, labels);
+  HIP_TRY(hipGetLastError());
+  if (parent_out)
+    for (int q = 0; q < n; ++q) parent_out[q] = parent[q];
+  // the work buffers are freed on return: wait for the kernels that use them
   HIP_TRY(hipStreamSynchronize(s));
   return DISCO_OK;
 }

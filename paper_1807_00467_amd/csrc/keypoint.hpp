@@ -1,0 +1,216 @@
+// Keypoint stage (Sec. II-C2, II-C3): the NGF matching cost of eq. 2 over a grid of
+// displacements, and min-sum belief propagation (eq. 4 with the regulariser of eq. 3)
+// on a tree over the keypoints.
+//
+// The patch offsets {-3,-1,1,3} are odd and the displacements (step 2) even, so every
+// voxel a keypoint's cost reads from the moving image, and every patch voxel of the fixed
+// image, has the parity (k + 1) mod 2 per axis.  The normalised gradient 4-vectors
+// (eta, grad I) / |(eta, grad I)| are therefore stored split by voxel parity: the voxels a
+// keypoint needs form a dense (2R + 4)^3 block of one parity sub-volume, staged through
+// LDS row by row with coalesced loads.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace disco {
+
+// parity-split volume of float4: sub-volume (px, py, pz) holds voxels (2x + px, 2y + py,
+// 2z + pz) at [((pz * 2 + py) * 2 + px)][z][y][x], each sub-volume hz x hy x hx with
+// h_a = (n_a + 1) / 2; entries past the volume hold the vector of a zero gradient.
+struct KpGeo {
+  int nx, ny, nz;
+  int hx, hy, hz;
+  float ihx2, ihy2, ihz2;  // 1 / (2 h_a): central differences in HU/mm
+};
+
+__device__ __forceinline__ int64_t kp_par_index(const KpGeo &g, int px, int py, int pz, int x, int y, int z) {
+  return ((((int64_t)((pz * 2 + py) * 2 + px) * g.hz + z) * g.hy + y) * g.hx + x);
+}
+
+// normalised 4-vectors of one image: thread per parity-split entry
+__global__ __launch_bounds__(256) void k_kp_normalize(KpGeo g, const float *__restrict__ img, float eta,
+                                                      float4 *__restrict__ out) {
+  const int x = blockIdx.x * 256 + threadIdx.x;
+  const int y = blockIdx.y;
+  const int zp = blockIdx.z;  // z + hz * parity index
+  if (x >= g.hx) return;
+  const int par = zp / g.hz, z = zp - par * g.hz;
+  const int px = par & 1, py = (par >> 1) & 1, pz = par >> 2;
+  const int vx = 2 * x + px, vy = 2 * y + py, vz = 2 * z + pz;
+  float4 r = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+  if (vx < g.nx && vy < g.ny && vz < g.nz) {
+    auto at = [&](int i, int j, int k) { return img[((int64_t)k * g.ny + j) * g.nx + i]; };
+    const float gx = (at(min(vx + 1, g.nx - 1), vy, vz) - at(max(vx - 1, 0), vy, vz)) * g.ihx2;
+    const float gy = (at(vx, min(vy + 1, g.ny - 1), vz) - at(vx, max(vy - 1, 0), vz)) * g.ihy2;
+    const float gz = (at(vx, vy, min(vz + 1, g.nz - 1)) - at(vx, vy, max(vz - 1, 0))) * g.ihz2;
+    const float inv = rsqrtf(eta * eta + gx * gx + gy * gy + gz * gz);
+    r = make_float4(eta * inv, gx * inv, gy * inv, gz * inv);
+  }
+  out[kp_par_index(g, px, py, pz, x, y, z)] = r;
+}
+
+constexpr int kKpRmax = 16;                  // label radius: 2R + 1 <= 33 labels per axis
+constexpr int kKpRows = 17;                  // label rows (y) per workgroup
+constexpr int kKpChunk = 4;                  // labels along x per thread
+constexpr int kKpThreads = 192;              // >= kKpRows * ceil(33 / kKpChunk) = 153
+constexpr int kKpW = 2 * kKpRmax + 4;        // staged block width: 36
+
+// D_KP(k, d) for one keypoint k, one label plane iz and up to kKpRows label rows iy:
+// stage the moving-image vectors of the 4 z-planes and rows + 3 y-rows the labels need,
+// and the 64 fixed-image patch vectors, then each thread accumulates sum r^2 for 4 labels
+// along x over the patch (every staged vector is used for up to 4 labels).
+__global__ __launch_bounds__(kKpThreads) void k_kp_cost(KpGeo g, const float4 *__restrict__ nF,
+                                                        const float4 *__restrict__ nM, int nkp,
+                                                        const int *__restrict__ kp, int R, float *__restrict__ cost) {
+  __shared__ float4 sM[4][kKpRows + 3][kKpW];
+  __shared__ float4 sF[64];
+  const int k = blockIdx.x, iz = blockIdx.y, iy0 = blockIdx.z * kKpRows;
+  const int nl = 2 * R + 1, W = 2 * R + 4;
+  const int nrow = min(kKpRows, nl - iy0);
+  if (nrow <= 0) return;
+  const int kx = kp[3 * k], ky = kp[3 * k + 1], kz = kp[3 * k + 2];
+  const int px = (kx + 1) & 1, py = (ky + 1) & 1, pz = (kz + 1) & 1;
+  // lattice coordinate of voxel k + o + d: base + oi + i (oi = patch index, i = label index)
+  const int bx = (kx + 1 - px) / 2 - 2 - R, by = (ky + 1 - py) / 2 - 2 - R, bz = (kz + 1 - pz) / 2 - 2 - R;
+  const int t = threadIdx.x;
+  // stage: planes z' = bz + iz + (0..3), rows y' = by + iy0 + (0..nrow+2), columns x' = bx + (0..W-1)
+  const int nst = 4 * (nrow + 3) * W;
+  for (int e = t; e < nst; e += kKpThreads) {
+    const int xx = e % W, rr = (e / W) % (nrow + 3), pl = e / (W * (nrow + 3));
+    const int x = bx + xx, y = by + iy0 + rr, z = bz + iz + pl;
+    float4 v = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+    if ((unsigned)x < (unsigned)g.hx && (unsigned)y < (unsigned)g.hy && (unsigned)z < (unsigned)g.hz)
+      v = nM[kp_par_index(g, px, py, pz, x, y, z)];
+    sM[pl][rr][xx] = v;
+  }
+  if (t < 64) {
+    // patch voxel k + o: lattice (k + 1 - p) / 2 - 2 + oi
+    const int ox = t & 3, oy = (t >> 2) & 3, oz = t >> 4;
+    const int x = (kx + 1 - px) / 2 - 2 + ox, y = (ky + 1 - py) / 2 - 2 + oy, z = (kz + 1 - pz) / 2 - 2 + oz;
+    float4 v = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+    if ((unsigned)x < (unsigned)g.hx && (unsigned)y < (unsigned)g.hy && (unsigned)z < (unsigned)g.hz)
+      v = nF[kp_par_index(g, px, py, pz, x, y, z)];
+    sF[t] = v;
+  }
+  __syncthreads();
+  const int nch = (nl + kKpChunk - 1) / kKpChunk;
+  const int row = t / nch, ch = t - row * nch;
+  if (row >= nrow) return;
+  const int ix0 = ch * kKpChunk;
+  float acc[kKpChunk] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll 1
+  for (int oz = 0; oz < 4; ++oz) {
+#pragma unroll
+    for (int oy = 0; oy < 4; ++oy) {
+      float4 b[4];
+#pragma unroll
+      for (int ox = 0; ox < 4; ++ox) b[ox] = sF[(oz * 4 + oy) * 4 + ox];
+      float4 a[kKpChunk + 3];
+#pragma unroll
+      for (int j = 0; j < kKpChunk + 3; ++j) a[j] = sM[oz][row + oy][min(ix0 + j, W - 1)];
+#pragma unroll
+      for (int c = 0; c < kKpChunk; ++c)
+#pragma unroll
+        for (int ox = 0; ox < 4; ++ox) {
+          const float4 &u = a[c + ox];
+          const float r = u.x * b[ox].x + u.y * b[ox].y + u.z * b[ox].z + u.w * b[ox].w;
+          acc[c] = __builtin_fmaf(r, r, acc[c]);
+        }
+    }
+  }
+  const int64_t L = (int64_t)nl * nl * nl;
+  float *o = cost + (int64_t)k * L + ((int64_t)iz * nl + iy0 + row) * nl;
+#pragma unroll
+  for (int c = 0; c < kKpChunk; ++c)
+    if (ix0 + c < nl) o[ix0 + c] = 1.0f - acc[c] * (1.0f / 64.0f);
+}
+
+// ---- belief propagation on the tree, one tree level per launch ---------------------
+// every kernel: thread per (node of the level, label); nodes[] lists the level's nodes
+
+// h_k = D_k + sum of the inward messages of k's children (CSR: cstart, cidx)
+__global__ __launch_bounds__(256) void k_kp_gather_h(int nlev, const int *__restrict__ nodes, int64_t L,
+                                                     const float *__restrict__ D, const float *__restrict__ msg,
+                                                     const int *__restrict__ cstart, const int *__restrict__ cidx,
+                                                     float *__restrict__ h) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)nlev * L) return;
+  const int k = nodes[e / L];
+  const int64_t l = e % L;
+  float v = D[(int64_t)k * L + l];
+  for (int c = cstart[k]; c < cstart[k + 1]; ++c) v += msg[(int64_t)cidx[c] * L + l];
+  h[(int64_t)k * L + l] = v;
+}
+
+// src = marg[parent] - msg[k] (the outward message's input)
+__global__ __launch_bounds__(256) void k_kp_outward_in(int nlev, const int *__restrict__ nodes, int64_t L,
+                                                       const float *__restrict__ marg, const float *__restrict__ msg,
+                                                       const int *__restrict__ parent, float *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)nlev * L) return;
+  const int k = nodes[e / L];
+  const int64_t l = e % L;
+  out[(int64_t)k * L + l] = marg[(int64_t)parent[k] * L + l] - msg[(int64_t)k * L + l];
+}
+
+// one axis of the min-convolution with c_k |step h_a (i - j)|^2 (labels [iz][iy][ix]):
+// out(i) = min_j in(j) + pen_k (i - j)^2 along axis AX, pen_k = cw[k] (step h_a)^2;
+// with add != nullptr the result is added to add (out = add + min ...)
+template <int AX>
+__global__ __launch_bounds__(256) void k_kp_mincon_axis(int nlev, const int *__restrict__ nodes, int nl,
+                                                        const float *__restrict__ in, const float *__restrict__ cw,
+                                                        float step_mm, const float *__restrict__ add,
+                                                        float *__restrict__ out) {
+  const int64_t L = (int64_t)nl * nl * nl;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)nlev * L) return;
+  const int k = nodes[e / L];
+  const int64_t l = e % L;
+  const int ix = (int)(l % nl), iy = (int)((l / nl) % nl), iz = (int)(l / ((int64_t)nl * nl));
+  const int i = AX == 0 ? ix : (AX == 1 ? iy : iz);
+  const int64_t stride = AX == 0 ? 1 : (AX == 1 ? nl : (int64_t)nl * nl);
+  const float *src = in + (int64_t)k * L + (l - (int64_t)i * stride);
+  const float pen = cw[k] * step_mm * step_mm;
+  float best = INFINITY;
+  for (int j = 0; j < nl; ++j) {
+    const float dij = (float)(i - j);
+    best = fminf(best, src[(int64_t)j * stride] + pen * dij * dij);
+  }
+  const int64_t o = (int64_t)k * L + l;
+  out[o] = add ? add[o] + best : best;
+}
+
+// label of the smallest min-marginal per keypoint (lowest index on ties): one workgroup
+// per keypoint
+__global__ __launch_bounds__(256) void k_kp_argmin(int64_t L, const float *__restrict__ marg, int *__restrict__ lab) {
+  __shared__ float sv[256];
+  __shared__ int si[256];
+  const int k = blockIdx.x, t = threadIdx.x;
+  const float *m = marg + (int64_t)k * L;
+  float bv = INFINITY;
+  int bi = 0x7fffffff;
+  for (int64_t l = t; l < L; l += 256) {
+    const float v = m[l];
+    if (v < bv) {
+      bv = v;
+      bi = (int)l;
+    }
+  }
+  sv[t] = bv;
+  si[t] = bi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (t < s) {
+      const float ov = sv[t + s];
+      const int oi = si[t + s];
+      if (ov < sv[t] || (ov == sv[t] && oi < si[t])) {
+        sv[t] = ov;
+        si[t] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) lab[k] = si[0];
+}
+
+}  // namespace disco

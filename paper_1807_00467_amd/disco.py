@@ -85,6 +85,11 @@ _SIGS = {
     "lbfgs_step": ([_P, ctypes.POINTER(_Params), ctypes.POINTER(_Lbfgs), _P, _P, _P, _P], ctypes.c_int),
     "lbfgs_reset": ([_P], ctypes.c_int),
     "disco_set_masks": ([_P, _P, _P, _P], ctypes.c_int),
+    "disco_kp_create": ([_P, _P, ctypes.POINTER(_P)], ctypes.c_int),
+    "disco_kp_destroy": ([_P], None),
+    "disco_kp_set_images": ([_P, _P, _P, _D, _P], ctypes.c_int),
+    "disco_kp_cost": ([_P, _I, _P, _I, _P, _P], ctypes.c_int),
+    "disco_kp_regularise": ([_P, _I, _P, _P, _I, _P, _D, _D, _P, _P, _P, _P], ctypes.c_int),
     "objective_linearise": ([_P, ctypes.POINTER(_Params), _P, _P, _P, _P, _P], ctypes.c_int),
     "pyramid_plan": ([_P, _P, _I, _P, _P, _P, _P], ctypes.c_int),
     "pyramid_downsample": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -527,3 +532,68 @@ def multilevel_register(R: torch.Tensor, T: torch.Tensor, spacing: Sequence[floa
                                         t.ctypes.data_as(_P), ctypes.byref(cfg), _ptr(u), _ptr(rep), ctypes.byref(L),
                                         ctypes.byref(delta), _stream_of(R)), "multilevel_register")
     return u, rep[:rows], L.value, delta.value
+
+
+# ---- keypoint stage (Sec. II-C2, II-C3) -------------------------------------------------
+
+class KeypointStage:
+    """NGF matching cost over a displacement grid and its regularisation on a tree of
+    keypoints (see disco_kp_* in include/disco.h)."""
+
+    def __init__(self, shape: Sequence[int], spacing: Sequence[float] = (1.0, 1.0, 1.0),
+                 device: Optional[torch.device] = None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.shape = tuple(int(s) for s in shape)
+        self.spacing = tuple(float(h) for h in spacing)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(_lib.disco_kp_create(_i3(self.shape), (ctypes.c_double * 3)(*self.spacing), ctypes.byref(h)),
+                   "disco_kp_create")
+        self._h = h
+
+    def close(self):
+        if self._h:
+            _lib.disco_kp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def set_images(self, F: torch.Tensor, M: torch.Tensor, eta: float):
+        nx, ny, nz = self.shape
+        for t in (F, M):
+            if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != (nz, ny, nx):
+                raise ValueError("images must be contiguous float32 CUDA tensors [Nz][Ny][Nx]")
+        self._imgs = (F, M)
+        _check(_lib.disco_kp_set_images(self._h, _ptr(F), _ptr(M), float(eta), self._stream()), "disco_kp_set_images")
+
+    def cost(self, kp_vox: torch.Tensor, R: int = 16) -> torch.Tensor:
+        """D_KP [nkp][(2R+1)^3] for int32 CUDA keypoints [nkp][3] (voxel indices x, y, z)."""
+        if kp_vox.dtype != torch.int32 or not kp_vox.is_cuda or not kp_vox.is_contiguous():
+            raise ValueError("keypoints must be a contiguous int32 CUDA tensor [nkp][3]")
+        n = kp_vox.shape[0]
+        out = torch.empty((n, (2 * R + 1) ** 3), dtype=torch.float32, device=self.device)
+        _check(_lib.disco_kp_cost(self._h, n, _ptr(kp_vox), R, _ptr(out), self._stream()), "disco_kp_cost")
+        return out
+
+    def regularise(self, x_mm, inten, cost: torch.Tensor, R: int = 16, alpha_kp: float = 1.0 / 45.0,
+                   sigma_I: float = 150.0, marginals: bool = True):
+        """Min-sum belief propagation on the keypoint MST.  Returns (min-marginals or None,
+        labels int32 CUDA [nkp], parent numpy int32 [nkp])."""
+        import numpy as np
+        x = np.ascontiguousarray(np.asarray(x_mm, dtype=np.float32).reshape(-1, 3))
+        it = np.ascontiguousarray(np.asarray(inten, dtype=np.float32).ravel())
+        n = len(x)
+        marg = torch.empty_like(cost) if marginals else None
+        lab = torch.empty(n, dtype=torch.int32, device=self.device)
+        par = np.empty(n, dtype=np.int32)
+        _check(_lib.disco_kp_regularise(self._h, n, x.ctypes.data_as(_P), it.ctypes.data_as(_P), R, _ptr(cost),
+                                        float(alpha_kp), float(sigma_I), _ptr(marg), _ptr(lab),
+                                        par.ctypes.data_as(_P), self._stream()), "disco_kp_regularise")
+        return marg, lab, par

@@ -70,6 +70,10 @@ CONFIGS: Dict[str, PairConfig] = {
     "cfg2": PairConfig(shape=(192, 192, 160), spacing=(1.0, 1.0, 1.0), n_tubes=120,
                        field="breathing", amp_z=25.0, amp_y=8.0, n_kp=2000,
                        kp_noise=1.0, seed=200),
+    # keypoint stage: the full-size field of view resampled to 1 mm isotropic, 3500
+    # keypoints in the lungs
+    "kp": PairConfig(shape=(356, 356, 320), spacing=(1.0, 1.0, 1.0), n_tubes=300,
+                     field="breathing", amp_z=25.0, amp_y=8.0, n_kp=3500, seed=5),
     # precision form: 512 x 512 x 256 at 0.7 x 0.7 x 1.25 mm
     "cfg4": PairConfig(shape=(512, 512, 256), spacing=(0.7, 0.7, 1.25), n_tubes=300,
                        field="breathing", amp_z=25.0, amp_y=8.0, n_kp=2000,

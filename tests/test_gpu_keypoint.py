@@ -1,0 +1,119 @@
+"""Keypoint stage (Sec. II-C2, II-C3) on the device against the FP64 oracle: the NGF
+matching cost of eq. 2 over all 33^3 displacements (keypoints in the interior, at the
+border and of every voxel parity), sampled at the benchmark's workload, and the
+regularisation by min-sum belief propagation on the keypoint MST."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+ETA = 12.0
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def disco():
+    from paper_1807_00467_amd import disco as d
+    return d
+
+
+def stage(disco, d):
+    st = disco.KeypointStage(d["shape"], d["spacing"], device=DEV)
+    st.set_images(torch.from_numpy(d["R"]).to(DEV), torch.from_numpy(d["T"]).to(DEV), ETA)
+    return st
+
+
+def vox_of(d):
+    return np.floor(np.asarray(d["kp_x"], np.float64) / np.asarray(d["spacing"])).astype(np.int32)
+
+
+@pytest.mark.parametrize("R", [16, 3])
+def test_kp_cost_matches_oracle(disco, R):
+    say(f"[kp] cost R={R}")
+    d = synth.small_pair(shape=(64, 56, 44), spacing=(1.0, 1.0, 1.0), seed=41, n_tubes=10, n_kp=6, field_max=4.0)
+    nx, ny, nz = d["shape"]
+    kps = np.concatenate([vox_of(d), np.array([[0, 0, 0], [nx - 1, ny - 1, nz - 1], [1, ny - 2, 5], [nx - 2, 3, nz - 1],
+                                                [31, 28, 22], [32, 27, 21]], np.int32)]).astype(np.int32)
+    st = stage(disco, d)
+    got = st.cost(torch.from_numpy(kps).to(DEV), R).cpu().numpy()
+    ref = oracle.kp_cost_volume(d["R"], d["T"], d["spacing"], kps, ETA, R=R, step=2)
+    err = np.max(np.abs(got - ref))
+    say(f"  {len(kps)} keypoints x {ref.shape[1]} labels: max abs error {err:.2e}")
+    assert err < 2e-6
+
+
+def test_kp_cost_fullsize_sampled(disco):
+    """The benchmark's workload (1 mm, 3500 keypoints in the lungs): 12 keypoints against
+    the oracle over all labels."""
+    say("[kp] cost, benchmark workload sampled")
+    d = synth.make_pair("kp")
+    st = stage(disco, d)
+    kps = vox_of(d)
+    got = st.cost(torch.from_numpy(kps).to(DEV), 16)
+    idx = np.random.default_rng(5).choice(len(kps), 12, replace=False)
+    ref = oracle.kp_cost_volume(d["R"], d["T"], d["spacing"], kps[idx], ETA, R=16, step=2)
+    err = float(np.max(np.abs(got[torch.from_numpy(idx).to(DEV)].cpu().numpy() - ref)))
+    say(f"  {len(kps)} keypoints; sampled max abs error {err:.2e}")
+    assert len(kps) == 3500 and err < 2e-6
+
+
+def test_kp_regularise_matches_oracle(disco):
+    say("[kp] belief propagation")
+    d = synth.small_pair(shape=(64, 56, 44), spacing=(1.0, 1.0, 1.0), seed=42, n_tubes=10, n_kp=40, field_max=4.0)
+    st = stage(disco, d)
+    kps = vox_of(d)
+    cost = st.cost(torch.from_numpy(kps).to(DEV), 16)
+    x = (kps + 0.5) * np.asarray(d["spacing"])
+    inten = d["R"][kps[:, 2], kps[:, 1], kps[:, 0]]
+    alpha = 1.0 / 45.0
+    marg, lab, par = st.regularise(x, inten, cost, 16, alpha, 150.0)
+    torch.cuda.synchronize()
+    parent, order = oracle.kp_mst(x.astype(np.float32), inten)
+    np.testing.assert_array_equal(par, parent)
+    D = cost.cpu().numpy().astype(np.float64)  # the same data cost on both sides
+    om, _ = oracle.kp_belief_propagation(D, parent, order, x.astype(np.float32), inten, alpha, R=16, step=2)
+    gm = marg.cpu().numpy()
+    scale = np.max(np.abs(om), axis=1, keepdims=True)
+    err = float(np.max(np.abs(gm - om) / scale))
+    say(f"  {len(kps)} keypoints, tree depth {tree_depth(parent, order)}: marginals max rel error {err:.2e}")
+    assert err < 1e-5
+    # labels: the unique minimum must agree; near-ties only need an equally good label
+    gl = lab.cpu().numpy()
+    ol = oracle.kp_argmin(om)
+    tol = 2e-5 * scale[:, 0]
+    srt = np.sort(om, axis=1)
+    for k in range(len(kps)):
+        if srt[k, 1] - srt[k, 0] > tol[k]:
+            assert gl[k] == ol[k], k
+        else:
+            assert om[k, gl[k]] - srt[k, 0] <= tol[k], k
+
+
+def tree_depth(parent, order):
+    dep = np.zeros(len(parent), int)
+    for k in order[1:]:
+        dep[k] = dep[parent[k]] + 1
+    return int(dep.max())
+
+
+def test_kp_argument_errors(disco):
+    d = synth.small_pair(shape=(16, 16, 12), spacing=(1.0, 1.0, 1.0), seed=43)
+    st = disco.KeypointStage(d["shape"], d["spacing"], device=DEV)
+    kp = torch.zeros((1, 3), dtype=torch.int32, device=DEV)
+    with pytest.raises(disco.DiscoError) as e:
+        st.cost(kp, 4)  # images not set
+    assert e.value.code == disco.ERR_STATE
+    st.set_images(torch.from_numpy(d["R"]).to(DEV), torch.from_numpy(d["T"]).to(DEV), ETA)
+    with pytest.raises(disco.DiscoError) as e:
+        st.cost(kp, 17)
+    assert e.value.code == disco.ERR_ARG
