@@ -86,6 +86,8 @@ struct disco_kp {
   KpGeo g{};
   double h[3] = {1.0, 1.0, 1.0};
   float4 *nF = nullptr, *nM = nullptr;
+  float4 *patch = nullptr;  // [cap][64] patch vectors of the keypoints of the last cost call
+  int patch_cap = 0;
   bool images = false;
 };
 
@@ -1929,6 +1931,7 @@ void disco_kp_destroy(disco_kp *k) {
   (void)hipDeviceSynchronize();
   if (k->nF) (void)hipFree(k->nF);
   if (k->nM) (void)hipFree(k->nM);
+  if (k->patch) (void)hipFree(k->patch);
   delete k;
 }
 
@@ -1953,9 +1956,25 @@ int disco_kp_cost(disco_kp *k, int32_t nkp, const int32_t *kp_vox, int32_t R, fl
   if (nkp == 0) return DISCO_OK;
   if (!aligned4(kp_vox) || !aligned4(cost)) return DISCO_ERR_SHAPE;
   HIP_TRY(hipSetDevice(k->device));
+  hipStream_t s = S(stream);
+  if (nkp > k->patch_cap) {
+    HIP_TRY(hipStreamSynchronize(s));
+    if (k->patch) (void)hipFree(k->patch);
+    k->patch = nullptr;
+    k->patch_cap = 0;
+    if (hipMalloc(reinterpret_cast<void **>(&k->patch), sizeof(float4) * 64 * (size_t)nkp) != hipSuccess) {
+      k->patch = nullptr;
+      return DISCO_ERR_NOMEM;
+    }
+    k->patch_cap = nkp;
+  }
+  hipLaunchKernelGGL(k_kp_patch, dim3((unsigned)nkp), dim3(64), 0, s, k->g, k->nF, nkp, kp_vox, k->patch);
   const int nl = 2 * R + 1;
-  const dim3 grid((unsigned)nkp, (unsigned)nl, (unsigned)((nl + kKpRows - 1) / kKpRows));
-  hipLaunchKernelGGL(k_kp_cost, grid, dim3(kKpThreads), 0, S(stream), k->g, k->nF, k->nM, nkp, kp_vox, R, cost);
+  const int64_t items = (int64_t)nkp * nl * ((nl + kKpRows - 1) / kKpRows);
+  if (items >= ((int64_t)1 << 31) - 8) return DISCO_ERR_SHAPE;
+  const int run = (int)((items + 7) / 8);  // contiguous items per XCD
+  hipLaunchKernelGGL(k_kp_cost, dim3((unsigned)(8 * run)), dim3(kKpThreads), 0, s, k->g, k->nM, k->patch, nkp,
+                     kp_vox, R, (int)items, run, cost);
   HIP_TRY(hipGetLastError());
   return DISCO_OK;
 }

@@ -49,31 +49,71 @@ __global__ __launch_bounds__(256) void k_kp_normalize(KpGeo g, const float *__re
   out[kp_par_index(g, px, py, pz, x, y, z)] = r;
 }
 
-constexpr int kKpRmax = 16;                  // label radius: 2R + 1 <= 33 labels per axis
-constexpr int kKpRows = 17;                  // label rows (y) per workgroup
-constexpr int kKpChunk = 4;                  // labels along x per thread
-constexpr int kKpThreads = 192;              // >= kKpRows * ceil(33 / kKpChunk) = 153
-constexpr int kKpW = 2 * kKpRmax + 4;        // staged block width: 36
+constexpr int kKpRmax = 16;  // label radius: 2R + 1 <= 33 labels per axis
+#ifndef DISCO_KP_ROWS
+#define DISCO_KP_ROWS 17
+#endif
+#ifndef DISCO_KP_CHUNK
+#define DISCO_KP_CHUNK 4
+#endif
+constexpr int kKpRows = DISCO_KP_ROWS;    // label rows (y) per workgroup
+constexpr int kKpChunk = DISCO_KP_CHUNK;  // labels along x per thread
+#ifndef DISCO_KP_PAD
+#define DISCO_KP_PAD 1
+#endif
+#ifndef DISCO_KP_OYU
+#define DISCO_KP_OYU 2
+#endif
+#ifndef DISCO_KP_OZU
+#define DISCO_KP_OZU 1
+#endif
+// (LDS padding 1, oy unrolled by 2: measured best of the variants tried)
+constexpr int kKpW = 2 * kKpRmax + 4;     // staged block width: 36
+constexpr int kKpWP = kKpW + DISCO_KP_PAD;  // LDS row stride (float4)
+constexpr int kKpNch = (2 * kKpRmax + 1 + kKpChunk - 1) / kKpChunk;
+constexpr int kKpThreads = ((kKpRows * kKpNch + 63) / 64) * 64;
+
+// the 64 fixed-image patch vectors of every keypoint, [nkp][64] (o = (ox, oy, oz) with
+// index (oz * 4 + oy) * 4 + ox)
+__global__ __launch_bounds__(64) void k_kp_patch(KpGeo g, const float4 *__restrict__ nF, int nkp,
+                                                 const int *__restrict__ kp, float4 *__restrict__ patch) {
+  const int k = blockIdx.x, t = threadIdx.x;
+  const int kx = kp[3 * k], ky = kp[3 * k + 1], kz = kp[3 * k + 2];
+  const int px = (kx + 1) & 1, py = (ky + 1) & 1, pz = (kz + 1) & 1;
+  const int ox = t & 3, oy = (t >> 2) & 3, oz = t >> 4;
+  // patch voxel k + o (o = 2 oi - 3): lattice (k + 1 - p) / 2 - 2 + oi
+  const int x = (kx + 1 - px) / 2 - 2 + ox, y = (ky + 1 - py) / 2 - 2 + oy, z = (kz + 1 - pz) / 2 - 2 + oz;
+  float4 v = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+  if ((unsigned)x < (unsigned)g.hx && (unsigned)y < (unsigned)g.hy && (unsigned)z < (unsigned)g.hz)
+    v = nF[kp_par_index(g, px, py, pz, x, y, z)];
+  patch[(int64_t)k * 64 + t] = v;
+}
 
 // D_KP(k, d) for one keypoint k, one label plane iz and up to kKpRows label rows iy:
 // stage the moving-image vectors of the 4 z-planes and rows + 3 y-rows the labels need,
-// and the 64 fixed-image patch vectors, then each thread accumulates sum r^2 for 4 labels
-// along x over the patch (every staged vector is used for up to 4 labels).
-__global__ __launch_bounds__(kKpThreads) void k_kp_cost(KpGeo g, const float4 *__restrict__ nF,
-                                                        const float4 *__restrict__ nM, int nkp,
-                                                        const int *__restrict__ kp, int R, float *__restrict__ cost) {
-  __shared__ float4 sM[4][kKpRows + 3][kKpW];
-  __shared__ float4 sF[64];
-  const int k = blockIdx.x, iz = blockIdx.y, iy0 = blockIdx.z * kKpRows;
+// then each thread accumulates sum r^2 for kKpChunk labels along x over the patch (each
+// staged vector serves up to 4 labels).  Work items are ordered keypoint-major and dealt
+// to the 8 XCDs in contiguous runs, so that the items of one keypoint, whose staged
+// blocks overlap, share an L2.
+__global__ __launch_bounds__(kKpThreads) void k_kp_cost(KpGeo g, const float4 *__restrict__ nM,
+                                                        const float4 *__restrict__ patch, int nkp,
+                                                        const int *__restrict__ kp, int R, int items, int run,
+                                                        float *__restrict__ cost) {
+  __shared__ float4 sM[4][kKpRows + 3][kKpWP];
+  __shared__ float4 sP[64];  // the keypoint's patch vectors, read by all threads at one address
+  const int hw = blockIdx.x;
+  const int item = (hw & 7) * run + (hw >> 3);
+  if (item >= items) return;
   const int nl = 2 * R + 1, W = 2 * R + 4;
+  const int nh = (nl + kKpRows - 1) / kKpRows;
+  const int k = item / (nl * nh), rem = item - k * (nl * nh);
+  const int iz = rem / nh, iy0 = (rem - iz * nh) * kKpRows;
   const int nrow = min(kKpRows, nl - iy0);
-  if (nrow <= 0) return;
   const int kx = kp[3 * k], ky = kp[3 * k + 1], kz = kp[3 * k + 2];
   const int px = (kx + 1) & 1, py = (ky + 1) & 1, pz = (kz + 1) & 1;
   // lattice coordinate of voxel k + o + d: base + oi + i (oi = patch index, i = label index)
   const int bx = (kx + 1 - px) / 2 - 2 - R, by = (ky + 1 - py) / 2 - 2 - R, bz = (kz + 1 - pz) / 2 - 2 - R;
   const int t = threadIdx.x;
-  // stage: planes z' = bz + iz + (0..3), rows y' = by + iy0 + (0..nrow+2), columns x' = bx + (0..W-1)
   const int nst = 4 * (nrow + 3) * W;
   for (int e = t; e < nst; e += kKpThreads) {
     const int xx = e % W, rr = (e / W) % (nrow + 3), pl = e / (W * (nrow + 3));
@@ -83,28 +123,23 @@ __global__ __launch_bounds__(kKpThreads) void k_kp_cost(KpGeo g, const float4 *_
       v = nM[kp_par_index(g, px, py, pz, x, y, z)];
     sM[pl][rr][xx] = v;
   }
-  if (t < 64) {
-    // patch voxel k + o: lattice (k + 1 - p) / 2 - 2 + oi
-    const int ox = t & 3, oy = (t >> 2) & 3, oz = t >> 4;
-    const int x = (kx + 1 - px) / 2 - 2 + ox, y = (ky + 1 - py) / 2 - 2 + oy, z = (kz + 1 - pz) / 2 - 2 + oz;
-    float4 v = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
-    if ((unsigned)x < (unsigned)g.hx && (unsigned)y < (unsigned)g.hy && (unsigned)z < (unsigned)g.hz)
-      v = nF[kp_par_index(g, px, py, pz, x, y, z)];
-    sF[t] = v;
-  }
+  if (t < 64) sP[t] = patch[(int64_t)k * 64 + t];
   __syncthreads();
   const int nch = (nl + kKpChunk - 1) / kKpChunk;
   const int row = t / nch, ch = t - row * nch;
   if (row >= nrow) return;
   const int ix0 = ch * kKpChunk;
-  float acc[kKpChunk] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll 1
-  for (int oz = 0; oz < 4; ++oz) {
+  const float4 *pk = sP;
+  float acc[kKpChunk];
 #pragma unroll
+  for (int c = 0; c < kKpChunk; ++c) acc[c] = 0.0f;
+#pragma unroll DISCO_KP_OZU
+  for (int oz = 0; oz < 4; ++oz) {
+#pragma unroll DISCO_KP_OYU
     for (int oy = 0; oy < 4; ++oy) {
       float4 b[4];
 #pragma unroll
-      for (int ox = 0; ox < 4; ++ox) b[ox] = sF[(oz * 4 + oy) * 4 + ox];
+      for (int ox = 0; ox < 4; ++ox) b[ox] = pk[(oz * 4 + oy) * 4 + ox];
       float4 a[kKpChunk + 3];
 #pragma unroll
       for (int j = 0; j < kKpChunk + 3; ++j) a[j] = sM[oz][row + oy][min(ix0 + j, W - 1)];
