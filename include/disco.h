@@ -329,7 +329,9 @@ int disco_kp_cost(disco_kp *kp, int32_t nkp, const int32_t *kp_vox, int32_t R, f
    the tree with the data cost `cost` (as written by disco_kp_cost) and the regulariser of
    eq. 3, alpha_kp |d_k - d_q|^2 / w_kq (|.| in mm), each message a min-convolution done as
    three exact 1-D minimisations (x, y, z), one tree level per launch.  x_mm (HOST
-   float32 [nkp][3]) and inten (HOST float32 [nkp], F at the keypoint) define w.  Writes
+   float32 [nkp][3]) and inten (HOST float32 [nkp], F at the keypoint) define w; the
+   keypoints must be distinct (w > 0).  The tree is built on the device (one workgroup)
+   for up to 4096 keypoints, on the host beyond.  Writes
    the min-marginal energies to marg (device float32 [nkp][(2R+1)^3], nullable), the label
    of the smallest one per keypoint (lowest index on ties) to labels (device int32 [nkp])
    and the tree to parent_out (HOST int32 [nkp], nullable; -1 at the root).  Allocates

@@ -1970,7 +1970,7 @@ int disco_kp_cost(disco_kp *k, int32_t nkp, const int32_t *kp_vox, int32_t R, fl
   }
   hipLaunchKernelGGL(k_kp_patch, dim3((unsigned)nkp), dim3(64), 0, s, k->g, k->nF, nkp, kp_vox, k->patch);
   const int nl = 2 * R + 1;
-  const int64_t items = (int64_t)nkp * nl * ((nl + kKpRows - 1) / kKpRows);
+  const int64_t items = (int64_t)nkp * ((nl + kKpRows - 1) / kKpRows);
   if (items >= ((int64_t)1 << 31) - 8) return DISCO_ERR_SHAPE;
   const int run = (int)((items + 7) / 8);  // contiguous items per XCD
   hipLaunchKernelGGL(k_kp_cost, dim3((unsigned)(8 * run)), dim3(kKpThreads), 0, s, k->g, k->nM, k->patch, nkp,
@@ -2023,8 +2023,23 @@ int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float
   const int n = nkp, nl = 2 * R + 1;
   const int64_t L = (int64_t)nl * nl * nl;
   // tree, levels (depth from the root), children lists, per-edge weights (host)
-  std::vector<int> parent, order;
-  kp_mst(n, x_mm, inten, sigma_I, parent, order);
+  std::vector<int> parent(n), order(n);
+  if (n <= 1024 * kPrimSlots) {
+    // Prim on the device (one workgroup), the tree copied back for the level schedule
+    MlBuffers P;
+    float *dx = nullptr, *di = nullptr;
+    int *dp = nullptr, *dord = nullptr;
+    if (!P.alloc(&dx, 3 * (size_t)n) || !P.alloc(&di, n) || !P.alloc(&dp, n) || !P.alloc(&dord, n))
+      return DISCO_ERR_NOMEM;
+    HIP_TRY(hipMemcpyAsync(dx, x_mm, sizeof(float) * 3 * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(di, inten, sizeof(float) * n, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_kp_prim, dim3(1), dim3(1024), 0, s, n, dx, di, sigma_I, dp, dord);
+    HIP_TRY(hipMemcpyAsync(parent.data(), dp, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(order.data(), dord, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  } else {
+    kp_mst(n, x_mm, inten, sigma_I, parent, order);
+  }
   std::vector<int> depth(n, 0);
   int maxd = 0;
   for (size_t i = 1; i < order.size(); ++i) {
@@ -2070,15 +2085,17 @@ int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float
   HIP_TRY(hipMemcpyAsync(d_cw, cw.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));
   const float sx = (float)(2.0 * k->h[0]), sy = (float)(2.0 * k->h[1]), sz = (float)(2.0 * k->h[2]);
   auto grid_of = [&](int cnt) { return dim3((unsigned)(((int64_t)cnt * L + 255) / 256)); };
+  const int64_t nl2 = (int64_t)nl * nl;
+  auto lines_of = [&](int cnt) { return dim3((unsigned)(((int64_t)cnt * nl2 + 255) / 256)); };
   // inward pass, deepest level first: h_k, then m_k = min-convolution of h_k (x, y, z)
   for (int d = maxd; d >= 0; --d) {
     const int cnt = lstart[d + 1] - lstart[d];
     const int *nodes = d_lnodes + lstart[d];
     hipLaunchKernelGGL(k_kp_gather_h, grid_of(cnt), dim3(256), 0, s, cnt, nodes, L, cost, msg, d_cstart, d_cidx, h);
     if (d == 0) break;
-    hipLaunchKernelGGL(k_kp_mincon_axis<0>, grid_of(cnt), dim3(256), 0, s, cnt, nodes, nl, h, d_cw, sx, nullptr, t1);
-    hipLaunchKernelGGL(k_kp_mincon_axis<1>, grid_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t1, d_cw, sy, nullptr, t2);
-    hipLaunchKernelGGL(k_kp_mincon_axis<2>, grid_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t2, d_cw, sz, nullptr, msg);
+    hipLaunchKernelGGL(k_kp_line_axis<0>, lines_of(cnt), dim3(256), 0, s, cnt, nodes, nl, h, d_cw, sx, nullptr, t1);
+    hipLaunchKernelGGL(k_kp_line_axis<1>, lines_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t1, d_cw, sy, nullptr, t2);
+    hipLaunchKernelGGL(k_kp_line_axis<2>, lines_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t2, d_cw, sz, nullptr, msg);
   }
   // outward pass: M_root = h_root; M_k = h_k + min-convolution of (M_parent - m_k)
   HIP_TRY(hipMemcpyAsync(mg + (int64_t)order[0] * L, h + (int64_t)order[0] * L, sizeof(float) * L,
@@ -2087,9 +2104,9 @@ int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float
     const int cnt = lstart[d + 1] - lstart[d];
     const int *nodes = d_lnodes + lstart[d];
     hipLaunchKernelGGL(k_kp_outward_in, grid_of(cnt), dim3(256), 0, s, cnt, nodes, L, mg, msg, d_parent, t1);
-    hipLaunchKernelGGL(k_kp_mincon_axis<0>, grid_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t1, d_cw, sx, nullptr, t2);
-    hipLaunchKernelGGL(k_kp_mincon_axis<1>, grid_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t2, d_cw, sy, nullptr, t1);
-    hipLaunchKernelGGL(k_kp_mincon_axis<2>, grid_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t1, d_cw, sz, h, mg);
+    hipLaunchKernelGGL(k_kp_line_axis<0>, lines_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t1, d_cw, sx, nullptr, t2);
+    hipLaunchKernelGGL(k_kp_line_axis<1>, lines_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t2, d_cw, sy, nullptr, t1);
+    hipLaunchKernelGGL(k_kp_line_axis<2>, lines_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t1, d_cw, sz, h, mg);
   }
   hipLaunchKernelGGL(k_kp_argmin, dim3((unsigned)n), dim3(256), 0, s, L, mg, labels);
   HIP_TRY(hipGetLastError());

@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void k_kp_normalize(KpGeo g, const float *__re
 
 constexpr int kKpRmax = 16;  // label radius: 2R + 1 <= 33 labels per axis
 #ifndef DISCO_KP_ROWS
-#define DISCO_KP_ROWS 17
+#define DISCO_KP_ROWS 11
 #endif
 #ifndef DISCO_KP_CHUNK
 #define DISCO_KP_CHUNK 4
@@ -89,81 +89,207 @@ __global__ __launch_bounds__(64) void k_kp_patch(KpGeo g, const float4 *__restri
   patch[(int64_t)k * 64 + t] = v;
 }
 
-// D_KP(k, d) for one keypoint k, one label plane iz and up to kKpRows label rows iy:
-// stage the moving-image vectors of the 4 z-planes and rows + 3 y-rows the labels need,
-// then each thread accumulates sum r^2 for kKpChunk labels along x over the patch (each
-// staged vector serves up to 4 labels).  Work items are ordered keypoint-major and dealt
-// to the 8 XCDs in contiguous runs, so that the items of one keypoint, whose staged
-// blocks overlap, share an L2.
+// D_KP(k, d) for one keypoint k and up to kKpRows label rows iy, all label planes iz in
+// turn.  The moving-image vectors the labels need lie in a (2R + 4)^3 block of one parity
+// sub-volume; the workgroup keeps a ring of kKpRing lattice planes (rows + 3 rows of
+// 2R + 4 vectors each) in LDS: plane iz + 4 is loaded into registers while the labels of
+// plane iz are computed from planes iz .. iz + 3, then stored into the ring slot that is no
+// longer needed.  Each thread accumulates sum r^2 for kKpChunk labels along x (every staged
+// vector serves up to 4 labels); the keypoint's 64 patch vectors are read from LDS by
+// broadcast.  Work items are ordered keypoint-major and dealt to the 8 XCDs in contiguous
+// runs.
+constexpr int kKpRing = 5;
+constexpr int kKpPlane = (kKpRows + 3) * kKpW;                        // vectors per staged plane
+constexpr int kKpPre = (kKpPlane + kKpThreads - 1) / kKpThreads;      // prefetched vectors per thread
+
 __global__ __launch_bounds__(kKpThreads) void k_kp_cost(KpGeo g, const float4 *__restrict__ nM,
                                                         const float4 *__restrict__ patch, int nkp,
                                                         const int *__restrict__ kp, int R, int items, int run,
                                                         float *__restrict__ cost) {
-  __shared__ float4 sM[4][kKpRows + 3][kKpWP];
+  __shared__ float4 sM[kKpRing][kKpRows + 3][kKpWP];
   __shared__ float4 sP[64];  // the keypoint's patch vectors, read by all threads at one address
   const int hw = blockIdx.x;
   const int item = (hw & 7) * run + (hw >> 3);
   if (item >= items) return;
   const int nl = 2 * R + 1, W = 2 * R + 4;
   const int nh = (nl + kKpRows - 1) / kKpRows;
-  const int k = item / (nl * nh), rem = item - k * (nl * nh);
-  const int iz = rem / nh, iy0 = (rem - iz * nh) * kKpRows;
+  const int k = item / nh, iy0 = (item - k * nh) * kKpRows;
   const int nrow = min(kKpRows, nl - iy0);
   const int kx = kp[3 * k], ky = kp[3 * k + 1], kz = kp[3 * k + 2];
   const int px = (kx + 1) & 1, py = (ky + 1) & 1, pz = (kz + 1) & 1;
   // lattice coordinate of voxel k + o + d: base + oi + i (oi = patch index, i = label index)
   const int bx = (kx + 1 - px) / 2 - 2 - R, by = (ky + 1 - py) / 2 - 2 - R, bz = (kz + 1 - pz) / 2 - 2 - R;
   const int t = threadIdx.x;
-  const int nst = 4 * (nrow + 3) * W;
-  for (int e = t; e < nst; e += kKpThreads) {
-    const int xx = e % W, rr = (e / W) % (nrow + 3), pl = e / (W * (nrow + 3));
-    const int x = bx + xx, y = by + iy0 + rr, z = bz + iz + pl;
+  const int npl = (nrow + 3) * W;  // vectors of one staged plane
+  auto fetch = [&](int e, int zl) {
+    const int xx = e % W, rr = e / W;
+    const int x = bx + xx, y = by + iy0 + rr, z = bz + zl;
     float4 v = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
     if ((unsigned)x < (unsigned)g.hx && (unsigned)y < (unsigned)g.hy && (unsigned)z < (unsigned)g.hz)
       v = nM[kp_par_index(g, px, py, pz, x, y, z)];
-    sM[pl][rr][xx] = v;
+    return v;
+  };
+  // planes 0..3 of the window into ring slots 0..3
+  for (int e = t; e < 4 * npl; e += kKpThreads) {
+    const int pl = e / npl, r = e - pl * npl;
+    sM[pl][r / W][r % W] = fetch(r, pl);
   }
   if (t < 64) sP[t] = patch[(int64_t)k * 64 + t];
   __syncthreads();
   const int nch = (nl + kKpChunk - 1) / kKpChunk;
   const int row = t / nch, ch = t - row * nch;
-  if (row >= nrow) return;
+  const bool active = row < nrow;
   const int ix0 = ch * kKpChunk;
-  const float4 *pk = sP;
-  float acc[kKpChunk];
+  const int64_t L = (int64_t)nl * nl * nl;
+  for (int iz = 0; iz < nl; ++iz) {
+    // prefetch window plane iz + 4 (the last label plane needs planes up to nl + 2)
+    const bool pre = iz + 4 < nl + 3;
+    float4 nxt[kKpPre];
 #pragma unroll
-  for (int c = 0; c < kKpChunk; ++c) acc[c] = 0.0f;
-#pragma unroll DISCO_KP_OZU
-  for (int oz = 0; oz < 4; ++oz) {
+    for (int q = 0; q < kKpPre; ++q) {
+      const int e = t + q * kKpThreads;
+      nxt[q] = (pre && e < npl) ? fetch(e, iz + 4) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    if (active) {
+      float acc[kKpChunk];
+#pragma unroll
+      for (int c = 0; c < kKpChunk; ++c) acc[c] = 0.0f;
+#pragma unroll 1
+      for (int oz = 0; oz < 4; ++oz) {
+        const int slot = (iz + oz) % kKpRing;
 #pragma unroll DISCO_KP_OYU
-    for (int oy = 0; oy < 4; ++oy) {
-      float4 b[4];
+        for (int oy = 0; oy < 4; ++oy) {
+          float4 b[4];
 #pragma unroll
-      for (int ox = 0; ox < 4; ++ox) b[ox] = pk[(oz * 4 + oy) * 4 + ox];
-      float4 a[kKpChunk + 3];
+          for (int ox = 0; ox < 4; ++ox) b[ox] = sP[(oz * 4 + oy) * 4 + ox];
+          float4 a[kKpChunk + 3];
 #pragma unroll
-      for (int j = 0; j < kKpChunk + 3; ++j) a[j] = sM[oz][row + oy][min(ix0 + j, W - 1)];
+          for (int j = 0; j < kKpChunk + 3; ++j) a[j] = sM[slot][row + oy][min(ix0 + j, W - 1)];
+#pragma unroll
+          for (int c = 0; c < kKpChunk; ++c)
+#pragma unroll
+            for (int ox = 0; ox < 4; ++ox) {
+              const float4 &u = a[c + ox];
+              const float r = u.x * b[ox].x + u.y * b[ox].y + u.z * b[ox].z + u.w * b[ox].w;
+              acc[c] = __builtin_fmaf(r, r, acc[c]);
+            }
+        }
+      }
+      float *o = cost + (int64_t)k * L + ((int64_t)iz * nl + iy0 + row) * nl;
 #pragma unroll
       for (int c = 0; c < kKpChunk; ++c)
-#pragma unroll
-        for (int ox = 0; ox < 4; ++ox) {
-          const float4 &u = a[c + ox];
-          const float r = u.x * b[ox].x + u.y * b[ox].y + u.z * b[ox].z + u.w * b[ox].w;
-          acc[c] = __builtin_fmaf(r, r, acc[c]);
-        }
+        if (ix0 + c < nl) o[ix0 + c] = 1.0f - acc[c] * (1.0f / 64.0f);
     }
-  }
-  const int64_t L = (int64_t)nl * nl * nl;
-  float *o = cost + (int64_t)k * L + ((int64_t)iz * nl + iy0 + row) * nl;
+    // plane iz + 4 goes to the slot of plane iz - 1, which no thread reads any more
+    if (pre) {
+      const int slot = (iz + 4) % kKpRing;
 #pragma unroll
-  for (int c = 0; c < kKpChunk; ++c)
-    if (ix0 + c < nl) o[ix0 + c] = 1.0f - acc[c] * (1.0f / 64.0f);
+      for (int q = 0; q < kKpPre; ++q) {
+        const int e = t + q * kKpThreads;
+        if (e < npl) sM[slot][e / W][e % W] = nxt[q];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- minimum spanning tree (Prim) in one workgroup ---------------------------------
+// Keypoint q is held by thread q % 1024 in slot q / 1024.  Each step takes the keypoint
+// outside the tree with the smallest key (lowest index on ties), adds it, and relaxes
+// the keys of the others with w = |x_q - x_k| + |I_q - I_k| / sigma_I, computed in double
+// precision in a fixed order without fused multiply-adds.
+constexpr int kPrimSlots = 4;  // up to 4096 keypoints (more: on the host)
+
+__device__ __forceinline__ void argmin_pair(double &v, int &i, double ov, int oi) {
+  if (ov < v || (ov == v && oi < i)) {
+    v = ov;
+    i = oi;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_kp_prim(int n, const float *__restrict__ x, const float *__restrict__ inten,
+                                                  double sigma_I, int *__restrict__ parent, int *__restrict__ order) {
+#pragma clang fp contract(off)
+  __shared__ double wv[16];
+  __shared__ int wi[16];
+  __shared__ double sk[4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  float X[kPrimSlots], Y[kPrimSlots], Z[kPrimSlots], I[kPrimSlots];
+  double key[kPrimSlots];
+  int par[kPrimSlots];
+  bool in[kPrimSlots];
+#pragma unroll
+  for (int j = 0; j < kPrimSlots; ++j) {
+    const int q = t + 1024 * j;
+    const bool ok = q < n;
+    X[j] = ok ? x[3 * q] : 0.0f;
+    Y[j] = ok ? x[3 * q + 1] : 0.0f;
+    Z[j] = ok ? x[3 * q + 2] : 0.0f;
+    I[j] = ok ? inten[q] : 0.0f;
+    key[j] = (ok && q == 0) ? 0.0 : INFINITY;
+    par[j] = -1;
+    in[j] = !ok;  // slots past n count as already in the tree
+  }
+  for (int it = 0; it < n; ++it) {
+    double bv = INFINITY;
+    int bi = 0x7fffffff;
+#pragma unroll
+    for (int j = 0; j < kPrimSlots; ++j)
+      if (!in[j]) argmin_pair(bv, bi, key[j], t + 1024 * j);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double ov = __shfl_xor(bv, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      argmin_pair(bv, bi, ov, oi);
+    }
+    if (lane == 0) {
+      wv[w] = bv;
+      wi[w] = bi;
+    }
+    __syncthreads();
+    double v = wv[0];
+    int k = wi[0];
+    for (int u = 1; u < 16; ++u) argmin_pair(v, k, wv[u], wi[u]);
+    // the owner publishes the new tree node
+    if ((k & 1023) == t) {
+      const int j = k >> 10;
+#pragma unroll
+      for (int s = 0; s < kPrimSlots; ++s)
+        if (s == j) {
+          in[s] = true;
+          sk[0] = X[s];
+          sk[1] = Y[s];
+          sk[2] = Z[s];
+          sk[3] = I[s];
+        }
+      order[it] = k;
+    }
+    __syncthreads();
+    const double xk = sk[0], yk = sk[1], zk = sk[2], ik = sk[3];
+#pragma unroll
+    for (int j = 0; j < kPrimSlots; ++j) {
+      const double dx = (double)X[j] - xk, dy = (double)Y[j] - yk, dz = (double)Z[j] - zk;
+      const double ss = (dx * dx + dy * dy) + dz * dz;
+      const double wq = sqrt(ss) + fabs((double)I[j] - ik) / sigma_I;
+      if (!in[j] && wq < key[j]) {
+        key[j] = wq;
+        par[j] = k;
+      }
+    }
+    __syncthreads();  // sk and wv/wi are rewritten in the next step
+  }
+#pragma unroll
+  for (int j = 0; j < kPrimSlots; ++j) {
+    const int q = t + 1024 * j;
+    if (q < n) parent[q] = par[j];
+  }
 }
 
 // ---- belief propagation on the tree, one tree level per launch ---------------------
-// every kernel: thread per (node of the level, label); nodes[] lists the level's nodes
+// nodes[] lists the nodes of the level
 
-// h_k = D_k + sum of the inward messages of k's children (CSR: cstart, cidx)
+// h_k = D_k + sum of the inward messages of k's children (CSR: cstart, cidx); thread per
+// (node, label)
 __global__ __launch_bounds__(256) void k_kp_gather_h(int nlev, const int *__restrict__ nodes, int64_t L,
                                                      const float *__restrict__ D, const float *__restrict__ msg,
                                                      const int *__restrict__ cstart, const int *__restrict__ cidx,
@@ -177,9 +303,9 @@ __global__ __launch_bounds__(256) void k_kp_gather_h(int nlev, const int *__rest
   h[(int64_t)k * L + l] = v;
 }
 
-// src = marg[parent] - msg[k] (the outward message's input)
+// src = M_parent - m_k (the outward message's input); thread per (node, label)
 __global__ __launch_bounds__(256) void k_kp_outward_in(int nlev, const int *__restrict__ nodes, int64_t L,
-                                                       const float *__restrict__ marg, const float *__restrict__ msg,
+                                                       const float *marg, const float *__restrict__ msg,
                                                        const int *__restrict__ parent, float *__restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= (int64_t)nlev * L) return;
@@ -188,31 +314,48 @@ __global__ __launch_bounds__(256) void k_kp_outward_in(int nlev, const int *__re
   out[(int64_t)k * L + l] = marg[(int64_t)parent[k] * L + l] - msg[(int64_t)k * L + l];
 }
 
-// one axis of the min-convolution with c_k |step h_a (i - j)|^2 (labels [iz][iy][ix]):
-// out(i) = min_j in(j) + pen_k (i - j)^2 along axis AX, pen_k = cw[k] (step h_a)^2;
-// with add != nullptr the result is added to add (out = add + min ...)
+// One axis of the min-convolution, one line of labels per thread: out(i) = min_j in(j) +
+// pen_k (i - j)^2 along axis AX (labels [iz][iy][ix]), pen_k = cw[k] (step h_a)^2, the
+// line's inputs held in registers; with add != nullptr the result is added to add.
+constexpr int kKpNl = 2 * kKpRmax + 1;  // 33
+
 template <int AX>
-__global__ __launch_bounds__(256) void k_kp_mincon_axis(int nlev, const int *__restrict__ nodes, int nl,
-                                                        const float *__restrict__ in, const float *__restrict__ cw,
-                                                        float step_mm, const float *__restrict__ add,
-                                                        float *__restrict__ out) {
-  const int64_t L = (int64_t)nl * nl * nl;
+__global__ __launch_bounds__(256) void k_kp_line_axis(int nlev, const int *__restrict__ nodes, int nl,
+                                                      const float *__restrict__ in, const float *__restrict__ cw,
+                                                      float step_mm, const float *__restrict__ add,
+                                                      float *__restrict__ out) {
+  const int64_t nl2 = (int64_t)nl * nl, L = nl2 * nl;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)nlev * L) return;
-  const int k = nodes[e / L];
-  const int64_t l = e % L;
-  const int ix = (int)(l % nl), iy = (int)((l / nl) % nl), iz = (int)(l / ((int64_t)nl * nl));
-  const int i = AX == 0 ? ix : (AX == 1 ? iy : iz);
-  const int64_t stride = AX == 0 ? 1 : (AX == 1 ? nl : (int64_t)nl * nl);
-  const float *src = in + (int64_t)k * L + (l - (int64_t)i * stride);
-  const float pen = cw[k] * step_mm * step_mm;
-  float best = INFINITY;
-  for (int j = 0; j < nl; ++j) {
-    const float dij = (float)(i - j);
-    best = fminf(best, src[(int64_t)j * stride] + pen * dij * dij);
+  if (e >= (int64_t)nlev * nl2) return;
+  const int k = nodes[e / nl2];
+  const int line = (int)(e % nl2);
+  // line start and stride: x lines (iz, iy), y lines (iz, ix), z lines (iy, ix)
+  int64_t base, stride;
+  if (AX == 0) {
+    base = (int64_t)line * nl;
+    stride = 1;
+  } else if (AX == 1) {
+    const int iz = line / nl, ix = line - iz * nl;
+    base = (int64_t)iz * nl2 + ix;
+    stride = nl;
+  } else {
+    base = line;
+    stride = nl2;
   }
-  const int64_t o = (int64_t)k * L + l;
-  out[o] = add ? add[o] + best : best;
+  const int64_t o = (int64_t)k * L + base;
+  float v[kKpNl];
+#pragma unroll
+  for (int j = 0; j < kKpNl; ++j) v[j] = j < nl ? in[o + j * stride] : INFINITY;
+  const float pen = cw[k] * step_mm * step_mm;
+  for (int i = 0; i < nl; ++i) {
+    float best = INFINITY;
+#pragma unroll
+    for (int j = 0; j < kKpNl; ++j) {
+      const float dij = (float)(i - j);
+      best = fminf(best, v[j] + pen * dij * dij);
+    }
+    out[o + i * stride] = add ? add[o + i * stride] + best : best;
+  }
 }
 
 // label of the smallest min-marginal per keypoint (lowest index on ties): one workgroup

@@ -80,6 +80,33 @@ def test_host_validation_codes_without_device(lib):
     assert lib.lbfgs_step(None, None, None, None, None, None, None) == -1
     lib.lbfgs_reset.argtypes = [V]
     assert lib.lbfgs_reset(None) == -1
+    lib.objective_linearise.argtypes = [V, V, V, V, V, V, V]
+    assert lib.objective_linearise(None, None, None, None, None, None, None) == -1
+    lib.disco_set_masks.argtypes = [V, V, V, V]
+    assert lib.disco_set_masks(None, None, None, None) == -1
+    lib.multilevel_register.argtypes = [V] * 12
+    assert lib.multilevel_register(*([None] * 12)) == -1
+    lib.pyramid_downsample.argtypes = [V] * 6
+    assert lib.pyramid_downsample(*([None] * 6)) == -1
+    lib.pyramid_prolong.argtypes = [V] * 5
+    assert lib.pyramid_prolong(*([None] * 5)) == -1
+    # keypoint stage: argument checks before any device call
+    lib.disco_kp_create.argtypes = [V, V, V]
+    kp = ctypes.c_void_p(7)
+    n3 = (ctypes.c_int32 * 3)(32, 32, 0)
+    h3 = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    assert lib.disco_kp_create(n3, h3, ctypes.byref(kp)) == -2 and kp.value is None
+    n3 = (ctypes.c_int32 * 3)(32, 32, 32)
+    h3 = (ctypes.c_double * 3)(1.0, float("inf"), 1.0)
+    assert lib.disco_kp_create(n3, h3, ctypes.byref(kp)) == -4
+    assert lib.disco_kp_create(None, h3, ctypes.byref(kp)) == -1
+    lib.disco_kp_cost.argtypes = [V, ctypes.c_int32, V, ctypes.c_int32, V, V]
+    assert lib.disco_kp_cost(None, 1, None, 16, None, None) == -1
+    lib.disco_kp_regularise.argtypes = [V, ctypes.c_int32, V, V, ctypes.c_int32, V, ctypes.c_double,
+                                        ctypes.c_double, V, V, V, V]
+    assert lib.disco_kp_regularise(None, 1, None, None, 16, None, 0.1, 150.0, None, None, None, None) == -1
+    lib.disco_kp_destroy.argtypes = [V]
+    lib.disco_kp_destroy(None)
     lib.disco_destroy.argtypes = [V]
     lib.disco_destroy(None)
     for code in (0, -1, -2, -3, -4, -5):

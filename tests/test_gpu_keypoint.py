@@ -117,3 +117,29 @@ def test_kp_argument_errors(disco):
     with pytest.raises(disco.DiscoError) as e:
         st.cost(kp, 17)
     assert e.value.code == disco.ERR_ARG
+
+
+@pytest.mark.parametrize("n", [3500, 4200])
+def test_kp_tree_and_messages_at_scale(disco, n):
+    """3500 keypoints (the tree built on the device) and 4200 (built on the host): the MST
+    equals the oracle's, and the min-marginals agree, with 27 labels (R = 1)."""
+    say(f"[kp] MST + BP with {n} keypoints")
+    d = synth.small_pair(shape=(64, 56, 44), spacing=(1.0, 1.0, 1.0), seed=44, n_tubes=10, n_kp=8, field_max=4.0)
+    r = np.random.default_rng(n)
+    nx, ny, nz = d["shape"]
+    flat = r.choice(nx * ny * nz, n, replace=False)  # distinct keypoints
+    kps = np.stack([flat % nx, (flat // nx) % ny, flat // (nx * ny)], 1).astype(np.int32)
+    st = stage(disco, d)
+    cost = st.cost(torch.from_numpy(kps).to(DEV), 1)
+    x = (kps + 0.5).astype(np.float32)
+    inten = d["R"][kps[:, 2], kps[:, 1], kps[:, 0]]
+    marg, lab, par = st.regularise(x, inten, cost, 1, 1.0 / 45.0, 150.0)
+    torch.cuda.synchronize()
+    parent, order = oracle.kp_mst(x, inten)
+    np.testing.assert_array_equal(par, parent)
+    om, _ = oracle.kp_belief_propagation(cost.cpu().numpy().astype(np.float64), parent, order, x, inten, 1.0 / 45.0,
+                                         R=1, step=2)
+    gm = marg.cpu().numpy()
+    err = float(np.max(np.abs(gm - om) / np.max(np.abs(om), axis=1, keepdims=True)))
+    say(f"  tree depth {tree_depth(parent, order)}; marginals max rel error {err:.2e}")
+    assert err < 1e-5
