@@ -963,6 +963,13 @@ __device__ __forceinline__ void load_corners(const float *fb, const Geo &g, bool
 // ---------------------------------------------------------------------------------
 // The voxel-brick kernel.
 // ---------------------------------------------------------------------------------
+// unrolling of the voxel rows (y) and layers (z) of a cell in the objective pass
+#ifndef DISCO_EVAL_JV
+#define DISCO_EVAL_JV 1
+#endif
+#ifndef DISCO_EVAL_KV
+#define DISCO_EVAL_KV 1
+#endif
 #ifndef DISCO_HV_WAVES
 #define DISCO_HV_WAVES 1
 #endif
@@ -1149,7 +1156,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
               float accY[FS][2][3] = {};
               RowCache rc;
               rc.valid = false;
-    #pragma unroll (MODE == M_HV ? 4 : 1)
+    #pragma unroll (MODE == M_HV ? 4 : (MODE == M_EVAL ? DISCO_EVAL_JV : 1))
               for (int jv = 0; jv < 4; ++jv) {
                 const float wy = (jv + 0.5f) * 0.25f;
                 const int iy = cy * 4 + jv;
@@ -1275,7 +1282,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
     #pragma unroll
               for (int kv = 0; kv < 4; ++kv) zrow(kv);
             } else {
-    #pragma unroll 1
+    #pragma unroll (MODE == M_EVAL ? DISCO_EVAL_KV : 1)
               for (int kv = 0; kv < 4; ++kv) zrow(kv);
             }
           }
