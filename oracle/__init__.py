@@ -757,25 +757,51 @@ def kp_edge_weight(x, inten, k, q, sigma_I: float = 150.0):
 
 def kp_mst(x, inten, sigma_I: float = 150.0):
     """Minimum spanning tree over all keypoint pairs with the edge cost of eq. 3's
-    denominator (Prim's algorithm from keypoint 0; ties to the lowest index).  Returns
-    (parent [n] with parent[0] = -1, visit order)."""
+    denominator.  Ties between edge costs are broken by the strict order (cost, lower
+    index, higher index), which makes the tree unique; Kruskal's algorithm on that order.
+    The tree is rooted at keypoint 0 and visited breadth first (neighbours in increasing
+    order).  Returns (parent [n] with parent[0] = -1, visit order)."""
     x = _f64(x).reshape(-1, 3)
     inten = _f64(inten).ravel()
     n = len(x)
-    key = np.full(n, np.inf)
+    ii, jj = np.triu_indices(n, 1)
+    d = x[jj] - x[ii]
+    w = np.sqrt((d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]) + d[:, 2] * d[:, 2]) + np.abs(inten[jj] - inten[ii]) / sigma_I
+    srt = np.lexsort((jj, ii, w))
+    uf = list(range(n))
+
+    def find(a):
+        while uf[a] != a:
+            uf[a] = uf[uf[a]]
+            a = uf[a]
+        return a
+
+    adj = [[] for _ in range(n)]
+    taken = 0
+    for e in srt:
+        if taken == n - 1:
+            break
+        a, b = int(ii[e]), int(jj[e])
+        ra, rb = find(a), find(b)
+        if ra == rb:
+            continue
+        uf[max(ra, rb)] = min(ra, rb)
+        adj[a].append(b)
+        adj[b].append(a)
+        taken += 1
     parent = np.full(n, -1, np.int64)
-    done = np.zeros(n, bool)
-    key[0] = 0.0
-    order = []
-    for _ in range(n):
-        cand = np.where(done, np.inf, key)
-        k = int(np.argmin(cand))
-        done[k] = True
-        order.append(k)
-        w = np.sqrt(np.sum((x - x[k]) ** 2, axis=1)) + np.abs(inten - inten[k]) / sigma_I
-        upd = (~done) & (w < key)
-        key[upd] = w[upd]
-        parent[upd] = k
+    seen = np.zeros(n, bool)
+    seen[0] = True
+    order = [0]
+    h = 0
+    while h < len(order):
+        a = order[h]
+        h += 1
+        for b in sorted(adj[a]):
+            if not seen[b]:
+                seen[b] = True
+                parent[b] = a
+                order.append(b)
     return parent, np.asarray(order, np.int64)
 
 

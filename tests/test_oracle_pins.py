@@ -1018,3 +1018,19 @@ def test_kp_belief_propagation_gives_exact_min_marginals():
         np.testing.assert_allclose(marg[k], ref, rtol=1e-12, atol=1e-12)
     marg2, _ = oracle.kp_belief_propagation(D, parent, order, x, inten, alpha, R=R, step=step)
     np.testing.assert_allclose(marg2, marg, rtol=1e-12, atol=1e-12)
+
+
+def test_kp_mst_ties_follow_the_edge_order():
+    """Keypoints on a unit lattice with equal intensities: every nearest-neighbour edge
+    costs 1, so the tree is fixed by the order (cost, lower index, higher index); brute
+    force over Kruskal's rule written out for this case gives the same edges."""
+    g = np.array([[i, j, 0] for j in range(3) for i in range(4)], np.float64)
+    inten = np.zeros(len(g))
+    parent, order = oracle.kp_mst(g, inten)
+    edges = {tuple(sorted((k, int(parent[k])))) for k in range(len(g)) if parent[k] >= 0}
+    # by hand: unit edges sorted by (lower, higher) are (0,1), (0,4), (1,2), (1,5), (2,3),
+    # (2,6), (3,7), (4,5), (4,8), ...; Kruskal keeps the first row's horizontal edges and
+    # every vertical edge, all later horizontal edges close a cycle
+    expect = {(0, 1), (1, 2), (2, 3), (0, 4), (1, 5), (2, 6), (3, 7), (4, 8), (5, 9), (6, 10), (7, 11)}
+    assert edges == expect
+    assert list(order[:3]) == [0, 1, 4]
