@@ -324,14 +324,15 @@ int disco_kp_set_images(disco_kp *kp, const float *F, const float *M, double eta
 int disco_kp_cost(disco_kp *kp, int32_t nkp, const int32_t *kp_vox, int32_t R, float *cost, disco_stream stream);
 
 /* Regularised correspondences (Sec. II-C3): minimum spanning tree over all keypoint pairs
-   with edge cost w_kq = |x_k - x_q| + |I_k - I_q| / sigma_I (Prim's algorithm on the host
-   from keypoint 0, ties to the lowest index), then two-pass min-sum belief propagation on
+   with edge cost w_kq = |x_k - x_q| + |I_k - I_q| / sigma_I (Boruvka rounds: the cheapest
+   edge of every keypoint found on the device, components merged on the host, edges
+   ordered by (w, lower index, higher index); rooted at keypoint 0), then two-pass min-sum
+   belief propagation on
    the tree with the data cost `cost` (as written by disco_kp_cost) and the regulariser of
    eq. 3, alpha_kp |d_k - d_q|^2 / w_kq (|.| in mm), each message a min-convolution done as
    three exact 1-D minimisations (x, y, z), one tree level per launch.  x_mm (HOST
    float32 [nkp][3]) and inten (HOST float32 [nkp], F at the keypoint) define w; the
-   keypoints must be distinct (w > 0).  The tree is built on the device (one workgroup)
-   for up to 4096 keypoints, on the host beyond.  Writes
+   keypoints must be distinct (w > 0).  Writes
    the min-marginal energies to marg (device float32 [nkp][(2R+1)^3], nullable), the label
    of the smallest one per keypoint (lowest index on ties) to labels (device int32 [nkp])
    and the tree to parent_out (HOST int32 [nkp], nullable; -1 at the root).  Allocates

@@ -1979,38 +1979,6 @@ int disco_kp_cost(disco_kp *k, int32_t nkp, const int32_t *kp_vox, int32_t R, fl
   return DISCO_OK;
 }
 
-// minimum spanning tree over all keypoint pairs (Prim from keypoint 0, ties to the lowest
-// index) with the cost |x_k - x_q| + |I_k - I_q| / sigma_I; parent[0] = -1
-static void kp_mst(int n, const float *x, const float *inten, double sigma_I, std::vector<int> &parent,
-                   std::vector<int> &order) {
-  std::vector<double> key(n, INFINITY);
-  std::vector<char> done(n, 0);
-  parent.assign(n, -1);
-  order.clear();
-  key[0] = 0.0;
-  for (int it = 0; it < n; ++it) {
-    int k = -1;
-    double best = INFINITY;
-    for (int q = 0; q < n; ++q)
-      if (!done[q] && (k < 0 || key[q] < best)) {
-        best = key[q];
-        k = q;
-      }
-    done[k] = 1;
-    order.push_back(k);
-    const double xk = x[3 * k], yk = x[3 * k + 1], zk = x[3 * k + 2], ik = inten[k];
-    for (int q = 0; q < n; ++q) {
-      if (done[q]) continue;
-      const double dx = x[3 * q] - xk, dy = x[3 * q + 1] - yk, dz = x[3 * q + 2] - zk;
-      const double w = std::sqrt(dx * dx + dy * dy + dz * dz) + std::fabs((double)inten[q] - ik) / sigma_I;
-      if (w < key[q]) {
-        key[q] = w;
-        parent[q] = k;
-      }
-    }
-  }
-}
-
 int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float *inten, int32_t R,
                         const float *cost, double alpha_kp, double sigma_I, float *marg, int32_t *labels,
                         int32_t *parent_out, disco_stream stream) {
@@ -2024,21 +1992,75 @@ int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float
   const int64_t L = (int64_t)nl * nl * nl;
   // tree, levels (depth from the root), children lists, per-edge weights (host)
   std::vector<int> parent(n), order(n);
-  if (n <= 1024 * kPrimSlots) {
-    // Prim on the device (one workgroup), the tree copied back for the level schedule
+  {
+    // Boruvka rounds on the device (cheapest outgoing edge per keypoint), components merged
+    // on the host; the tree is then rooted at keypoint 0 (breadth first, neighbours in
+    // increasing order)
     MlBuffers P;
     float *dx = nullptr, *di = nullptr;
-    int *dp = nullptr, *dord = nullptr;
-    if (!P.alloc(&dx, 3 * (size_t)n) || !P.alloc(&di, n) || !P.alloc(&dp, n) || !P.alloc(&dord, n))
+    int *dcomp = nullptr, *dj = nullptr;
+    double *dw = nullptr;
+    if (!P.alloc(&dx, 3 * (size_t)n) || !P.alloc(&di, n) || !P.alloc(&dcomp, n) || !P.alloc(&dj, n) ||
+        !P.alloc(&dw, n))
       return DISCO_ERR_NOMEM;
     HIP_TRY(hipMemcpyAsync(dx, x_mm, sizeof(float) * 3 * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(di, inten, sizeof(float) * n, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_kp_prim, dim3(1), dim3(1024), 0, s, n, dx, di, sigma_I, dp, dord);
-    HIP_TRY(hipMemcpyAsync(parent.data(), dp, sizeof(int) * n, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(order.data(), dord, sizeof(int) * n, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-  } else {
-    kp_mst(n, x_mm, inten, sigma_I, parent, order);
+    std::vector<int> uf(n), comp(n), bj(n);
+    std::vector<double> bw(n);
+    std::iota(uf.begin(), uf.end(), 0);
+    auto find = [&](int a) {
+      while (uf[a] != a) a = uf[a] = uf[uf[a]];
+      return a;
+    };
+    std::vector<std::vector<int>> adj(n);
+    int ncomp = n;
+    while (ncomp > 1) {
+      for (int q = 0; q < n; ++q) comp[q] = find(q);
+      HIP_TRY(hipMemcpyAsync(dcomp, comp.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_kp_boruvka, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, dx, di, sigma_I, dcomp, dw,
+                         dj);
+      HIP_TRY(hipMemcpyAsync(bw.data(), dw, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(bj.data(), dj, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      // cheapest edge per component under the order (w, min(i, j), max(i, j))
+      std::vector<int> ce(n, -1);
+      auto less = [&](int a, int b) {
+        if (bw[a] != bw[b]) return bw[a] < bw[b];
+        const int la = std::min(a, bj[a]), lb = std::min(b, bj[b]);
+        if (la != lb) return la < lb;
+        return std::max(a, bj[a]) < std::max(b, bj[b]);
+      };
+      for (int q = 0; q < n; ++q) {
+        const int c = comp[q];
+        if (ce[c] < 0 || less(q, ce[c])) ce[c] = q;
+      }
+      for (int c = 0; c < n; ++c) {
+        if (ce[c] < 0) continue;
+        const int a = ce[c], b = bj[a];
+        const int ra = find(a), rb = find(b);
+        if (ra == rb) continue;  // the same edge chosen from both sides
+        uf[std::max(ra, rb)] = std::min(ra, rb);
+        adj[a].push_back(b);
+        adj[b].push_back(a);
+        --ncomp;
+      }
+    }
+    // root at keypoint 0
+    std::vector<char> seen(n, 0);
+    order.clear();
+    order.push_back(0);
+    seen[0] = 1;
+    parent.assign(n, -1);
+    for (size_t h = 0; h < order.size(); ++h) {
+      const int a = order[h];
+      std::sort(adj[a].begin(), adj[a].end());
+      for (int b : adj[a])
+        if (!seen[b]) {
+          seen[b] = 1;
+          parent[b] = a;
+          order.push_back(b);
+        }
+    }
   }
   std::vector<int> depth(n, 0);
   int maxd = 0;

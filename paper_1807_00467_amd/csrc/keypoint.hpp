@@ -193,13 +193,7 @@ __global__ __launch_bounds__(kKpThreads) void k_kp_cost(KpGeo g, const float4 *_
   }
 }
 
-// ---- minimum spanning tree (Prim) in one workgroup ---------------------------------
-// Keypoint q is held by thread q % 1024 in slot q / 1024.  Each step takes the keypoint
-// outside the tree with the smallest key (lowest index on ties), adds it, and relaxes
-// the keys of the others with w = |x_q - x_k| + |I_q - I_k| / sigma_I, computed in double
-// precision in a fixed order without fused multiply-adds.
-constexpr int kPrimSlots = 4;  // up to 4096 keypoints (more: on the host)
-
+// (weight, index) minimum with ties to the lowest index
 __device__ __forceinline__ void argmin_pair(double &v, int &i, double ov, int oi) {
   if (ov < v || (ov == v && oi < i)) {
     v = ov;
@@ -207,81 +201,38 @@ __device__ __forceinline__ void argmin_pair(double &v, int &i, double ov, int oi
   }
 }
 
-__global__ __launch_bounds__(1024) void k_kp_prim(int n, const float *__restrict__ x, const float *__restrict__ inten,
-                                                  double sigma_I, int *__restrict__ parent, int *__restrict__ order) {
+// ---- minimum spanning tree by Boruvka rounds ------------------------------------------
+// One round: for every keypoint i, the cheapest edge (i, j) to a keypoint of another
+// component (comp[j] != comp[i]), ties to the lowest j; one wave per keypoint.  Edge
+// costs |x_i - x_j| + |I_i - I_j| / sigma_I in double precision from the float inputs, in
+// a fixed order without fused multiply-adds, so they are symmetric.
+__global__ __launch_bounds__(256) void k_kp_boruvka(int n, const float *__restrict__ x,
+                                                    const float *__restrict__ inten, double sigma_I,
+                                                    const int *__restrict__ comp, double *__restrict__ best_w,
+                                                    int *__restrict__ best_j) {
 #pragma clang fp contract(off)
-  __shared__ double wv[16];
-  __shared__ int wi[16];
-  __shared__ double sk[4];
-  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  float X[kPrimSlots], Y[kPrimSlots], Z[kPrimSlots], I[kPrimSlots];
-  double key[kPrimSlots];
-  int par[kPrimSlots];
-  bool in[kPrimSlots];
-#pragma unroll
-  for (int j = 0; j < kPrimSlots; ++j) {
-    const int q = t + 1024 * j;
-    const bool ok = q < n;
-    X[j] = ok ? x[3 * q] : 0.0f;
-    Y[j] = ok ? x[3 * q + 1] : 0.0f;
-    Z[j] = ok ? x[3 * q + 2] : 0.0f;
-    I[j] = ok ? inten[q] : 0.0f;
-    key[j] = (ok && q == 0) ? 0.0 : INFINITY;
-    par[j] = -1;
-    in[j] = !ok;  // slots past n count as already in the tree
-  }
-  for (int it = 0; it < n; ++it) {
-    double bv = INFINITY;
-    int bi = 0x7fffffff;
-#pragma unroll
-    for (int j = 0; j < kPrimSlots; ++j)
-      if (!in[j]) argmin_pair(bv, bi, key[j], t + 1024 * j);
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const double ov = __shfl_xor(bv, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      argmin_pair(bv, bi, ov, oi);
-    }
-    if (lane == 0) {
-      wv[w] = bv;
-      wi[w] = bi;
-    }
-    __syncthreads();
-    double v = wv[0];
-    int k = wi[0];
-    for (int u = 1; u < 16; ++u) argmin_pair(v, k, wv[u], wi[u]);
-    // the owner publishes the new tree node
-    if ((k & 1023) == t) {
-      const int j = k >> 10;
-#pragma unroll
-      for (int s = 0; s < kPrimSlots; ++s)
-        if (s == j) {
-          in[s] = true;
-          sk[0] = X[s];
-          sk[1] = Y[s];
-          sk[2] = Z[s];
-          sk[3] = I[s];
-        }
-      order[it] = k;
-    }
-    __syncthreads();
-    const double xk = sk[0], yk = sk[1], zk = sk[2], ik = sk[3];
-#pragma unroll
-    for (int j = 0; j < kPrimSlots; ++j) {
-      const double dx = (double)X[j] - xk, dy = (double)Y[j] - yk, dz = (double)Z[j] - zk;
-      const double ss = (dx * dx + dy * dy) + dz * dz;
-      const double wq = sqrt(ss) + fabs((double)I[j] - ik) / sigma_I;
-      if (!in[j] && wq < key[j]) {
-        key[j] = wq;
-        par[j] = k;
-      }
-    }
-    __syncthreads();  // sk and wv/wi are rewritten in the next step
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2], ii = inten[i];
+  const int ci = comp[i];
+  double bw = INFINITY;
+  int bj = 0x7fffffff;
+  for (int j = lane; j < n; j += 64) {
+    if (comp[j] == ci) continue;
+    const double dx = (double)x[3 * j] - xi, dy = (double)x[3 * j + 1] - yi, dz = (double)x[3 * j + 2] - zi;
+    const double ss = (dx * dx + dy * dy) + dz * dz;
+    const double w = sqrt(ss) + fabs((double)inten[j] - ii) / sigma_I;
+    argmin_pair(bw, bj, w, j);
   }
 #pragma unroll
-  for (int j = 0; j < kPrimSlots; ++j) {
-    const int q = t + 1024 * j;
-    if (q < n) parent[q] = par[j];
+  for (int o = 32; o >= 1; o >>= 1) {
+    const double ov = __shfl_xor(bw, o, 64);
+    const int oj = __shfl_xor(bj, o, 64);
+    argmin_pair(bw, bj, ov, oj);
+  }
+  if (lane == 0) {
+    best_w[i] = bw;
+    best_j[i] = bj;
   }
 }
 

@@ -121,8 +121,8 @@ def test_kp_argument_errors(disco):
 
 @pytest.mark.parametrize("n", [3500, 4200])
 def test_kp_tree_and_messages_at_scale(disco, n):
-    """3500 keypoints (the tree built on the device) and 4200 (built on the host): the MST
-    equals the oracle's, and the min-marginals agree, with 27 labels (R = 1)."""
+    """3500 and 4200 keypoints: the MST (Boruvka rounds on the device) equals the oracle's
+    (Prim's algorithm), and the min-marginals agree, with 27 labels (R = 1)."""
     say(f"[kp] MST + BP with {n} keypoints")
     d = synth.small_pair(shape=(64, 56, 44), spacing=(1.0, 1.0, 1.0), seed=44, n_tubes=10, n_kp=8, field_max=4.0)
     r = np.random.default_rng(n)
