@@ -965,7 +965,7 @@ __device__ __forceinline__ void load_corners(const float *fb, const Geo &g, bool
 // ---------------------------------------------------------------------------------
 // unrolling of the voxel rows (y) and layers (z) of a cell in the objective pass
 #ifndef DISCO_EVAL_JV
-#define DISCO_EVAL_JV 1
+#define DISCO_EVAL_JV 2
 #endif
 #ifndef DISCO_EVAL_KV
 #define DISCO_EVAL_KV 1
