@@ -177,3 +177,25 @@ def test_masks_argument_errors(disco):
     ctx.set_masks(None, None)
     ctx.gn_hessvec(p, u)  # without masks beta is ignored
     torch.cuda.synchronize()
+
+
+def test_boundary_term_isolated_fp16_storage(disco):
+    """The boundary term keeps its own FP32 vectors: with FP16 storage of the image
+    gradients and s-cache (all NGF quantities are zero for R = T = 0) it matches the oracle
+    as tightly as with FP32 storage."""
+    say("[boundary] isolated, FP16 storage")
+    d = synth.small_pair(shape=(48, 40, 28), spacing=(1.2, 1.4, 2.2), seed=25, n_tubes=6, n_kp=10, field_max=4.0)
+    ctx = disco.Disco(d["shape"], d["spacing"], storage="fp16", device=DEV)
+    z = torch.zeros(d["R"].shape, dtype=torch.float32, device=DEV)
+    ctx.set_images(z, z)
+    ctx.set_masks(torch.from_numpy(d["mask_R"]).to(DEV), torch.from_numpy(d["mask_T"]).to(DEV))
+    beta = 0.9
+    p = disco.Params(eta=ETA, alpha=0.0, gamma=0.0, delta=0.0, beta=beta)
+    u = d["u_true"].astype(np.float32) * 0.6
+    out = ctx.objective_linearise(p, torch.from_numpy(u).to(DEV))
+    Hv = ctx.gn_hessvec(p, torch.from_numpy(d["v"]).to(DEV))
+    torch.cuda.synchronize()
+    ref = oracle.mask_term(d["mask_R"], d["mask_T"], d["spacing"], u)
+    assert abs(out["B"] - ref["B"]) <= 1e-5 * ref["B"]
+    assert rel_l2(out["g"], beta * ref["g"]) < 1e-4
+    assert rel_l2(Hv, beta * oracle.mask_hv(ref["sb"], d["spacing"], d["v"])) < 1e-4

@@ -122,3 +122,28 @@ def test_lbfgs_argument_errors(disco):
         with pytest.raises(disco.DiscoError) as e:
             ctx.lbfgs_step(params, bad, u)
         assert e.value.code == code, bad
+
+
+def test_lbfgs_fp16_storage_decreases_objective(disco):
+    """With FP16 storage the iterations differ from the FP64 oracle by the storage error
+    (documented for the FP16 form), so here only the run itself is checked: every accepted
+    step lowers J and the first J agrees with the oracle to the FP16 form's bound."""
+    say("[lbfgs] FP16 storage")
+    d = synth.small_pair(shape=(48, 32, 24), spacing=(1.2, 1.4, 2.2), seed=65, n_tubes=8, n_kp=30, field_max=4.0)
+    ctx = disco.Disco(d["shape"], d["spacing"], storage="fp16", device=DEV)
+    ctx.set_images(torch.from_numpy(d["R"]).to(DEV), torch.from_numpy(d["T"]).to(DEV))
+    ctx.set_keypoints(d["kp_x"], d["kp_t"])
+    P = oracle.Problem(d["R"], d["T"], d["spacing"], d["kp_x"], d["kp_t"],
+                       oracle.Weights(eta=ETA, alpha=ALPHA, gamma=GAMMA, delta=1.0))
+    params = disco.Params(eta=ETA, alpha=ALPHA, gamma=GAMMA, delta=1.0, ls_max=10, flags=disco.FLAG_LS_DEVICE)
+    lb = disco.Lbfgs(m=5, h0_iters=60, h0_tol=1e-7)
+    u = torch.zeros((3,) + tuple(ctx.nodes[::-1]), device=DEV)
+    reps = []
+    for _ in range(5):
+        rep, st = ctx.lbfgs_step(params, lb, u)
+        reps.append((disco.Disco.report_dict(rep), int(st.item())))
+    torch.cuda.synchronize()
+    J0 = P.objective(np.zeros(u.shape))["J"]
+    assert abs(reps[0][0]["J"] - J0) <= 2e-3 * abs(J0)
+    for r, st in reps:
+        assert st == 0 and r["t"] > 0 and r["J_new"] < r["J"]

@@ -108,3 +108,23 @@ def test_multilevel_register_matches_oracle(disco, optimizer, levels, iters):
     e = float(np.linalg.norm(u.cpu().numpy() - uo) / np.linalg.norm(uo))
     say(f"  final u rel-L2 {e:.2e}")
     assert e < 2e-3
+
+
+def test_multilevel_register_fp16_storage_runs(disco):
+    """A coarse-to-fine run with FP16 storage on every level lowers J on every level."""
+    say("[pyramid] multilevel, FP16 storage")
+    d = synth.small_pair(shape=(32, 32, 24), spacing=(1.5, 1.5, 2.0), seed=10, n_tubes=8, n_kp=30, field_max=4.0)
+    prm = disco.Params(eta=10.0, alpha=1.0, gamma=0.1, delta=0.0, ls_max=10, flags=disco.FLAG_LS_DEVICE)
+    ml = disco.Multilevel(levels=3, optimizer="lbfgs", iters=(4, 3, 2), adaptive_delta=True, storage="fp16")
+    u, rep, L, delta = disco.multilevel_register(torch.from_numpy(d["R"]).to(DEV), torch.from_numpy(d["T"]).to(DEV),
+                                                 d["spacing"], d["kp_x"], d["kp_t"], prm, ml,
+                                                 disco.Lbfgs(h0_iters=60, h0_tol=1e-7))
+    torch.cuda.synchronize()
+    rep = rep.cpu().numpy()
+    assert L == 3 and delta > 0 and torch.isfinite(u).all()
+    row = 0
+    for n in (4, 3, 2):
+        r = rep[row:row + n]
+        r = r[~np.isnan(r[:, 0])]
+        assert len(r) >= 1 and r[-1, 10] < r[0, 0]
+        row += n
