@@ -348,6 +348,26 @@ def bench_lbfgs(args):
     ctx.close()
 
 
+def tree_depths(parent, root):
+    """Hop distance of every node from root in the tree given by a parent array."""
+    import numpy as np
+    n = len(parent)
+    adj = [[] for _ in range(n)]
+    for k, p in enumerate(parent):
+        if p >= 0:
+            adj[k].append(int(p))
+            adj[int(p)].append(k)
+    dep = np.full(n, -1, int)
+    dep[root] = 0
+    queue = [root]
+    for a in queue:
+        for b in adj[a]:
+            if dep[b] < 0:
+                dep[b] = dep[a] + 1
+                queue.append(b)
+    return dep
+
+
 def bench_keypoints(args):
     """Keypoint stage at the paper's size: 3500 keypoints, 33^3 = 35937 displacements, 64
     patch voxels each (8.05e9 NGF terms); K cost evaluations timed with events on the
@@ -379,18 +399,18 @@ def bench_keypoints(args):
     cost_s = e0.elapsed_time(e1) / 1e3 / args.steps
     x = (kps + 0.5) * np.asarray(d["spacing"])
     inten = d["R"][kps[:, 2], kps[:, 1], kps[:, 0]]
-    st.regularise(x, inten, cost, R)  # warm
+    st.regularise(x, inten, cost, R)  # warm (allocates the handle's work memory)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    marg, lab, par = st.regularise(x, inten, cost, R)
-    torch.cuda.synchronize()
-    reg_s = time.perf_counter() - t0
-    dep = np.zeros(len(par), int)
-    for k in range(len(par)):
-        q, n_ = k, 0
-        while par[q] >= 0:
-            q, n_ = par[q], n_ + 1
-        dep[k] = n_
+    reg = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        marg, lab, par = st.regularise(x, inten, cost, R)
+        torch.cuda.synchronize()
+        reg.append(time.perf_counter() - t0)
+    reg_s = float(np.median(reg))
+    dep = tree_depths(par, 0)
+    far = int(np.argmax(dep))
+    diameter = int(tree_depths(par, far).max())
     terms = len(kps) * L * 64
     flops = 10.0 * terms  # per term: 4-component dot and r^2 accumulation, 5 fused multiply-adds
     achieved = flops / cost_s / 1e12
@@ -418,6 +438,7 @@ def bench_keypoints(args):
         "cost_ms": 1e3 * cost_s,
         "regularise_ms": 1e3 * reg_s,
         "tree_depth": int(dep.max()),
+        "bp_levels": (diameter + 1) // 2,
         "roofline": {
             "kernel": "k_kp_cost (NGF matching cost, eq. 2)",
             "bound": "alu",

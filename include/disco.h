@@ -326,18 +326,21 @@ int disco_kp_cost(disco_kp *kp, int32_t nkp, const int32_t *kp_vox, int32_t R, f
 /* Regularised correspondences (Sec. II-C3): minimum spanning tree over all keypoint pairs
    with edge cost w_kq = |x_k - x_q| + |I_k - I_q| / sigma_I (Boruvka rounds: the cheapest
    edge of every keypoint found on the device, components merged on the host, edges
-   ordered by (w, lower index, higher index); rooted at keypoint 0), then two-pass min-sum
-   belief propagation on
-   the tree with the data cost `cost` (as written by disco_kp_cost) and the regulariser of
-   eq. 3, alpha_kp |d_k - d_q|^2 / w_kq (|.| in mm), each message a min-convolution done as
-   three exact 1-D minimisations (x, y, z), one tree level per launch.  x_mm (HOST
+   ordered by (w, lower index, higher index); returned rooted at keypoint 0), then
+   two-pass min-sum belief propagation on the tree with the data cost `cost` (as written by
+   disco_kp_cost) and the regulariser of eq. 3, alpha_kp |d_k - d_q|^2 / w_kq (|.| in mm),
+   each message a min-convolution done as three exact 1-D minimisations (x, y, z), one tree
+   level per launch pair.  The messages are scheduled from the tree's centre (the middle
+   of a longest path), which halves the levels; min-marginals do not depend on the root.
+   x_mm (HOST
    float32 [nkp][3]) and inten (HOST float32 [nkp], F at the keypoint) define w; the
    keypoints must be distinct (w > 0).  Writes
    the min-marginal energies to marg (device float32 [nkp][(2R+1)^3], nullable), the label
    of the smallest one per keypoint (lowest index on ties) to labels (device int32 [nkp])
-   and the tree to parent_out (HOST int32 [nkp], nullable; -1 at the root).  Allocates
-   4 x nkp x (2R+1)^3 floats of work memory for the call and waits for the stream before
-   returning. */
+   and the tree to parent_out (HOST int32 [nkp], nullable; -1 at the root).  Work memory
+   of 3 x nkp x (2R+1)^3 floats (4 x when marg is null) is kept in the handle, grown when a
+   call needs more and freed by disco_kp_destroy; the call waits for the stream before
+   returning, and calls on one handle must not overlap. */
 int disco_kp_regularise(disco_kp *kp, int32_t nkp, const float *x_mm, const float *inten, int32_t R,
                         const float *cost, double alpha_kp, double sigma_I, float *marg, int32_t *labels,
                         int32_t *parent_out, disco_stream stream);

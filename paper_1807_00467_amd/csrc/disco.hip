@@ -88,6 +88,8 @@ struct disco_kp {
   float4 *nF = nullptr, *nM = nullptr;
   float4 *patch = nullptr;  // [cap][64] patch vectors of the keypoints of the last cost call
   int patch_cap = 0;
+  float *bp = nullptr;  // belief-propagation work memory, grown as needed
+  size_t bp_cap = 0;    // floats
   bool images = false;
 };
 
@@ -1932,6 +1934,7 @@ void disco_kp_destroy(disco_kp *k) {
   if (k->nF) (void)hipFree(k->nF);
   if (k->nM) (void)hipFree(k->nM);
   if (k->patch) (void)hipFree(k->patch);
+  if (k->bp) (void)hipFree(k->bp);
   delete k;
 }
 
@@ -1979,6 +1982,47 @@ int disco_kp_cost(disco_kp *k, int32_t nkp, const int32_t *kp_vox, int32_t R, fl
   return DISCO_OK;
 }
 
+extern "C++" {
+// inward pass, deepest level first: h, then m = min-convolution of h (x, y, z); root:
+// M_root = h_root; outward pass: M = h + min-convolution of (M_parent - m)
+template <int NL>
+static void kp_messages(int nl, int maxd, const std::vector<int> &lstart, const KpNode *nodes, const float *cw,
+                        const float *cost, int64_t L, float sx, float sy, float sz, float *h, float *msg, float *t1,
+                        float *mg, hipStream_t s) {
+  for (int d = maxd; d >= 1; --d) {
+    const dim3 grid((unsigned)(lstart[d + 1] - lstart[d]), (unsigned)nl);
+    hipLaunchKernelGGL((k_kp_plane_xy<false, NL>), grid, dim3(256), 0, s, nl, lstart[d], nodes, cw, cost, msg, sx, sy,
+                       h, t1);
+    hipLaunchKernelGGL((k_kp_plane_z<false, NL>), grid, dim3(256), 0, s, nl, lstart[d], nodes, cw, sz, t1, h, msg);
+  }
+  hipLaunchKernelGGL(k_kp_root, dim3((unsigned)((L + 255) / 256)), dim3(256), 0, s, L, nodes, cost, msg, h, mg);
+  for (int d = 1; d <= maxd; ++d) {
+    const dim3 grid((unsigned)(lstart[d + 1] - lstart[d]), (unsigned)nl);
+    hipLaunchKernelGGL((k_kp_plane_xy<true, NL>), grid, dim3(256), 0, s, nl, lstart[d], nodes, cw, mg, msg, sx, sy,
+                       nullptr, t1);
+    hipLaunchKernelGGL((k_kp_plane_z<true, NL>), grid, dim3(256), 0, s, nl, lstart[d], nodes, cw, sz, t1, h, mg);
+  }
+}
+
+}  // extern "C++"
+
+// breadth-first rooting of a tree given as sorted adjacency lists
+static void bfs_tree(const std::vector<std::vector<int>> &adj, int root, std::vector<int> &parent, std::vector<int> &order) {
+  const int n = (int)adj.size();
+  parent.assign(n, -1);
+  order.clear();
+  order.push_back(root);
+  std::vector<char> seen(n, 0);
+  seen[root] = 1;
+  for (size_t h = 0; h < order.size(); ++h)
+    for (int b : adj[order[h]])
+      if (!seen[b]) {
+        seen[b] = 1;
+        parent[b] = order[h];
+        order.push_back(b);
+      }
+}
+
 int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float *inten, int32_t R,
                         const float *cost, double alpha_kp, double sigma_I, float *marg, int32_t *labels,
                         int32_t *parent_out, disco_stream stream) {
@@ -1991,7 +2035,7 @@ int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float
   const int n = nkp, nl = 2 * R + 1;
   const int64_t L = (int64_t)nl * nl * nl;
   // tree, levels (depth from the root), children lists, per-edge weights (host)
-  std::vector<int> parent(n), order(n);
+  std::vector<int> parent(n), order(n), tree_out;
   {
     // Boruvka rounds on the device (cheapest outgoing edge per keypoint), components merged
     // on the host; the tree is then rooted at keypoint 0 (breadth first, neighbours in
@@ -2045,95 +2089,71 @@ int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float
         --ncomp;
       }
     }
-    // root at keypoint 0
-    std::vector<char> seen(n, 0);
-    order.clear();
-    order.push_back(0);
-    seen[0] = 1;
-    parent.assign(n, -1);
-    for (size_t h = 0; h < order.size(); ++h) {
-      const int a = order[h];
-      std::sort(adj[a].begin(), adj[a].end());
-      for (int b : adj[a])
-        if (!seen[b]) {
-          seen[b] = 1;
-          parent[b] = a;
-          order.push_back(b);
-        }
+    // root at keypoint 0 (the tree returned), breadth first with neighbours in increasing
+    // order; the messages are scheduled from the tree's centre (below)
+    for (auto &a : adj) std::sort(a.begin(), a.end());
+    bfs_tree(adj, 0, parent, order);
+    tree_out = parent;
+    // centre: the middle of a longest path (ends: the farthest node from 0, then the
+    // farthest from that one); rooted there the tree has half the levels, and the
+    // min-marginals do not depend on the root
+    const int a = order.back();
+    bfs_tree(adj, a, parent, order);
+    std::vector<int> path;
+    for (int q = order.back(); q >= 0; q = parent[q]) path.push_back(q);
+    bfs_tree(adj, path[path.size() / 2], parent, order);
+  }
+  // breadth-first positions: levels and each node's children are contiguous ranges
+  std::vector<int> pos_of(n), lstart(1, 0), depth(n, 0);
+  for (int p = 0; p < n; ++p) pos_of[order[p]] = p;
+  std::vector<KpNode> nodes(n);
+  std::vector<float> cw(n, 0.0f);
+  for (int p = 0; p < n; ++p) {
+    const int q = order[p];
+    nodes[p] = KpNode{q, parent[q], 0, 0};
+    if (p > 0) {
+      depth[q] = depth[parent[q]] + 1;
+      if (depth[q] != depth[order[p - 1]]) lstart.push_back(p);
+      KpNode &pn = nodes[pos_of[parent[q]]];
+      if (pn.ccount++ == 0) pn.cfirst = p;
+      const int r = parent[q];
+      const double dx = (double)x_mm[3 * q] - x_mm[3 * r], dy = (double)x_mm[3 * q + 1] - x_mm[3 * r + 1],
+                   dz = (double)x_mm[3 * q + 2] - x_mm[3 * r + 2];
+      const double w = std::sqrt(dx * dx + dy * dy + dz * dz) + std::fabs((double)inten[q] - inten[r]) / sigma_I;
+      cw[p] = (float)(alpha_kp / w);
     }
   }
-  std::vector<int> depth(n, 0);
-  int maxd = 0;
-  for (size_t i = 1; i < order.size(); ++i) {
-    const int q = order[i];
-    depth[q] = depth[parent[q]] + 1;
-    maxd = std::max(maxd, depth[q]);
-  }
-  std::vector<int> lstart(maxd + 2, 0), lnodes(n), cstart(n + 1, 0), cidx(std::max(n - 1, 1));
-  for (int q = 0; q < n; ++q) ++lstart[depth[q] + 1];
-  for (int d = 0; d <= maxd; ++d) lstart[d + 1] += lstart[d];
-  {
-    std::vector<int> fill(lstart.begin(), lstart.end() - 1);
-    for (int q : order) lnodes[fill[depth[q]]++] = q;
-  }
-  for (int q = 0; q < n; ++q)
-    if (parent[q] >= 0) ++cstart[parent[q] + 1];
-  for (int q = 0; q < n; ++q) cstart[q + 1] += cstart[q];
-  {
-    std::vector<int> fill(cstart.begin(), cstart.end() - 1);
-    for (int q : order)
-      if (parent[q] >= 0) cidx[fill[parent[q]]++] = q;
-  }
-  std::vector<float> cw(n, 0.0f);
-  for (int q = 0; q < n; ++q) {
-    if (parent[q] < 0) continue;
-    const int p = parent[q];
-    const double dx = (double)x_mm[3 * q] - x_mm[3 * p], dy = (double)x_mm[3 * q + 1] - x_mm[3 * p + 1],
-                 dz = (double)x_mm[3 * q + 2] - x_mm[3 * p + 2];
-    const double w = std::sqrt(dx * dx + dy * dy + dz * dz) + std::fabs((double)inten[q] - inten[p]) / sigma_I;
-    cw[q] = (float)(alpha_kp / w);
-  }
+  lstart.push_back(n);
+  const int maxd = (int)lstart.size() - 2;
   MlBuffers B;
-  int *d_lnodes = nullptr, *d_cstart = nullptr, *d_cidx = nullptr, *d_parent = nullptr;
-  float *d_cw = nullptr, *h = nullptr, *msg = nullptr, *t1 = nullptr, *t2 = nullptr, *mg = marg;
-  if (!B.alloc(&d_lnodes, n) || !B.alloc(&d_cstart, n + 1) || !B.alloc(&d_cidx, cidx.size()) ||
-      !B.alloc(&d_parent, n) || !B.alloc(&d_cw, n) || !B.alloc(&h, (size_t)n * L) || !B.alloc(&msg, (size_t)n * L) ||
-      !B.alloc(&t1, (size_t)n * L) || !B.alloc(&t2, (size_t)n * L) || (!mg && !B.alloc(&mg, (size_t)n * L)))
-    return DISCO_ERR_NOMEM;
-  HIP_TRY(hipMemcpyAsync(d_lnodes, lnodes.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(d_cstart, cstart.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(d_cidx, cidx.data(), sizeof(int) * cidx.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(d_parent, parent.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  KpNode *d_nodes = nullptr;
+  float *d_cw = nullptr;
+  if (!B.alloc(&d_nodes, n) || !B.alloc(&d_cw, n)) return DISCO_ERR_NOMEM;
+  // h, m and a temporary per node (and the min-marginals when marg is null), kept in the
+  // handle; the previous call on the handle has finished (each call waits for its stream)
+  const size_t need = (size_t)(marg ? 3 : 4) * n * L;
+  if (need > k->bp_cap) {
+    if (k->bp) (void)hipFree(k->bp);
+    k->bp = nullptr;
+    k->bp_cap = 0;
+    if (hipMalloc(reinterpret_cast<void **>(&k->bp), sizeof(float) * need) != hipSuccess) {
+      k->bp = nullptr;
+      return DISCO_ERR_NOMEM;
+    }
+    k->bp_cap = need;
+  }
+  float *h = k->bp, *msg = h + (size_t)n * L, *t1 = msg + (size_t)n * L, *mg = marg ? marg : t1 + (size_t)n * L;
+  HIP_TRY(hipMemcpyAsync(d_nodes, nodes.data(), sizeof(KpNode) * n, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(d_cw, cw.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));
   const float sx = (float)(2.0 * k->h[0]), sy = (float)(2.0 * k->h[1]), sz = (float)(2.0 * k->h[2]);
-  auto grid_of = [&](int cnt) { return dim3((unsigned)(((int64_t)cnt * L + 255) / 256)); };
-  const int64_t nl2 = (int64_t)nl * nl;
-  auto lines_of = [&](int cnt) { return dim3((unsigned)(((int64_t)cnt * nl2 + 255) / 256)); };
-  // inward pass, deepest level first: h_k, then m_k = min-convolution of h_k (x, y, z)
-  for (int d = maxd; d >= 0; --d) {
-    const int cnt = lstart[d + 1] - lstart[d];
-    const int *nodes = d_lnodes + lstart[d];
-    hipLaunchKernelGGL(k_kp_gather_h, grid_of(cnt), dim3(256), 0, s, cnt, nodes, L, cost, msg, d_cstart, d_cidx, h);
-    if (d == 0) break;
-    hipLaunchKernelGGL(k_kp_line_axis<0>, lines_of(cnt), dim3(256), 0, s, cnt, nodes, nl, h, d_cw, sx, nullptr, t1);
-    hipLaunchKernelGGL(k_kp_line_axis<1>, lines_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t1, d_cw, sy, nullptr, t2);
-    hipLaunchKernelGGL(k_kp_line_axis<2>, lines_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t2, d_cw, sz, nullptr, msg);
-  }
-  // outward pass: M_root = h_root; M_k = h_k + min-convolution of (M_parent - m_k)
-  HIP_TRY(hipMemcpyAsync(mg + (int64_t)order[0] * L, h + (int64_t)order[0] * L, sizeof(float) * L,
-                         hipMemcpyDeviceToDevice, s));
-  for (int d = 1; d <= maxd; ++d) {
-    const int cnt = lstart[d + 1] - lstart[d];
-    const int *nodes = d_lnodes + lstart[d];
-    hipLaunchKernelGGL(k_kp_outward_in, grid_of(cnt), dim3(256), 0, s, cnt, nodes, L, mg, msg, d_parent, t1);
-    hipLaunchKernelGGL(k_kp_line_axis<0>, lines_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t1, d_cw, sx, nullptr, t2);
-    hipLaunchKernelGGL(k_kp_line_axis<1>, lines_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t2, d_cw, sy, nullptr, t1);
-    hipLaunchKernelGGL(k_kp_line_axis<2>, lines_of(cnt), dim3(256), 0, s, cnt, nodes, nl, t1, d_cw, sz, h, mg);
-  }
+  if (nl == kKpNl)
+    kp_messages<kKpNl>(nl, maxd, lstart, d_nodes, d_cw, cost, L, sx, sy, sz, h, msg, t1, mg, s);
+  else
+    kp_messages<0>(nl, maxd, lstart, d_nodes, d_cw, cost, L, sx, sy, sz, h, msg, t1, mg, s);
   hipLaunchKernelGGL(k_kp_argmin, dim3((unsigned)n), dim3(256), 0, s, L, mg, labels);
   HIP_TRY(hipGetLastError());
   if (parent_out)
-    for (int q = 0; q < n; ++q) parent_out[q] = parent[q];
+    for (int q = 0; q < n; ++q) parent_out[q] = tree_out[q];
   // the work buffers are freed on return: wait for the kernels that use them
   HIP_TRY(hipStreamSynchronize(s));
   return DISCO_OK;

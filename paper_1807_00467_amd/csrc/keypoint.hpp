@@ -237,76 +237,176 @@ __global__ __launch_bounds__(256) void k_kp_boruvka(int n, const float *__restri
 }
 
 // ---- belief propagation on the tree, one tree level per launch ---------------------
-// nodes[] lists the nodes of the level
+// The work buffers (h, inward messages m, temporaries) are indexed by breadth-first
+// position from the root, so a level is a contiguous range of positions and so are the
+// children of a node. Per position: KpNode {keypoint id, parent's keypoint id (-1 at the
+// root), first child's position, child count} and the pairwise weight cw of the edge to
+// the parent. The data cost D and the min-marginals M are indexed by keypoint id.
+struct KpNode {
+  int kid, pkid, cfirst, ccount;
+};
 
-// h_k = D_k + sum of the inward messages of k's children (CSR: cstart, cidx); thread per
-// (node, label)
-__global__ __launch_bounds__(256) void k_kp_gather_h(int nlev, const int *__restrict__ nodes, int64_t L,
-                                                     const float *__restrict__ D, const float *__restrict__ msg,
-                                                     const int *__restrict__ cstart, const int *__restrict__ cidx,
-                                                     float *__restrict__ h) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)nlev * L) return;
-  const int k = nodes[e / L];
-  const int64_t l = e % L;
-  float v = D[(int64_t)k * L + l];
-  for (int c = cstart[k]; c < cstart[k + 1]; ++c) v += msg[(int64_t)cidx[c] * L + l];
-  h[(int64_t)k * L + l] = v;
-}
+// The min-convolution of a label volume with the quadratic pairwise cost,
+//   out(d) = min_d' in(d') + cw |d - d'|^2   (d in mm, labels [iz][iy][ix]),
+// is separable: three passes of the 1-D form out(i) = min_j in(j) + p (i - j)^2 with
+// p = cw step_a^2, x and y on a label plane of fixed iz, z on a plane of fixed iy. A
+// workgroup takes one (node, plane) and holds the plane in LDS (row pitch 33 whatever the
+// label count), so even a tree level with few nodes spreads over many workgroups.
+// Expanding the square, out(i) = min_j (in(j) + p j^2 - 2 p i j) + p i^2: one fused
+// multiply-add and a minimum per candidate, each candidate shared by the five outputs of
+// a line that one thread computes (seven threads per line).
+constexpr int kKpNl = 2 * kKpRmax + 1;                // 33
+constexpr int kKpPer = (kKpNl * kKpNl + 255) / 256;  // plane entries per thread when loading: 5
+constexpr int kKpG = 7;                               // threads per line
+constexpr int kKpR = (kKpNl + kKpG - 1) / kKpG;       // outputs per thread: 5
 
-// src = M_parent - m_k (the outward message's input); thread per (node, label)
-__global__ __launch_bounds__(256) void k_kp_outward_in(int nlev, const int *__restrict__ nodes, int64_t L,
-                                                       const float *marg, const float *__restrict__ msg,
-                                                       const int *__restrict__ parent, float *__restrict__ out) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)nlev * L) return;
-  const int k = nodes[e / L];
-  const int64_t l = e % L;
-  out[(int64_t)k * L + l] = marg[(int64_t)parent[k] * L + l] - msg[(int64_t)k * L + l];
-}
-
-// One axis of the min-convolution, one line of labels per thread: out(i) = min_j in(j) +
-// pen_k (i - j)^2 along axis AX (labels [iz][iy][ix]), pen_k = cw[k] (step h_a)^2, the
-// line's inputs held in registers; with add != nullptr the result is added to add.
-constexpr int kKpNl = 2 * kKpRmax + 1;  // 33
-
-template <int AX>
-__global__ __launch_bounds__(256) void k_kp_line_axis(int nlev, const int *__restrict__ nodes, int nl,
-                                                      const float *__restrict__ in, const float *__restrict__ cw,
-                                                      float step_mm, const float *__restrict__ add,
-                                                      float *__restrict__ out) {
-  const int64_t nl2 = (int64_t)nl * nl, L = nl2 * nl;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)nlev * nl2) return;
-  const int k = nodes[e / nl2];
-  const int line = (int)(e % nl2);
-  // line start and stride: x lines (iz, iy), y lines (iz, ix), z lines (iy, ix)
-  int64_t base, stride;
-  if (AX == 0) {
-    base = (int64_t)line * nl;
-    stride = 1;
-  } else if (AX == 1) {
-    const int iz = line / nl, ix = line - iz * nl;
-    base = (int64_t)iz * nl2 + ix;
-    stride = nl;
-  } else {
-    base = line;
-    stride = nl2;
+// The 1-D pass over the nl lines of a plane in LDS, line l holding src[l * LS + j * ES]
+// (j < nl); thread (l, g) computes the outputs i = g + 7 r and hands them to
+// store(l, i, value). NL = 33 fixes nl at compile time (R = 16), NL = 0 takes it at run time.
+template <int LS, int ES, int NL, class Store>
+__device__ __forceinline__ void kp_mincon_lines(const float *src, int nl, float p, Store store) {
+  const int tid = threadIdx.x;
+  if (tid >= nl * kKpG) return;
+  const int l = tid / kKpG, g = tid - l * kKpG;
+  float s[kKpR], best[kKpR];
+#pragma unroll
+  for (int r = 0; r < kKpR; ++r) {
+    s[r] = -2.0f * p * (float)(g + kKpG * r);
+    best[r] = INFINITY;
   }
-  const int64_t o = (int64_t)k * L + base;
-  float v[kKpNl];
 #pragma unroll
-  for (int j = 0; j < kKpNl; ++j) v[j] = j < nl ? in[o + j * stride] : INFINITY;
-  const float pen = cw[k] * step_mm * step_mm;
-  for (int i = 0; i < nl; ++i) {
-    float best = INFINITY;
+  for (int j = 0; j < kKpNl; ++j) {
+    if (NL == kKpNl || j < nl) {
+      const float A = src[l * LS + j * ES] + p * (float)(j * j);
 #pragma unroll
-    for (int j = 0; j < kKpNl; ++j) {
-      const float dij = (float)(i - j);
-      best = fminf(best, v[j] + pen * dij * dij);
+      for (int r = 0; r < kKpR; ++r) best[r] = fminf(best[r], fmaf(s[r], (float)j, A));
     }
-    out[o + i * stride] = add ? add[o + i * stride] + best : best;
   }
+#pragma unroll
+  for (int r = 0; r < kKpR; ++r) {
+    const int i = g + kKpG * r;
+    if (i < nl) store(l, i, r, best[r] + p * (float)(i * i));
+  }
+}
+
+// x and y passes on the plane iz = blockIdx.y of the node at position base + blockIdx.x.
+// The plane's input is, inward (OUT = false), h = D + the inward messages of the node's
+// children (h is also stored), outward (OUT = true), M_parent - m.
+template <bool OUT, int NL>
+__global__ __launch_bounds__(256) void k_kp_plane_xy(int nl_rt, int base, const KpNode *__restrict__ node,
+                                                     const float *__restrict__ cw, const float *src,
+                                                     const float *__restrict__ msg, float sx, float sy,
+                                                     float *__restrict__ h, float *__restrict__ out) {
+  __shared__ float a[kKpNl * kKpNl], b[kKpNl * kKpNl];
+  const int nl = NL ? NL : nl_rt;
+  const int pos = base + blockIdx.x;
+  const KpNode nd = node[pos];
+  const int nl2 = nl * nl;
+  const int64_t L = (int64_t)nl2 * nl, po = (int64_t)blockIdx.y * nl2;
+  float v[kKpPer];
+  if constexpr (OUT) {
+    const float *pp = src + (int64_t)nd.pkid * L + po, *m = msg + (int64_t)pos * L + po;
+#pragma unroll
+    for (int u = 0; u < kKpPer; ++u) {
+      const int t = threadIdx.x + 256 * u;
+      v[u] = t < nl2 ? pp[t] - m[t] : 0.0f;
+    }
+  } else {
+    const float *d = src + (int64_t)nd.kid * L + po;
+#pragma unroll
+    for (int u = 0; u < kKpPer; ++u) {
+      const int t = threadIdx.x + 256 * u;
+      v[u] = t < nl2 ? d[t] : 0.0f;
+    }
+    for (int c = 0; c < nd.ccount; ++c) {
+      const float *m = msg + (int64_t)(nd.cfirst + c) * L + po;
+#pragma unroll
+      for (int u = 0; u < kKpPer; ++u) {
+        const int t = threadIdx.x + 256 * u;
+        if (t < nl2) v[u] += m[t];
+      }
+    }
+    float *hp = h + (int64_t)pos * L + po;
+#pragma unroll
+    for (int u = 0; u < kKpPer; ++u) {
+      const int t = threadIdx.x + 256 * u;
+      if (t < nl2) hp[t] = v[u];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kKpPer; ++u) {
+    const int t = threadIdx.x + 256 * u;
+    if (t < nl2) {
+      const int iy = t / nl, ix = t - iy * nl;
+      a[iy * kKpNl + ix] = v[u];
+    }
+  }
+  __syncthreads();
+  const float w = cw[pos];
+  // x: line iy, outputs ix
+  kp_mincon_lines<kKpNl, 1, NL>(a, nl, w * sx * sx, [&](int iy, int ix, int, float val) { b[iy * kKpNl + ix] = val; });
+  __syncthreads();
+  // y: line ix, outputs iy
+  float *o = out + (int64_t)pos * L + po;
+  kp_mincon_lines<1, kKpNl, NL>(b, nl, w * sy * sy, [&](int ix, int iy, int, float val) { o[iy * nl + ix] = val; });
+}
+
+// z pass on the plane iy = blockIdx.y of the node at position base + blockIdx.x, input
+// in[position]. Inward (OUT = false) the result is the node's message m[position];
+// outward (OUT = true) M[keypoint id] = h[position] + the result.
+template <bool OUT, int NL>
+__global__ __launch_bounds__(256) void k_kp_plane_z(int nl_rt, int base, const KpNode *__restrict__ node,
+                                                    const float *__restrict__ cw, float sz, const float *__restrict__ in,
+                                                    const float *__restrict__ h, float *__restrict__ out) {
+  __shared__ float a[kKpNl * kKpNl];  // a[iz][ix] = in(iz, iy, ix)
+  const int nl = NL ? NL : nl_rt;
+  const int pos = base + blockIdx.x;
+  const int nl2 = nl * nl;
+  const int64_t L = (int64_t)nl2 * nl, po = (int64_t)pos * L + (int64_t)blockIdx.y * nl;
+  float v[kKpPer];
+#pragma unroll
+  for (int u = 0; u < kKpPer; ++u) {
+    const int t = threadIdx.x + 256 * u;
+    const int iz = t / nl, ix = t - iz * nl;
+    v[u] = t < nl2 ? in[po + (int64_t)iz * nl2 + ix] : 0.0f;
+  }
+  // outward: the h values this thread's outputs add to (line ix = l, outputs iz = g + 7 r)
+  float hv[kKpR];
+  {
+    const int tid = threadIdx.x, l = tid / kKpG, g = tid - l * kKpG;
+#pragma unroll
+    for (int r = 0; r < kKpR; ++r) {
+      const int iz = g + kKpG * r;
+      hv[r] = OUT && tid < nl * kKpG && iz < nl ? h[po + (int64_t)iz * nl2 + l] : 0.0f;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kKpPer; ++u) {
+    const int t = threadIdx.x + 256 * u;
+    if (t < nl2) {
+      const int iz = t / nl, ix = t - iz * nl;
+      a[iz * kKpNl + ix] = v[u];
+    }
+  }
+  __syncthreads();
+  const int64_t oo = OUT ? (int64_t)node[pos].kid * L + (int64_t)blockIdx.y * nl : po;
+  // z: line ix, outputs iz
+  kp_mincon_lines<1, kKpNl, NL>(a, nl, cw[pos] * sz * sz, [&](int ix, int iz, int r, float val) {
+    out[oo + (int64_t)iz * nl2 + ix] = OUT ? hv[r] + val : val;
+  });
+}
+
+// root (position 0): h = D + its children's inward messages, and M = h; thread per label
+__global__ __launch_bounds__(256) void k_kp_root(int64_t L, const KpNode *__restrict__ node, const float *__restrict__ D,
+                                                 const float *__restrict__ msg, float *__restrict__ h,
+                                                 float *__restrict__ M) {
+  const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (l >= L) return;
+  const KpNode nd = node[0];
+  float v = D[(int64_t)nd.kid * L + l];
+  for (int c = 0; c < nd.ccount; ++c) v += msg[(int64_t)(nd.cfirst + c) * L + l];
+  h[l] = v;
+  M[(int64_t)nd.kid * L + l] = v;
 }
 
 // label of the smallest min-marginal per keypoint (lowest index on ties): one workgroup

@@ -122,7 +122,8 @@ def test_kp_argument_errors(disco):
 @pytest.mark.parametrize("n", [3500, 4200])
 def test_kp_tree_and_messages_at_scale(disco, n):
     """3500 and 4200 keypoints: the MST (Boruvka rounds on the device) equals the oracle's
-    (Prim's algorithm), and the min-marginals agree, with 27 labels (R = 1)."""
+    (Kruskal's algorithm under the same edge order), and the min-marginals agree, with 27
+    labels (R = 1)."""
     say(f"[kp] MST + BP with {n} keypoints")
     d = synth.small_pair(shape=(64, 56, 44), spacing=(1.0, 1.0, 1.0), seed=44, n_tubes=10, n_kp=8, field_max=4.0)
     r = np.random.default_rng(n)
@@ -143,3 +144,40 @@ def test_kp_tree_and_messages_at_scale(disco, n):
     err = float(np.max(np.abs(gm - om) / np.max(np.abs(om), axis=1, keepdims=True)))
     say(f"  tree depth {tree_depth(parent, order)}; marginals max rel error {err:.2e}")
     assert err < 1e-5
+
+
+def test_kp_regularise_reuses_work_memory(disco):
+    """Calls on one handle of growing size, with and without the min-marginals output (the
+    handle's work memory is grown, then reused): labels and marginals equal those of a
+    fresh handle bitwise, and the labels match the oracle's."""
+    say("[kp] work memory reuse")
+    d = synth.small_pair(shape=(64, 56, 44), spacing=(1.0, 1.0, 1.0), seed=45, n_tubes=10, n_kp=8, field_max=4.0)
+    st = stage(disco, d)
+    r = np.random.default_rng(9)
+    nx, ny, nz = d["shape"]
+    runs = []
+    for n, marginals in ((30, True), (90, False), (60, True)):
+        flat = r.choice(nx * ny * nz, n, replace=False)
+        kps = np.stack([flat % nx, (flat // nx) % ny, flat // (nx * ny)], 1).astype(np.int32)
+        cost = st.cost(torch.from_numpy(kps).to(DEV), 4)
+        x = (kps + 0.5).astype(np.float32)
+        inten = d["R"][kps[:, 2], kps[:, 1], kps[:, 0]]
+        marg, lab, par = st.regularise(x, inten, cost, 4, 1.0 / 45.0, 150.0, marginals=marginals)
+        fresh = stage(disco, d)
+        marg2, lab2, _ = fresh.regularise(x, inten, cost, 4, 1.0 / 45.0, 150.0, marginals=True)
+        torch.cuda.synchronize()
+        assert torch.equal(lab, lab2), n
+        if marginals:
+            assert torch.equal(marg, marg2), n
+        parent, order = oracle.kp_mst(x, inten)
+        om, _ = oracle.kp_belief_propagation(cost.cpu().numpy().astype(np.float64), parent, order, x, inten,
+                                             1.0 / 45.0, R=4, step=2)
+        ol = oracle.kp_argmin(om)
+        scale = np.max(np.abs(om), axis=1)
+        srt = np.sort(om, axis=1)
+        gl = lab.cpu().numpy()
+        for k in range(n):
+            if srt[k, 1] - srt[k, 0] > 2e-5 * scale[k]:
+                assert gl[k] == ol[k], (n, k)
+        runs.append(n)
+    say(f"  sizes {runs} ok")
