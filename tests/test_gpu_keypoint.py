@@ -181,3 +181,29 @@ def test_kp_regularise_reuses_work_memory(disco):
                 assert gl[k] == ol[k], (n, k)
         runs.append(n)
     say(f"  sizes {runs} ok")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_kp_regularise_tiny_trees(disco, n):
+    """Degenerate trees: one keypoint (its min-marginals are its data cost, bitwise), two
+    and three keypoints (against the oracle)."""
+    say(f"[kp] tiny tree n={n}")
+    d = synth.small_pair(shape=(40, 36, 32), spacing=(1.0, 1.0, 1.0), seed=46, n_tubes=6, n_kp=4, field_max=4.0)
+    st = stage(disco, d)
+    kps = np.array([[12, 10, 8], [20, 18, 15], [27, 25, 21]], np.int32)[:n]
+    cost = st.cost(torch.from_numpy(kps).to(DEV), 16)
+    x = (kps + 0.5).astype(np.float32)
+    inten = d["R"][kps[:, 2], kps[:, 1], kps[:, 0]]
+    marg, lab, par = st.regularise(x, inten, cost, 16, 1.0 / 45.0, 150.0)
+    torch.cuda.synchronize()
+    parent, order = oracle.kp_mst(x, inten)
+    np.testing.assert_array_equal(par, parent)
+    if n == 1:
+        assert torch.equal(marg, cost)
+        assert int(lab[0]) == int(torch.argmin(cost[0]))
+        return
+    om, _ = oracle.kp_belief_propagation(cost.cpu().numpy().astype(np.float64), parent, order, x, inten, 1.0 / 45.0,
+                                         R=16, step=2)
+    err = float(np.max(np.abs(marg.cpu().numpy() - om) / np.max(np.abs(om), axis=1, keepdims=True)))
+    say(f"  marginals max rel error {err:.2e}")
+    assert err < 1e-5
