@@ -119,7 +119,7 @@ __global__ __launch_bounds__(256) void k_b_curv_Lp(const PairDesc<ST> *D, const 
     const int pr = find_pair(start, npairs, item);
     const PairDesc<ST> &P = D[pr];
     const int64_t nbu = (P.n3 + 256 * kUpdK - 1) / (256 * kUpdK);
-    curv_Lp_body(P.g, it, P.sc, P.tol, P.blk_upd, nbu, P.z, P.p[(it - 1) & 1], P.p[it & 1], P.Lw,
+    curv_Lp_body<1>(P.g, it, P.sc, P.tol, P.blk_upd, nbu, P.z, P.p[(it - 1) & 1], P.p[it & 1], P.Lw,
                  grid_blk(item - start[pr], node_gx(P.g), node_gy(P.g)));
     __syncthreads();
   }

@@ -133,7 +133,7 @@ inline dim3 node_grid(const Geo &g) { return dim3((g.px + 63) / 64, (g.py + 3) /
 inline int64_t node_blocks(const Geo &g) { return (int64_t)((g.px + 63) / 64) * ((g.py + 3) / 4) * g.pz; }
 // workgroups of the CG vector update, and the grid of the fused p update + L p pass
 inline int64_t upd_blocks(const Geo &g) { return (3 * g.nnodes + 256 * kUpdK - 1) / (256 * kUpdK); }
-inline dim3 lp_grid(const Geo &g) { return node_grid(g); }
+inline dim3 lp_grid(const Geo &g) { return dim3((g.px + 63) / 64, (g.py + 3) / 4, (g.pz + kLpZ - 1) / kLpZ); }
 // 3-D grid over the voxels (rows of 256)
 inline dim3 vox_grid(const Geo &g) { return dim3((g.nx + 255) / 256, g.ny, g.nz); }
 

@@ -118,41 +118,38 @@ __global__ __launch_bounds__(256) void k_pcg_update(int64_t n, double *sc, int i
 // the previous update; beta = <r,z>_new / <r,z>_old; stop when the tolerance is met.
 // Otherwise p_new = z + beta p_old (written to p_new) and L p_new (the curvature
 // operator of the next product) in the same pass: L at node m needs p_new at the
-// 6 neighbours, which are formed from z and p_old there.  One node plane per workgroup;
-// all loads are requested before the first wait.
+// 6 neighbours, which are formed from z and p_old there.  A workgroup takes a 64 x 4 node
+// tile of NZ consecutive planes, walking up in z with the -z, centre and +z values rolled
+// in registers, so that each plane is read once per tile; the first plane's loads are
+// requested before the first wait.  Stencil neighbours outside the interior (chi = 0)
+// carry weight zero.
+template <int NZ>
 __device__ __forceinline__ void curv_Lp_body(const Geo &g, int it, double *sc, double tol, const double *upd_blocks,
                                              int64_t upd_nb, const float *__restrict__ z,
                                              const float *__restrict__ p_old, float *__restrict__ p_new,
                                              float *__restrict__ Lw, const Blk &B) {
-  const int px = B.x * 64 + (threadIdx.x & 63), py = B.y * 4 + (threadIdx.x >> 6), pz = B.z;
-  const bool in = px < g.px && py < g.py;
-  const int pp[3] = {in ? px : 0, in ? py : 0, pz};
-  const int nn[3] = {g.px, g.py, g.pz};
-  const int64_t st[3] = {1, g.px, (int64_t)g.px * g.py};
-  const int64_t nidx = ((int64_t)pp[2] * g.py + pp[1]) * g.px + pp[0];
-  // stencil neighbours that L uses (chi), else the centre (weight zero)
-  int64_t om[3], op[3];
-  float wgt[3];
+  const int px = B.x * 64 + (threadIdx.x & 63), py = B.y * 4 + (threadIdx.x >> 6), z0 = B.z * NZ;
+  const bool in = px < g.px && py < g.py && z0 < g.pz;
+  const int qx = in ? px : 0, qy = in ? py : 0, qz = in ? z0 : 0;
+  const int64_t sy = g.px, sz = (int64_t)g.px * g.py;
+  const bool ux = chi(qx, g.px) != 0, uy = chi(qy, g.py) != 0;
+  const int64_t oxm = ux ? -1 : 0, oxp = ux ? 1 : 0, oym = uy ? -sy : 0, oyp = uy ? sy : 0;
+  const float wx = ux ? 1.0f : 0.0f, wy = uy ? 1.0f : 0.0f;
+  // [component][centre, -x, +x, -y, +y, -z, +z] of z and p_old at plane qz; -z and +z
+  // clamped to the volume
+  float zc[3][7], pc[3][7];
+  int64_t nidx = ((int64_t)qz * g.py + qy) * g.px + qx;
+  {
+    const int64_t ozm = qz > 0 ? -sz : 0, ozp = qz < g.pz - 1 ? sz : 0;
+    const int64_t offs[7] = {0, oxm, oxp, oym, oyp, ozm, ozp};
 #pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    const bool use = chi(pp[ax], nn[ax]);
-    om[ax] = use ? -st[ax] : 0;
-    op[ax] = use ? st[ax] : 0;
-    wgt[ax] = use ? 1.0f : 0.0f;
-  }
-  float zc[3][7], pc[3][7];  // [component][centre, -x, +x, -y, +y, -z, +z]
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int64_t off = c * g.nnodes + nidx;
-    zc[c][0] = z[off];
-    pc[c][0] = p_old[off];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      zc[c][1 + 2 * ax] = z[off + om[ax]];
-      pc[c][1 + 2 * ax] = p_old[off + om[ax]];
-      zc[c][2 + 2 * ax] = z[off + op[ax]];
-      pc[c][2 + 2 * ax] = p_old[off + op[ax]];
-    }
+      for (int m = 0; m < 7; ++m) {
+        const int64_t off = c * g.nnodes + nidx + offs[m];
+        zc[c][m] = z[off];
+        pc[c][m] = p_old[off];
+      }
   }
   const double rz_prev = sc[SC_RZ + ((it - 1) & 1)];
   double sums[2], stop;
@@ -171,23 +168,63 @@ __device__ __forceinline__ void curv_Lp_body(const Geo &g, int it, double *sc, d
   const float b = (float)beta;
   const float ih2[3] = {g.iHx * g.iHx, g.iHy * g.iHy, g.iHz * g.iHz};
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    float w[7];
+  for (int k = 0; k < NZ; ++k) {
+    const int pz = z0 + k;
+    if (pz >= g.pz) break;
+    // the next plane's x, y neighbours and +z centre are requested before this plane's
+    // arithmetic; its -z and centre values are this plane's centre and +z
+    const bool more = k + 1 < NZ && pz + 1 < g.pz;
+    float zn[3][5], pn[3][5];
+    if (more) {
+      const int64_t ozp = pz + 1 < g.pz - 1 ? sz : 0;
+      const int64_t offs[5] = {oxm, oxp, oym, oyp, ozp};
 #pragma unroll
-    for (int m = 0; m < 7; ++m) w[m] = zc[c][m] + b * pc[c][m];
-    float acc = 0.0f;
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) acc += wgt[ax] * (w[1 + 2 * ax] - 2.0f * w[0] + w[2 + 2 * ax]) * ih2[ax];
-    const int64_t off = c * g.nnodes + nidx;
-    p_new[off] = w[0];
-    Lw[off] = acc;
+        for (int m = 0; m < 5; ++m) {
+          const int64_t off = c * g.nnodes + nidx + sz + offs[m];
+          zn[c][m] = z[off];
+          pn[c][m] = p_old[off];
+        }
+    }
+    const float wz = chi(pz, g.pz) ? 1.0f : 0.0f;
+    const float wgt[3] = {wx, wy, wz};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float w[7];
+#pragma unroll
+      for (int m = 0; m < 7; ++m) w[m] = zc[c][m] + b * pc[c][m];
+      float acc = 0.0f;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) acc += wgt[ax] * (w[1 + 2 * ax] - 2.0f * w[0] + w[2 + 2 * ax]) * ih2[ax];
+      const int64_t off = c * g.nnodes + nidx;
+      p_new[off] = w[0];
+      Lw[off] = acc;
+    }
+    if (more) {
+      nidx += sz;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        zc[c][5] = zc[c][0];
+        pc[c][5] = pc[c][0];
+        zc[c][0] = zc[c][6];
+        pc[c][0] = pc[c][6];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+          zc[c][m < 4 ? 1 + m : 6] = zn[c][m];
+          pc[c][m < 4 ? 1 + m : 6] = pn[c][m];
+        }
+      }
+    }
   }
 }
+
+constexpr int kLpZ = 4;  // node planes per workgroup of k_curv_Lp
 __global__ __launch_bounds__(256) void k_curv_Lp(Geo g, int it, double *sc, double tol, const double *upd_blocks,
                                                  int64_t upd_nb, const float *__restrict__ z,
                                                  const float *__restrict__ p_old, float *__restrict__ p_new,
                                                  float *__restrict__ Lw) {
-  curv_Lp_body(g, it, sc, tol, upd_blocks, upd_nb, z, p_old, p_new, Lw, hw_blk());
+  curv_Lp_body<kLpZ>(g, it, sc, tol, upd_blocks, upd_nb, z, p_old, p_new, Lw, hw_blk());
 }
 
 // per-block <a, b>
