@@ -1034,3 +1034,35 @@ def test_kp_mst_ties_follow_the_edge_order():
     expect = {(0, 1), (1, 2), (2, 3), (0, 4), (1, 5), (2, 6), (3, 7), (4, 8), (5, 9), (6, 10), (7, 11)}
     assert edges == expect
     assert list(order[:3]) == [0, 1, 4]
+
+
+def test_kp_min_marginals_do_not_depend_on_the_root():
+    """The two-pass schedule gives exact min-marginals, so re-rooting the tree (here at
+    several keypoints, the device schedules from the tree's centre) leaves them unchanged
+    up to rounding."""
+    r = rng(37)
+    n, R, step = 30, 2, 2
+    L = (2 * R + 1) ** 3
+    x = r.uniform(0, 40, (n, 3))
+    inten = r.normal(-800, 80, n)
+    D = r.uniform(0, 1, (n, L))
+    parent, order = oracle.kp_mst(x, inten)
+    ref, _ = oracle.kp_belief_propagation(D, parent, order, x, inten, 0.5, R=R, step=step)
+    adj = [[] for _ in range(n)]
+    for k in range(n):
+        if parent[k] >= 0:
+            adj[k].append(int(parent[k]))
+            adj[int(parent[k])].append(k)
+    for root in (7, 13, n - 1):
+        par = np.full(n, -1)
+        seen = np.zeros(n, bool)
+        seen[root] = True
+        ordr = [root]
+        for a in ordr:
+            for b in sorted(adj[a]):
+                if not seen[b]:
+                    seen[b] = True
+                    par[b] = a
+                    ordr.append(b)
+        marg, _ = oracle.kp_belief_propagation(D, par, ordr, x, inten, 0.5, R=R, step=step)
+        np.testing.assert_allclose(marg, ref, rtol=1e-12, atol=1e-12)
