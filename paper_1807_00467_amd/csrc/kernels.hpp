@@ -1697,21 +1697,35 @@ __global__ __launch_bounds__(256) void k_curv_L(Geo g, const float *__restrict__
   curv_L_body(g, a, b, Lw, blocks, stop, hw_blk());
 }
 
-// central-difference image gradient with replicated border, stored as ST
+// central-difference image gradient with replicated border, stored as ST.  A workgroup
+// takes a 64 x 4 voxel tile of kImgZ consecutive planes and walks up in z with the -z and
+// +z values rolled in registers, so that each plane of the tile is read from memory once;
+// the x and y neighbours lie in the plane just read (cache hits).
+constexpr int kImgZ = 16;
 template <class ST>
-__global__ __launch_bounds__(256) void k_imgrad(Geo g, const float *img, typename ST::elem *out, float sq) {
-  const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
-  if (i >= g.nx) return;
-  const int64_t v = ((int64_t)k * g.ny + j) * g.nx + i;
-  const int64_t sx = 1, sy = g.nx, sz = (int64_t)g.nx * g.ny;
-  const int64_t xm = i > 0 ? v - sx : v, xp = i < g.nx - 1 ? v + sx : v;
-  const int64_t ym = j > 0 ? v - sy : v, yp = j < g.ny - 1 ? v + sy : v;
-  const int64_t zm = k > 0 ? v - sz : v, zp = k < g.nz - 1 ? v + sz : v;
-  float o[3];
-  o[0] = (img[xp] - img[xm]) * (0.5f * g.ihx);
-  o[1] = (img[yp] - img[ym]) * (0.5f * g.ihy);
-  o[2] = (img[zp] - img[zm]) * (0.5f * g.ihz);
-  ST::store(out, v, sq, o);
+__global__ __launch_bounds__(256) void k_imgrad(Geo g, const float *__restrict__ img, typename ST::elem *__restrict__ out,
+                                                float sq) {
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63), j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int z0 = blockIdx.z * kImgZ, z1 = min(z0 + kImgZ, g.nz);
+  if (i >= g.nx || j >= g.ny || z0 >= g.nz) return;
+  const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny, col = (int64_t)j * g.nx + i;
+  const int64_t dxm = i > 0 ? -1 : 0, dxp = i < g.nx - 1 ? 1 : 0;
+  const int64_t dym = j > 0 ? -sy : 0, dyp = j < g.ny - 1 ? sy : 0;
+  const float cx = 0.5f * g.ihx, cy = 0.5f * g.ihy, cz = 0.5f * g.ihz;
+  float zm = img[(int64_t)(z0 > 0 ? z0 - 1 : 0) * sz + col];  // plane k - 1 (replicated at 0)
+  float zc = img[(int64_t)z0 * sz + col];                     // plane k
+#pragma unroll 4
+  for (int k = z0; k < z1; ++k) {
+    const int64_t v = (int64_t)k * sz + col;
+    const float zp = k < g.nz - 1 ? img[v + sz] : zc;  // plane k + 1 (replicated at the top)
+    float o[3];
+    o[0] = (img[v + dxp] - img[v + dxm]) * cx;
+    o[1] = (img[v + dyp] - img[v + dym]) * cy;
+    o[2] = (zp - zm) * cz;
+    ST::store(out, v, sq, o);
+    zm = zc;
+    zc = zp;
+  }
 }
 
 // max |grad| of a volume in blocks (for the FP16 scale)
