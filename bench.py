@@ -98,6 +98,9 @@ def main():
     ap.add_argument("--config", default="cfg1")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ls", default="host", choices=["host", "device"],
+                    help="Armijo line search decided on the host (stops at the accepted trial) or on "
+                         "the device (all ls_max trials enqueued, later ones exit at once)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (HBM counter calibration)")
     ap.add_argument("--print-source-hash", action="store_true")
@@ -166,7 +169,8 @@ def main():
     D0 = ctx.ngf_eval(zero, 10.0).item()
     K0 = ctx.keypoint_penalty(1.0, zero, grad=False, diag=False)["K"].item()
     params = disco.Params(eta=10.0, alpha=1.0, gamma=0.1, delta=D0 / K0 if K0 > 0 else 0.0,
-                          pcg_iters=PCG_ITERS, pcg_tol=0.0, ls_max=10)
+                          pcg_iters=PCG_ITERS, pcg_tol=0.0, ls_max=10,
+                          flags=disco.FLAG_LS_DEVICE if args.ls == "device" else 0)
     log(f"[bench] delta = {params.delta:.4g}")
     if args.boundary:
         ctx.set_masks(torch.from_numpy(d["mask_R"]).to(dev), torch.from_numpy(d["mask_T"]).to(dev))
@@ -234,7 +238,7 @@ def main():
                         f"(linearise + {PCG_ITERS} PCG GN products + Armijo)"
                         + ("; with the lung-boundary term" if args.boundary else ""),
             "eta": params.eta, "alpha": params.alpha, "gamma": params.gamma, "delta": params.delta,
-            "beta": params.beta, "storage": args.storage,
+            "beta": params.beta, "storage": args.storage, "line_search": args.ls,
         },
         "gvoxel_per_s_hv_kernel": nvox / hv_s / 1e9,
         "hv_kernel_us": hv_s * 1e6,
