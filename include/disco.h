@@ -214,8 +214,10 @@ int gn_hessvec(disco_ctx *ctx, const disco_params *p, const float *v, float *Hv,
    p^T H p <= 0); Armijo backtracking t = 1, 1/2, ... (at most ls_max trials) accepting
    the first t with J(u + t p) finite and <= J(u) + c1 t g^T p.  report_dev (nullable)
    receives DISCO_REP_SIZE doubles; status_dev (nullable) the DISCO_STATUS_* bits.
-   Without DISCO_FLAG_LS_DEVICE the host waits for the stream once per line-search
-   trial; with it the call never synchronises and can be graph captured. */
+   Without DISCO_FLAG_LS_DEVICE the host waits, once per line-search trial, for the
+   acceptance flag of the previous trial while the GPU runs the next one (one trial past
+   the accepted one is enqueued and does nothing); with it the call never synchronises and
+   can be graph captured. */
 int gn_pcg_step(disco_ctx *ctx, const disco_params *p, float *u_inout, double *report_dev, int32_t *status_dev,
                 disco_stream stream);
 

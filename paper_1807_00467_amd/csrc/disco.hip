@@ -71,6 +71,7 @@ struct disco_ctx {
   bool lb_pending = false;  // the last step started a pair in slot lb_next
   int *status = nullptr;
   double *host_sc = nullptr;  // pinned
+  hipEvent_t ls_ev[2] = {nullptr, nullptr};  // line search: trial flags copied to host_sc[0..1]
   // keypoints
   int32_t nkp = 0;
   float *kloc = nullptr, *ktgt = nullptr;
@@ -515,6 +516,8 @@ void disco_destroy(disco_ctx *c) {
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->host_sc) (void)hipHostFree(c->host_sc);
+  for (hipEvent_t e : c->ls_ev)
+    if (e) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -600,6 +603,11 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
     c->host_sc = nullptr;
     okm = false;
   }
+  for (hipEvent_t &e : c->ls_ev)
+    if (okm && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      okm = false;
+    }
   if (!okm) {
     disco_destroy(c);
     return DISCO_ERR_NOMEM;
@@ -1015,9 +1023,15 @@ static int line_search(disco_ctx *c, const disco_params *p, float *u, const Post
     launch_brick(c, b, s);
     launch_finish(POST_LS_BRICK, pa, acc, s, src_brick(c, sc + SC_TMP0), src_curv(c, sc + SC_TSRAW));
     if (!dev_ls) {
-      HIP_TRY(hipMemcpyAsync(c->host_sc, sc + SC_ACCEPT, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      if (c->host_sc[0] != 0.0) break;
+      // the acceptance flag of trial t is copied to the host and read once trial t + 1 is
+      // enqueued, so the GPU runs the next trial while the host waits; a trial enqueued
+      // after the accepted one does nothing (its kernels test the flag first)
+      HIP_TRY(hipMemcpyAsync(c->host_sc + (t & 1), sc + SC_ACCEPT, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipEventRecord(c->ls_ev[t & 1], s));
+      if (t > 0) {
+        HIP_TRY(hipEventSynchronize(c->ls_ev[(t - 1) & 1]));
+        if (c->host_sc[(t - 1) & 1] != 0.0) break;
+      }
     }
   }
   pre();
