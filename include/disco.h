@@ -340,8 +340,9 @@ int disco_kp_cost(disco_kp *kp, int32_t nkp, const int32_t *kp_vox, int32_t R, f
    the min-marginal energies to marg (device float32 [nkp][(2R+1)^3], nullable), the label
    of the smallest one per keypoint (lowest index on ties) to labels (device int32 [nkp])
    and the tree to parent_out (HOST int32 [nkp], nullable; -1 at the root).  Work memory
-   of 3 x nkp x (2R+1)^3 floats (4 x when marg is null) is kept in the handle, grown when a
-   call needs more and freed by disco_kp_destroy; the call waits for the stream before
+   of 3 x nkp x (2R+1)^3 floats (4 x when marg is null) and about 2 kB per 32 keypoints of
+   tree set-up buffers (pinned host and device) are kept in the handle, grown when a call
+   needs more and freed by disco_kp_destroy; the call waits for the stream before
    returning, and calls on one handle must not overlap. */
 int disco_kp_regularise(disco_kp *kp, int32_t nkp, const float *x_mm, const float *inten, int32_t R,
                         const float *cost, double alpha_kp, double sigma_I, float *marg, int32_t *labels,

@@ -91,6 +91,9 @@ struct disco_kp {
   int patch_cap = 0;
   float *bp = nullptr;  // belief-propagation work memory, grown as needed
   size_t bp_cap = 0;    // floats
+  char *th = nullptr;   // tree set-up buffers for up to tcap keypoints: pinned host staging
+  char *td = nullptr;   // and their device copies (see KpTreeBuf)
+  int tcap = 0;
   bool images = false;
 };
 
@@ -1951,6 +1954,8 @@ void disco_kp_destroy(disco_kp *k) {
   if (k->nM) (void)hipFree(k->nM);
   if (k->patch) (void)hipFree(k->patch);
   if (k->bp) (void)hipFree(k->bp);
+  if (k->th) (void)hipHostFree(k->th);
+  if (k->td) (void)hipFree(k->td);
   delete k;
 }
 
@@ -2022,6 +2027,32 @@ static void kp_messages(int nl, int maxd, const std::vector<int> &lstart, const 
 
 }  // extern "C++"
 
+// Tree set-up arrays of n keypoints carved from one block (host staging or device copy):
+// Boruvka round results w, j and components comp, keypoint positions x and intensities
+// i, node descriptors and edge weights of the message schedule.
+struct KpTreeBuf {
+  double *w;
+  KpNode *nodes;
+  float *x, *i, *cw;
+  int *comp, *j;
+};
+static size_t kp_tree_layout(int n, char *base, KpTreeBuf *b) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char *p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  b->w = reinterpret_cast<double *>(take(sizeof(double) * n));
+  b->nodes = reinterpret_cast<KpNode *>(take(sizeof(KpNode) * n));
+  b->x = reinterpret_cast<float *>(take(sizeof(float) * 3 * n));
+  b->i = reinterpret_cast<float *>(take(sizeof(float) * n));
+  b->cw = reinterpret_cast<float *>(take(sizeof(float) * n));
+  b->comp = reinterpret_cast<int *>(take(sizeof(int) * n));
+  b->j = reinterpret_cast<int *>(take(sizeof(int) * n));
+  return off;
+}
+
 // breadth-first rooting of a tree given as sorted adjacency lists
 static void bfs_tree(const std::vector<std::vector<int>> &adj, int root, std::vector<int> &parent, std::vector<int> &order) {
   const int n = (int)adj.size();
@@ -2052,35 +2083,53 @@ int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float
   const int64_t L = (int64_t)nl * nl * nl;
   // tree, levels (depth from the root), children lists, per-edge weights (host)
   std::vector<int> parent(n), order(n), tree_out;
+  // set-up buffers kept in the handle; the previous call on it has finished
+  if (n > k->tcap) {
+    if (k->th) (void)hipHostFree(k->th);
+    if (k->td) (void)hipFree(k->td);
+    k->th = k->td = nullptr;
+    k->tcap = 0;
+    KpTreeBuf sz;
+    const size_t bytes = kp_tree_layout(n, nullptr, &sz);
+    if (hipHostMalloc(reinterpret_cast<void **>(&k->th), bytes) != hipSuccess) {
+      k->th = nullptr;
+      return DISCO_ERR_NOMEM;
+    }
+    if (hipMalloc(reinterpret_cast<void **>(&k->td), bytes) != hipSuccess) {
+      k->td = nullptr;
+      return DISCO_ERR_NOMEM;
+    }
+    k->tcap = n;
+  }
+  KpTreeBuf H, D;
+  kp_tree_layout(n, k->th, &H);
+  kp_tree_layout(n, k->td, &D);
+  std::vector<std::vector<int>> adj(n);
   {
     // Boruvka rounds on the device (cheapest outgoing edge per keypoint), components merged
     // on the host; the tree is then rooted at keypoint 0 (breadth first, neighbours in
     // increasing order)
-    MlBuffers P;
-    float *dx = nullptr, *di = nullptr;
-    int *dcomp = nullptr, *dj = nullptr;
-    double *dw = nullptr;
-    if (!P.alloc(&dx, 3 * (size_t)n) || !P.alloc(&di, n) || !P.alloc(&dcomp, n) || !P.alloc(&dj, n) ||
-        !P.alloc(&dw, n))
-      return DISCO_ERR_NOMEM;
-    HIP_TRY(hipMemcpyAsync(dx, x_mm, sizeof(float) * 3 * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(di, inten, sizeof(float) * n, hipMemcpyHostToDevice, s));
-    std::vector<int> uf(n), comp(n), bj(n);
-    std::vector<double> bw(n);
+    std::vector<int> uf(n);
     std::iota(uf.begin(), uf.end(), 0);
     auto find = [&](int a) {
       while (uf[a] != a) a = uf[a] = uf[uf[a]];
       return a;
     };
-    std::vector<std::vector<int>> adj(n);
+    std::memcpy(H.x, x_mm, sizeof(float) * 3 * n);
+    std::memcpy(H.i, inten, sizeof(float) * n);
+    HIP_TRY(hipMemcpyAsync(D.x, H.x, sizeof(float) * 3 * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(D.i, H.i, sizeof(float) * n, hipMemcpyHostToDevice, s));
+    const double *bw = H.w;
+    const int *bj = H.j;
+    int *comp = H.comp;
     int ncomp = n;
     while (ncomp > 1) {
       for (int q = 0; q < n; ++q) comp[q] = find(q);
-      HIP_TRY(hipMemcpyAsync(dcomp, comp.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_kp_boruvka, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, dx, di, sigma_I, dcomp, dw,
-                         dj);
-      HIP_TRY(hipMemcpyAsync(bw.data(), dw, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipMemcpyAsync(bj.data(), dj, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(D.comp, comp, sizeof(int) * n, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_kp_boruvka, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, n, D.x, D.i, sigma_I, D.comp,
+                         D.w, D.j);
+      HIP_TRY(hipMemcpyAsync(H.w, D.w, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(H.j, D.j, sizeof(int) * n, hipMemcpyDeviceToHost, s));
       HIP_TRY(hipStreamSynchronize(s));
       // cheapest edge per component under the order (w, min(i, j), max(i, j))
       std::vector<int> ce(n, -1);
@@ -2122,11 +2171,12 @@ int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float
   // breadth-first positions: levels and each node's children are contiguous ranges
   std::vector<int> pos_of(n), lstart(1, 0), depth(n, 0);
   for (int p = 0; p < n; ++p) pos_of[order[p]] = p;
-  std::vector<KpNode> nodes(n);
-  std::vector<float> cw(n, 0.0f);
+  KpNode *nodes = H.nodes;
+  float *cw = H.cw;
   for (int p = 0; p < n; ++p) {
     const int q = order[p];
     nodes[p] = KpNode{q, parent[q], 0, 0};
+    cw[p] = 0.0f;
     if (p > 0) {
       depth[q] = depth[parent[q]] + 1;
       if (depth[q] != depth[order[p - 1]]) lstart.push_back(p);
@@ -2141,10 +2191,8 @@ int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float
   }
   lstart.push_back(n);
   const int maxd = (int)lstart.size() - 2;
-  MlBuffers B;
-  KpNode *d_nodes = nullptr;
-  float *d_cw = nullptr;
-  if (!B.alloc(&d_nodes, n) || !B.alloc(&d_cw, n)) return DISCO_ERR_NOMEM;
+  KpNode *d_nodes = D.nodes;
+  float *d_cw = D.cw;
   // h, m and a temporary per node (and the min-marginals when marg is null), kept in the
   // handle; the previous call on the handle has finished (each call waits for its stream)
   const size_t need = (size_t)(marg ? 3 : 4) * n * L;
@@ -2159,8 +2207,8 @@ int disco_kp_regularise(disco_kp *k, int32_t nkp, const float *x_mm, const float
     k->bp_cap = need;
   }
   float *h = k->bp, *msg = h + (size_t)n * L, *t1 = msg + (size_t)n * L, *mg = marg ? marg : t1 + (size_t)n * L;
-  HIP_TRY(hipMemcpyAsync(d_nodes, nodes.data(), sizeof(KpNode) * n, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(d_cw, cw.data(), sizeof(float) * n, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_nodes, nodes, sizeof(KpNode) * n, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(d_cw, cw, sizeof(float) * n, hipMemcpyHostToDevice, s));
   const float sx = (float)(2.0 * k->h[0]), sy = (float)(2.0 * k->h[1]), sz = (float)(2.0 * k->h[2]);
   if (nl == kKpNl)
     kp_messages<kKpNl>(nl, maxd, lstart, d_nodes, d_cw, cost, L, sx, sy, sz, h, msg, t1, mg, s);
