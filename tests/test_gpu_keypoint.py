@@ -207,3 +207,38 @@ def test_kp_regularise_tiny_trees(disco, n):
     err = float(np.max(np.abs(marg.cpu().numpy() - om) / np.max(np.abs(om), axis=1, keepdims=True)))
     say(f"  marginals max rel error {err:.2e}")
     assert err < 1e-5
+
+
+def test_kp_regularise_fullsize_invariants(disco):
+    """The benchmark's workload (3500 keypoints, 35 937 labels), where the oracle's full
+    belief propagation is too slow to run: the tree equals the oracle's, every keypoint's
+    smallest min-marginal is the same number (the minimum of the joint energy), and the
+    labels the device picks form a labeling whose energy, evaluated in FP64 from the data
+    costs and eq. 3 on the tree, is that minimum.  Bound 1e-5 relative: FP32 messages are
+    summed along paths of about 160 tree levels (measured spread 4e-6)."""
+    say("[kp] full-size invariants")
+    d = synth.make_pair("kp")
+    st = stage(disco, d)
+    kps = vox_of(d)
+    cost = st.cost(torch.from_numpy(kps).to(DEV), 16)
+    x = (kps + 0.5) * np.asarray(d["spacing"])
+    inten = d["R"][kps[:, 2], kps[:, 1], kps[:, 0]]
+    alpha = 1.0 / 45.0
+    marg, lab, par = st.regularise(x, inten, cost, 16, alpha, 150.0)
+    torch.cuda.synchronize()
+    parent, _ = oracle.kp_mst(x.astype(np.float32), inten)
+    np.testing.assert_array_equal(par, parent)
+    mins = marg.min(dim=1).values.double().cpu().numpy()
+    labs = lab.long()
+    data = cost[torch.arange(len(kps), device=DEV), labs].double().cpu().numpy()
+    disp = oracle.kp_labels(16, 2).astype(np.float64)[labs.cpu().numpy()]
+    E = float(np.sum(data))
+    for k in range(len(kps)):
+        if parent[k] >= 0:
+            w = oracle.kp_edge_weight(x.astype(np.float32).astype(np.float64), inten, k, parent[k])
+            E += alpha / w * float(np.sum((disp[k] - disp[parent[k]]) ** 2))
+    spread = float((mins.max() - mins.min()) / abs(E))
+    err = abs(float(np.median(mins)) - E) / abs(E)
+    say(f"  {len(kps)} keypoints: min energy {E:.6f}; min-marginal spread {spread:.2e}, vs labeling {err:.2e}")
+    assert len(kps) == 3500
+    assert spread < 1e-5 and err < 1e-5
