@@ -140,8 +140,10 @@ inline int64_t upd_blocks(const Geo &g) { return (3 * g.nnodes + 256 * kUpdK - 1
 inline dim3 lp_grid(const Geo &g) { return dim3((g.px + 63) / 64, (g.py + 3) / 4, (g.pz + kLpZ - 1) / kLpZ); }
 // 3-D grid over the voxels (rows of 256)
 inline dim3 vox_grid(const Geo &g) { return dim3((g.nx + 255) / 256, g.ny, g.nz); }
-// k_imgrad: 64 x 4 voxel tiles of kImgZ planes
-inline dim3 imgrad_grid(const Geo &g) { return dim3((g.nx + 63) / 64, (g.ny + 3) / 4, (g.nz + kImgZ - 1) / kImgZ); }
+// k_imgrad: 64 x kImgY voxel tiles of kImgZ planes, 64 kImgY threads
+inline dim3 imgrad_grid(const Geo &g) {
+  return dim3((g.nx + 63) / 64, (g.ny + kImgY - 1) / kImgY, (g.nz + kImgZ - 1) / kImgZ);
+}
 
 struct ProfScope {
   disco_ctx *c;
@@ -658,14 +660,14 @@ int disco_set_images(disco_ctx *c, const float *R, const float *T, disco_stream 
     c->sR = 1.0f / scales[0];
     c->sT = 1.0f / scales[1];
     c->max_gT = maxes[1];
-    hipLaunchKernelGGL(k_imgrad<F16x3>, imgrad_grid(g), dim3(256), 0, s, g, R, reinterpret_cast<__half *>(c->gR),
+    hipLaunchKernelGGL(k_imgrad<F16x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, R, reinterpret_cast<__half *>(c->gR),
                        scales[0]);
-    hipLaunchKernelGGL(k_imgrad<F16x3>, imgrad_grid(g), dim3(256), 0, s, g, T, reinterpret_cast<__half *>(c->gT),
+    hipLaunchKernelGGL(k_imgrad<F16x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, T, reinterpret_cast<__half *>(c->gT),
                        scales[1]);
   } else {
-    hipLaunchKernelGGL(k_imgrad<F32x3>, imgrad_grid(g), dim3(256), 0, s, g, R, reinterpret_cast<float *>(c->gR),
+    hipLaunchKernelGGL(k_imgrad<F32x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, R, reinterpret_cast<float *>(c->gR),
                        1.0f);
-    hipLaunchKernelGGL(k_imgrad<F32x3>, imgrad_grid(g), dim3(256), 0, s, g, T, reinterpret_cast<float *>(c->gT),
+    hipLaunchKernelGGL(k_imgrad<F32x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, T, reinterpret_cast<float *>(c->gT),
                        1.0f);
   }
   HIP_TRY(hipGetLastError());

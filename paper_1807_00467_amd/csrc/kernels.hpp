@@ -1698,14 +1698,14 @@ __global__ __launch_bounds__(256) void k_curv_L(Geo g, const float *__restrict__
 }
 
 // central-difference image gradient with replicated border, stored as ST.  A workgroup
-// takes a 64 x 4 voxel tile of kImgZ consecutive planes and walks up in z with the -z and
+// takes a 64 x kImgY voxel tile of kImgZ consecutive planes and walks up in z with the -z and
 // +z values rolled in registers, so that each plane of the tile is read from memory once;
 // the x and y neighbours lie in the plane just read (cache hits).
-constexpr int kImgZ = 16;
+constexpr int kImgZ = 16, kImgY = 16;
 template <class ST>
-__global__ __launch_bounds__(256) void k_imgrad(Geo g, const float *__restrict__ img, typename ST::elem *__restrict__ out,
+__global__ __launch_bounds__(64 * kImgY) void k_imgrad(Geo g, const float *__restrict__ img, typename ST::elem *__restrict__ out,
                                                 float sq) {
-  const int i = blockIdx.x * 64 + (threadIdx.x & 63), j = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63), j = blockIdx.y * kImgY + (threadIdx.x >> 6);
   const int z0 = blockIdx.z * kImgZ, z1 = min(z0 + kImgZ, g.nz);
   if (i >= g.nx || j >= g.ny || z0 >= g.nz) return;
   const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny, col = (int64_t)j * g.nx + i;
