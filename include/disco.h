@@ -388,8 +388,9 @@ int disco_batch_prepare(disco_batch *batch, const disco_params *params, float *c
 /* One GN step of every pair on `stream`. */
 int disco_batch_gn_step(disco_batch *batch, disco_stream stream);
 
-/* Launch shape of the persistent loops: workgroups per compute unit for the brick passes
-   (pass 0, 1..4 useful), the node passes (1) and the vector passes (2).  Invalidates a
+/* Launch shape of the batched passes: workgroups per compute unit of a persistent grid
+   for the brick passes (pass 0), the node passes (1) and the vector passes (2), capped at
+   each kernel's residency; 0 launches one workgroup per work item instead.  Invalidates a
    captured graph. */
 int disco_batch_set_launch(disco_batch *batch, int32_t pass, int32_t wg_per_cu);
 

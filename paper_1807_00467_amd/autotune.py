@@ -19,7 +19,8 @@ import torch
 
 from .disco import Batch, Disco, Params
 
-CANDIDATES = {Batch.PASS_BRICK: (1, 2, 3, 4), Batch.PASS_NODE: (2, 4, 8, 16), Batch.PASS_VEC: (2, 4, 8, 16)}
+# 0: one workgroup per work item; n > 0: a persistent grid of n workgroups per compute unit
+CANDIDATES = {Batch.PASS_BRICK: (0, 1, 2, 3, 4), Batch.PASS_NODE: (0, 2, 4, 8, 16), Batch.PASS_VEC: (0, 2, 4, 8, 16)}
 DEFAULT = {Batch.PASS_BRICK: 4, Batch.PASS_NODE: 8, Batch.PASS_VEC: 8}
 
 

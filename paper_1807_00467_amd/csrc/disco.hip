@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -110,6 +111,7 @@ struct disco_batch {
   int pcg_iters = 0, ls_max = 0;
   int ncu = 0;
   int wpc[3] = {4, 8, 8};        // workgroups per compute unit: brick, node, vector passes
+  std::unordered_map<const void *, int> occ;  // resident workgroups per compute unit, per kernel
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1487,31 +1489,59 @@ int disco_batch_prepare(disco_batch *b, const disco_params *params, float *const
 }
 
 int disco_batch_set_launch(disco_batch *b, int32_t pass, int32_t wg_per_cu) {
-  if (!b || pass < 0 || pass > 2 || wg_per_cu < 1 || wg_per_cu > 64) return DISCO_ERR_ARG;
+  if (!b || pass < 0 || pass > 2 || wg_per_cu < 0 || wg_per_cu > 64) return DISCO_ERR_ARG;
   b->wpc[pass] = wg_per_cu;
   batch_free_graph(b);  // a captured graph keeps the old launch shape
   return DISCO_OK;
 }
 
 extern "C++" {
+// With a persistent grid (wpc > 0) the workgroups loop over the items, so a workgroup that
+// is not resident from the start would begin only once a resident one has finished all of
+// its items: such grids are capped at the kernel's residency (workgroups per compute unit
+// for its register and LDS use, queried once per kernel and batch).  wpc = 0 launches one
+// workgroup per item.
+template <class F>
+static unsigned b_cap(disco_batch *b, int pass, F f, int threads, unsigned grid) {
+  if (b->wpc[pass] == 0) return grid;  // one workgroup per item
+  const void *key = reinterpret_cast<const void *>(f);
+  int o = 0;
+  const auto it = b->occ.find(key);
+  if (it != b->occ.end())
+    o = it->second;
+  else if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, f, threads, 0) == hipSuccess && o > 0)
+    b->occ[key] = o;
+  else
+    o = 0;
+  return o > 0 ? std::min(grid, (unsigned)(b->ncu * o)) : grid;
+}
+
+template <class ST, int MODE, bool NGF, bool VCC, bool KP>
+static void b_brick_go(disco_batch *b, unsigned grid, const PairDesc<ST> *D, const int *st, int n, int sel, int acc,
+                       hipStream_t s) {
+  constexpr int threads = brick_threads<MODE, NGF, VCC || KP>();
+  grid = b_cap(b, 0, k_b_brick<ST, MODE, NGF, VCC, KP>, threads, grid);
+  hipLaunchKernelGGL((k_b_brick<ST, MODE, NGF, VCC, KP>), dim3(grid), dim3(threads), 0, s, D, st, n, sel, acc);
+}
+
 template <class ST, int MODE, bool NGF>
 static void launch_b_brick(disco_batch *b, unsigned grid, const int *st, int n, int sel, int acc, hipStream_t s) {
   const PairDesc<ST> *D = reinterpret_cast<const PairDesc<ST> *>(b->desc);
   const int key = (b->vcc ? 2 : 0) | (b->kp ? 1 : 0);
   if constexpr (NGF && MODE != M_HV) {
-    hipLaunchKernelGGL((k_b_brick<ST, MODE, true, false, false>), dim3(grid), dim3(brick_threads<MODE, true, false || false>()), 0, s, D, st, n, sel, acc);
+    b_brick_go<ST, MODE, true, false, false>(b, grid, D, st, n, sel, acc, s);
   } else if constexpr (NGF) {
     switch (key) {
-      case 3: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, true, true>), dim3(grid), dim3(brick_threads<MODE, true, true || true>()), 0, s, D, st, n, sel, acc); break;
-      case 2: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, true, false>), dim3(grid), dim3(brick_threads<MODE, true, true || false>()), 0, s, D, st, n, sel, acc); break;
-      case 1: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, false, true>), dim3(grid), dim3(brick_threads<MODE, true, false || true>()), 0, s, D, st, n, sel, acc); break;
-      default: hipLaunchKernelGGL((k_b_brick<ST, MODE, true, false, false>), dim3(grid), dim3(brick_threads<MODE, true, false || false>()), 0, s, D, st, n, sel, acc); break;
+      case 3: b_brick_go<ST, MODE, true, true, true>(b, grid, D, st, n, sel, acc, s); break;
+      case 2: b_brick_go<ST, MODE, true, true, false>(b, grid, D, st, n, sel, acc, s); break;
+      case 1: b_brick_go<ST, MODE, true, false, true>(b, grid, D, st, n, sel, acc, s); break;
+      default: b_brick_go<ST, MODE, true, false, false>(b, grid, D, st, n, sel, acc, s); break;
     }
   } else {
     switch (key) {
-      case 3: hipLaunchKernelGGL((k_b_brick<ST, MODE, false, true, true>), dim3(grid), dim3(brick_threads<MODE, false, true || true>()), 0, s, D, st, n, sel, acc); break;
-      case 2: hipLaunchKernelGGL((k_b_brick<ST, MODE, false, true, false>), dim3(grid), dim3(brick_threads<MODE, false, true || false>()), 0, s, D, st, n, sel, acc); break;
-      case 1: hipLaunchKernelGGL((k_b_brick<ST, MODE, false, false, true>), dim3(grid), dim3(brick_threads<MODE, false, false || true>()), 0, s, D, st, n, sel, acc); break;
+      case 3: b_brick_go<ST, MODE, false, true, true>(b, grid, D, st, n, sel, acc, s); break;
+      case 2: b_brick_go<ST, MODE, false, true, false>(b, grid, D, st, n, sel, acc, s); break;
+      case 1: b_brick_go<ST, MODE, false, false, true>(b, grid, D, st, n, sel, acc, s); break;
       default: break;
     }
   }
@@ -1530,49 +1560,53 @@ static void batch_step_t(disco_batch *b, hipStream_t s) {
       t += w == WL_BRICK ? c->nwg : (w == WL_NODE ? c->nodeblocks : (w == WL_VEC ? (int64_t)nblk(3 * c->g.nnodes) : upd_blocks(c->g)));
     tot[w] = (int)t;
   }
-  auto grid = [&](int w, int pass) { return (unsigned)std::max(1, std::min(tot[w], b->ncu * b->wpc[pass])); };
+  // wpc 0: one workgroup per item (the hardware schedules them); else a persistent grid of
+  // wpc workgroups per compute unit, capped at each kernel's residency
+  auto grid = [&](int w, int pass) {
+    return (unsigned)std::max(1, b->wpc[pass] == 0 ? tot[w] : std::min(tot[w], b->ncu * b->wpc[pass]));
+  };
   const unsigned gb = grid(WL_BRICK, 0), gn = grid(WL_NODE, 1), gv = grid(WL_VEC, 2), gu = grid(WL_UPD, 2);
   const bool cells = b->vcc || b->kp;
   const unsigned pairs_grid = (unsigned)std::min(n, b->ncu * 4);
 
   hipLaunchKernelGGL(k_b_status<ST>, dim3((n + 63) / 64), dim3(64), 0, s, D, n, 0);
   // linearisation: objective, gradient, GN diagonal, s cache
-  if (b->curv) hipLaunchKernelGGL(k_b_curv_L<ST>, dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 0);
+  if (b->curv) hipLaunchKernelGGL(k_b_curv_L<ST>, dim3(b_cap(b, 1, k_b_curv_L<ST>, 256, gn)), dim3(256), 0, s, D, wl[WL_NODE], n, 0);
   if (cells) launch_b_brick<ST, M_GRAD, false>(b, gb, wl[WL_BRICK], n, 0, 0, s);
   launch_b_brick<ST, M_GRAD, true>(b, gb, wl[WL_BRICK], n, 0, cells ? 1 : 0, s);
   if (b->curv)
-    hipLaunchKernelGGL((k_b_gather<ST, 2, 2, true>), dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 0);
+    hipLaunchKernelGGL((k_b_gather<ST, 2, 2, true>), dim3(b_cap(b, 1, k_b_gather<ST, 2, 2, true>, 256, gn)), dim3(256), 0, s, D, wl[WL_NODE], n, 0);
   else
-    hipLaunchKernelGGL((k_b_gather<ST, 2, 2, false>), dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 0);
+    hipLaunchKernelGGL((k_b_gather<ST, 2, 2, false>), dim3(b_cap(b, 1, k_b_gather<ST, 2, 2, false>, 256, gn)), dim3(256), 0, s, D, wl[WL_NODE], n, 0);
   hipLaunchKernelGGL(k_b_finish<ST>, dim3(pairs_grid), dim3(1024), 0, s, D, n, 0);
-  hipLaunchKernelGGL(k_b_vec<ST>, dim3(gv), dim3(256), 0, s, D, wl[WL_VEC], n, 0, 0);  // u_lin = u
+  hipLaunchKernelGGL(k_b_vec<ST>, dim3(b_cap(b, 2, k_b_vec<ST>, 256, gv)), dim3(256), 0, s, D, wl[WL_VEC], n, 0, 0);  // u_lin = u
   // Jacobi-PCG
-  hipLaunchKernelGGL(k_b_vec<ST>, dim3(gv), dim3(256), 0, s, D, wl[WL_VEC], n, 1, 0);
+  hipLaunchKernelGGL(k_b_vec<ST>, dim3(b_cap(b, 2, k_b_vec<ST>, 256, gv)), dim3(256), 0, s, D, wl[WL_VEC], n, 1, 0);
   hipLaunchKernelGGL(k_b_finish<ST>, dim3(pairs_grid), dim3(1024), 0, s, D, n, 1);
   for (int it = 0; it < b->pcg_iters; ++it) {
     if (it == 0) {
-      if (b->curv) hipLaunchKernelGGL(k_b_curv_L<ST>, dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 1);
+      if (b->curv) hipLaunchKernelGGL(k_b_curv_L<ST>, dim3(b_cap(b, 1, k_b_curv_L<ST>, 256, gn)), dim3(256), 0, s, D, wl[WL_NODE], n, 1);
     } else {
-      hipLaunchKernelGGL(k_b_curv_Lp<ST>, dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, it);
+      hipLaunchKernelGGL(k_b_curv_Lp<ST>, dim3(b_cap(b, 1, k_b_curv_Lp<ST>, 256, gn)), dim3(256), 0, s, D, wl[WL_NODE], n, it);
     }
     launch_b_brick<ST, M_HV, true>(b, gb, wl[WL_BRICK], n, 1 + (it & 1), 0, s);
     if (b->curv)
-      hipLaunchKernelGGL((k_b_gather<ST, 1, 1, true>), dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 1 + (it & 1));
+      hipLaunchKernelGGL((k_b_gather<ST, 1, 1, true>), dim3(b_cap(b, 1, k_b_gather<ST, 1, 1, true>, 256, gn)), dim3(256), 0, s, D, wl[WL_NODE], n, 1 + (it & 1));
     else
-      hipLaunchKernelGGL((k_b_gather<ST, 1, 1, false>), dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 1 + (it & 1));
-    hipLaunchKernelGGL(k_b_pcg_update<ST>, dim3(gu), dim3(256), 0, s, D, wl[WL_UPD], n, it);
+      hipLaunchKernelGGL((k_b_gather<ST, 1, 1, false>), dim3(b_cap(b, 1, k_b_gather<ST, 1, 1, false>, 256, gn)), dim3(256), 0, s, D, wl[WL_NODE], n, 1 + (it & 1));
+    hipLaunchKernelGGL(k_b_pcg_update<ST>, dim3(b_cap(b, 2, k_b_pcg_update<ST>, 256, gu)), dim3(256), 0, s, D, wl[WL_UPD], n, it);
   }
   // Armijo line search on the device (ls_max trials, skipped once accepted)
-  hipLaunchKernelGGL(k_b_vec<ST>, dim3(gv), dim3(256), 0, s, D, wl[WL_VEC], n, 2, 0);
+  hipLaunchKernelGGL(k_b_vec<ST>, dim3(b_cap(b, 2, k_b_vec<ST>, 256, gv)), dim3(256), 0, s, D, wl[WL_VEC], n, 2, 0);
   hipLaunchKernelGGL(k_b_finish<ST>, dim3(pairs_grid), dim3(1024), 0, s, D, n, 2);
   for (int t = 0; t < b->ls_max; ++t) {
-    hipLaunchKernelGGL(k_b_vec<ST>, dim3(gv), dim3(256), 0, s, D, wl[WL_VEC], n, 3, t);
-    hipLaunchKernelGGL(k_b_curv_L<ST>, dim3(gn), dim3(256), 0, s, D, wl[WL_NODE], n, 2);
+    hipLaunchKernelGGL(k_b_vec<ST>, dim3(b_cap(b, 2, k_b_vec<ST>, 256, gv)), dim3(256), 0, s, D, wl[WL_VEC], n, 3, t);
+    hipLaunchKernelGGL(k_b_curv_L<ST>, dim3(b_cap(b, 1, k_b_curv_L<ST>, 256, gn)), dim3(256), 0, s, D, wl[WL_NODE], n, 2);
     if (cells) launch_b_brick<ST, M_EVAL, false>(b, gb, wl[WL_BRICK], n, 3, 0, s);
     launch_b_brick<ST, M_EVAL, true>(b, gb, wl[WL_BRICK], n, 3, cells ? 1 : 0, s);
     hipLaunchKernelGGL(k_b_finish<ST>, dim3(pairs_grid), dim3(1024), 0, s, D, n, 3);
   }
-  hipLaunchKernelGGL(k_b_vec<ST>, dim3(gv), dim3(256), 0, s, D, wl[WL_VEC], n, 4, 0);
+  hipLaunchKernelGGL(k_b_vec<ST>, dim3(b_cap(b, 2, k_b_vec<ST>, 256, gv)), dim3(256), 0, s, D, wl[WL_VEC], n, 4, 0);
   hipLaunchKernelGGL(k_b_status<ST>, dim3((n + 63) / 64), dim3(64), 0, s, D, n, 1);
 }
 

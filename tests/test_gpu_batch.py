@@ -175,3 +175,31 @@ def test_batch_argument_errors(disco, pairs):
         batch.set_launch(3, 4)
     assert e.value.code == disco.ERR_ARG
     batch.close()
+
+
+@pytest.mark.parametrize("shape", [(0, 0, 0), (1, 2, 2), (4, 16, 16), (3, 0, 8)])
+def test_batch_launch_shapes_agree(disco, pairs, shape):
+    """The launch shape only changes which workgroup takes which work item: persistent grids
+    of 1..16 workgroups per compute unit (capped at each kernel's residency) and one
+    workgroup per item (0) give the same step bitwise."""
+    say(f"[batch] launch shape {shape}")
+    ctx_a = [make_ctx(disco, d) for d in pairs]
+    ctx_b = [make_ctx(disco, d) for d in pairs]
+    params = [params_for(disco, c, d) for c, d in zip(ctx_a, pairs)]
+    u0 = [torch.from_numpy(d["u_true"]).to(DEV) * 0.5 for d in pairs]
+    ua = [u.clone() for u in u0]
+    ub = [u.clone() for u in u0]
+    ba, bb = disco.Batch(ctx_a), disco.Batch(ctx_b)
+    ra, _ = ba.prepare(params, ua)
+    rb, _ = bb.prepare(params, ub)
+    for p_, w in enumerate(shape):
+        bb.set_launch(p_, w)
+    for _ in range(2):
+        ba.gn_step()
+        bb.gn_step()
+    torch.cuda.synchronize()
+    assert torch.equal(ra, rb)
+    for x, y in zip(ua, ub):
+        assert torch.equal(x, y)
+    ba.close()
+    bb.close()
