@@ -66,7 +66,7 @@ __device__ __forceinline__ int node_gy(const Geo &g) { return (g.py + 3) / 4; }
 // ---- brick passes -------------------------------------------------------------------
 // sel: 0 = linearisation, 1/2 = GN product with p[0]/p[1], 3 = line-search trial
 template <class ST, int MODE, bool NGF, bool VCC, bool KP>
-__global__ __launch_bounds__((brick_threads<MODE, NGF, VCC || KP>()), MODE == M_HV ? DISCO_HV_WAVES : 1) void k_b_brick(const PairDesc<ST> *D,
+__global__ __launch_bounds__(256, 1) void k_b_brick(const PairDesc<ST> *D,
                                                                                    const int *start, int npairs,
                                                                                    int sel, int acc) {
   const int total = start[npairs];
@@ -74,7 +74,7 @@ __global__ __launch_bounds__((brick_threads<MODE, NGF, VCC || KP>()), MODE == M_
     const int pr = find_pair(start, npairs, item);
     const PairDesc<ST> &P = D[pr];
     const BrickArgs<ST> &A = sel == 0 ? P.lin : (sel == 3 ? P.eval : P.hv[sel - 1]);
-    brick_body<ST, MODE, NGF, VCC, KP, 4>(A, grid_blk(item - start[pr], A.g.nbx, A.g.nby), acc);
+    brick_body<ST, MODE, NGF, VCC, KP, 4, false, true>(A, grid_blk(item - start[pr], A.g.nbx, A.g.nby), acc);
     __syncthreads();  // the next item reuses the workgroup's LDS
   }
 }

@@ -1519,7 +1519,7 @@ static unsigned b_cap(disco_batch *b, int pass, F f, int threads, unsigned grid)
 template <class ST, int MODE, bool NGF, bool VCC, bool KP>
 static void b_brick_go(disco_batch *b, unsigned grid, const PairDesc<ST> *D, const int *st, int n, int sel, int acc,
                        hipStream_t s) {
-  constexpr int threads = brick_threads<MODE, NGF, VCC || KP>();
+  constexpr int threads = 256;
   grid = b_cap(b, 0, k_b_brick<ST, MODE, NGF, VCC, KP>, threads, grid);
   hipLaunchKernelGGL((k_b_brick<ST, MODE, NGF, VCC, KP>), dim3(grid), dim3(threads), 0, s, D, st, n, sel, acc);
 }

@@ -1026,7 +1026,7 @@ __device__ __forceinline__ void sample_mask(const uint8_t *__restrict__ mM, cons
 
 // MASK adds the lung-boundary term (eq. 6) to the voxel pass: it needs NGF (the voxel
 // pass of the data terms)
-template <class ST, int MODE, bool NGF, bool VCC, bool KP, int ZC, bool MASK = false>
+template <class ST, int MODE, bool NGF, bool VCC, bool KP, int ZC, bool MASK = false, bool NOSPLIT = false>
 __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B, int acc) {
   static_assert(!MASK || NGF, "the boundary term rides on the voxel pass");
   constexpr int F = (MODE == M_GRAD) ? 2 : ((MODE == M_HV) ? 1 : 0);
@@ -1042,7 +1042,7 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
 
   if (A.stop && *A.stop != 0.0) return;
   const Geo &g = A.g;
-  constexpr int WGS = brick_threads<MODE, NGF, CELLT>();
+  constexpr int WGS = NOSPLIT ? 256 : brick_threads<MODE, NGF, CELLT>();
   constexpr bool SPLIT = WGS != 256;
   constexpr int NCW = SPLIT ? kCellWaves : 4;  // waves that take cell layers
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
