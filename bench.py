@@ -93,7 +93,9 @@ def cpu_baseline(d, params, budget_s=25.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20; 10 L-BFGS iterations with --lbfgs, the workload its "
+                         "figures are quoted on)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="cfg1")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
@@ -121,6 +123,8 @@ def main():
                     help="optimiser of --multilevel")
     ap.add_argument("--iters", default="40,20,10,5", help="--multilevel iterations per level, coarsest first")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 10 if args.lbfgs else 20
     if args.print_source_hash:
         print(kernel_source_hash())
         return
