@@ -333,14 +333,13 @@ int disco_kp_cost(disco_kp *kp, int32_t nkp, const int32_t *kp_vox, int32_t R, f
    disco_kp_cost) and the regulariser of eq. 3, alpha_kp |d_k - d_q|^2 / w_kq (|.| in mm),
    each message a min-convolution done as three exact 1-D minimisations (x, y, z), one tree
    level per launch pair.  The messages are scheduled from the tree's centre (the middle
-   of a longest path), which halves the levels; min-marginals do not depend on the root.
-   x_mm (HOST
-   float32 [nkp][3]) and inten (HOST float32 [nkp], F at the keypoint) define w; the
-   keypoints must be distinct (w > 0).  Writes
-   the min-marginal energies to marg (device float32 [nkp][(2R+1)^3], nullable), the label
-   of the smallest one per keypoint (lowest index on ties) to labels (device int32 [nkp])
-   and the tree to parent_out (HOST int32 [nkp], nullable; -1 at the root).  Work memory
-   of 3 x nkp x (2R+1)^3 floats (4 x when marg is null) and about 2 kB per 32 keypoints of
+   of a longest path), which brings the levels down to the tree's radius; min-marginals do
+   not depend on the root.  x_mm (HOST float32 [nkp][3]) and inten (HOST float32 [nkp], F
+   at the keypoint) define w; the keypoints must be distinct (w > 0).  Writes the
+   min-marginal energies to marg (device float32 [nkp][(2R+1)^3], nullable), the label of
+   the smallest one per keypoint (lowest index on ties) to labels (device int32 [nkp]) and
+   the tree to parent_out (HOST int32 [nkp], nullable; -1 at the root).  Work memory of
+   3 x nkp x (2R+1)^3 floats (4 x when marg is null) and about 100 bytes per keypoint of
    tree set-up buffers (pinned host and device) are kept in the handle, grown when a call
    needs more and freed by disco_kp_destroy; the call waits for the stream before
    returning, and calls on one handle must not overlap. */
