@@ -134,6 +134,13 @@ void disco_destroy(disco_ctx *ctx);
    eq. 1).  Invalidates the linearisation. */
 int disco_set_images(disco_ctx *ctx, const float *R, const float *T, disco_stream stream);
 
+/* Replace the moving image T of eq. 1 (device float32 [Nz][Ny][Nx]) and rebuild only its
+   gradient volume; grad R is kept.  For callers that evaluate one fixed image against
+   many moving images (the loss form).  DISCO_ERR_STATE if no images were set; on a
+   device error the context has no images until the next disco_set_images.
+   Invalidates the linearisation. */
+int disco_set_moving(disco_ctx *ctx, const float *T, disco_stream stream);
+
 /* Set n keypoints x_i and targets y_KP(x_i) of eq. 10 (HOST float32 [n][3], mm).  Every
    x_i must lie in the closed box [0, N_a h_a] (else DISCO_ERR_SHAPE).  n = 0 clears
    them.  Copies and bins them by control-grid cell; the host arrays may be reused on
@@ -146,14 +153,18 @@ int disco_set_reference(disco_ctx *ctx, const float *u_ref, disco_stream stream)
 /* NGF distance of eq. 1 at displacement u: *D_dev = h_x h_y h_z sum_v (1 - r_v^2). */
 int ngf_eval(disco_ctx *ctx, double eta, const float *u, double *D_dev, disco_stream stream);
 
-/* NGF distance and its gradient g = dD/du (node field).  diag (nullable) receives the
-   diagonal of the Gauss-Newton matrix 2 h^3 J^T J.  Also records u as the
-   linearisation point and stores s_v = J_G^T dr/da per voxel for ngf_hessvec. */
+/* NGF distance of eq. 1 and its gradient g = dD/du (node field) by the matrix-free
+   derivative rules of Sec. II-D3: g = -2 h^3 sum_v phi_v r_v s_v with
+   s_v = J_G(y_v)^T dr/da the chain rule through the trilinear sample of grad T.  diag
+   (nullable) receives the diagonal of the Gauss-Newton matrix 2 h^3 J^T J.  Also records
+   u as the linearisation point and stores s_v per voxel for ngf_hessvec. */
 int ngf_grad(disco_ctx *ctx, double eta, const float *u, double *D_dev, float *g, float *diag,
              disco_stream stream);
 
-/* Hv = 2 h^3 J^T (J v) of the NGF term at the last linearisation (ngf_grad or
-   gn_pcg_step); DISCO_ERR_STATE if there is none. */
+/* Gauss-Newton product of the NGF term of eq. 1 (Sec. II-D3, matrix-free):
+   Hv = 2 h^3 J^T (J v) = 2 h^3 sum_v phi_v s_v (s_v . (P v)(x_v)) with the s_v of the last
+   linearisation (ngf_grad or gn_pcg_step); DISCO_ERR_STATE if there is none.  v and Hv
+   are device node fields [3][nz][ny][nx]. */
 int ngf_hessvec(disco_ctx *ctx, const float *v, float *Hv, disco_stream stream);
 
 /* Set the binary lung masks b_F of R and b_M of T (device uint8 [Nz][Ny][Nx], values 0
@@ -172,6 +183,12 @@ int disco_set_masks(disco_ctx *ctx, const uint8_t *bF, const uint8_t *bM, disco_
    used by gn_hessvec. */
 int objective_linearise(disco_ctx *ctx, const disco_params *p, const float *u, double *terms_dev, float *g,
                         float *diag, disco_stream stream);
+
+/* The joint objective of eq. 11 at u without derivatives (one pass over the voxels, as a
+   line-search trial): terms_dev (device doubles [8], 8-byte aligned, required) receives J,
+   D, S, V (+inf on a fold), K, B, the fold count and NaN in the |grad J| slot.  Only the
+   weights and eta of p are used.  Leaves the linearisation and the s vectors unchanged. */
+int objective_eval(disco_ctx *ctx, const disco_params *p, const float *u, double *terms_dev, disco_stream stream);
 
 /* Derivative of the NGF distance of eq. 1 with respect to the moving image values at
    displacement u: dT (device float32 [Nz][Ny][Nx]) = dD/dT, through the trilinear

@@ -75,6 +75,10 @@ def _load():
         lib.or_ngf_grad_T.restype = None
         lib.or_mask.argtypes = [P, P, P, P, P, P, P, P, P, P]
         lib.or_mask.restype = D
+        lib.or_ngf_ties.argtypes = [P, P, P, D, P, P, P, P, P, P, P, P]
+        lib.or_ngf_ties.restype = I64
+        lib.or_mask_ties.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
+        lib.or_mask_ties.restype = I64
         lib.or_kp_cost.argtypes = [P, P, P, I64, P, D, I64, I64, P]
         lib.or_kp_cost.restype = None
         lib.or_num_threads.argtypes = []
@@ -152,6 +156,45 @@ def ngf(gR, gT, spacing, eta, u, m=(4, 4, 4), want=("g", "diag", "s", "r", "c"))
     D = _load().or_ngf(_p(n), _p(_f64(spacing)), _p(mm), float(eta), _p(gR), _p(gT), _p(u),
                        _p(g), _p(diag), _p(s), _p(r), _p(c))
     return dict(D=D, g=g, diag=diag, s=s, r=r, c=c)
+
+
+def ngf_ties(gR, gT, spacing, eta, u, v=None, m=(4, 4, 4), want_s=False):
+    """Sample-cell ties of eq. 1 at u (see ``or_ngf_ties``): voxels whose warped point
+    lies within single-precision rounding of a cell face of the moving image, where
+    either one-sided derivative is correct.  Returns dict(n = number of such voxels,
+    g, diag [, hv] = per-node allowance fields (sum over those voxels of the largest
+    difference between the one-sided choices), s = per-voxel allowance of the s
+    vectors when want_s)."""
+    gR = _f64(gR)
+    gT = _f64(gT)
+    nz, ny, nx, _ = gR.shape
+    nn = [nx // m[0] + 1, ny // m[1] + 1, nz // m[2] + 1]
+    u = _f64(u)
+    assert u.shape == (3, nn[2], nn[1], nn[0]), (u.shape, nn)
+    g = np.empty((3, nn[2], nn[1], nn[0]))
+    diag = np.empty_like(g)
+    hv = np.empty_like(g) if v is not None else None
+    s = np.empty((nz, ny, nx, 3)) if want_s else None
+    nt = _load().or_ngf_ties(_p(_i64([nx, ny, nz])), _p(_f64(spacing)), _p(_i64(m)), float(eta), _p(gR), _p(gT),
+                             _p(u), _p(None if v is None else _f64(v)), _p(g), _p(diag), _p(hv), _p(s))
+    return dict(n=int(nt), g=g, diag=diag, hv=hv, s=s)
+
+
+def mask_ties(bF, bM, spacing, u, v=None, m=(4, 4, 4), want_s=False):
+    """Sample-cell ties of the lung-boundary term (eq. 6), as ``ngf_ties``; the per-voxel
+    field (when want_s) is the allowance of the mask gradient sb."""
+    bF = _f64(bF)
+    bM = _f64(bM)
+    nz, ny, nx = bF.shape
+    nn = [nx // m[0] + 1, ny // m[1] + 1, nz // m[2] + 1]
+    u = _f64(u)
+    g = np.empty((3, nn[2], nn[1], nn[0]))
+    diag = np.empty_like(g)
+    hv = np.empty_like(g) if v is not None else None
+    sb = np.empty((nz, ny, nx, 3)) if want_s else None
+    nt = _load().or_mask_ties(_p(_i64([nx, ny, nz])), _p(_f64(spacing)), _p(_i64(m)), _p(bF), _p(bM), _p(u),
+                              _p(None if v is None else _f64(v)), _p(g), _p(diag), _p(hv), _p(sb))
+    return dict(n=int(nt), g=g, diag=diag, hv=hv, s=sb)
 
 
 def ngf_grad_T(gR, gT, spacing, eta, u, m=(4, 4, 4)):
@@ -330,6 +373,19 @@ class Problem:
         D = self.ngf(u0, want=())["D"]
         K = self.keypoints(u0)["K"]
         return D / K if K > 0 else 0.0
+
+    def ties(self, u, v=None):
+        """Allowance fields of the sample-cell ties at u for the joint gradient, GN
+        diagonal and (with v) GN product of eq. 11: the NGF term's plus beta times the
+        boundary term's (the other terms take no sampling decision)."""
+        t = ngf_ties(self.gR, self.gT, self.spacing, self.w.eta, u, v, self.m)
+        if self.w.beta != 0.0 and self.bF is not None:
+            tb = mask_ties(self.bF, self.bM, self.spacing, u, v, self.m)
+            t["n"] += tb["n"]
+            for k in ("g", "diag", "hv"):
+                if t[k] is not None:
+                    t[k] = t[k] + self.w.beta * tb[k]
+        return t
 
     # joint objective -----------------------------------------------------------------
     def objective(self, u):

@@ -57,25 +57,14 @@ void or_image_gradient(const int64_t *n, const double *h, const float *img, doub
 }
 
 /* ------------------------------------------------------------------------------ */
-/* Trilinear sampling of a 3-vector field g ([N][3]) at continuous voxel index q    */
-/* (q_a = y_a/h_a - 1/2), zero outside the volume.  Returns the value G(q) and the   */
-/* Jacobian JG[c][a] = dG_c/dy_a = (1/h_a) dG_c/dq_a.  At integer q_a the floor puts */
-/* the point in the cell to its right, so the derivative is that cell's one.        */
+/* Trilinear sampling of a 3-vector field g ([N][3]) at continuous voxel index      */
+/* q = i0 + t (i0 integer, t in [0,1]), zero outside the volume.  Returns the value  */
+/* G and the Jacobian JG[c][a] = dG_c/dy_a = (1/h_a) dG_c/dq_a of the trilinear     */
+/* interpolant inside the cell with lower corner i0.                                 */
 /* ------------------------------------------------------------------------------ */
-static void sample_vec(const int64_t *n, const double *h, const double *g, const double q[3],
-                       double G[3], double JG[3][3])
+static void sample_vec_at(const int64_t *n, const double *h, const double *g, const int64_t i0[3],
+                          const double t[3], double G[3], double JG[3][3])
 {
-    double t[3];
-    int64_t i0[3];
-    for (int a = 0; a < 3; ++a) {
-        double qa = q[a];
-        /* far outside: every corner is outside, result is zero whatever t is */
-        if (!(qa > -2.0)) qa = -2.0;
-        if (!(qa < (double)n[a] + 1.0)) qa = (double)n[a] + 1.0;
-        double f = floor(qa);
-        i0[a] = (int64_t)f;
-        t[a] = qa - f;
-    }
     for (int c = 0; c < 3; ++c) {
         G[c] = 0.0;
         JG[c][0] = JG[c][1] = JG[c][2] = 0.0;
@@ -98,32 +87,31 @@ static void sample_vec(const int64_t *n, const double *h, const double *g, const
             }
 }
 
-/* Same sampling with the integer corner i0 of the sample point given (t = q - i0). */
-static void sample_vec_at(const int64_t *n, const double *h, const double *g, const double q[3],
-                          const int64_t i0[3], double G[3], double JG[3][3])
+/* The cell of a sample point along one axis.  The continuous index is q = idx + uh   */
+/* (idx the voxel index, uh = u/h the displacement in voxels); since idx is an integer, */
+/* floor(q) = idx + floor(uh) exactly, and t = uh - floor(uh).  Splitting this way     */
+/* keeps the displacement's own precision where |uh| is far below idx (forming idx + uh */
+/* first would round such displacements away).  At an integer q the floor puts the     */
+/* point in the cell to its right.  Far outside [-2, n+1] every corner is outside the   */
+/* volume and the sample is zero whatever the cell, so uh is clamped there.            */
+static void split_axis(int64_t idx, double uh, int64_t n, int64_t *i0, double *t)
 {
+    const double lo = -2.0 - (double)idx, hi = (double)n + 1.0 - (double)idx;
+    if (!(uh > lo)) uh = lo;
+    if (!(uh < hi)) uh = hi;
+    const double f = floor(uh);
+    *i0 = idx + (int64_t)f;
+    *t = uh - f;
+}
+
+/* sample at continuous index q (any real): the cell is floor(q) */
+static void sample_vec(const int64_t *n, const double *h, const double *g, const double q[3],
+                       double G[3], double JG[3][3])
+{
+    int64_t i0[3];
     double t[3];
-    for (int a = 0; a < 3; ++a) t[a] = q[a] - (double)i0[a];
-    for (int c = 0; c < 3; ++c) {
-        G[c] = 0.0;
-        JG[c][0] = JG[c][1] = JG[c][2] = 0.0;
-    }
-    for (int cz = 0; cz < 2; ++cz)
-        for (int cy = 0; cy < 2; ++cy)
-            for (int cx = 0; cx < 2; ++cx) {
-                int64_t ii = i0[0] + cx, jj = i0[1] + cy, kk = i0[2] + cz;
-                if (ii < 0 || ii >= n[0] || jj < 0 || jj >= n[1] || kk < 0 || kk >= n[2]) continue;
-                double wx = cx ? t[0] : 1.0 - t[0], dwx = cx ? 1.0 : -1.0;
-                double wy = cy ? t[1] : 1.0 - t[1], dwy = cy ? 1.0 : -1.0;
-                double wz = cz ? t[2] : 1.0 - t[2], dwz = cz ? 1.0 : -1.0;
-                const double *gv = g + 3 * IDX3(ii, jj, kk, n[0], n[1]);
-                for (int c = 0; c < 3; ++c) {
-                    G[c] += wx * wy * wz * gv[c];
-                    JG[c][0] += dwx * wy * wz * gv[c] / h[0];
-                    JG[c][1] += wx * dwy * wz * gv[c] / h[1];
-                    JG[c][2] += wx * wy * dwz * gv[c] / h[2];
-                }
-            }
+    for (int a = 0; a < 3; ++a) split_axis(0, q[a], n[a], &i0[a], &t[a]);
+    sample_vec_at(n, h, g, i0, t, G, JG);
 }
 
 void or_sample_points(const int64_t *n, const double *h, const double *g, int64_t npts,
@@ -189,45 +177,43 @@ static void scatter_voxel(const int64_t *nn, const int64_t *m, double *f, int64_
             }
 }
 
-/* ------------------------------------------------------------------------------ */
-/* Which cell of the moving-image grid holds a sample point is an integer decision     */
-/* taken by floating point: where q is within rounding of an integer the left and     */
-/* right cells give different derivatives J_G.  The paper fixes no precision, so the   */
-/* decision is taken in the GPU library's precision and evaluation order (single      */
-/* precision; the node displacements interpolated along x, then z, then y, one fused  */
-/* multiply-add each; then multiplied by 1/h rounded to single precision), while all   */
-/* arithmetic of the oracle stays in double precision.  Returns the lower corner i0.  */
-/* ------------------------------------------------------------------------------ */
-static void decide_cells_f32(const int64_t *nn, const int64_t *m, const int64_t *n, const double *h,
-                             const double *u, int64_t i, int64_t j, int64_t k, int64_t out[3])
-{
-    const int64_t nnodes = nn[0] * nn[1] * nn[2];
-    const int64_t idx[3] = {i, j, k};
-    const int64_t c0 = i / m[0], c1 = j / m[1], c2 = k / m[2];
-    const float wx = ((float)(i % m[0]) + 0.5f) / (float)m[0];
-    const float wy = ((float)(j % m[1]) + 0.5f) / (float)m[1];
-    const float wz = ((float)(k % m[2]) + 0.5f) / (float)m[2];
-    for (int a = 0; a < 3; ++a) {
-        const double *f = u + a * nnodes;
-        float fx[2][2]; /* [z][y] */
-        for (int kz = 0; kz < 2; ++kz)
-            for (int jy = 0; jy < 2; ++jy) {
-                const float a0 = (float)f[IDX3(c0, c1 + jy, c2 + kz, nn[0], nn[1])];
-                const float a1 = (float)f[IDX3(c0 + 1, c1 + jy, c2 + kz, nn[0], nn[1])];
-                fx[kz][jy] = fmaf(wx, a1 - a0, a0);
-            }
-        float fz[2];
-        for (int jy = 0; jy < 2; ++jy) fz[jy] = fmaf(wz, fx[1][jy] - fx[0][jy], fx[0][jy]);
-        const float f3 = fmaf(wy, fz[1] - fz[0], fz[0]);
-        const float uh = f3 * (float)(1.0 / h[a]);
-        const float d = fminf(fmaxf(uh, (float)(-2 - idx[a])), (float)(n[a] + 1 - idx[a]));
-        out[a] = idx[a] + (int64_t)floorf(d);
-    }
-}
-
 static void node_counts(const int64_t *n, const int64_t *m, int64_t nn[3])
 {
     for (int a = 0; a < 3; ++a) nn[a] = n[a] / m[a] + 1;
+}
+
+/* displacement of voxel (i,j,k) in voxels of the moving image along each axis:    */
+/* uh_a = (Pu)_a(x_v) / h_a, so that the warped point has continuous index q = idx + uh */
+static void voxel_uh(const int64_t *nn, const int64_t *m, const double *h, const double *u, int64_t i,
+                     int64_t j, int64_t k, double uh[3])
+{
+    double uv[3];
+    interp_voxel(nn, m, u, i, j, k, uv);
+    for (int a = 0; a < 3; ++a) uh[a] = uv[a] / h[a];
+}
+
+/* NGF quantities of one voxel (eq. 1) with the sample of grad T taken in the cell with */
+/* lower corner i0 at fractions t: r, c = 1 - r^2 and s = JG^T dr/da.  b = grad R[v].  */
+static void ngf_voxel(const int64_t *n, const double *h, double e2, const double *gT, const double *b,
+                      const int64_t i0[3], const double t[3], double *r, double *c, double s[3])
+{
+    double a[3], JG[3][3];
+    sample_vec_at(n, h, gT, i0, t, a, JG);
+    const double Da = e2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
+    const double Db = e2 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    const double P = e2 + a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    const double sq = sqrt(Da * Db);
+    *r = P / sq;
+    /* 1 - r^2 written without cancellation (Lagrange's identity for the 4-vectors
+       (eta, a) and (eta, b)) */
+    const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    const double cx = a[1] * b[2] - a[2] * b[1];
+    const double cy = a[2] * b[0] - a[0] * b[2];
+    const double cz = a[0] * b[1] - a[1] * b[0];
+    *c = (e2 * (dx * dx + dy * dy + dz * dz) + cx * cx + cy * cy + cz * cz) / (Da * Db);
+    double dr[3];
+    for (int q = 0; q < 3; ++q) dr[q] = (b[q] - (P / Da) * a[q]) / sq;
+    for (int q = 0; q < 3; ++q) s[q] = JG[0][q] * dr[0] + JG[1][q] * dr[1] + JG[2][q] * dr[2];
 }
 
 /* ------------------------------------------------------------------------------ */
@@ -265,32 +251,13 @@ double or_ngf(const int64_t *n, const double *h, const int64_t *m, double eta, c
         for (int64_t j = 0; j < ny; ++j)
             for (int64_t i = 0; i < nx; ++i) {
                 const int64_t v = IDX3(i, j, k, nx, ny);
-                double uv[3], q[3], a[3], JG[3][3];
-                interp_voxel(nn, m, u, i, j, k, uv);
-                /* y = x + u; continuous index q = y/h - 1/2 = index + u/h */
-                q[0] = (double)i + uv[0] / h[0];
-                q[1] = (double)j + uv[1] / h[1];
-                q[2] = (double)k + uv[2] / h[2];
+                const int64_t idx[3] = {i, j, k};
+                double uh[3], t[3];
                 int64_t i0[3];
-                decide_cells_f32(nn, m, n, h, u, i, j, k, i0);
-                sample_vec_at(n, h, gT, q, i0, a, JG);
-                const double *b = gR + 3 * v;
-                double Da = e2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
-                double Db = e2 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-                double P = e2 + a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-                double sq = sqrt(Da * Db);
-                r[v] = P / sq;
-                /* 1 - r^2 written without cancellation (Lagrange's identity for the
-                   4-vectors (eta, a) and (eta, b)) */
-                double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
-                double cx = a[1] * b[2] - a[2] * b[1];
-                double cy = a[2] * b[0] - a[0] * b[2];
-                double cz = a[0] * b[1] - a[1] * b[0];
-                c[v] = (e2 * (dx * dx + dy * dy + dz * dz) + cx * cx + cy * cy + cz * cz) / (Da * Db);
-                double dr[3];
-                for (int t = 0; t < 3; ++t) dr[t] = (b[t] - (P / Da) * a[t]) / sq;
-                for (int t = 0; t < 3; ++t)
-                    s[3 * v + t] = JG[0][t] * dr[0] + JG[1][t] * dr[1] + JG[2][t] * dr[2];
+                /* y = x + u; continuous index q = y/h - 1/2 = index + u/h */
+                voxel_uh(nn, m, h, u, i, j, k, uh);
+                for (int a = 0; a < 3; ++a) split_axis(idx[a], uh[a], n[a], &i0[a], &t[a]);
+                ngf_voxel(n, h, e2, gT, gR + 3 * v, i0, t, &r[v], &c[v], s + 3 * v);
             }
 
     double D = 0.0;
@@ -357,6 +324,158 @@ void or_ngf_hv(const int64_t *n, const double *h, const int64_t *m, const double
                 scatter_voxel(nn, m, Hv, i, j, k, val, 0);
             }
     free(w);
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Sample-cell ties.  Which cell of the moving-image grid holds a warped point is an  */
+/* integer decision (the floor of q = idx + uh).  The trilinear interpolant is        */
+/* continuous across cell faces, so the sampled value (and with it r, c and D) does   */
+/* not depend on that decision, but its derivative JG jumps across a face: s, and     */
+/* through s the gradient, GN diagonal and GN product, are one-sided there.  Where uh  */
+/* lies within rounding of an integer, a single-precision evaluation of uh may land   */
+/* on either side of the face, and both one-sided results are correct.                */
+/*                                                                                    */
+/* Bound.  uh_a is the trilinear interpolant of the 8 node values u_a of the voxel's   */
+/* cell divided by h_a.  Evaluated in IEEE single precision by nested linear            */
+/* interpolation (at most three levels of one subtraction and one multiply-add, then   */
+/* one multiplication by a rounded 1/h_a), each rounding contributes at most           */
+/* 2^-24 of a quantity bounded by 2 M_a (M_a = max over the 8 nodes of |u_a| / h_a),    */
+/* so |uh_single - uh| < 12 * 2^-24 * M_a.  Axis a of a voxel is a tie when            */
+/* dist(uh_a, nearest integer) < TIE_REL * M_a with TIE_REL = 2^-19 (32 * 2^-24, a     */
+/* margin of more than two on the bound).  uh = 0 exactly from all-zero nodes          */
+/* (M_a = 0) is never a tie.                                                          */
+/*                                                                                    */
+/* For every voxel with at least one tie axis the routine evaluates every other choice */
+/* of cell on its tie axes (2^k - 1 alternatives for k tie axes; the other side of the */
+/* face is taken at t = 1 on the left cell or t = 0 on the right cell) and returns,    */
+/* per node, the sum over those voxels of the largest difference to the reference      */
+/* (floor) choice, weighted like the quantity itself:                                 */
+/*   ag   = sum_v phi_v   max |2h^3 (r' s'_c - r s_c)|            (gradient)          */
+/*   adg  = sum_v phi_v^2 max |2h^3 (s'_c^2 - s_c^2)|             (GN diagonal)       */
+/*   ahv  = sum_v phi_v   max |2h^3 (s'_c (s'.w) - s_c (s.w))|, w = (Pv)(x_v)  (GN v) */
+/* and per voxel sdev = max |s'_c - s_c| (for the s vectors themselves).  Any of the   */
+/* outputs may be NULL (v may be NULL when ahv is).  Returns the number of voxels with */
+/* a tie.                                                                             */
+/* ------------------------------------------------------------------------------ */
+#define TIE_REL 1.9073486328125e-06 /* 2^-19 */
+
+/* tie axes of voxel (i,j,k): bit a set when axis a is a tie; alt_i0/alt_t give the   */
+/* other side of the face on those axes                                               */
+static int tie_axes(const int64_t *nn, const int64_t *m, const int64_t *n, const double *h, const double *u,
+                    int64_t i, int64_t j, int64_t k, const double uh[3], int64_t alt_i0[3], double alt_t[3])
+{
+    const int64_t nnodes = nn[0] * nn[1] * nn[2];
+    const int64_t idx[3] = {i, j, k};
+    const int64_t c0 = i / m[0], c1 = j / m[1], c2 = k / m[2];
+    int mask = 0;
+    for (int a = 0; a < 3; ++a) {
+        double M = 0.0;
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx) {
+                    const double x = fabs(u[a * nnodes + IDX3(c0 + dx, c1 + dy, c2 + dz, nn[0], nn[1])]);
+                    if (x > M) M = x;
+                }
+        M /= h[a];
+        const double kint = nearbyint(uh[a]);
+        if (!(fabs(uh[a] - kint) < TIE_REL * M)) continue;
+        /* far outside the volume every corner is outside on both sides */
+        if (idx[a] + kint < -2.0 || idx[a] + kint > (double)n[a] + 1.0) continue;
+        mask |= 1 << a;
+        if (uh[a] >= kint) { /* reference cell starts at the integer: other side is the left cell */
+            alt_i0[a] = idx[a] + (int64_t)kint - 1;
+            alt_t[a] = 1.0;
+        } else { /* reference cell ends at the integer: other side is the right cell */
+            alt_i0[a] = idx[a] + (int64_t)kint;
+            alt_t[a] = 0.0;
+        }
+    }
+    return mask;
+}
+
+int64_t or_ngf_ties(const int64_t *n, const double *h, const int64_t *m, double eta, const double *gR,
+                    const double *gT, const double *u, const double *v, double *ag, double *adg, double *ahv,
+                    double *sdev)
+{
+    const int64_t nx = n[0], ny = n[1], nz = n[2];
+    const int64_t nvox = nx * ny * nz;
+    int64_t nn[3];
+    node_counts(n, m, nn);
+    const int64_t nnodes = nn[0] * nn[1] * nn[2];
+    const double h3 = h[0] * h[1] * h[2];
+    const double e2 = eta * eta;
+    uint8_t *flag = (uint8_t *)malloc((size_t)nvox);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                double uh[3], at[3];
+                int64_t ai[3];
+                voxel_uh(nn, m, h, u, i, j, k, uh);
+                flag[IDX3(i, j, k, nx, ny)] = (uint8_t)tie_axes(nn, m, n, h, u, i, j, k, uh, ai, at);
+            }
+    int64_t nt = 0;
+    for (int64_t q = 0; q < nvox; ++q) nt += flag[q] != 0;
+    int64_t *list = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nt > 0 ? nt : 1));
+    nt = 0;
+    for (int64_t q = 0; q < nvox; ++q)
+        if (flag[q]) list[nt++] = q;
+    double *dv = (double *)calloc((size_t)(12 * (nt > 0 ? nt : 1)), sizeof(double)); /* dg, dd, dh, ds */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t e = 0; e < nt; ++e) {
+        const int64_t vox = list[e];
+        const int64_t i = vox % nx, j = (vox / nx) % ny, k = vox / (nx * ny);
+        const int64_t idx[3] = {i, j, k};
+        double uh[3], t0[3], at[3], w[3] = {0.0, 0.0, 0.0};
+        int64_t i00[3], ai[3];
+        voxel_uh(nn, m, h, u, i, j, k, uh);
+        const int mask = tie_axes(nn, m, n, h, u, i, j, k, uh, ai, at);
+        for (int a = 0; a < 3; ++a) split_axis(idx[a], uh[a], n[a], &i00[a], &t0[a]);
+        if (v) interp_voxel(nn, m, v, i, j, k, w);
+        double r0, c0, s0[3];
+        ngf_voxel(n, h, e2, gT, gR + 3 * vox, i00, t0, &r0, &c0, s0);
+        const double sw0 = s0[0] * w[0] + s0[1] * w[1] + s0[2] * w[2];
+        double *o = dv + 12 * e;
+        for (int combo = 1; combo < 8; ++combo) {
+            if (combo & ~mask) continue;
+            int64_t i1[3];
+            double t1[3], r1, c1, s1[3];
+            for (int a = 0; a < 3; ++a) {
+                i1[a] = (combo >> a & 1) ? ai[a] : i00[a];
+                t1[a] = (combo >> a & 1) ? at[a] : t0[a];
+            }
+            ngf_voxel(n, h, e2, gT, gR + 3 * vox, i1, t1, &r1, &c1, s1);
+            const double sw1 = s1[0] * w[0] + s1[1] * w[1] + s1[2] * w[2];
+            for (int q = 0; q < 3; ++q) {
+                const double dg = fabs(2.0 * h3 * (r1 * s1[q] - r0 * s0[q]));
+                const double dd = fabs(2.0 * h3 * (s1[q] * s1[q] - s0[q] * s0[q]));
+                const double dh = fabs(2.0 * h3 * (s1[q] * sw1 - s0[q] * sw0));
+                const double ds = fabs(s1[q] - s0[q]);
+                if (dg > o[q]) o[q] = dg;
+                if (dd > o[3 + q]) o[3 + q] = dd;
+                if (dh > o[6 + q]) o[6 + q] = dh;
+                if (ds > o[9 + q]) o[9 + q] = ds;
+            }
+        }
+    }
+    if (ag) memset(ag, 0, sizeof(double) * 3 * nnodes);
+    if (adg) memset(adg, 0, sizeof(double) * 3 * nnodes);
+    if (ahv) memset(ahv, 0, sizeof(double) * 3 * nnodes);
+    if (sdev) memset(sdev, 0, sizeof(double) * 3 * nvox);
+    for (int64_t e = 0; e < nt; ++e) {
+        const int64_t vox = list[e];
+        const int64_t i = vox % nx, j = (vox / nx) % ny, k = vox / (nx * ny);
+        const double *o = dv + 12 * e;
+        if (ag) scatter_voxel(nn, m, ag, i, j, k, o, 0);
+        if (adg) scatter_voxel(nn, m, adg, i, j, k, o + 3, 1);
+        if (ahv) scatter_voxel(nn, m, ahv, i, j, k, o + 6, 0);
+        if (sdev)
+            for (int q = 0; q < 3; ++q) sdev[3 * vox + q] = o[9 + q];
+    }
+    free(dv);
+    free(list);
+    free(flag);
+    return nt;
 }
 
 /* ------------------------------------------------------------------------------ */
@@ -777,37 +896,34 @@ void or_ngf_grad_T(const int64_t *n, const double *h, const int64_t *m, double e
     const double e2 = eta * eta;
     double *wv = (double *)malloc(sizeof(double) * 3 * nvox); /* -2 h^3 r dr/da per voxel */
     int64_t *cell = (int64_t *)malloc(sizeof(int64_t) * 3 * nvox);
-    double *qq = (double *)malloc(sizeof(double) * 3 * nvox);
+    double *tt = (double *)malloc(sizeof(double) * 3 * nvox);
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < nz; ++k)
         for (int64_t j = 0; j < ny; ++j)
             for (int64_t i = 0; i < nx; ++i) {
                 const int64_t v = IDX3(i, j, k, nx, ny);
-                double uv[3], q[3], a[3], JG[3][3];
-                interp_voxel(nn, m, u, i, j, k, uv);
-                q[0] = (double)i + uv[0] / h[0];
-                q[1] = (double)j + uv[1] / h[1];
-                q[2] = (double)k + uv[2] / h[2];
+                const int64_t idx[3] = {i, j, k};
+                double uh[3], t[3], a[3], JG[3][3];
                 int64_t i0[3];
-                decide_cells_f32(nn, m, n, h, u, i, j, k, i0);
-                sample_vec_at(n, h, gT, q, i0, a, JG);
+                voxel_uh(nn, m, h, u, i, j, k, uh);
+                for (int q = 0; q < 3; ++q) split_axis(idx[q], uh[q], n[q], &i0[q], &t[q]);
+                sample_vec_at(n, h, gT, i0, t, a, JG);
                 const double *b = gR + 3 * v;
                 double Da = e2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
                 double Db = e2 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
                 double P = e2 + a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
                 double sq = sqrt(Da * Db);
                 double r = P / sq;
-                for (int t = 0; t < 3; ++t) {
-                    wv[3 * v + t] = -2.0 * h3 * r * (b[t] - (P / Da) * a[t]) / sq;
-                    cell[3 * v + t] = i0[t];
-                    qq[3 * v + t] = q[t];
+                for (int q = 0; q < 3; ++q) {
+                    wv[3 * v + q] = -2.0 * h3 * r * (b[q] - (P / Da) * a[q]) / sq;
+                    cell[3 * v + q] = i0[q];
+                    tt[3 * v + q] = t[q];
                 }
             }
     /* scatter onto the grad-T grid with the trilinear weights (zero outside) */
     double *W = (double *)calloc((size_t)(3 * nvox), sizeof(double));
     for (int64_t v = 0; v < nvox; ++v) {
-        double t[3];
-        for (int a = 0; a < 3; ++a) t[a] = qq[3 * v + a] - (double)cell[3 * v + a];
+        const double *t = tt + 3 * v;
         for (int cz = 0; cz < 2; ++cz)
             for (int cy = 0; cy < 2; ++cy)
                 for (int cx = 0; cx < 2; ++cx) {
@@ -836,28 +952,25 @@ void or_ngf_grad_T(const int64_t *n, const double *h, const int64_t *m, double e
     free(W);
     free(wv);
     free(cell);
-    free(qq);
+    free(tt);
 }
 
 /* ------------------------------------------------------------------------------ */
 /* Lung-boundary term, eq. 6: B = 1/2 int (b_M(y(x)) - b_F(x))^2 dx with the binary  */
 /* masks b_F (fixed, at the voxel centres) and b_M (moving, sampled at y(x_v) by      */
-/* trilinear interpolation with zero outside the volume, like grad T in eq. 1, in the  */
-/* cell decided by decide_cells_f32):                                                 */
+/* trilinear interpolation with zero outside the volume, like grad T in eq. 1):      */
 /*   res_v = b_M(y_v) - b_F(x_v),   B = 1/2 h^3 sum_v res_v^2.                        */
-/* With sb_v = grad b_M(y_v) (the gradient of the trilinear interpolant in mm,        */
-/* inside the decided cell):                                                          */
+/* With sb_v = grad b_M(y_v) (the gradient of the trilinear interpolant in mm, in    */
+/* the cell floor(q), one-sided on a face like JG in eq. 1):                          */
 /*   grad B = h^3 sum_v phi_v res_v sb_v,                                             */
 /*   Gauss-Newton matrix h^3 J^T J with J_v = phi_v sb_v^T (exact form of the SSD     */
 /*   Gauss-Newton matrix), diagonal h^3 sum_v phi_v^2 sb_v^2.                          */
 /* bF, bM are [N] volumes; u a node field; g, diag, sb ([N][3]), res ([N]) optional.  */
 /* Returns B.                                                                          */
 /* ------------------------------------------------------------------------------ */
-static void sample_scalar_at(const int64_t *n, const double *h, const double *f, const double q[3],
-                             const int64_t i0[3], double *val, double grad[3])
+static void sample_scalar_at(const int64_t *n, const double *h, const double *f, const int64_t i0[3],
+                             const double t[3], double *val, double grad[3])
 {
-    double t[3];
-    for (int a = 0; a < 3; ++a) t[a] = q[a] - (double)i0[a];
     *val = 0.0;
     grad[0] = grad[1] = grad[2] = 0.0;
     for (int cz = 0; cz < 2; ++cz)
@@ -892,14 +1005,12 @@ double or_mask(const int64_t *n, const double *h, const int64_t *m, const double
         for (int64_t j = 0; j < ny; ++j)
             for (int64_t i = 0; i < nx; ++i) {
                 const int64_t v = IDX3(i, j, k, nx, ny);
-                double uv[3], q[3], val;
-                interp_voxel(nn, m, u, i, j, k, uv);
-                q[0] = (double)i + uv[0] / h[0];
-                q[1] = (double)j + uv[1] / h[1];
-                q[2] = (double)k + uv[2] / h[2];
+                const int64_t idx[3] = {i, j, k};
+                double uh[3], t[3], val;
                 int64_t i0[3];
-                decide_cells_f32(nn, m, n, h, u, i, j, k, i0);
-                sample_scalar_at(n, h, bM, q, i0, &val, sb + 3 * v);
+                voxel_uh(nn, m, h, u, i, j, k, uh);
+                for (int q = 0; q < 3; ++q) split_axis(idx[q], uh[q], n[q], &i0[q], &t[q]);
+                sample_scalar_at(n, h, bM, i0, t, &val, sb + 3 * v);
                 res[v] = val - bF[v];
             }
     double B = 0.0;
@@ -928,6 +1039,74 @@ double or_mask(const int64_t *n, const double *h, const int64_t *m, const double
     free(res);
     free(sb);
     return B;
+}
+
+/* Sample-cell ties of the lung-boundary term (see or_ngf_ties for the tie rule): the  */
+/* sampled mask value is continuous across a face, its gradient sb is one-sided.  Per  */
+/* node: ag = sum_v phi_v max |h^3 res (sb'_c - sb_c)|, adg = sum_v phi_v^2             */
+/* max |h^3 (sb'_c^2 - sb_c^2)|, ahv = sum_v phi_v max |h^3 (sb'_c (sb'.w) - sb_c       */
+/* (sb.w))| with w = (Pv)(x_v); per voxel sbdev = max |sb'_c - sb_c|.  Returns the     */
+/* number of voxels with a tie.                                                       */
+int64_t or_mask_ties(const int64_t *n, const double *h, const int64_t *m, const double *bF, const double *bM,
+                     const double *u, const double *v, double *ag, double *adg, double *ahv, double *sbdev)
+{
+    const int64_t nx = n[0], ny = n[1], nz = n[2];
+    const int64_t nvox = nx * ny * nz;
+    int64_t nn[3];
+    node_counts(n, m, nn);
+    const int64_t nnodes = nn[0] * nn[1] * nn[2];
+    const double h3 = h[0] * h[1] * h[2];
+    if (ag) memset(ag, 0, sizeof(double) * 3 * nnodes);
+    if (adg) memset(adg, 0, sizeof(double) * 3 * nnodes);
+    if (ahv) memset(ahv, 0, sizeof(double) * 3 * nnodes);
+    if (sbdev) memset(sbdev, 0, sizeof(double) * 3 * nvox);
+    int64_t nt = 0;
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                const int64_t vox = IDX3(i, j, k, nx, ny);
+                const int64_t idx[3] = {i, j, k};
+                double uh[3], t0[3], at[3], w[3] = {0.0, 0.0, 0.0};
+                int64_t i00[3], ai[3];
+                voxel_uh(nn, m, h, u, i, j, k, uh);
+                const int mask = tie_axes(nn, m, n, h, u, i, j, k, uh, ai, at);
+                if (!mask) continue;
+                ++nt;
+                for (int a = 0; a < 3; ++a) split_axis(idx[a], uh[a], n[a], &i00[a], &t0[a]);
+                if (v) interp_voxel(nn, m, v, i, j, k, w);
+                double val0, sb0[3];
+                sample_scalar_at(n, h, bM, i00, t0, &val0, sb0);
+                const double res = val0 - bF[vox];
+                const double sw0 = sb0[0] * w[0] + sb0[1] * w[1] + sb0[2] * w[2];
+                double o[12] = {0.0};
+                for (int combo = 1; combo < 8; ++combo) {
+                    if (combo & ~mask) continue;
+                    int64_t i1[3];
+                    double t1[3], val1, sb1[3];
+                    for (int a = 0; a < 3; ++a) {
+                        i1[a] = (combo >> a & 1) ? ai[a] : i00[a];
+                        t1[a] = (combo >> a & 1) ? at[a] : t0[a];
+                    }
+                    sample_scalar_at(n, h, bM, i1, t1, &val1, sb1);
+                    const double sw1 = sb1[0] * w[0] + sb1[1] * w[1] + sb1[2] * w[2];
+                    for (int q = 0; q < 3; ++q) {
+                        const double dg = fabs(h3 * res * (sb1[q] - sb0[q]));
+                        const double dd = fabs(h3 * (sb1[q] * sb1[q] - sb0[q] * sb0[q]));
+                        const double dh = fabs(h3 * (sb1[q] * sw1 - sb0[q] * sw0));
+                        const double ds = fabs(sb1[q] - sb0[q]);
+                        if (dg > o[q]) o[q] = dg;
+                        if (dd > o[3 + q]) o[3 + q] = dd;
+                        if (dh > o[6 + q]) o[6 + q] = dh;
+                        if (ds > o[9 + q]) o[9 + q] = ds;
+                    }
+                }
+                if (ag) scatter_voxel(nn, m, ag, i, j, k, o, 0);
+                if (adg) scatter_voxel(nn, m, adg, i, j, k, o + 3, 1);
+                if (ahv) scatter_voxel(nn, m, ahv, i, j, k, o + 6, 0);
+                if (sbdev)
+                    for (int q = 0; q < 3; ++q) sbdev[3 * vox + q] = o[9 + q];
+            }
+    return nt;
 }
 
 /* ------------------------------------------------------------------------------ */

@@ -630,51 +630,71 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
   return DISCO_OK;
 }
 
+}  // extern "C"
+
+// central-difference gradient volume of one image (which = 0: R into gR, 1: T into gT);
+// FP16 storage first finds the image's power-of-two scale (max |grad| * scale <= 2^14)
+static int build_gradient(disco_ctx *c, const float *img, int which, hipStream_t s) {
+  const Geo &g = c->g;
+  if (c->storage == DISCO_STORAGE_FP16) {
+    const unsigned nb = nblk(g.nvox);
+    double *blk = nullptr;
+    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&blk), sizeof(double) * nb, s));
+    hipLaunchKernelGGL(k_absmax_grad, dim3(nb), dim3(256), 0, s, g, img, blk);
+    launch_reduce(blk, nb, 1, 1, 1u, c->sc + SC_TMP0, nullptr, s);
+    double mx = 0.0;
+    HIP_TRY(hipMemcpyAsync(&mx, c->sc + SC_TMP0, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipFreeAsync(blk, s));
+    int ex = 0;
+    if (mx > 0.0 && std::isfinite(mx)) ex = (int)std::floor(std::log2(16384.0 / mx));
+    ex = std::max(-100, std::min(100, ex));
+    const float scale = std::ldexp(1.0f, ex);
+    if (which == 0) {
+      c->sR = 1.0f / scale;
+    } else {
+      c->sT = 1.0f / scale;
+      c->max_gT = mx;
+    }
+    hipLaunchKernelGGL(k_imgrad<F16x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, img,
+                       reinterpret_cast<__half *>(which == 0 ? c->gR : c->gT), scale);
+  } else {
+    hipLaunchKernelGGL(k_imgrad<F32x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, img,
+                       reinterpret_cast<float *>(which == 0 ? c->gR : c->gT), 1.0f);
+  }
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+extern "C" {
+
 int disco_set_images(disco_ctx *c, const float *R, const float *T, disco_stream stream) {
   if (!c) return DISCO_ERR_ARG;
   int e;
   if ((e = check_field(R)) || (e = check_field(T))) return e;
   if ((e = set_device(c))) return e;
   hipStream_t s = S(stream);
-  const Geo &g = c->g;
   ProfScope ps(c, 3, s);
-  if (c->storage == DISCO_STORAGE_FP16) {
-    // per-volume power-of-two scale so that max |grad| * scale <= 2^14
-    const unsigned nb = nblk(g.nvox);
-    double *blk = nullptr;
-    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&blk), sizeof(double) * nb, s));
-    float scales[2];
-    double maxes[2] = {0.0, 0.0};
-    const float *imgs[2] = {R, T};
-    for (int k = 0; k < 2; ++k) {
-      hipLaunchKernelGGL(k_absmax_grad, dim3(nb), dim3(256), 0, s, g, imgs[k], blk);
-      launch_reduce(blk, nb, 1, 1, 1u, c->sc + SC_TMP0, nullptr, s);
-      double mx = 0.0;
-      HIP_TRY(hipMemcpyAsync(&mx, c->sc + SC_TMP0, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      int ex = 0;
-      if (mx > 0.0 && std::isfinite(mx)) ex = (int)std::floor(std::log2(16384.0 / mx));
-      ex = std::max(-100, std::min(100, ex));
-      scales[k] = std::ldexp(1.0f, ex);
-      maxes[k] = mx;
-    }
-    HIP_TRY(hipFreeAsync(blk, s));
-    c->sR = 1.0f / scales[0];
-    c->sT = 1.0f / scales[1];
-    c->max_gT = maxes[1];
-    hipLaunchKernelGGL(k_imgrad<F16x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, R, reinterpret_cast<__half *>(c->gR),
-                       scales[0]);
-    hipLaunchKernelGGL(k_imgrad<F16x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, T, reinterpret_cast<__half *>(c->gT),
-                       scales[1]);
-  } else {
-    hipLaunchKernelGGL(k_imgrad<F32x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, R, reinterpret_cast<float *>(c->gR),
-                       1.0f);
-    hipLaunchKernelGGL(k_imgrad<F32x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, T, reinterpret_cast<float *>(c->gT),
-                       1.0f);
-  }
-  HIP_TRY(hipGetLastError());
-  c->images = true;
+  c->images = false;
   c->lin = false;
+  if ((e = build_gradient(c, R, 0, s)) || (e = build_gradient(c, T, 1, s))) return e;
+  c->images = true;
+  return DISCO_OK;
+}
+
+int disco_set_moving(disco_ctx *c, const float *T, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_field(T))) return e;
+  if (!c->images) return DISCO_ERR_STATE;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  ProfScope ps(c, 3, s);
+  c->lin = false;
+  if ((e = build_gradient(c, T, 1, s))) {
+    c->images = false;
+    return e;
+  }
   return DISCO_OK;
 }
 
@@ -1265,6 +1285,30 @@ int objective_linearise(disco_ctx *c, const disco_params *p, const float *u, dou
   if (g) HIP_TRY(hipMemcpyAsync(g, c->vg, nf, hipMemcpyDeviceToDevice, s));
   if (diag) HIP_TRY(hipMemcpyAsync(diag, c->vdiag, nf, hipMemcpyDeviceToDevice, s));
   if (terms_dev) hipLaunchKernelGGL(k_terms, dim3(1), dim3(1), 0, s, c->sc, ch_of(c), terms_dev);
+  HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+int objective_eval(disco_ctx *c, const disco_params *p, const float *u, double *terms_dev, disco_stream stream) {
+  if (!c || !terms_dev) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_params(p))) return e;
+  if ((e = check_field(u))) return e;
+  if ((reinterpret_cast<uintptr_t>(terms_dev) & 7u) != 0) return DISCO_ERR_SHAPE;
+  if (!c->images) return DISCO_ERR_STATE;
+  if ((e = set_device(c))) return e;
+  hipStream_t s = S(stream);
+  PostArgs pa = post_args(c, p->alpha, p->gamma, p->delta);
+  pa.beta = c->masks ? p->beta : 0.0;
+  pa.dst = terms_dev;
+  const bool vcc = p->gamma != 0.0;
+  const bool kp = p->delta != 0.0 && c->nkp > 0;
+  launch_curv_L(c, u, c->u_ref, c->Lw, true, nullptr, s);
+  BrickCall b{M_EVAL, true, vcc, kp, (float)(p->eta * p->eta), (float)p->gamma, (float)p->delta, u, nullptr, nullptr,
+              nullptr, nullptr};
+  b.beta = p->beta;
+  launch_brick(c, b, s);
+  launch_finish(POST_EVAL, pa, nullptr, s, src_brick(c, c->sc + SC_TMP0), src_curv(c, c->sc + SC_ESRAW));
   HIP_TRY(hipGetLastError());
   return DISCO_OK;
 }

@@ -167,7 +167,8 @@ enum {
   POST_LS_BEGIN,   // g^T p -> start of the line search
   POST_STORE,      // out values only
   POST_LB_PAIR,    // s.y, s.s, y.y of a new L-BFGS pair -> rho (0 if s.y <= eps |s||y|)
-  POST_LB_ALPHA    // alpha_idx = rho_idx * (s_idx . q)
+  POST_LB_ALPHA,   // alpha_idx = rho_idx * (s_idx . q)
+  POST_EVAL        // objective only: J and its terms -> dst[0..7] (J, D, S, V, K, B, folds, NaN)
 };
 
 struct PostArgs {
@@ -200,13 +201,14 @@ enum {
   SC_JT, SC_DT, SC_ST, SC_VT, SC_KT,           // accepted (or last) trial values
   SC_TMP0, SC_TMP1, SC_TMP2, SC_TMP3, SC_TMP4,
   SC_B, SC_TB,                                 // lung-boundary term B at the linearisation / trial point
+  SC_ESRAW,                                    // sum (L(u - uhat))^2 of an objective-only evaluation
   SC_LB_RHO = 48,     // L-BFGS: rho_i = 1 / s_i.y_i of the stored pairs (0: pair skipped)
   SC_LB_ALPHA = 56,   // L-BFGS: alpha_i of the first loop
   SC_LB_DOT = 64,     // L-BFGS: dot product scratch
   SC_COUNT = 72
 };
 constexpr int kLbfgsMax = 8;  // longest L-BFGS history
-static_assert(SC_TB < SC_LB_RHO && SC_TMP0 + kRedVals - 1 == SC_TMP4 && SC_LB_RHO + kLbfgsMax <= SC_LB_ALPHA && SC_LB_ALPHA + kLbfgsMax <= SC_LB_DOT &&
+static_assert(SC_ESRAW < SC_LB_RHO && SC_TMP0 + kRedVals - 1 == SC_TMP4 && SC_LB_RHO + kLbfgsMax <= SC_LB_ALPHA && SC_LB_ALPHA + kLbfgsMax <= SC_LB_DOT &&
                   SC_LB_DOT < SC_COUNT,
               "scalar slots overlap");
 
@@ -266,6 +268,18 @@ __device__ inline void run_post(int post, const PostArgs &a, const double *r) {
     case POST_LB_ALPHA:
       sc[SC_LB_ALPHA + a.idx] = sc[SC_LB_RHO + a.idx] * r[0];
       break;
+    case POST_EVAL: {
+      const double D = r[0] * a.h3, B = 0.5 * a.h3 * r[4];
+      a.dst[0] = total_J(a, D, sc[SC_ESRAW], r[1], r[2], r[3], B);
+      a.dst[1] = D;
+      a.dst[2] = 0.5 * a.CH * sc[SC_ESRAW];
+      a.dst[3] = r[3] > 0.0 ? INFINITY : r[1];
+      a.dst[4] = r[2];
+      a.dst[5] = B;
+      a.dst[6] = r[3];
+      a.dst[7] = NAN;
+      break;
+    }
     case POST_LS_BEGIN:
       // residual of the last completed CG update (its partials were reduced into SC_TMP1)
       if (sc[SC_ITERS] > 0.0) sc[SC_RR] = sc[SC_TMP1 + 1];

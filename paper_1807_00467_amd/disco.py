@@ -71,6 +71,7 @@ _SIGS = {
     "disco_create": ([ctypes.POINTER(_Geom), _I, ctypes.POINTER(_P)], ctypes.c_int),
     "disco_destroy": ([_P], None),
     "disco_set_images": ([_P, _P, _P, _P], ctypes.c_int),
+    "disco_set_moving": ([_P, _P, _P], ctypes.c_int),
     "disco_set_keypoints": ([_P, _I, _P, _P, _P], ctypes.c_int),
     "disco_set_reference": ([_P, _P, _P], ctypes.c_int),
     "ngf_eval": ([_P, _D, _P, _P, _P], ctypes.c_int),
@@ -91,6 +92,7 @@ _SIGS = {
     "disco_kp_cost": ([_P, _I, _P, _I, _P, _P], ctypes.c_int),
     "disco_kp_regularise": ([_P, _I, _P, _P, _I, _P, _D, _D, _P, _P, _P, _P], ctypes.c_int),
     "objective_linearise": ([_P, ctypes.POINTER(_Params), _P, _P, _P, _P, _P], ctypes.c_int),
+    "objective_eval": ([_P, ctypes.POINTER(_Params), _P, _P, _P], ctypes.c_int),
     "pyramid_plan": ([_P, _P, _I, _P, _P, _P, _P], ctypes.c_int),
     "pyramid_downsample": ([_P, _P, _P, _P, _P, _P], ctypes.c_int),
     "pyramid_prolong": ([_P, _P, _P, _P, _P], ctypes.c_int),
@@ -165,6 +167,22 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+class _Token:
+    """Identity of a tensor's contents at one moment.  The token keeps the tensor alive, so
+    no other allocation can take its address: a tensor with the same address, shape,
+    strides and in-place version (shared by every view of the same storage) holds the
+    same values."""
+
+    def __init__(self, t: torch.Tensor):
+        self.t = t
+        self.version = t._version
+
+    def same(self, x: torch.Tensor) -> bool:
+        t = self.t
+        return (x.data_ptr() == t.data_ptr() and x.device == t.device and x.dtype == t.dtype
+                and tuple(x.shape) == tuple(t.shape) and x.stride() == t.stride() and x._version == self.version)
+
+
 class Disco:
     """One image-pair context on the current (or given) HIP device."""
 
@@ -182,6 +200,7 @@ class Disco:
             _check(_lib.disco_create(ctypes.byref(geom), self.storage, ctypes.byref(h)), "disco_create")
         self._h = h
         self._scalars = torch.zeros(64, dtype=torch.float64, device=self.device)
+        self._images = None
         self._ints = torch.zeros(8, dtype=torch.int32, device=self.device)
 
     def close(self):
@@ -221,8 +240,30 @@ class Disco:
 
     # ---- state --------------------------------------------------------------------------
     def set_images(self, R: torch.Tensor, T: torch.Tensor):
+        self._images = None
         _check(_lib.disco_set_images(self._h, _ptr(self._volume(R, "R")), _ptr(self._volume(T, "T")),
                                      self._stream()), "disco_set_images")
+        self._images = (_Token(R), _Token(T))
+
+    def set_moving(self, T: torch.Tensor):
+        """Replace T only (grad R is kept)."""
+        R = self._images[0] if self._images else None
+        self._images = None
+        _check(_lib.disco_set_moving(self._h, _ptr(self._volume(T, "T")), self._stream()), "disco_set_moving")
+        if R is not None:
+            self._images = (R, _Token(T))
+
+    def holds_images(self, R: torch.Tensor, T: torch.Tensor) -> bool:
+        """Whether the gradient volumes were built from these very tensors, unmodified since."""
+        return self._images is not None and self._images[0].same(R) and self._images[1].same(T)
+
+    def use_images(self, R: torch.Tensor, T: torch.Tensor):
+        """Make (R, T) the context's images, rebuilding only what changed."""
+        if self._images is not None and self._images[0].same(R):
+            if not self._images[1].same(T):
+                self.set_moving(T)
+        else:
+            self.set_images(R, T)
 
     def set_keypoints(self, x_mm, t_mm):
         import numpy as np
@@ -245,18 +286,28 @@ class Disco:
                 raise ValueError("masks must be contiguous uint8 CUDA tensors [Nz][Ny][Nx]")
         _check(_lib.disco_set_masks(self._h, _ptr(bF), _ptr(bM), self._stream()), "disco_set_masks")
 
-    def objective_linearise(self, params: Params, u: torch.Tensor, grad: bool = True, diag: bool = True):
-        """J and its terms (dict of TERM_FIELDS), grad J and the GN diagonal at u (sets the
-        linearisation used by gn_hessvec)."""
-        terms = torch.zeros(8, dtype=torch.float64, device=self.device)
+    def objective_linearise(self, params: Params, u: torch.Tensor, grad: bool = True, diag: bool = True,
+                            terms: bool = True):
+        """J and its terms (dict of TERM_FIELDS, read back to the host when `terms`), grad J and
+        the GN diagonal at u (sets the linearisation used by gn_hessvec)."""
+        tv = torch.zeros(8, dtype=torch.float64, device=self.device) if terms else None
         g = torch.empty_like(u) if grad else None
         d = torch.empty_like(u) if diag else None
         p = params.c()
-        _check(_lib.objective_linearise(self._h, ctypes.byref(p), _ptr(self._field(u, "u")), _ptr(terms), _ptr(g),
+        _check(_lib.objective_linearise(self._h, ctypes.byref(p), _ptr(self._field(u, "u")), _ptr(tv), _ptr(g),
                                         _ptr(d), self._stream()), "objective_linearise")
-        out = dict(zip(TERM_FIELDS, terms.cpu().tolist()))
+        out = dict(zip(TERM_FIELDS, tv.cpu().tolist())) if terms else {}
         out["g"] = g
         out["diag"] = d
+        return out
+
+    def objective_eval(self, params: Params, u: torch.Tensor, terms: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """J and its terms at u, no derivatives: device float64 tensor [8] in TERM_FIELDS order
+        (gnorm NaN); the linearisation is left unchanged."""
+        out = torch.empty(8, dtype=torch.float64, device=self.device) if terms is None else terms
+        p = params.c()
+        _check(_lib.objective_eval(self._h, ctypes.byref(p), _ptr(self._field(u, "u")), _ptr(out), self._stream()),
+               "objective_eval")
         return out
 
     def set_reference(self, u_ref: Optional[torch.Tensor]):

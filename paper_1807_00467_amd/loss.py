@@ -2,10 +2,17 @@
 
 L(u, T) = D_NGF(R, T(y)) + alpha S(u) + gamma Vhat(u)  (eq. 1, 5, 9; eq. 11 without the
 keypoint and lung-boundary terms), with y = x + u trilinear on the 4-voxel node grid.
-The forward pass evaluates the objective with the library's kernels; the backward pass
-returns the hand-written adjoints: dL/du from the gradient passes (ngf_grad,
-curvature_apply, volchange_eval) and dL/dT from ngf_grad_T.  Nothing is recorded on
-PyTorch's tape inside: this Function is the whole derivative.
+The forward pass evaluates the objective with the library (objective_eval); the backward
+pass returns the hand-written adjoints: dL/du from the library's linearisation
+(objective_linearise) and dL/dT from ngf_grad_T.  Nothing is recorded on PyTorch's tape
+inside: this Function is the whole derivative, and the binding only scales the library's
+gradients by the incoming gradient (the chain rule).
+
+The context keeps the gradient volumes of one (R, T) pair.  The forward pass saves R and
+T, and the backward pass rebuilds the context's volumes from them when the context has
+been given other images in between (several forward passes on one context before one
+backward pass, gradient accumulation); autograd's version check rejects a T modified in
+place after the forward pass.
 """
 from __future__ import annotations
 
@@ -13,40 +20,39 @@ from typing import Sequence
 
 import torch
 
-from .disco import Disco
+from .disco import Disco, Params
 
 
 class NGFLossFn(torch.autograd.Function):
-    """loss = D + alpha S + gamma Vhat for one pair; R is fixed in the context."""
+    """loss = D + alpha S + gamma Vhat for one pair."""
 
     @staticmethod
     def forward(fctx, u: torch.Tensor, T: torch.Tensor, ctx: Disco, R: torch.Tensor, eta: float, alpha: float,
                 gamma: float):
         u = u.detach().contiguous()
-        T = T.detach().contiguous()
-        ctx.set_images(R, T)
-        D = ctx.ngf_eval(u, eta)
-        S, _, _ = ctx.curvature_apply(alpha, u, None, energy=True, grad=False, diag=False)
-        V = ctx.volchange_eval(gamma, u, None, energy=True, grad=False, diag=False)["V"]
+        Td = T.detach()
+        Tc = Td.contiguous()
+        ctx.use_images(R, Tc)
+        params = Params(eta=eta, alpha=alpha, gamma=gamma, delta=0.0, beta=0.0)
+        terms = ctx.objective_eval(params, u)
         fctx.disco = ctx
-        fctx.consts = (eta, alpha, gamma)
-        fctx.save_for_backward(u)
-        return (D + S + V)[0]
+        fctx.params = params
+        # Tc is T itself when T is contiguous, so the saved tensor keeps T's version check
+        fctx.save_for_backward(u, Tc, R)
+        return terms[0].clone()
 
     @staticmethod
     def backward(fctx, grad_out: torch.Tensor):
-        (u,) = fctx.saved_tensors
+        u, T, R = fctx.saved_tensors
         ctx: Disco = fctx.disco
-        eta, alpha, gamma = fctx.consts
+        params: Params = fctx.params
         need_u, need_T = fctx.needs_input_grad[0], fctx.needs_input_grad[1]
+        ctx.use_images(R, T)
         gu = gT = None
         if need_u:
-            _, g, _ = ctx.ngf_grad(u, eta, diag=False)
-            _, gs, _ = ctx.curvature_apply(alpha, u, None, energy=False, grad=True, diag=False)
-            gv = ctx.volchange_eval(gamma, u, None, energy=False, grad=True, diag=False)["g"]
-            gu = (g + gs + gv) * grad_out
+            gu = ctx.objective_linearise(params, u, grad=True, diag=False, terms=False)["g"] * grad_out
         if need_T:
-            gT = ctx.ngf_grad_T(u, eta) * grad_out
+            gT = ctx.ngf_grad_T(u, params.eta) * grad_out
         return gu, gT, None, None, None, None, None
 
 
@@ -59,7 +65,8 @@ def ngf_loss(ctx: Disco, u: torch.Tensor, T: torch.Tensor, R: torch.Tensor, eta:
 class NGFLoss(torch.nn.Module):
     """Sum of the pair losses over a batch of pairs with a shared geometry.
 
-    One library context per pair keeps each pair's gradient volumes resident."""
+    One library context per pair keeps that pair's grad R resident: a forward pass
+    rebuilds only grad T (and grad R only when a different fixed image is given)."""
 
     def __init__(self, shape: Sequence[int], spacing: Sequence[float], fixed: Sequence[torch.Tensor],
                  eta: float = 10.0, alpha: float = 1.0, gamma: float = 0.1, storage: str = "fp32"):
@@ -70,7 +77,6 @@ class NGFLoss(torch.nn.Module):
 
     def forward(self, u: torch.Tensor, T: torch.Tensor) -> torch.Tensor:
         """u: [B][3][nz][ny][nx], T: [B][Nz][Ny][Nx]."""
-        total = u.new_zeros(())
-        for b, (ctx, R) in enumerate(zip(self.ctxs, self.fixed)):
-            total = total + ngf_loss(ctx, u[b], T[b], R, self.eta, self.alpha, self.gamma)
-        return total
+        losses = [ngf_loss(ctx, u[b], T[b], R, self.eta, self.alpha, self.gamma)
+                  for b, (ctx, R) in enumerate(zip(self.ctxs, self.fixed))]
+        return torch.stack(losses).sum()

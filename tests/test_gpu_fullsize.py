@@ -1,36 +1,31 @@
 """Full-size parity on the workloads the benchmark times.
 
 512 x 512 x 128 at 0.7 x 0.7 x 2.5 mm (node grid 129 x 129 x 33, 2000 keypoints), FP32
-storage, linearised at the true displacement with the benchmark's weights: the whole
-gradient, GN diagonal and GN product fields and one full GN step are compared with the
-FP64 oracle.  512 x 512 x 256 at 0.7 x 0.7 x 1.25 mm checks the largest case in both
-storage forms.
+storage, with the benchmark's weights, linearised at the true displacement (whose
+x component is near zero over much of the volume, so many warped points sit within
+single-precision rounding of a cell face: compared beyond the oracle's tie allowance)
+and at a generic point 0.0137 mm off it (ties only on the thin surfaces where u/h
+crosses an integer): the whole gradient, GN diagonal and
+GN product fields, element by element, and one full GN step are compared with the FP64
+oracle.  512 x 512 x 256 at 0.7 x 0.7 x 1.25 mm checks the largest case in both storage
+forms.
 """
-import sys
-
 import numpy as np
 import pytest
 import torch
 
 import oracle
 import synth
+from tests.fields import check_field, rel, say, say_ties
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 DEV = torch.device("cuda:0")
 ETA, ALPHA, GAMMA = 10.0, 1.0, 0.1
+GENERIC = np.float32(0.0137)
 
 
-def say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
-
-
-def rel_l2(a, b):
-    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
-
-
-def rel(a, b):
-    return abs(float(a) - float(b)) / abs(float(b))
+def point(d, name):
+    return d["u_true"] if name == "true" else (d["u_true"] + GENERIC).astype(np.float32)
 
 
 @pytest.fixture(scope="module")
@@ -62,38 +57,49 @@ def test_fullsize_adaptive_delta(cfg1):
     assert rel(D0 / K0, P.w.delta) < 1e-5
 
 
-def test_fullsize_linearisation_and_gn_product(cfg1, disco):
+@pytest.mark.parametrize("where", ["true", "generic"])
+def test_fullsize_linearisation_and_gn_product(cfg1, disco, where):
     d, P, ctx, params = cfg1
-    say("[fullsize] ngf_grad + gn_hessvec at u_true")
-    u = torch.from_numpy(d["u_true"]).to(DEV)
+    say(f"[fullsize] ngf_grad + gn_hessvec at u_{where}")
+    u0 = point(d, where)
+    u = torch.from_numpy(u0).to(DEV)
     D, g, diag = ctx.ngf_grad(u, ETA)
-    hv = ctx.gn_hessvec(params, torch.from_numpy(d["v"]).to(DEV)).cpu().numpy()
-    lin = P.linearise(d["u_true"].astype(np.float64))
-    nd = P.ngf(d["u_true"], want=("g", "diag"))
+    hv = ctx.gn_hessvec(params, torch.from_numpy(d["v"]).to(DEV))
+    torch.cuda.synchronize()
+    u64 = u0.astype(np.float64)
+    lin = P.linearise(u64)
+    nd = P.ngf(u64, want=("g", "diag"))
     ref_hv = P.gn_hv(d["v"].astype(np.float64))
-    eD, eg, ediag, ehv = rel(D.item(), lin["D"]), rel_l2(g.cpu().numpy(), nd["g"]), \
-        rel_l2(diag.cpu().numpy(), nd["diag"]), rel_l2(hv, ref_hv)
-    say(f"  D rel {eD:.2e}  grad rel-L2 {eg:.2e}  diag rel-L2 {ediag:.2e}  GN Hv rel-L2 {ehv:.2e}")
-    assert eD < 1e-5 and eg < 1e-4 and ediag < 1e-4 and ehv < 1e-4
+    ties = P.ties(u64, d["v"])
+    say_ties(where, ties)
+    if where == "generic":
+        # off the true displacement only the voxels where u/h crosses an integer within
+        # rounding remain: a thin set of surfaces
+        assert ties["n"] < 1e-4 * np.prod(d["shape"])
+    eD = rel(D.item(), lin["D"])
+    say(f"  D rel {eD:.2e}")
+    assert eD < 1e-5
+    check_field("grad", g, nd["g"], ties["g"], 1e-4)
+    check_field("diag", diag, nd["diag"], ties["diag"], 1e-4)
+    check_field("GN Hv", hv, ref_hv, ties["hv"], 1e-4)
 
 
 def test_fullsize_gn_step(cfg1, disco):
     d, P, ctx, params = cfg1
-    say("[fullsize] gn_pcg_step from u_true")
-    u = torch.from_numpy(d["u_true"]).to(DEV)
+    say("[fullsize] gn_pcg_step from u_true + 0.0137 mm")
+    u0 = point(d, "generic")
+    u = torch.from_numpy(u0.copy()).to(DEV)
     rep, st = ctx.gn_pcg_step(params, u)
     r = disco.Disco.report_dict(rep)
-    u1, ref = oracle.gn_pcg_step(P, d["u_true"].astype(np.float64), oracle.StepParams(pcg_iters=20))
+    u1, ref = oracle.gn_pcg_step(P, u0.astype(np.float64), oracle.StepParams(pcg_iters=20))
     say(f"  gpu J {r['J']:.8e} t={r['t']} J_new {r['J_new']:.8e}; oracle J {ref['J']:.8e} t={ref['t']} "
         f"J_new {ref['trial']['J']:.8e}")
     assert int(st.item()) == 0
     for k in ("J", "D", "S", "V", "K"):
         assert rel(r[k], ref[k]) < 1e-5, k
     assert r["t"] == ref["t"]
-    step = u.cpu().numpy().astype(np.float64) - d["u_true"]
-    es = rel_l2(step, u1 - d["u_true"])
-    say(f"  step rel-L2 {es:.2e}")
-    assert es < 1e-3
+    step = u.cpu().numpy().astype(np.float64) - u0
+    check_field("step", step, u1 - u0, None, 1e-3)
     assert rel(r["J_new"], ref["trial"]["J"]) < 1e-4
 
 
@@ -105,12 +111,18 @@ def test_largest_case_both_storages(disco, storage, tol_D, tol_f):
     ctx.set_images(torch.from_numpy(d["R"]).to(DEV), torch.from_numpy(d["T"]).to(DEV))
     u = torch.from_numpy(d["u_true"]).to(DEV)
     D, g, _ = ctx.ngf_grad(u, ETA)
-    hv = ctx.ngf_hessvec(torch.from_numpy(d["v"]).to(DEV)).cpu().numpy()
+    hv = ctx.ngf_hessvec(torch.from_numpy(d["v"]).to(DEV))
+    torch.cuda.synchronize()
     gR = oracle.image_gradient(d["R"], d["spacing"])
     gT = oracle.image_gradient(d["T"], d["spacing"])
     ref = oracle.ngf(gR, gT, d["spacing"], ETA, d["u_true"], want=("g", "s"))
     ref_hv = oracle.ngf_hv(ref["s"], d["spacing"], d["v"])
-    eD, eg, eh = rel(D.item(), ref["D"]), rel_l2(g.cpu().numpy(), ref["g"]), rel_l2(hv, ref_hv)
-    say(f"  D rel {eD:.2e}  grad rel-L2 {eg:.2e}  NGF Hv rel-L2 {eh:.2e}")
-    assert eD < tol_D and eg < tol_f and eh < tol_f
+    ties = oracle.ngf_ties(gR, gT, d["spacing"], ETA, d["u_true"], d["v"])
+    say_ties("true", ties)
+    eD = rel(D.item(), ref["D"])
+    say(f"  D rel {eD:.2e}")
+    assert eD < tol_D
+    # FP16 storage: the element-wise bound is the form's documented relative accuracy
+    check_field("grad", g, ref["g"], ties["g"], tol_f, elem_tol=10 * tol_f if storage == "fp16" else None)
+    check_field("NGF Hv", hv, ref_hv, ties["hv"], tol_f, elem_tol=10 * tol_f if storage == "fp16" else None)
     ctx.close()

@@ -1,7 +1,8 @@
 """Keypoint stage (Sec. II-C2, II-C3) on the device against the FP64 oracle: the NGF
 matching cost of eq. 2 over all 33^3 displacements (keypoints in the interior, at the
 border and of every voxel parity), sampled at the benchmark's workload, and the
-regularisation by min-sum belief propagation on the keypoint MST."""
+regularisation by min-sum belief propagation on the keypoint MST, where both sides take
+the oracle's cost volume as the data term."""
 import sys
 
 import numpy as np
@@ -72,7 +73,9 @@ def test_kp_regularise_matches_oracle(disco):
     d = synth.small_pair(shape=(64, 56, 44), spacing=(1.0, 1.0, 1.0), seed=42, n_tubes=10, n_kp=40, field_max=4.0)
     st = stage(disco, d)
     kps = vox_of(d)
-    cost = st.cost(torch.from_numpy(kps).to(DEV), 16)
+    # both sides regularise the oracle's data cost (single precision, the device's input type)
+    D32 = oracle.kp_cost_volume(d["R"], d["T"], d["spacing"], kps, ETA, R=16, step=2).astype(np.float32)
+    cost = torch.from_numpy(D32).to(DEV)
     x = (kps + 0.5) * np.asarray(d["spacing"])
     inten = d["R"][kps[:, 2], kps[:, 1], kps[:, 0]]
     alpha = 1.0 / 45.0
@@ -80,8 +83,8 @@ def test_kp_regularise_matches_oracle(disco):
     torch.cuda.synchronize()
     parent, order = oracle.kp_mst(x.astype(np.float32), inten)
     np.testing.assert_array_equal(par, parent)
-    D = cost.cpu().numpy().astype(np.float64)  # the same data cost on both sides
-    om, _ = oracle.kp_belief_propagation(D, parent, order, x.astype(np.float32), inten, alpha, R=16, step=2)
+    om, _ = oracle.kp_belief_propagation(D32.astype(np.float64), parent, order, x.astype(np.float32), inten, alpha,
+                                         R=16, step=2)
     gm = marg.cpu().numpy()
     scale = np.max(np.abs(om), axis=1, keepdims=True)
     err = float(np.max(np.abs(gm - om) / scale))
@@ -131,15 +134,15 @@ def test_kp_tree_and_messages_at_scale(disco, n):
     flat = r.choice(nx * ny * nz, n, replace=False)  # distinct keypoints
     kps = np.stack([flat % nx, (flat // nx) % ny, flat // (nx * ny)], 1).astype(np.int32)
     st = stage(disco, d)
-    cost = st.cost(torch.from_numpy(kps).to(DEV), 1)
+    D32 = oracle.kp_cost_volume(d["R"], d["T"], d["spacing"], kps, ETA, R=1, step=2).astype(np.float32)
+    cost = torch.from_numpy(D32).to(DEV)
     x = (kps + 0.5).astype(np.float32)
     inten = d["R"][kps[:, 2], kps[:, 1], kps[:, 0]]
     marg, lab, par = st.regularise(x, inten, cost, 1, 1.0 / 45.0, 150.0)
     torch.cuda.synchronize()
     parent, order = oracle.kp_mst(x, inten)
     np.testing.assert_array_equal(par, parent)
-    om, _ = oracle.kp_belief_propagation(cost.cpu().numpy().astype(np.float64), parent, order, x, inten, 1.0 / 45.0,
-                                         R=1, step=2)
+    om, _ = oracle.kp_belief_propagation(D32.astype(np.float64), parent, order, x, inten, 1.0 / 45.0, R=1, step=2)
     gm = marg.cpu().numpy()
     err = float(np.max(np.abs(gm - om) / np.max(np.abs(om), axis=1, keepdims=True)))
     say(f"  tree depth {tree_depth(parent, order)}; marginals max rel error {err:.2e}")
@@ -220,7 +223,9 @@ def test_kp_regularise_fullsize_invariants(disco):
     d = synth.make_pair("kp")
     st = stage(disco, d)
     kps = vox_of(d)
-    cost = st.cost(torch.from_numpy(kps).to(DEV), 16)
+    # both sides regularise the oracle's data cost (single precision, the device's input type)
+    D32 = oracle.kp_cost_volume(d["R"], d["T"], d["spacing"], kps, ETA, R=16, step=2).astype(np.float32)
+    cost = torch.from_numpy(D32).to(DEV)
     x = (kps + 0.5) * np.asarray(d["spacing"])
     inten = d["R"][kps[:, 2], kps[:, 1], kps[:, 0]]
     alpha = 1.0 / 45.0
