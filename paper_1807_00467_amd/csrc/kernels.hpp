@@ -75,6 +75,19 @@ struct Geo {
 struct F32x3 {
   typedef float elem;
   static constexpr int W = 3;  // elements per voxel
+  // a voxel's stored words, loaded now and converted later (lets a pass request many
+  // loads before it uses the first)
+  struct raw {
+    float x, y, z;
+  };
+  __device__ static inline raw fetch(const float *q) { return raw{q[0], q[1], q[2]}; }
+  __device__ static inline void unpack(const raw &r, const float *q, float s, float o[3]) {
+    o[0] = r.x;
+    o[1] = r.y;
+    o[2] = r.z;
+    (void)q;
+    (void)s;
+  }
   __device__ static inline void loadp(const float *q, float s, float o[3]) {
     o[0] = q[0];
     o[1] = q[1];
@@ -110,6 +123,20 @@ struct F32x3 {
 struct F16x3 {
   typedef __half elem;
   static constexpr int W = 3;  // elements per voxel
+  struct raw {
+    uint2 w;
+  };
+  __device__ static inline raw fetch(const __half *q) {
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(q);
+    return raw{*reinterpret_cast<const uint2 *>(addr & ~(uintptr_t)3)};
+  }
+  __device__ static inline void unpack(const raw &r, const __half *q, float s, float o[3]) {
+    const uintptr_t addr = reinterpret_cast<uintptr_t>(q);
+    const uint64_t v = ((uint64_t)r.w.y << 32 | r.w.x) >> ((addr & 3u) * 8u);
+    o[0] = __half2float(__ushort_as_half((unsigned short)(v & 0xFFFFu))) * s;
+    o[1] = __half2float(__ushort_as_half((unsigned short)((v >> 16) & 0xFFFFu))) * s;
+    o[2] = __half2float(__ushort_as_half((unsigned short)((v >> 32) & 0xFFFFu))) * s;
+  }
   __device__ static inline void loadp(const __half *q, float s, float o[3]) {
     const uintptr_t addr = reinterpret_cast<uintptr_t>(q);
     const uint2 w = *reinterpret_cast<const uint2 *>(addr & ~(uintptr_t)3);
@@ -1159,6 +1186,17 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
             }
             const typename ST::elem *sp = A.sc + vbase * ST::W;
             const typename ST::elem *rp = A.gR + vbase * ST::W;
+            // GN product: the layer's 16 s rows are requested before the first is used, so
+            // that a wave keeps 12 KB in flight (the scheduler otherwise interleaves loads and
+            // arithmetic and keeps only a few rows outstanding)
+            typename ST::raw srow[(MODE == M_HV && !MASK) ? 4 : 1][4];
+            if constexpr (MODE == M_HV && !MASK) {
+    #pragma unroll
+              for (int kv = 0; kv < 4; ++kv)
+    #pragma unroll
+                for (int jv = 0; jv < 4; ++jv) srow[kv][jv] = ST::fetch(sp + (kv * nxy + jv * g.nx) * ST::W);
+              __builtin_amdgcn_sched_barrier(0);
+            }
             auto zrow = [&](const int kv) {
               const float wz = (kv + 0.5f) * 0.25f;
               const int iz = czi * 4 + kv;
@@ -1180,7 +1218,10 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
                 for (int c = 0; c < 3; ++c) f3[c] = __builtin_fmaf(wy, fz[1][c] - fz[0][c], fz[0][c]);
                 if (MODE == M_HV) {
                   float s[3];
-                  ST::loadp(sp + voff, A.sS_load, s);
+                  if constexpr (MASK)
+                    ST::loadp(sp + voff, A.sS_load, s);
+                  else
+                    ST::unpack(srow[kv][jv], sp + voff, A.sS_load, s);
                   const float w = s[0] * f3[0] + s[1] * f3[1] + s[2] * f3[2];
     #pragma unroll
                   for (int c = 0; c < 3; ++c) {

@@ -66,3 +66,32 @@ def check_field(name, got, ref, allow=None, tol=1e-4, elem_tol=None):
 
 def say_ties(label, ties):
     say(f"  {label}: {ties['n']} voxels with a sample-cell tie")
+
+
+def pcg_vector_rounding(hv, b, diag, iters):
+    """The Jacobi-PCG iteration of the oracle (x0 = 0, M = diag + 1e-12 max diag, a fixed
+    number of iterations) with every vector rounded to single precision after each update
+    (dot products in double precision, products hv in double precision then rounded).
+    It measures how far single-precision vector storage alone moves a fixed-iteration CG
+    result from the double-precision one on a given system: the tolerance of a
+    single-precision implementation's step is derived from it."""
+    f32 = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    M = f32(diag + 1e-12 * float(np.max(diag)))
+    x = np.zeros_like(b)
+    r = f32(b)
+    z = f32(r / M)
+    p = z.copy()
+    rz = float(np.sum(r * z))
+    for _ in range(iters):
+        q = f32(hv(p))
+        pq = float(np.sum(p * q))
+        if not pq > 0.0:
+            break
+        a = np.float32(rz / pq)
+        x = f32(x + a * p)
+        r = f32(r - a * q)
+        z = f32(r / M)
+        rz_new = float(np.sum(r * z))
+        p = f32(z + np.float32(rz_new / rz) * p)
+        rz = rz_new
+    return x
