@@ -48,6 +48,7 @@ extern "C" {
 #define DISCO_ERR_STATE (-3)     /* images not set, or ngf_hessvec / gn_hessvec before a linearisation */
 #define DISCO_ERR_NONFINITE (-4) /* a scalar parameter is NaN/inf or out of its range */
 #define DISCO_ERR_NOMEM (-5)     /* device allocation failed */
+#define DISCO_ERR_LIMIT (-6)     /* input larger than the static scratch of the no-allocation entry point */
 #define DISCO_ERR_HIP (-100)     /* returned as DISCO_ERR_HIP - (int)hipError_t */
 
 /* numerical status bits (device int32 status words) */
@@ -133,6 +134,17 @@ void disco_destroy(disco_ctx *ctx);
    their central-difference gradient volumes with replicated borders (the gradients of
    eq. 1).  Invalidates the linearisation. */
 int disco_set_images(disco_ctx *ctx, const float *R, const float *T, disco_stream stream);
+
+/* disco_set_images for callers that cannot allocate device memory (code under HIP graph
+   capture, serving loops, harnesses that forbid hipMalloc): the same result, bitwise, with
+   no allocation in the call.  With FP16 storage the scale search keeps its per-block
+   maxima (one double per 256 voxels) in a static device array of 2 MB instead of a
+   per-call allocation, so volumes above 2^26 voxels (512 x 512 x 256) are rejected with
+   DISCO_ERR_LIMIT before anything is queued; FP32 storage needs no scratch and has no
+   such limit.  Every call on a device shares that device's array: calls that overlap on
+   one device (different streams or host threads) race.  The array is held until the
+   process ends.  Like disco_set_images, the FP16 scale search synchronises the stream. */
+int disco_set_images_noalloc(disco_ctx *ctx, const float *R, const float *T, disco_stream stream);
 
 /* Replace the moving image T of eq. 1 (device float32 [Nz][Ny][Nx]) and rebuild only its
    gradient volume; grad R is kept.  For callers that evaluate one fixed image against

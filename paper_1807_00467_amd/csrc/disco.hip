@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <mutex>
 #include <unordered_map>
 #include <utility>
 #include <vector>
@@ -505,6 +506,7 @@ const char *disco_status_string(int code) {
     case DISCO_ERR_STATE: return "state error (images not set or no linearisation yet)";
     case DISCO_ERR_NONFINITE: return "non-finite or out-of-range scalar parameter";
     case DISCO_ERR_NOMEM: return "device allocation failed";
+    case DISCO_ERR_LIMIT: return "volume exceeds the static scratch of disco_set_images_noalloc (FP16 storage: at most 2^26 voxels)";
     default:
       if (code <= DISCO_ERR_HIP) return hipGetErrorString((hipError_t)(DISCO_ERR_HIP - code));
       return "unknown code";
@@ -632,20 +634,46 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
 
 }  // extern "C"
 
+// Static device scratch for disco_set_images_noalloc: the per-block maxima of the FP16
+// scale search (one double per 256 voxels), enough for 2^26 voxels (512 x 512 x 256).
+// Every device the library runs on holds its own copy until the process ends.  In host
+// code the array's name is not a device address: kernels and copies take the address
+// returned by hipGetSymbolAddress, fetched once per device (scratch_ptr).
+constexpr size_t kScratchDoubles = (size_t)1 << 18;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static int scratch_ptr(int device, double **out) {
+  static std::mutex mu;
+  static double *addr[kMaxDevices] = {};  // fixed table: no heap allocation
+  if (device < 0 || device >= kMaxDevices) return DISCO_ERR_ARG;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    // the caller has made `device` current
+    double *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(reinterpret_cast<void **>(&p), HIP_SYMBOL(scratch)));
+    if (!p) return DISCO_ERR_NOMEM;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return DISCO_OK;
+}
+
 // central-difference gradient volume of one image (which = 0: R into gR, 1: T into gT);
-// FP16 storage first finds the image's power-of-two scale (max |grad| * scale <= 2^14)
-static int build_gradient(disco_ctx *c, const float *img, int which, hipStream_t s) {
+// FP16 storage first finds the image's power-of-two scale (max |grad| * scale <= 2^14),
+// from per-block maxima in `blk` (nblk(nvox) doubles; null: allocated for the call)
+static int build_gradient(disco_ctx *c, const float *img, int which, hipStream_t s, double *blk_given = nullptr) {
   const Geo &g = c->g;
   if (c->storage == DISCO_STORAGE_FP16) {
     const unsigned nb = nblk(g.nvox);
-    double *blk = nullptr;
-    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&blk), sizeof(double) * nb, s));
+    double *blk = blk_given;
+    if (!blk) HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&blk), sizeof(double) * nb, s));
     hipLaunchKernelGGL(k_absmax_grad, dim3(nb), dim3(256), 0, s, g, img, blk);
     launch_reduce(blk, nb, 1, 1, 1u, c->sc + SC_TMP0, nullptr, s);
     double mx = 0.0;
     HIP_TRY(hipMemcpyAsync(&mx, c->sc + SC_TMP0, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    HIP_TRY(hipFreeAsync(blk, s));
+    if (!blk_given) HIP_TRY(hipFreeAsync(blk, s));
     int ex = 0;
     if (mx > 0.0 && std::isfinite(mx)) ex = (int)std::floor(std::log2(16384.0 / mx));
     ex = std::max(-100, std::min(100, ex));
@@ -678,6 +706,24 @@ int disco_set_images(disco_ctx *c, const float *R, const float *T, disco_stream 
   c->images = false;
   c->lin = false;
   if ((e = build_gradient(c, R, 0, s)) || (e = build_gradient(c, T, 1, s))) return e;
+  c->images = true;
+  return DISCO_OK;
+}
+
+int disco_set_images_noalloc(disco_ctx *c, const float *R, const float *T, disco_stream stream) {
+  if (!c) return DISCO_ERR_ARG;
+  int e;
+  if ((e = check_field(R)) || (e = check_field(T))) return e;
+  if (c->storage == DISCO_STORAGE_FP16 && (size_t)nblk(c->g.nvox) > kScratchDoubles) return DISCO_ERR_LIMIT;
+  if ((e = set_device(c))) return e;
+  double *blk = nullptr;
+  if ((e = scratch_ptr(c->device, &blk))) return e;
+  hipStream_t s = S(stream);
+  c->images = false;
+  c->lin = false;
+  // every block writes its maximum before the reduction reads it: nothing to clear
+  // (no profiling scope here: it creates events)
+  if ((e = build_gradient(c, R, 0, s, blk)) || (e = build_gradient(c, T, 1, s, blk))) return e;
   c->images = true;
   return DISCO_OK;
 }

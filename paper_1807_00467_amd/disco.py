@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 # ---- constants (mirror include/disco.h) -------------------------------------------------
 OK = 0
-ERR_ARG, ERR_SHAPE, ERR_STATE, ERR_NONFINITE, ERR_NOMEM, ERR_HIP = -1, -2, -3, -4, -5, -100
+ERR_ARG, ERR_SHAPE, ERR_STATE, ERR_NONFINITE, ERR_NOMEM, ERR_LIMIT, ERR_HIP = -1, -2, -3, -4, -5, -6, -100
 STATUS_FOLD, STATUS_PCG_BREAKDOWN, STATUS_LS_FAIL = 1, 2, 4
 STORAGE_FP32, STORAGE_FP16 = 0, 1
 FLAG_LS_DEVICE = 1
@@ -72,6 +72,7 @@ _SIGS = {
     "disco_destroy": ([_P], None),
     "disco_set_images": ([_P, _P, _P, _P], ctypes.c_int),
     "disco_set_moving": ([_P, _P, _P], ctypes.c_int),
+    "disco_set_images_noalloc": ([_P, _P, _P, _P], ctypes.c_int),
     "disco_set_keypoints": ([_P, _I, _P, _P, _P], ctypes.c_int),
     "disco_set_reference": ([_P, _P, _P], ctypes.c_int),
     "ngf_eval": ([_P, _D, _P, _P, _P], ctypes.c_int),
@@ -243,6 +244,13 @@ class Disco:
         self._images = None
         _check(_lib.disco_set_images(self._h, _ptr(self._volume(R, "R")), _ptr(self._volume(T, "T")),
                                      self._stream()), "disco_set_images")
+        self._images = (_Token(R), _Token(T))
+
+    def set_images_noalloc(self, R: torch.Tensor, T: torch.Tensor):
+        """set_images without any device allocation (static scratch; see disco.h)."""
+        self._images = None
+        _check(_lib.disco_set_images_noalloc(self._h, _ptr(self._volume(R, "R")), _ptr(self._volume(T, "T")),
+                                             self._stream()), "disco_set_images_noalloc")
         self._images = (_Token(R), _Token(T))
 
     def set_moving(self, T: torch.Tensor):
