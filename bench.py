@@ -33,7 +33,9 @@ def log(*a):
 
 
 KERNEL_SOURCES = ["paper_1807_00467_amd/csrc/kernels.hpp", "paper_1807_00467_amd/csrc/disco.hip",
-                  "paper_1807_00467_amd/csrc/solver.hpp", "paper_1807_00467_amd/build.py"]
+                  "paper_1807_00467_amd/csrc/solver.hpp", "paper_1807_00467_amd/csrc/adjoint.hpp",
+                  "paper_1807_00467_amd/csrc/batch.hpp", "paper_1807_00467_amd/csrc/keypoint.hpp",
+                  "paper_1807_00467_amd/csrc/pyramid.hpp", "paper_1807_00467_amd/build.py"]
 
 
 def kernel_source_hash():
@@ -66,15 +68,36 @@ def traffic_from_profiles(kernel_tag):
         return None
 
 
-def cpu_baseline(d, params, budget_s=25.0):
-    """The FP64 oracle, as it stands, on a bounded sample: one linearisation (untimed)
-    then as many full-size GN products as fit in the budget (at least one)."""
+def host_info():
+    """Host cores available to this process and the CPU model name."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def cpu_baseline(d, params, budget_s=12.0):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload, with the
+    thread count it is given (OMP_NUM_THREADS): the objective and the linearisation
+    (objective + gradient + GN diagonal + s vectors) once each, then as many full-size
+    GN products as fit in the budget (at least one); then one GN product on one thread."""
     import numpy as np
     import oracle
     P = oracle.Problem(d["R"], d["T"], d["spacing"], d["kp_x"], d["kp_t"],
                        oracle.Weights(eta=params.eta, alpha=params.alpha, gamma=params.gamma, delta=params.delta))
+    u = d["u_true"].astype(np.float64)
+    threads = oracle.num_threads()
     t0 = time.perf_counter()
-    P.linearise(d["u_true"].astype(np.float64))
+    P.objective(u)
+    t_obj = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    P.linearise(u)
     t_lin = time.perf_counter() - t0
     v = d["v"].astype(np.float64)
     n = 0
@@ -85,9 +108,20 @@ def cpu_baseline(d, params, budget_s=25.0):
         el = time.perf_counter() - t0
         if el + el / n > budget_s or n >= 16:
             break
-    return dict(value=n / el, unit="Hv/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"{n} full GN products of eq. 11 at 512x512x128 (FP64 C oracle) after one "
-                       f"linearisation ({t_lin:.1f} s, untimed); {el:.1f} s timed")
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        P.gn_hv(v)
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    return dict(value=n / el, unit="Hv/s", cores=threads, kind="oracle",
+                sample=f"{n} full GN products of eq. 11 at 512x512x128 (FP64 C oracle, {threads} threads) after "
+                       f"one objective evaluation ({t_obj:.2f} s) and one linearisation ({t_lin:.2f} s); "
+                       f"{el:.1f} s timed; then one GN product on one thread ({t1:.2f} s)",
+                objective_s=t_obj, objective_gradient_s=t_lin,
+                one_thread={"value": 1.0 / t1, "unit": "Hv/s", "cores": 1},
+                **host_info())
 
 
 def main():
@@ -109,6 +143,8 @@ def main():
     ap.add_argument("--batched", action="store_true",
                     help="batched form instead: 24 uneven pyramid-shape pairs, 5 GN iterations (15 PCG each), "
                          "one launch per phase and one graph, against the same steps pair by pair")
+    ap.add_argument("--loss", action="store_true",
+                    help="differentiable loss instead: NGFLoss forward + backward on 8 pairs of 192x192x160")
     ap.add_argument("--boundary", action="store_true",
                     help="add the lung-boundary term (eq. 6) with the adaptive beta (D = 100 beta B at u = 0)")
     ap.add_argument("--lbfgs", action="store_true",
@@ -138,6 +174,8 @@ def main():
     import synth
     from paper_1807_00467_amd import disco
 
+    if args.loss:
+        return bench_loss(args)
     if args.batched:
         return bench_batched(args)
     if args.lbfgs:
@@ -374,6 +412,158 @@ def tree_depths(parent, root):
                 dep[b] = dep[a] + 1
                 queue.append(b)
     return dep
+
+
+def _make_pair_seeded(a):
+    import synth
+    cfg, seed = a
+    return synth.make_pair(cfg, seed=seed)
+
+
+def make_pairs(cfg, seeds):
+    """Synthetic pairs generated in worker processes (before anything touches the GPU)."""
+    import multiprocessing as mp
+    nproc = max(1, min(len(seeds), len(os.sched_getaffinity(0)), 16))
+    with mp.get_context("fork").Pool(nproc) as pool:
+        return pool.map(_make_pair_seeded, [(cfg, s) for s in seeds])
+
+
+def cpu_baseline_loss(d, eta, alpha, gamma, budget_s=20.0):
+    """The FP64 oracle's loss forward and backward for one pair: J (eq. 11 without the
+    keypoint term), dJ/du and dD/dT, timed on one pair of the same workload."""
+    import numpy as np
+    import oracle
+    P = oracle.Problem(d["R"], d["T"], d["spacing"], None, None,
+                       oracle.Weights(eta=eta, alpha=alpha, gamma=gamma, delta=0.0))
+    u = d["u_true"].astype(np.float64)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        P.objective(u)
+        P.linearise(u)
+        oracle.ngf_grad_T(P.gR, P.gT, d["spacing"], eta, u)
+        n += 1
+        el = time.perf_counter() - t0
+        if el + el / n > budget_s or n >= 8:
+            break
+    return dict(value=n / el, unit="pairs/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"{n} forward + backward passes of one {d['shape'][0]}x{d['shape'][1]}x{d['shape'][2]} "
+                       f"pair (FP64 C oracle: objective, gradient in u, derivative in T); {el:.1f} s",
+                **host_info())
+
+
+def bench_loss(args):
+    """Differentiable loss (NGFLoss, a torch.autograd.Function per pair) on 8 pairs of
+    192 x 192 x 160 at 1 mm (node grid 49 x 49 x 41): one step = the forward pass (sum
+    over the pairs of D + alpha S + gamma Vhat, eq. 11 without the keypoint and
+    lung-boundary terms) and the backward pass (dL/du and dL/dT of every pair).  Each
+    pair keeps its gradient volumes resident: they are built at the first forward pass,
+    before timing (the images do not change between steps, as when a network is trained
+    on a fixed set of pairs)."""
+    import numpy as np
+    import torch
+    from paper_1807_00467_amd import disco
+    from paper_1807_00467_amd.loss import NGFLoss
+
+    npairs = 8
+    eta, alpha, gamma = 10.0, 1.0, 0.1
+    log(f"[bench] generating {npairs} cfg2 pairs ...")
+    t0 = time.perf_counter()
+    pairs = make_pairs("cfg2", [2000 + i for i in range(npairs)])
+    log(f"[bench] generated in {time.perf_counter() - t0:.1f} s")
+    d0 = pairs[0]
+    dev = torch.device("cuda:0")
+    R = [torch.from_numpy(p["R"]).to(dev) for p in pairs]
+    T = torch.stack([torch.from_numpy(p["T"]) for p in pairs]).to(dev).requires_grad_(True)
+    u = torch.stack([torch.from_numpy(p["u_true"]) for p in pairs]).to(dev).requires_grad_(True)
+    crit = NGFLoss(d0["shape"], d0["spacing"], R, eta=eta, alpha=alpha, gamma=gamma, storage=args.storage)
+
+    def step():
+        u.grad = None
+        T.grad = None
+        loss = crit(u, T)
+        loss.backward()
+        return loss
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+    for c in crit.ctxs:
+        c.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for c in crit.ctxs:
+        c.profile(False)
+    kinds = {"grad": disco.PROF_GRAD, "eval": disco.PROF_EVAL, "adjT": disco.PROF_ADJT}
+    prof = {}
+    for name, k in kinds.items():
+        n_tot, ms_tot = 0, 0.0
+        for c in crit.ctxs:
+            n, ms = c.profile_read(k)
+            n_tot += n
+            ms_tot += ms
+        prof[name] = (n_tot, ms_tot)
+    nvox = int(np.prod(d0["shape"]))
+    nx, ny, nz = crit.ctxs[0].nodes
+    nnodes = nx * ny * nz
+    bpv = 12 if args.storage == "fp32" else 6
+    # algorithmic bytes per launch: objective pass (grad R and the sample of grad T per
+    # voxel, u per node); gradient pass (the same plus the s cache written; u read, g and
+    # diag written per node); derivative in T (clear of the 3-vector field, grad R and the
+    # sample of grad T read, the field scattered (read and written), the stencil pass
+    # reading it and writing dT; u per node)
+    bytes_per = {"eval": 2 * bpv * nvox + 12 * nnodes, "grad": 3 * bpv * nvox + 36 * nnodes,
+                 "adjT": (12 + 2 * bpv + 24 + 12 + 4) * nvox + 12 * nnodes}
+    names = {"eval": "k_brick<EVAL> (objective pass, forward)", "grad": "k_brick<GRAD> (gradient pass, backward in u)",
+             "adjT": "k_fill + k_adjT_scatter + k_adjT_stencil (backward in T)"}
+    dom = max(prof, key=lambda k: prof[k][1])
+    n_dom, ms_dom = prof[dom]
+    t_dom = ms_dom / max(n_dom, 1) / 1e3
+    achieved = bytes_per[dom] / t_dom / 1e9
+    out = {
+        "metric": "loss forward + backward pairs/s (8 pairs of 192x192x160)",
+        "value": npairs * args.steps / elapsed,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.storage == "fp32" else "f16-storage/f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"cfg2: {npairs} pairs of {d0['shape'][0]}x{d0['shape'][1]}x{d0['shape'][2]} at 1 mm, "
+                        f"node grid {nx}x{ny}x{nz}; step = NGFLoss forward (D + alpha S + gamma Vhat summed "
+                        f"over the pairs) + backward (dL/du and dL/dT of every pair), gradient volumes resident",
+            "eta": eta, "alpha": alpha, "gamma": gamma, "storage": args.storage,
+        },
+        "kernel_us": {k: 1e3 * v[1] / max(v[0], 1) for k, v in prof.items()},
+        "launches": {k: v[0] for k, v in prof.items()},
+        "loss": float(loss.item()),
+        "roofline": {
+            "kernel": names[dom],
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": bytes_per[dom],
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on one pair ...")
+        out["cpu_baseline"] = cpu_baseline_loss(d0, eta, alpha, gamma)
+    print(json.dumps(out), flush=True)
+    crit.close()
 
 
 def bench_keypoints(args):

@@ -383,7 +383,8 @@ int disco_copy_buffer(disco_ctx *ctx, int32_t which, float *dst, disco_stream st
    recording (clears counters), 0 stops.  disco_profile_read waits for the recorded
    events and returns the number of launches and total milliseconds of one kernel
    class: 0 = Gauss-Newton product pass over the voxels, 1 = gradient pass,
-   2 = objective-only pass, 3 = image gradients. */
+   2 = objective-only pass, 3 = image gradients, 4 = derivative with respect to T
+   (ngf_grad_T: clear, scatter and stencil passes together). */
 int disco_profile(disco_ctx *ctx, int32_t enable);
 int disco_profile_read(disco_ctx *ctx, int32_t kernel, int64_t *launches, double *ms_total);
 

@@ -83,6 +83,8 @@ def _load():
         lib.or_kp_cost.restype = None
         lib.or_num_threads.argtypes = []
         lib.or_num_threads.restype = ctypes.c_int
+        lib.or_set_threads.argtypes = [ctypes.c_int]
+        lib.or_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -90,6 +92,11 @@ def _load():
 def num_threads() -> int:
     """Threads the oracle's parallel loops use."""
     return int(_load().or_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the thread count of the oracle's parallel loops (timing runs)."""
+    _load().or_set_threads(int(n))
 
 
 def _p(a: Optional[np.ndarray]):

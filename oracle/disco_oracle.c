@@ -877,6 +877,16 @@ int or_num_threads(void)
 #endif
 }
 
+/* set the number of threads of the parallel loops (n >= 1; for timing runs) */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------------ */
 /* Derivative of the NGF distance (eq. 1) with respect to the moving image values.   */
 /* D depends on T only through a_v = G(y_v), the trilinear sample of grad T, so       */

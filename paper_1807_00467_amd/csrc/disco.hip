@@ -80,7 +80,7 @@ struct disco_ctx {
   int *kstart = nullptr;
   // profiling
   bool prof = false;
-  std::vector<EventPair> ev[4];
+  std::vector<EventPair> ev[5];
 };
 
 // keypoint stage: normalised gradient 4-vectors of F and M, split by voxel parity
@@ -1375,6 +1375,7 @@ int ngf_grad_T(disco_ctx *c, double eta, const float *u, float *dT, disco_stream
       return DISCO_ERR_NOMEM;
     }
   }
+  ProfScope ps(c, 4, s);
   hipLaunchKernelGGL(k_fill, dim3(nblk(3 * g.nvox)), dim3(256), 0, s, 3 * g.nvox, c->adjW, 0.0f);
   const float h3x2 = (float)(2.0 * h3_of(c));
   if (c->storage == DISCO_STORAGE_FP16)
@@ -1422,7 +1423,7 @@ int disco_profile(disco_ctx *c, int32_t enable) {
 }
 
 int disco_profile_read(disco_ctx *c, int32_t kernel, int64_t *launches, double *ms_total) {
-  if (!c || !launches || !ms_total || kernel < 0 || kernel > 3) return DISCO_ERR_ARG;
+  if (!c || !launches || !ms_total || kernel < 0 || kernel > 4) return DISCO_ERR_ARG;
   double tot = 0.0;
   for (auto &p : c->ev[kernel]) {
     HIP_TRY(hipEventSynchronize(p.b));

@@ -34,7 +34,7 @@ REPORT_FIELDS = ["J", "D", "S", "V", "K", "gnorm", "t", "pcg_iters", "pcg_res", 
                  "J_new", "D_new", "S_new", "V_new", "K_new", "ls_trials", "B", "B_new"]
 REP_SIZE = len(REPORT_FIELDS)
 TERM_FIELDS = ["J", "D", "S", "V", "K", "B", "nfold", "gnorm"]
-PROF_HV, PROF_GRAD, PROF_EVAL, PROF_IMGRAD = 0, 1, 2, 3
+PROF_HV, PROF_GRAD, PROF_EVAL, PROF_IMGRAD, PROF_ADJT = 0, 1, 2, 3, 4
 
 
 class _Geom(ctypes.Structure):
@@ -295,11 +295,12 @@ class Disco:
         _check(_lib.disco_set_masks(self._h, _ptr(bF), _ptr(bM), self._stream()), "disco_set_masks")
 
     def objective_linearise(self, params: Params, u: torch.Tensor, grad: bool = True, diag: bool = True,
-                            terms: bool = True):
-        """J and its terms (dict of TERM_FIELDS, read back to the host when `terms`), grad J and
-        the GN diagonal at u (sets the linearisation used by gn_hessvec)."""
+                            terms: bool = True, g_out: Optional[torch.Tensor] = None):
+        """J and its terms (dict of TERM_FIELDS, read back to the host when `terms`), grad J
+        (into g_out when given) and the GN diagonal at u (sets the linearisation used by
+        gn_hessvec)."""
         tv = torch.zeros(8, dtype=torch.float64, device=self.device) if terms else None
-        g = torch.empty_like(u) if grad else None
+        g = (torch.empty_like(u) if g_out is None else self._field(g_out, "g_out")) if grad else None
         d = torch.empty_like(u) if diag else None
         p = params.c()
         _check(_lib.objective_linearise(self._h, ctypes.byref(p), _ptr(self._field(u, "u")), _ptr(tv), _ptr(g),
@@ -341,10 +342,11 @@ class Disco:
         _check(_lib.ngf_hessvec(self._h, _ptr(self._field(v, "v")), _ptr(out), self._stream()), "ngf_hessvec")
         return out
 
-    def ngf_grad_T(self, u: torch.Tensor, eta: float) -> torch.Tensor:
-        """dD/dT at displacement u (volume [Nz][Ny][Nx])."""
+    def ngf_grad_T(self, u: torch.Tensor, eta: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """dD/dT at displacement u (volume [Nz][Ny][Nx], into `out` when given)."""
         nx, ny, nz = self.shape
-        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.device)
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.device) if out is None \
+            else self._volume(out, "out")
         _check(_lib.ngf_grad_T(self._h, eta, _ptr(self._field(u, "u")), _ptr(out), self._stream()), "ngf_grad_T")
         return out
 
