@@ -251,7 +251,7 @@ def main():
     nvox = int(np.prod(d["shape"]))
     nx, ny, nz = ctx.nodes
     nnodes = nx * ny * nz
-    bpv = 12 if args.storage == "fp32" else 6
+    bpv = 12 if args.storage == "fp32" else 8
     hv_bytes = bpv * nvox + 36 * nnodes           # s stream + v, u (VCC) read + Hv write
     hv_s = ms_hv / max(n_hv, 1) / 1e3
     achieved = hv_bytes / hv_s / 1e9
@@ -300,6 +300,31 @@ def main():
         },
         "cpu_baseline": None,
     }
+    if args.storage == "fp16":
+        # the same steps with FP32 storage on the same GPU: the speedup of the storage form
+        log("[bench] the same steps with FP32 storage ...")
+        ctx32 = disco.Disco(d["shape"], d["spacing"], storage="fp32", device=dev)
+        ctx32.set_keypoints(d["kp_x"], d["kp_t"])
+        rep32 = torch.zeros_like(rep)
+
+        def step32():
+            u.copy_(u_true)
+            ctx32.set_images(R, T)
+            ctx32.gn_pcg_step(params, u, rep32, st)
+
+        for _ in range(args.warmup):
+            step32()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step32()
+        torch.cuda.synchronize()
+        ms32 = 1e3 * (time.perf_counter() - t0) / args.steps
+        r32 = disco.Disco.report_dict(rep32)
+        out["fp32_storage_ms_per_step"] = ms32
+        out["speedup_vs_fp32_storage"] = ms32 / out["ms_per_step"]
+        out["J_new_rel_diff_vs_fp32_storage"] = abs(r["J_new"] - r32["J_new"]) / abs(r32["J_new"])
+        ctx32.close()
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(d, params)
@@ -511,7 +536,7 @@ def bench_loss(args):
     nvox = int(np.prod(d0["shape"]))
     nx, ny, nz = crit.ctxs[0].nodes
     nnodes = nx * ny * nz
-    bpv = 12 if args.storage == "fp32" else 6
+    bpv = 12 if args.storage == "fp32" else 8
     # algorithmic bytes per launch: objective pass (grad R and the sample of grad T per
     # voxel, u per node); gradient pass (the same plus the s cache written; u read, g and
     # diag written per node); derivative in T (clear of the 3-vector field, grad R and the

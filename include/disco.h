@@ -122,8 +122,9 @@ typedef void *disco_stream; /* hipStream_t */
 
 /* Create a context for one image pair geometry on the current HIP device.  storage is
    DISCO_STORAGE_FP32 or DISCO_STORAGE_FP16.  Allocates the derived volumes (grad R,
-   grad T, per-voxel GN vectors: 3 x 12 B per voxel in FP32, 3 x 6 B in FP16) and small
-   workspaces.  The volume may hold at most (2^32 - 1) / 3 voxels (DISCO_ERR_SHAPE
+   grad T, per-voxel GN vectors: 3 x 12 B per voxel in FP32, 3 x 8 B in FP16, whose three
+   halfs are padded to one aligned 8-byte word) and small workspaces.  The volume may hold
+   at most (2^32 - 1) / 3 voxels in FP32 and (2^32 - 1) / 4 in FP16 (DISCO_ERR_SHAPE
    otherwise).  *out receives the context (NULL on error). */
 int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out);
 
@@ -137,11 +138,12 @@ int disco_set_images(disco_ctx *ctx, const float *R, const float *T, disco_strea
 
 /* disco_set_images for callers that cannot allocate device memory (code under HIP graph
    capture, serving loops, harnesses that forbid hipMalloc): the same result, bitwise, with
-   no allocation in the call.  With FP16 storage the scale search keeps its per-block
-   maxima (one double per 256 voxels) in a static device array of 2 MB instead of a
-   per-call allocation, so volumes above 2^26 voxels (512 x 512 x 256) are rejected with
-   DISCO_ERR_LIMIT before anything is queued; FP32 storage needs no scratch and has no
-   such limit.  Every call on a device shares that device's array: calls that overlap on
+   no allocation in the call.  With FP16 storage the scale search keeps its per-tile
+   maxima (one double per 64 x 16 x 16 voxel tile) in a static device array of 128 KB
+   instead of a buffer the context allocates at its first disco_set_images call, so
+   volumes of more than 2^14 tiles (ceil(Nx/64) ceil(Ny/16) ceil(Nz/16) > 16384, e.g.
+   beyond 512 x 512 x 1024) are rejected with DISCO_ERR_LIMIT before anything is queued;
+   FP32 storage needs no scratch and has no such limit.  Every call on a device shares that device's array: calls that overlap on
    one device (different streams or host threads) race.  The array is held until the
    process ends.  Like disco_set_images, the FP16 scale search synchronises the stream. */
 int disco_set_images_noalloc(disco_ctx *ctx, const float *R, const float *T, disco_stream stream);

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_adjT_scatter(Geo g, const typename ST::
   }
   const float uh[3] = {f3[0] * g.ihx, f3[1] * g.ihy, f3[2] * g.ihz};
   float a[3], JG[3][3], b[3];
-  sample_grad<ST>(gT, sT, g, ic, j, k, uh, a, JG);
+  sample_grad<ST, false>(gT, sT, g, ic, j, k, uh, a, JG);
   ST::loadp(gR + v * ST::W, sR, b);
   const float Da = eta2 + a[0] * a[0] + a[1] * a[1] + a[2] * a[2];
   const float Db = eta2 + b[0] * b[0] + b[1] * b[1] + b[2] * b[2];

@@ -59,6 +59,7 @@ struct disco_ctx {
   float *part = nullptr;
   double *blk_brick = nullptr, *blk_node = nullptr, *sc = nullptr;
   double *blk_curv = nullptr, *blk_upd = nullptr;
+  double *blk_img = nullptr;  // FP16 scale search: per-block maxima (allocated at first use)
   float *adjW = nullptr;  // dD/d(grad T) accumulator of ngf_grad_T, [N][3] (allocated on first use)
   // lung masks and the boundary term's GN vectors (allocated by disco_set_masks)
   uint8_t *mF = nullptr, *mM = nullptr, *rflag = nullptr;
@@ -146,6 +147,10 @@ inline dim3 vox_grid(const Geo &g) { return dim3((g.nx + 255) / 256, g.ny, g.nz)
 // k_imgrad: 64 x kImgY voxel tiles of kImgZ planes, 64 kImgY threads
 inline dim3 imgrad_grid(const Geo &g) {
   return dim3((g.nx + 63) / 64, (g.ny + kImgY - 1) / kImgY, (g.nz + kImgZ - 1) / kImgZ);
+}
+inline size_t image_tiles(const Geo &g) {
+  const dim3 t = imgrad_grid(g);
+  return (size_t)t.x * t.y * t.z;
 }
 
 struct ProfScope {
@@ -506,7 +511,7 @@ const char *disco_status_string(int code) {
     case DISCO_ERR_STATE: return "state error (images not set or no linearisation yet)";
     case DISCO_ERR_NONFINITE: return "non-finite or out-of-range scalar parameter";
     case DISCO_ERR_NOMEM: return "device allocation failed";
-    case DISCO_ERR_LIMIT: return "volume exceeds the static scratch of disco_set_images_noalloc (FP16 storage: at most 2^26 voxels)";
+    case DISCO_ERR_LIMIT: return "volume exceeds the static scratch of disco_set_images_noalloc (FP16 storage: at most 2^14 tiles of 64 x 16 x 16 voxels)";
     default:
       if (code <= DISCO_ERR_HIP) return hipGetErrorString((hipError_t)(DISCO_ERR_HIP - code));
       return "unknown code";
@@ -520,7 +525,7 @@ void disco_destroy(disco_ctx *c) {
   clear_profile(c);
   void *ptrs[] = {c->gR,  c->gT,  c->scache, c->u_lin, c->u_ref, c->Lw,   c->vg,   c->vdiag, c->vx,   c->vr,
                   c->vz,  c->vp,  c->vq,     c->vut,   c->tmp0,  c->tmp1, c->part, c->blk_brick, c->blk_node,
-                  c->sc,  c->status, c->kloc, c->ktgt, c->kstart, c->blk_curv, c->blk_upd, c->adjW, c->vp2, c->vinvm,
+                  c->sc,  c->status, c->kloc, c->ktgt, c->kstart, c->blk_curv, c->blk_upd, c->blk_img, c->adjW, c->vp2, c->vinvm,
                   c->lbS, c->lbY, c->mF, c->mM, c->rflag, c->sbc, c->zb};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -540,9 +545,9 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
     if (!std::isfinite(geom->h[a]) || !(geom->h[a] > 0.0)) return DISCO_ERR_NONFINITE;
   }
   // 32-bit node/voxel coordinates, 64-bit linear indices; the sampling addresses the
-  // 3-vector volumes with 32-bit element offsets (3 N < 2^32)
+  // 3-vector volumes with 32-bit element offsets (3 N < 2^32 in FP32, 4 N in FP16)
   const int64_t nvox = (int64_t)geom->n[0] * geom->n[1] * geom->n[2];
-  if (3 * nvox >= ((int64_t)1 << 32)) return DISCO_ERR_SHAPE;
+  if ((storage == DISCO_STORAGE_FP16 ? 4 : 3) * nvox >= ((int64_t)1 << 32)) return DISCO_ERR_SHAPE;
 
   disco_ctx *c = new (std::nothrow) disco_ctx();
   if (!c) return DISCO_ERR_NOMEM;
@@ -581,7 +586,7 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
   c->nwg = (int64_t)g.nbx * g.nby * g.nbz;
   c->nodeblocks = node_blocks(g);
 
-  const size_t vec3 = storage == DISCO_STORAGE_FP16 ? 6 : 12;  // bytes per voxel 3-vector
+  const size_t vec3 = storage == DISCO_STORAGE_FP16 ? 8 : 12;  // bytes per voxel 3-vector
   const size_t nf = 3 * (size_t)g.nnodes * sizeof(float);
   bool okm = true;
   auto alloc = [&](void **p, size_t bytes) {
@@ -634,12 +639,13 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
 
 }  // extern "C"
 
-// Static device scratch for disco_set_images_noalloc: the per-block maxima of the FP16
-// scale search (one double per 256 voxels), enough for 2^26 voxels (512 x 512 x 256).
+// Static device scratch for disco_set_images_noalloc: the per-tile maxima of the FP16
+// scale search (one double per 64 x 16 x 16 voxel tile), enough for 2^14 tiles
+// (512 x 512 x 1024 voxels).
 // Every device the library runs on holds its own copy until the process ends.  In host
 // code the array's name is not a device address: kernels and copies take the address
 // returned by hipGetSymbolAddress, fetched once per device (scratch_ptr).
-constexpr size_t kScratchDoubles = (size_t)1 << 18;
+constexpr size_t kScratchDoubles = (size_t)1 << 14;
 static __device__ __align__(256) double scratch[kScratchDoubles];
 
 constexpr int kMaxDevices = 64;
@@ -659,38 +665,61 @@ static int scratch_ptr(int device, double **out) {
   return DISCO_OK;
 }
 
-// central-difference gradient volume of one image (which = 0: R into gR, 1: T into gT);
-// FP16 storage first finds the image's power-of-two scale (max |grad| * scale <= 2^14),
-// from per-block maxima in `blk` (nblk(nvox) doubles; null: allocated for the call)
-static int build_gradient(disco_ctx *c, const float *img, int which, hipStream_t s, double *blk_given = nullptr) {
+// Central-difference gradient volumes of R (into gR) and/or T (into gT); null images are
+// skipped.  FP16 storage first finds each image's power-of-two scale (max |grad| x scale
+// <= 2^14) from per-tile maxima in `blk` (image_tiles(g) doubles, reused by the two
+// images in stream order), with one host wait for both.
+static int build_gradients(disco_ctx *c, const float *R, const float *T, hipStream_t s, double *blk) {
   const Geo &g = c->g;
+  const float *img[2] = {R, T};
   if (c->storage == DISCO_STORAGE_FP16) {
-    const unsigned nb = nblk(g.nvox);
-    double *blk = blk_given;
-    if (!blk) HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&blk), sizeof(double) * nb, s));
-    hipLaunchKernelGGL(k_absmax_grad, dim3(nb), dim3(256), 0, s, g, img, blk);
-    launch_reduce(blk, nb, 1, 1, 1u, c->sc + SC_TMP0, nullptr, s);
-    double mx = 0.0;
-    HIP_TRY(hipMemcpyAsync(&mx, c->sc + SC_TMP0, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (!blk_given) HIP_TRY(hipFreeAsync(blk, s));
-    int ex = 0;
-    if (mx > 0.0 && std::isfinite(mx)) ex = (int)std::floor(std::log2(16384.0 / mx));
-    ex = std::max(-100, std::min(100, ex));
-    const float scale = std::ldexp(1.0f, ex);
-    if (which == 0) {
-      c->sR = 1.0f / scale;
-    } else {
-      c->sT = 1.0f / scale;
-      c->max_gT = mx;
+    const dim3 tiles = imgrad_grid(g);
+    const unsigned nb = tiles.x * tiles.y * tiles.z;
+    for (int k = 0; k < 2; ++k) {
+      if (!img[k]) continue;
+      hipLaunchKernelGGL(k_absmax_grad, tiles, dim3(64 * kImgY), 0, s, g, img[k], blk);
+      launch_reduce(blk, nb, 1, 1, 1u, c->sc + SC_TMP0 + k, nullptr, s);
     }
-    hipLaunchKernelGGL(k_imgrad<F16x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, img,
-                       reinterpret_cast<__half *>(which == 0 ? c->gR : c->gT), scale);
+    HIP_TRY(hipMemcpyAsync(c->host_sc, c->sc + SC_TMP0, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < 2; ++k) {
+      if (!img[k]) continue;
+      const double mx = c->host_sc[k];
+      int ex = 0;
+      if (mx > 0.0 && std::isfinite(mx)) ex = (int)std::floor(std::log2(16384.0 / mx));
+      ex = std::max(-100, std::min(100, ex));
+      const float scale = std::ldexp(1.0f, ex);
+      if (k == 0) {
+        c->sR = 1.0f / scale;
+      } else {
+        c->sT = 1.0f / scale;
+        c->max_gT = mx;
+      }
+      hipLaunchKernelGGL(k_imgrad<F16x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, img[k],
+                         reinterpret_cast<__half *>(k == 0 ? c->gR : c->gT), scale);
+    }
   } else {
-    hipLaunchKernelGGL(k_imgrad<F32x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, img,
-                       reinterpret_cast<float *>(which == 0 ? c->gR : c->gT), 1.0f);
+    for (int k = 0; k < 2; ++k)
+      if (img[k])
+        hipLaunchKernelGGL(k_imgrad<F32x3>, imgrad_grid(g), dim3(64 * kImgY), 0, s, g, img[k],
+                           reinterpret_cast<float *>(k == 0 ? c->gR : c->gT), 1.0f);
   }
   HIP_TRY(hipGetLastError());
+  return DISCO_OK;
+}
+
+// the context's buffer for the FP16 scale search, allocated at its first use
+static int image_scratch(disco_ctx *c, hipStream_t s, double **blk) {
+  *blk = nullptr;
+  if (c->storage != DISCO_STORAGE_FP16) return DISCO_OK;
+  if (!c->blk_img) {
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hipMalloc(reinterpret_cast<void **>(&c->blk_img), sizeof(double) * image_tiles(c->g)) != hipSuccess) {
+      c->blk_img = nullptr;
+      return DISCO_ERR_NOMEM;
+    }
+  }
+  *blk = c->blk_img;
   return DISCO_OK;
 }
 
@@ -702,10 +731,12 @@ int disco_set_images(disco_ctx *c, const float *R, const float *T, disco_stream 
   if ((e = check_field(R)) || (e = check_field(T))) return e;
   if ((e = set_device(c))) return e;
   hipStream_t s = S(stream);
+  double *blk = nullptr;
+  if ((e = image_scratch(c, s, &blk))) return e;
   ProfScope ps(c, 3, s);
   c->images = false;
   c->lin = false;
-  if ((e = build_gradient(c, R, 0, s)) || (e = build_gradient(c, T, 1, s))) return e;
+  if ((e = build_gradients(c, R, T, s, blk))) return e;
   c->images = true;
   return DISCO_OK;
 }
@@ -714,7 +745,7 @@ int disco_set_images_noalloc(disco_ctx *c, const float *R, const float *T, disco
   if (!c) return DISCO_ERR_ARG;
   int e;
   if ((e = check_field(R)) || (e = check_field(T))) return e;
-  if (c->storage == DISCO_STORAGE_FP16 && (size_t)nblk(c->g.nvox) > kScratchDoubles) return DISCO_ERR_LIMIT;
+  if (c->storage == DISCO_STORAGE_FP16 && image_tiles(c->g) > kScratchDoubles) return DISCO_ERR_LIMIT;
   if ((e = set_device(c))) return e;
   double *blk = nullptr;
   if ((e = scratch_ptr(c->device, &blk))) return e;
@@ -723,7 +754,7 @@ int disco_set_images_noalloc(disco_ctx *c, const float *R, const float *T, disco
   c->lin = false;
   // every block writes its maximum before the reduction reads it: nothing to clear
   // (no profiling scope here: it creates events)
-  if ((e = build_gradient(c, R, 0, s, blk)) || (e = build_gradient(c, T, 1, s, blk))) return e;
+  if ((e = build_gradients(c, R, T, s, blk))) return e;
   c->images = true;
   return DISCO_OK;
 }
@@ -735,9 +766,11 @@ int disco_set_moving(disco_ctx *c, const float *T, disco_stream stream) {
   if (!c->images) return DISCO_ERR_STATE;
   if ((e = set_device(c))) return e;
   hipStream_t s = S(stream);
+  double *blk = nullptr;
+  if ((e = image_scratch(c, s, &blk))) return e;
   ProfScope ps(c, 3, s);
   c->lin = false;
-  if ((e = build_gradient(c, T, 1, s))) {
+  if ((e = build_gradients(c, nullptr, T, s, blk))) {
     c->images = false;
     return e;
   }

@@ -75,6 +75,7 @@ struct Geo {
 struct F32x3 {
   typedef float elem;
   static constexpr int W = 3;  // elements per voxel
+  static constexpr bool kScaled = false;  // stored values are the values
   // a voxel's stored words, loaded now and converted later (lets a pass request many
   // loads before it uses the first)
   struct raw {
@@ -116,42 +117,39 @@ struct F32x3 {
   }
 };
 
-// half precision, 3 halfs (6 B) per voxel, value = stored * s (s: per-volume power of two).
-// A voxel starts at a 2- or 4-byte boundary: it is read with one 4-byte-aligned 8-byte
-// load and a shift.  Buffers carry 16 bytes of padding so the last voxel's load stays in
-// bounds.
+// half precision, value = stored * s (s: per-volume power of two).  A voxel takes 4 halfs
+// (8 B, the fourth zero): every voxel is one aligned 8-byte word, read with one load
+// and converted from the two 32-bit halves of the word.
 struct F16x3 {
   typedef __half elem;
-  static constexpr int W = 3;  // elements per voxel
+  static constexpr int W = 4;  // elements per voxel (3 components and a zero)
+  static constexpr bool kScaled = true;  // stored values times the volume's scale
   struct raw {
     uint2 w;
   };
-  __device__ static inline raw fetch(const __half *q) {
-    const uintptr_t addr = reinterpret_cast<uintptr_t>(q);
-    return raw{*reinterpret_cast<const uint2 *>(addr & ~(uintptr_t)3)};
+  __device__ static inline float lo(uint32_t x) { return __half2float(__ushort_as_half((unsigned short)(x & 0xFFFFu))); }
+  __device__ static inline float hi(uint32_t x) { return __half2float(__ushort_as_half((unsigned short)(x >> 16))); }
+  // component c of a raw voxel word as a half (converted by the instruction that uses it)
+  __device__ static inline _Float16 comp(const raw &r, int c) {
+    const uint32_t w = c < 2 ? r.w.x : r.w.y;
+    return __builtin_bit_cast(_Float16, (unsigned short)((c & 1) ? (w >> 16) : (w & 0xFFFFu)));
   }
+  __device__ static inline raw fetch(const __half *q) { return raw{*reinterpret_cast<const uint2 *>(q)}; }
   __device__ static inline void unpack(const raw &r, const __half *q, float s, float o[3]) {
-    const uintptr_t addr = reinterpret_cast<uintptr_t>(q);
-    const uint64_t v = ((uint64_t)r.w.y << 32 | r.w.x) >> ((addr & 3u) * 8u);
-    o[0] = __half2float(__ushort_as_half((unsigned short)(v & 0xFFFFu))) * s;
-    o[1] = __half2float(__ushort_as_half((unsigned short)((v >> 16) & 0xFFFFu))) * s;
-    o[2] = __half2float(__ushort_as_half((unsigned short)((v >> 32) & 0xFFFFu))) * s;
+    o[0] = lo(r.w.x) * s;
+    o[1] = hi(r.w.x) * s;
+    o[2] = lo(r.w.y) * s;
+    (void)q;
   }
-  __device__ static inline void loadp(const __half *q, float s, float o[3]) {
-    const uintptr_t addr = reinterpret_cast<uintptr_t>(q);
-    const uint2 w = *reinterpret_cast<const uint2 *>(addr & ~(uintptr_t)3);
-    const uint64_t v = ((uint64_t)w.y << 32 | w.x) >> ((addr & 3u) * 8u);
-    o[0] = __half2float(__ushort_as_half((unsigned short)(v & 0xFFFFu))) * s;
-    o[1] = __half2float(__ushort_as_half((unsigned short)((v >> 16) & 0xFFFFu))) * s;
-    o[2] = __half2float(__ushort_as_half((unsigned short)((v >> 32) & 0xFFFFu))) * s;
-  }
+  __device__ static inline void loadp(const __half *q, float s, float o[3]) { unpack(fetch(q), q, s, o); }
   __device__ static inline void storep(__half *q, float s, const float v[3]) {
-    q[0] = __float2half_rn(v[0] * s);
-    q[1] = __float2half_rn(v[1] * s);
-    q[2] = __float2half_rn(v[2] * s);
+    const uint32_t h0 = __half_as_ushort(__float2half_rn(v[0] * s));
+    const uint32_t h1 = __half_as_ushort(__float2half_rn(v[1] * s));
+    const uint32_t h2 = __half_as_ushort(__float2half_rn(v[2] * s));
+    *reinterpret_cast<uint2 *>(q) = make_uint2(h0 | (h1 << 16), h2);
   }
-  __device__ static inline void load(const __half *p, int64_t i, float s, float o[3]) { loadp(p + 3 * i, s, o); }
-  __device__ static inline void store(__half *p, int64_t i, float s, const float v[3]) { storep(p + 3 * i, s, v); }
+  __device__ static inline void load(const __half *p, int64_t i, float s, float o[3]) { loadp(p + 4 * i, s, o); }
+  __device__ static inline void store(__half *p, int64_t i, float s, const float v[3]) { storep(p + 4 * i, s, v); }
 };
 
 
@@ -522,10 +520,6 @@ __device__ __forceinline__ void load_plane(const float *fb, int64_t poff, const 
 }
 
 // ---------------------------------------------------------------------------------
-// trilinear sample of a 3-vector volume at continuous index q (zero padding): value G
-// and Jacobian JG[c][a] = dG_c / dy_a.  q is split as (integer voxel index) + (u/h)
-// so that the fraction keeps full precision.
-// ---------------------------------------------------------------------------------
 // trilinear interpolation of the 8 corner values cv[z][y][x][c] at fractions t: value G
 // and (JGW) the Jacobian JG[c][a] = dG_c / dy_a.  x, then y, then z; derivatives from
 // differences of the lower-order interpolants.
@@ -570,6 +564,59 @@ __device__ __forceinline__ void interp_corners(const float cv[2][2][2][3], const
 // element offset and uniform strides without clamping or masking; otherwise corners
 // outside read a clamped voxel and are discarded.
 // ---------------------------------------------------------------------------------
+// interp_corners for half-precision corners given as stored words: the first level (along
+// x) takes the halves straight into mixed-precision multiply-adds (one rounding each, as
+// in FP32 after an exact conversion), the rest is interp_corners' arithmetic
+template <bool JGW>
+__device__ __forceinline__ void interp_corners_h(const F16x3::raw cw[2][2][2], const float t[3], const Geo &g,
+                                                 float G[3], float JG[3][3]) {
+  float gx[2][2][3], dx[2][2][3];
+#pragma unroll
+  for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+    for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float c0 = (float)F16x3::comp(cw[cz][cy][0], c), c1 = (float)F16x3::comp(cw[cz][cy][1], c);
+        dx[cz][cy][c] = c1 - c0;
+        gx[cz][cy][c] = __builtin_fmaf(t[0], c1, __builtin_fmaf(-t[0], c0, c0));
+      }
+  float gxy[2][3], dxy[2][3], dyy[2][3];
+#pragma unroll
+  for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      gxy[cz][c] = gx[cz][0][c] + t[1] * (gx[cz][1][c] - gx[cz][0][c]);
+      dxy[cz][c] = dx[cz][0][c] + t[1] * (dx[cz][1][c] - dx[cz][0][c]);
+      dyy[cz][c] = gx[cz][1][c] - gx[cz][0][c];
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    G[c] = gxy[0][c] + t[2] * (gxy[1][c] - gxy[0][c]);
+    if (JGW) {
+      JG[c][0] = (dxy[0][c] + t[2] * (dxy[1][c] - dxy[0][c])) * g.ihx;
+      JG[c][1] = (dyy[0][c] + t[2] * (dyy[1][c] - dyy[0][c])) * g.ihy;
+      JG[c][2] = (gxy[1][c] - gxy[0][c]) * g.ihz;
+    }
+  }
+}
+
+// Scaled storage: the samplers interpolate the stored values and apply the volume's
+// power-of-two scale once to the result (exact, and the same as scaling every corner).
+template <class ST, bool JGW>
+__device__ __forceinline__ void scale_sample(float s, float G[3], float JG[3][3]) {
+  if constexpr (ST::kScaled) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      G[c] *= s;
+      if (JGW) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) JG[c][a] *= s;
+      }
+    }
+  }
+}
+
 template <class ST, bool JGW = true>
 __device__ __forceinline__ void sample_grad(const typename ST::elem *gT, float sT, const Geo &g, int ix, int iy,
                                             int iz, const float uh[3], float G[3], float JG[3][3]) {
@@ -592,13 +639,28 @@ __device__ __forceinline__ void sample_grad(const typename ST::elem *gT, float s
     const uint32_t sy = (uint32_t)g.nx * ST::W, sz = (uint32_t)g.nx * (uint32_t)g.ny * ST::W;
     const uint32_t off = ((uint32_t)i0[2] * (uint32_t)g.ny + (uint32_t)i0[1]) * (uint32_t)g.nx * ST::W +
                          (uint32_t)i0[0] * ST::W;
+    if constexpr (ST::kScaled && !JGW) {
+      // value only: the halves go straight into mixed-precision multiply-adds (with the
+      // Jacobian, converting each corner once for both uses measured faster)
+      typename ST::raw cw[2][2][2];
+#pragma unroll
+      for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+          for (int cx = 0; cx < 2; ++cx)
+            cw[cz][cy][cx] = ST::fetch(gT + (off + (cz ? sz : 0u) + (cy ? sy : 0u) + (cx ? (uint32_t)ST::W : 0u)));
+      interp_corners_h<JGW>(cw, t, g, G, JG);
+      scale_sample<ST, JGW>(sT, G, JG);
+      return;
+    }
 #pragma unroll
     for (int cz = 0; cz < 2; ++cz)
 #pragma unroll
       for (int cy = 0; cy < 2; ++cy)
 #pragma unroll
         for (int cx = 0; cx < 2; ++cx)
-          ST::loadp(gT + (off + (cz ? sz : 0u) + (cy ? sy : 0u) + (cx ? (uint32_t)ST::W : 0u)), sT, cv[cz][cy][cx]);
+          ST::loadp(gT + (off + (cz ? sz : 0u) + (cy ? sy : 0u) + (cx ? (uint32_t)ST::W : 0u)), 1.0f, cv[cz][cy][cx]);
   } else {
     const bool vx0 = (unsigned)i0[0] < (unsigned)g.nx, vx1 = (unsigned)(i0[0] + 1) < (unsigned)g.nx;
     const bool vy0 = (unsigned)i0[1] < (unsigned)g.ny, vy1 = (unsigned)(i0[1] + 1) < (unsigned)g.ny;
@@ -616,12 +678,13 @@ __device__ __forceinline__ void sample_grad(const typename ST::elem *gT, float s
           const bool ok = (cz ? vz1 : vz0) && (cy ? vy1 : vy0) && (cx ? vx1 : vx0);
           const unsigned vi = (unsigned)(Z[cz] + Y[cy] + X[cx]);
           float t3[3];
-          ST::loadp(gT + (uint64_t)vi * ST::W, sT, t3);
+          ST::loadp(gT + (uint64_t)vi * ST::W, 1.0f, t3);
 #pragma unroll
           for (int c = 0; c < 3; ++c) cv[cz][cy][cx][c] = ok ? t3[c] : 0.0f;
         }
   }
   interp_corners<JGW>(cv, t, g, G, JG);
+  scale_sample<ST, JGW>(sT, G, JG);
 }
 
 // wave-wide shift: lane i receives the value of lane i + 1; lane 63 and lanes whose
@@ -684,8 +747,8 @@ __device__ __forceinline__ void sample_grad_row(const typename ST::elem *gT, flo
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const bool need = (r & 1) || !reuse;
-    if (need) ST::loadp(gT + (uint32_t)key[r] * W, sT, cx0[r]);
-    if (need && !share[r]) ST::loadp(gT + ((uint32_t)key[r] * W + W), sT, cx1[r]);
+    if (need) ST::loadp(gT + (uint32_t)key[r] * W, 1.0f, cx0[r]);
+    if (need && !share[r]) ST::loadp(gT + ((uint32_t)key[r] * W + W), 1.0f, cx1[r]);
   }
   float cv[2][2][2][3];  // [z][y][x][c]
 #pragma unroll
@@ -710,6 +773,7 @@ __device__ __forceinline__ void sample_grad_row(const typename ST::elem *gT, flo
   for (int a = 0; a < 3; ++a) rc.i0[a] = i0[a];
   rc.valid = true;
   interp_corners<JGW>(cv, t, g, G, JG);
+  scale_sample<ST, JGW>(sT, G, JG);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1006,7 +1070,7 @@ __device__ __forceinline__ void load_corners(const float *fb, const Geo &g, bool
 // ---------------------------------------------------------------------------------
 // unrolling of the voxel rows (y) and layers (z) of a cell in the objective pass
 #ifndef DISCO_EVAL_JV
-#define DISCO_EVAL_JV 2
+#define DISCO_EVAL_JV 4
 #endif
 #ifndef DISCO_EVAL_KV
 #define DISCO_EVAL_KV 1
@@ -1250,10 +1314,12 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
                   // cell holding the sample point is a reproducible FP32 decision.
                   const float uh[3] = {f3[0] * g.ihx, f3[1] * g.ihy, f3[2] * g.ihz};
                   float a[3], JG[3][3], b[3];
-                  // objective pass: row sampler (shared corners); gradient pass: plain sampler,
-                  // which measured faster there
-                  if constexpr (MODE == M_EVAL)
+                  // objective pass: row sampler (shared corners) in FP32 storage; gradient pass
+                  // and half-precision storage: plain sampler (measured faster there)
+                  if constexpr (MODE == M_EVAL && !ST::kScaled)
                     sample_grad_row<ST, false>(A.gT, A.sT, g, ix, iy, iz, uh, rc, a, JG);
+                  else if constexpr (MODE == M_EVAL)
+                    sample_grad<ST, false>(A.gT, A.sT, g, ix, iy, iz, uh, a, JG);
                   else
                     sample_grad<ST, true>(A.gT, A.sT, g, ix, iy, iz, uh, a, JG);
                   ST::loadp(rp + voff, A.sR, b);
@@ -1783,29 +1849,42 @@ __global__ __launch_bounds__(64 * kImgY) void k_imgrad(Geo g, const float *__res
   }
 }
 
-// max |grad| of a volume in blocks (for the FP16 scale)
-__global__ __launch_bounds__(256) void k_absmax_grad(Geo g, const float *img, double *blocks) {
-  __shared__ double red[256];
-  const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  double m = 0.0;
-  if (v < g.nvox) {
-    const int i = (int)(v % g.nx), j = (int)((v / g.nx) % g.ny), k = (int)(v / ((int64_t)g.nx * g.ny));
-    const int64_t sx = 1, sy = g.nx, sz = (int64_t)g.nx * g.ny;
-    const int64_t xm = i > 0 ? v - sx : v, xp = i < g.nx - 1 ? v + sx : v;
-    const int64_t ym = j > 0 ? v - sy : v, yp = j < g.ny - 1 ? v + sy : v;
-    const int64_t zm = k > 0 ? v - sz : v, zp = k < g.nz - 1 ? v + sz : v;
-    m = fmax(fabs((double)((img[xp] - img[xm]) * (0.5f * g.ihx))),
-             fmax(fabs((double)((img[yp] - img[ym]) * (0.5f * g.ihy))),
-                  fabs((double)((img[zp] - img[zm]) * (0.5f * g.ihz)))));
+// max |grad component| of a volume per tile (for the FP16 scale): the traversal and the
+// gradient values of k_imgrad (before scaling), one maximum per 64 x kImgY x kImgZ tile
+__global__ __launch_bounds__(64 * kImgY) void k_absmax_grad(Geo g, const float *__restrict__ img, double *blocks) {
+  __shared__ float wmax[kImgY];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane, j = blockIdx.y * kImgY + wave;
+  const int z0 = blockIdx.z * kImgZ, z1 = min(z0 + kImgZ, g.nz);
+  float m = 0.0f;
+  if (i < g.nx && j < g.ny && z0 < g.nz) {
+    const int64_t sy = g.nx, sz = (int64_t)g.nx * g.ny, col = (int64_t)j * g.nx + i;
+    const int64_t dxm = i > 0 ? -1 : 0, dxp = i < g.nx - 1 ? 1 : 0;
+    const int64_t dym = j > 0 ? -sy : 0, dyp = j < g.ny - 1 ? sy : 0;
+    const float cx = 0.5f * g.ihx, cy = 0.5f * g.ihy, cz = 0.5f * g.ihz;
+    float zm = img[(int64_t)(z0 > 0 ? z0 - 1 : 0) * sz + col];
+    float zc = img[(int64_t)z0 * sz + col];
+#pragma unroll 4
+    for (int k = z0; k < z1; ++k) {
+      const int64_t v = (int64_t)k * sz + col;
+      const float zp = k < g.nz - 1 ? img[v + sz] : zc;
+      m = fmaxf(m, fabsf((img[v + dxp] - img[v + dxm]) * cx));
+      m = fmaxf(m, fabsf((img[v + dyp] - img[v + dym]) * cy));
+      m = fmaxf(m, fabsf((zp - zm) * cz));
+      zm = zc;
+      zc = zp;
+    }
   }
-  const int t = threadIdx.x;
-  red[t] = m;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if (lane == 0) wmax[wave] = m;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (t < s) red[t] = fmax(red[t], red[t + s]);
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    float r = wmax[0];
+#pragma unroll
+    for (int w = 1; w < kImgY; ++w) r = fmaxf(r, wmax[w]);
+    blocks[((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = (double)r;
   }
-  if (t == 0) blocks[blockIdx.x] = red[0];
 }
 
 // convert a stored 3-vector volume to float32 [N][3]
