@@ -425,6 +425,13 @@ int disco_batch_gn_step(disco_batch *batch, disco_stream stream);
    captured graph. */
 int disco_batch_set_launch(disco_batch *batch, int32_t pass, int32_t wg_per_cu);
 
+/* Brick tile of the batched passes: bricks of 16 x 4 x cells_z cells, cells_z = 4 (the
+   single-pair tile, default) or 2 (twice the bricks, half the depth: more work items for
+   batches of small pairs).  The tile changes the order in which brick contributions are
+   summed, so steps on the two tiles agree to rounding.  Invalidates a captured graph and
+   the prepared descriptors: call disco_batch_prepare again before the next step. */
+int disco_batch_set_tile(disco_batch *batch, int32_t cells_z);
+
 /* Capture nsteps GN steps into a graph owned by the batch (library stream; no host
    synchronisation inside), and replay it on `stream`.  A replay works on the arrays
    given to disco_batch_prepare. */

@@ -64,8 +64,10 @@ __device__ __forceinline__ int node_gx(const Geo &g) { return (g.px + 63) / 64; 
 __device__ __forceinline__ int node_gy(const Geo &g) { return (g.py + 3) / 4; }
 
 // ---- brick passes -------------------------------------------------------------------
-// sel: 0 = linearisation, 1/2 = GN product with p[0]/p[1], 3 = line-search trial
-template <class ST, int MODE, bool NGF, bool VCC, bool KP>
+// sel: 0 = linearisation, 1/2 = GN product with p[0]/p[1], 3 = line-search trial; ZC: cell
+// layers per brick (the batch's tile; the descriptors' geometry carries the matching
+// brick counts)
+template <class ST, int MODE, bool NGF, bool VCC, bool KP, int ZC>
 __global__ __launch_bounds__(256, 1) void k_b_brick(const PairDesc<ST> *D,
                                                                                    const int *start, int npairs,
                                                                                    int sel, int acc) {
@@ -74,21 +76,21 @@ __global__ __launch_bounds__(256, 1) void k_b_brick(const PairDesc<ST> *D,
     const int pr = find_pair(start, npairs, item);
     const PairDesc<ST> &P = D[pr];
     const BrickArgs<ST> &A = sel == 0 ? P.lin : (sel == 3 ? P.eval : P.hv[sel - 1]);
-    brick_body<ST, MODE, NGF, VCC, KP, 4, false, true>(A, grid_blk(item - start[pr], A.g.nbx, A.g.nby), acc);
+    brick_body<ST, MODE, NGF, VCC, KP, ZC, false, true>(A, grid_blk(item - start[pr], A.g.nbx, A.g.nby), acc);
     __syncthreads();  // the next item reuses the workgroup's LDS
   }
 }
 
 // ---- node-parallel passes -----------------------------------------------------------
-// sel: 0 = after linearisation, 1/2 = after the product with p[0]/p[1]
-template <class ST, int F, int NF, bool CURV>
+// sel: 0 = after linearisation, 1/2 = after the product with p[0]/p[1]; ZC as in k_b_brick
+template <class ST, int F, int NF, bool CURV, int ZC>
 __global__ __launch_bounds__(256) void k_b_gather(const PairDesc<ST> *D, const int *start, int npairs, int sel) {
   const int total = start[npairs];
   for (int item = blockIdx.x; item < total; item += gridDim.x) {
     const int pr = find_pair(start, npairs, item);
     const PairDesc<ST> &P = D[pr];
     const GatherArgs &A = sel == 0 ? P.glin : P.ghv[sel - 1];
-    gather_body<4, F, NF, CURV>(A, grid_blk(item - start[pr], node_gx(P.g), node_gy(P.g)));
+    gather_body<ZC, F, NF, CURV>(A, grid_blk(item - start[pr], node_gx(P.g), node_gy(P.g)));
     __syncthreads();
   }
 }

@@ -113,6 +113,7 @@ struct disco_batch {
   int pcg_iters = 0, ls_max = 0;
   int ncu = 0;
   int wpc[3] = {4, 8, 8};        // workgroups per compute unit: brick, node, vector passes
+  int zc = kZC;                  // brick tile of the batched passes: cell layers per brick (2 or 4)
   std::unordered_map<const void *, int> occ;  // resident workgroups per compute unit, per kernel
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -138,6 +139,14 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // 3-D grid of 64 x 4 thread blocks over the node grid
 inline dim3 node_grid(const Geo &g) { return dim3((g.px + 63) / 64, (g.py + 3) / 4, g.pz); }
+// geometry for bricks of zc cell layers (the batched passes' tile); bricks of that tile
+inline Geo tile_geo(Geo g, int zc) {
+  g.zc = zc;
+  g.nbz = (g.cz + zc - 1) / zc;
+  return g;
+}
+inline int64_t tile_bricks(const Geo &g, int zc) { return (int64_t)g.nbx * g.nby * ((g.cz + zc - 1) / zc); }
+constexpr int kTileZ[2] = {4, 2};  // brick tiles of the batched passes
 inline int64_t node_blocks(const Geo &g) { return (int64_t)((g.px + 63) / 64) * ((g.py + 3) / 4) * g.pz; }
 // workgroups of the CG vector update, and the grid of the fused p update + L p pass
 inline int64_t upd_blocks(const Geo &g) { return (3 * g.nnodes + 256 * kUpdK - 1) / (256 * kUpdK); }
@@ -433,9 +442,10 @@ FinishArgs finish_args(int post, const PostArgs &pa, const double *stop, RedSrc 
 }
 
 template <class ST>
-PairDesc<ST> pair_desc(disco_ctx *c, const disco_params *p, float *u, double *report, int32_t *status_out) {
+PairDesc<ST> pair_desc(disco_ctx *c, const disco_params *p, float *u, double *report, int32_t *status_out, int zc) {
   PairDesc<ST> d{};
   const Geo &g = c->g;
+  const Geo tg = tile_geo(g, zc);  // the batch's brick tile
   const bool vcc = p->gamma != 0.0;
   const bool kp = p->delta != 0.0 && c->nkp > 0;
   const bool curv = p->alpha != 0.0;
@@ -482,17 +492,23 @@ PairDesc<ST> pair_desc(disco_ctx *c, const disco_params *p, float *u, double *re
   for (int k = 0; k < 2; ++k)
     D.ghv[k] = gather_args<ST>(c, 1, 1, c->vq, nullptr, curv ? c->Lw : nullptr, (float)(p->alpha * CH), 0,
                                p->tau != 0.0 ? D.p[k] : nullptr, (float)p->tau, D.p[k], c->sc + SC_STOP);
+  // the brick passes and the gathers of their partials work on the batch's brick tile
+  D.lin.g = D.eval.g = D.hv[0].g = D.hv[1].g = tg;
+  D.glin.g = D.ghv[0].g = D.ghv[1].g = tg;
+  const RedSrc bricks{c->blk_brick, tile_bricks(g, zc), BS_N, BS_N, 0u, nullptr};
   PostArgs pa = post_args(c, p->alpha, p->gamma, p->delta);
   pa.c1 = p->armijo_c1;
   pa.tol = p->pcg_tol;
   double *sc = c->sc;
   const int64_t nb3 = nblk(3 * g.nnodes);
-  D.fin_lin = finish_args(POST_LIN_BRICK, pa, nullptr, src_brick(c, sc + SC_TMP0), src_curv(c, sc + SC_SRAW),
-                          src_gather(c, sc + SC_DOT));
+  RedSrc b_lin = bricks, b_trial = bricks;
+  b_lin.out = sc + SC_TMP0;
+  b_trial.out = sc + SC_TMP0;
+  D.fin_lin = finish_args(POST_LIN_BRICK, pa, nullptr, b_lin, src_curv(c, sc + SC_SRAW), src_gather(c, sc + SC_DOT));
   D.fin_pcg = finish_args(POST_PCG_START, pa, nullptr, src_pairs(c->blk_node, nb3, 2, sc + SC_TMP0));
   D.fin_lsb = finish_args(POST_LS_BEGIN, pa, nullptr, src_pairs(c->blk_node, nb3, 1, sc + SC_TMP0),
                           src_pairs(c->blk_upd, upd_blocks(g), 2, sc + SC_TMP1));
-  D.fin_trial = finish_args(POST_LS_BRICK, pa, sc + SC_ACCEPT, src_brick(c, sc + SC_TMP0), src_curv(c, sc + SC_TSRAW));
+  D.fin_trial = finish_args(POST_LS_BRICK, pa, sc + SC_ACCEPT, b_trial, src_curv(c, sc + SC_TSRAW));
   return d;
 }
 
@@ -603,8 +619,15 @@ int disco_create(const disco_geom *geom, int32_t storage, disco_ctx **out) {
   float **nodebufs[] = {&c->u_lin, &c->Lw, &c->vg, &c->vdiag, &c->vx, &c->vr, &c->vz, &c->vp, &c->vq, &c->vut,
                         &c->tmp0, &c->tmp1, &c->vp2, &c->vinvm};
   for (float **p : nodebufs) alloc(reinterpret_cast<void **>(p), nf);
-  alloc(reinterpret_cast<void **>(&c->part), sizeof(float) * (size_t)c->nwg * (kZC + 1) * 6 * kNBOX);
-  alloc(reinterpret_cast<void **>(&c->blk_brick), sizeof(double) * (size_t)c->nwg * BS_N);
+  // brick partials and per-brick sums, sized for every brick tile (the batched passes may
+  // use bricks of 2 cell layers)
+  size_t part_planes = 0, nbrick = 0;
+  for (int zc : kTileZ) {
+    part_planes = std::max(part_planes, (size_t)tile_bricks(g, zc) * (zc + 1));
+    nbrick = std::max(nbrick, (size_t)tile_bricks(g, zc));
+  }
+  alloc(reinterpret_cast<void **>(&c->part), sizeof(float) * part_planes * 6 * kNBOX);
+  alloc(reinterpret_cast<void **>(&c->blk_brick), sizeof(double) * nbrick * BS_N);
   // node-parallel reductions: 3 values per block over nnodes, or 3 per 256 elements of 3 nnodes
   alloc(reinterpret_cast<void **>(&c->blk_node),
         sizeof(double) * ((size_t)std::max<int64_t>(c->nodeblocks * 6, 3 * (int64_t)nblk(3 * g.nnodes)) + 16));
@@ -1474,6 +1497,28 @@ int disco_profile_read(disco_ctx *c, int32_t kernel, int64_t *launches, double *
 // ------------------------------------------------------------------------------
 enum { WL_BRICK = 0, WL_NODE = 1, WL_VEC = 2, WL_UPD = 3 };
 
+// work lists of the batch (bricks of its tile, node blocks, 256-element vector blocks, CG
+// update blocks): item offsets of every pair, copied to the device (synchronous)
+static int batch_worklists(disco_batch *b) {
+  const int npairs = (int)b->ctx.size();
+  std::vector<int> st(4 * (size_t)(npairs + 1), 0);
+  int64_t acc[4] = {0, 0, 0, 0};
+  for (int i = 0; i < npairs; ++i) {
+    const disco_ctx *c = b->ctx[i];
+    const int64_t cnt[4] = {tile_bricks(c->g, b->zc), c->nodeblocks, (int64_t)nblk(3 * c->g.nnodes), upd_blocks(c->g)};
+    for (int w = 0; w < 4; ++w) {
+      st[w * (npairs + 1) + i] = (int)acc[w];
+      acc[w] += cnt[w];
+    }
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (acc[w] >= ((int64_t)1 << 31)) return DISCO_ERR_SHAPE;
+    st[w * (npairs + 1) + npairs] = (int)acc[w];
+  }
+  if (hipMemcpy(b->start, st.data(), sizeof(int) * st.size(), hipMemcpyHostToDevice) != hipSuccess) return DISCO_ERR_NOMEM;
+  return DISCO_OK;
+}
+
 static void batch_free_graph(disco_batch *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -1514,31 +1559,12 @@ int disco_batch_create(int32_t npairs, disco_ctx *const *ctxs, disco_batch **out
     delete b;
     return DISCO_ERR_NOMEM;
   }
-  // work lists: bricks, node blocks, 256-element vector blocks, CG update blocks
-  std::vector<int> st(4 * (size_t)(npairs + 1), 0);
-  int64_t acc[4] = {0, 0, 0, 0};
-  for (int i = 0; i < npairs; ++i) {
-    const disco_ctx *c = b->ctx[i];
-    const int64_t cnt[4] = {c->nwg, c->nodeblocks, (int64_t)nblk(3 * c->g.nnodes), upd_blocks(c->g)};
-    for (int w = 0; w < 4; ++w) {
-      st[w * (npairs + 1) + i] = (int)acc[w];
-      acc[w] += cnt[w];
-    }
-  }
-  for (int w = 0; w < 4; ++w) {
-    if (acc[w] >= ((int64_t)1 << 31)) {
-      (void)hipFree(b->desc);
-      (void)hipFree(b->start);
-      delete b;
-      return DISCO_ERR_SHAPE;
-    }
-    st[w * (npairs + 1) + npairs] = (int)acc[w];
-  }
-  if (hipMemcpy(b->start, st.data(), sizeof(int) * st.size(), hipMemcpyHostToDevice) != hipSuccess) {
+  const int e = batch_worklists(b);
+  if (e) {
     (void)hipFree(b->desc);
     (void)hipFree(b->start);
     delete b;
-    return DISCO_ERR_NOMEM;
+    return e;
   }
   *out = b;
   return DISCO_OK;
@@ -1564,7 +1590,7 @@ static int batch_prepare_t(disco_batch *b, const disco_params *params, float *co
   for (int i = 0; i < n; ++i) {
     const int ci = b->order[i];
     d[i] = pair_desc<ST>(b->ctx[i], &params[ci], u[ci], report_dev ? report_dev + DISCO_REP_SIZE * (size_t)ci : nullptr,
-                         status_dev ? status_dev + ci : nullptr);
+                         status_dev ? status_dev + ci : nullptr, b->zc);
   }
   HIP_TRY(hipMemcpy(b->desc, d.data(), sizeof(PairDesc<ST>) * (size_t)n, hipMemcpyHostToDevice));
   return DISCO_OK;
@@ -1619,6 +1645,17 @@ int disco_batch_set_launch(disco_batch *b, int32_t pass, int32_t wg_per_cu) {
   return DISCO_OK;
 }
 
+int disco_batch_set_tile(disco_batch *b, int32_t cells_z) {
+  if (!b || (cells_z != 2 && cells_z != 4)) return DISCO_ERR_ARG;
+  int e;
+  if ((e = set_device(b->ctx[0]))) return e;
+  batch_free_graph(b);
+  b->prepared = false;  // the descriptors carry the tile's brick geometry
+  b->zc = cells_z;
+  b->occ.clear();
+  return batch_worklists(b);
+}
+
 extern "C++" {
 // With a persistent grid (wpc > 0) the workgroups loop over the items, so a workgroup that
 // is not resident from the start would begin only once a resident one has finished all of
@@ -1644,8 +1681,26 @@ template <class ST, int MODE, bool NGF, bool VCC, bool KP>
 static void b_brick_go(disco_batch *b, unsigned grid, const PairDesc<ST> *D, const int *st, int n, int sel, int acc,
                        hipStream_t s) {
   constexpr int threads = 256;
-  grid = b_cap(b, 0, k_b_brick<ST, MODE, NGF, VCC, KP>, threads, grid);
-  hipLaunchKernelGGL((k_b_brick<ST, MODE, NGF, VCC, KP>), dim3(grid), dim3(threads), 0, s, D, st, n, sel, acc);
+  if (b->zc == 2) {
+    const unsigned gr = b_cap(b, 0, k_b_brick<ST, MODE, NGF, VCC, KP, 2>, threads, grid);
+    hipLaunchKernelGGL((k_b_brick<ST, MODE, NGF, VCC, KP, 2>), dim3(gr), dim3(threads), 0, s, D, st, n, sel, acc);
+  } else {
+    const unsigned gr = b_cap(b, 0, k_b_brick<ST, MODE, NGF, VCC, KP, 4>, threads, grid);
+    hipLaunchKernelGGL((k_b_brick<ST, MODE, NGF, VCC, KP, 4>), dim3(gr), dim3(threads), 0, s, D, st, n, sel, acc);
+  }
+}
+
+// gather of the batch's brick partials (sel as in k_b_gather), on the batch's tile
+template <class ST, int F, int NF, bool CURV>
+static void b_gather_go(disco_batch *b, unsigned grid, const PairDesc<ST> *D, const int *st, int n, int sel,
+                        hipStream_t s) {
+  if (b->zc == 2) {
+    const unsigned gr = b_cap(b, 1, k_b_gather<ST, F, NF, CURV, 2>, 256, grid);
+    hipLaunchKernelGGL((k_b_gather<ST, F, NF, CURV, 2>), dim3(gr), dim3(256), 0, s, D, st, n, sel);
+  } else {
+    const unsigned gr = b_cap(b, 1, k_b_gather<ST, F, NF, CURV, 4>, 256, grid);
+    hipLaunchKernelGGL((k_b_gather<ST, F, NF, CURV, 4>), dim3(gr), dim3(256), 0, s, D, st, n, sel);
+  }
 }
 
 template <class ST, int MODE, bool NGF>
@@ -1681,7 +1736,8 @@ static void batch_step_t(disco_batch *b, hipStream_t s) {
   for (int w = 0; w < 4; ++w) {
     int64_t t = 0;
     for (auto *c : b->ctx)
-      t += w == WL_BRICK ? c->nwg : (w == WL_NODE ? c->nodeblocks : (w == WL_VEC ? (int64_t)nblk(3 * c->g.nnodes) : upd_blocks(c->g)));
+      t += w == WL_BRICK ? tile_bricks(c->g, b->zc)
+                         : (w == WL_NODE ? c->nodeblocks : (w == WL_VEC ? (int64_t)nblk(3 * c->g.nnodes) : upd_blocks(c->g)));
     tot[w] = (int)t;
   }
   // wpc 0: one workgroup per item (the hardware schedules them); else a persistent grid of
@@ -1699,9 +1755,9 @@ static void batch_step_t(disco_batch *b, hipStream_t s) {
   if (cells) launch_b_brick<ST, M_GRAD, false>(b, gb, wl[WL_BRICK], n, 0, 0, s);
   launch_b_brick<ST, M_GRAD, true>(b, gb, wl[WL_BRICK], n, 0, cells ? 1 : 0, s);
   if (b->curv)
-    hipLaunchKernelGGL((k_b_gather<ST, 2, 2, true>), dim3(b_cap(b, 1, k_b_gather<ST, 2, 2, true>, 256, gn)), dim3(256), 0, s, D, wl[WL_NODE], n, 0);
+    b_gather_go<ST, 2, 2, true>(b, gn, D, wl[WL_NODE], n, 0, s);
   else
-    hipLaunchKernelGGL((k_b_gather<ST, 2, 2, false>), dim3(b_cap(b, 1, k_b_gather<ST, 2, 2, false>, 256, gn)), dim3(256), 0, s, D, wl[WL_NODE], n, 0);
+    b_gather_go<ST, 2, 2, false>(b, gn, D, wl[WL_NODE], n, 0, s);
   hipLaunchKernelGGL(k_b_finish<ST>, dim3(pairs_grid), dim3(1024), 0, s, D, n, 0);
   hipLaunchKernelGGL(k_b_vec<ST>, dim3(b_cap(b, 2, k_b_vec<ST>, 256, gv)), dim3(256), 0, s, D, wl[WL_VEC], n, 0, 0);  // u_lin = u
   // Jacobi-PCG
@@ -1715,9 +1771,9 @@ static void batch_step_t(disco_batch *b, hipStream_t s) {
     }
     launch_b_brick<ST, M_HV, true>(b, gb, wl[WL_BRICK], n, 1 + (it & 1), 0, s);
     if (b->curv)
-      hipLaunchKernelGGL((k_b_gather<ST, 1, 1, true>), dim3(b_cap(b, 1, k_b_gather<ST, 1, 1, true>, 256, gn)), dim3(256), 0, s, D, wl[WL_NODE], n, 1 + (it & 1));
+      b_gather_go<ST, 1, 1, true>(b, gn, D, wl[WL_NODE], n, 1 + (it & 1), s);
     else
-      hipLaunchKernelGGL((k_b_gather<ST, 1, 1, false>), dim3(b_cap(b, 1, k_b_gather<ST, 1, 1, false>, 256, gn)), dim3(256), 0, s, D, wl[WL_NODE], n, 1 + (it & 1));
+      b_gather_go<ST, 1, 1, false>(b, gn, D, wl[WL_NODE], n, 1 + (it & 1), s);
     hipLaunchKernelGGL(k_b_pcg_update<ST>, dim3(b_cap(b, 2, k_b_pcg_update<ST>, 256, gu)), dim3(256), 0, s, D, wl[WL_UPD], n, it);
   }
   // Armijo line search on the device (ls_max trials, skipped once accepted)

@@ -73,6 +73,7 @@ _SIGS = {
     "disco_set_images": ([_P, _P, _P, _P], ctypes.c_int),
     "disco_set_moving": ([_P, _P, _P], ctypes.c_int),
     "disco_set_images_noalloc": ([_P, _P, _P, _P], ctypes.c_int),
+    "disco_batch_set_tile": ([_P, _I], ctypes.c_int),
     "disco_set_keypoints": ([_P, _I, _P, _P, _P], ctypes.c_int),
     "disco_set_reference": ([_P, _P, _P], ctypes.c_int),
     "ngf_eval": ([_P, _D, _P, _P, _P], ctypes.c_int),
@@ -477,19 +478,30 @@ class Batch:
             raise ValueError("one Params and one u per pair")
         for c, u in zip(self.ctxs, us):
             c._field(u, "u")
-        pa = (_Params * n)(*[p.c() for p in params])
-        ua = (_P * n)(*[u.data_ptr() for u in us])
         rep = torch.zeros((n, REP_SIZE), dtype=torch.float64, device=self.device)
         st = torch.zeros(n, dtype=torch.int32, device=self.device)
-        _check(_lib.disco_batch_prepare(self._h, pa, ua, _ptr(rep), _ptr(st)), "disco_batch_prepare")
-        self._keep = (list(us), rep, st)
+        self._prepare(list(params), list(us), rep, st)
         return rep, st
+
+    def _prepare(self, params, us, rep, st):
+        n = len(self.ctxs)
+        pa = (_Params * n)(*[p.c() for p in params])
+        ua = (_P * n)(*[u.data_ptr() for u in us])
+        _check(_lib.disco_batch_prepare(self._h, pa, ua, _ptr(rep), _ptr(st)), "disco_batch_prepare")
+        self._keep = (params, us, rep, st)
 
     def gn_step(self):
         _check(_lib.disco_batch_gn_step(self._h, self._stream()), "disco_batch_gn_step")
 
     def set_launch(self, pass_: int, wg_per_cu: int):
         _check(_lib.disco_batch_set_launch(self._h, pass_, wg_per_cu), "disco_batch_set_launch")
+
+    def set_tile(self, cells_z: int):
+        """Brick tile of the batched passes (16 x 4 x cells_z cells, cells_z 4 or 2); a
+        prepared batch is prepared again with the same parameters, fields and report tensors."""
+        _check(_lib.disco_batch_set_tile(self._h, int(cells_z)), "disco_batch_set_tile")
+        if self._keep is not None:
+            self._prepare(*self._keep)
 
     def graph_capture(self, nsteps: int):
         _check(_lib.disco_batch_graph_capture(self._h, nsteps), "disco_batch_graph_capture")

@@ -51,9 +51,12 @@ def params_for(disco, ctx, d, iters=6, ls_max=6):
                         flags=disco.FLAG_LS_DEVICE)
 
 
+@pytest.mark.parametrize("tile", [4, 2])
 @pytest.mark.parametrize("storage", ["fp32", "fp16"])
-def test_batch_step_equals_single_pair(disco, pairs, storage):
-    say(f"[batch] {len(pairs)} pairs, storage={storage}")
+def test_batch_step_equals_single_pair(disco, pairs, storage, tile):
+    """Both brick tiles (16 x 4 x 4 and 16 x 4 x 2 cells): the tile changes the order in
+    which brick contributions are summed, so the comparison is to rounding."""
+    say(f"[batch] {len(pairs)} pairs, storage={storage}, tile cells_z={tile}")
     cb = [make_ctx(disco, d, storage) for d in pairs]
     cs = [make_ctx(disco, d, storage) for d in pairs]
     params = [params_for(disco, c, d) for c, d in zip(cb, pairs)]
@@ -62,6 +65,7 @@ def test_batch_step_equals_single_pair(disco, pairs, storage):
     us = [u.clone() for u in u0]
     batch = disco.Batch(cb)
     rep, st = batch.prepare(params, ub)
+    batch.set_tile(tile)
     batch.gn_step()
     torch.cuda.synchronize()
     rep1 = rep.clone()
@@ -86,13 +90,15 @@ def test_batch_step_equals_single_pair(disco, pairs, storage):
     batch.close()
 
 
-def test_batch_step_matches_oracle(disco, pairs):
+@pytest.mark.parametrize("tile", [4, 2])
+def test_batch_step_matches_oracle(disco, pairs, tile):
     """The largest pair of the batch, one step from u_true / 2, against the FP64 oracle."""
-    say("[batch] oracle check")
+    say(f"[batch] oracle check, tile cells_z={tile}")
     cb = [make_ctx(disco, d) for d in pairs]
     params = [params_for(disco, c, d) for c, d in zip(cb, pairs)]
     u0 = [(torch.from_numpy(d["u_true"]) * 0.5).to(DEV) for d in pairs]
     batch = disco.Batch(cb)
+    batch.set_tile(tile)
     rep, st = batch.prepare(params, u0)
     batch.gn_step()
     torch.cuda.synchronize()
@@ -192,5 +198,51 @@ def test_batch_launch_shapes_agree(disco, pairs, shape):
     assert torch.equal(ra, rb)
     for x, y in zip(ua, ub):
         assert torch.equal(x, y)
+    ba.close()
+    bb.close()
+
+
+def test_autotune_choice_and_cache(disco, pairs, tmp_path, monkeypatch):
+    """The tuner returns a tile and launch shapes from its candidate sets, stores them under
+    the batch's key, and a later call with the same key returns the stored choice without
+    timing anything; the choice applied to a prepared batch steps like the default."""
+    from paper_1807_00467_amd import autotune
+    say("[batch] autotune")
+    ctxs = [make_ctx(disco, d) for d in pairs]
+    params = [params_for(disco, c, d, iters=3, ls_max=3) for c, d in zip(ctxs, pairs)]
+    u0 = [torch.from_numpy(d["u_true"]).to(DEV) * 0.5 for d in pairs]
+    keep = [u.clone() for u in u0]
+    cache = str(tmp_path / "autotune.json")
+    choice = autotune.tune(ctxs, params, u0, reps=1, cache=cache, log=say)
+    say(f"  choice {choice}")
+    assert set(choice) == set(autotune.CANDIDATES)
+    for k, w in choice.items():
+        assert w in autotune.CANDIDATES[k]
+    for a, b in zip(u0, keep):
+        assert torch.equal(a, b)  # the timing ran on copies
+    import json
+    with open(cache) as f:
+        table = json.load(f)
+    assert table[autotune.batch_key(ctxs, params)] == {str(k): v for k, v in choice.items()}
+
+    def no_timing(*a, **k):
+        raise AssertionError("a cache hit must not time")
+
+    monkeypatch.setattr(autotune, "_time_steps", no_timing)
+    assert autotune.tune(ctxs, params, u0, cache=cache) == choice
+    # the choice applied after prepare (set_tile prepares again) against the default shapes
+    ua = [u.clone() for u in u0]
+    ub = [u.clone() for u in u0]
+    ba, bb = disco.Batch(ctxs), disco.Batch([make_ctx(disco, d) for d in pairs])
+    ra, _ = ba.prepare(params, ua)
+    autotune.apply(ba, choice)
+    rb, _ = bb.prepare(params, ub)
+    ba.gn_step()
+    bb.gn_step()
+    torch.cuda.synchronize()
+    for i in range(len(pairs)):
+        x, y = disco.Disco.report_dict(ra[i]), disco.Disco.report_dict(rb[i])
+        assert abs(x["J_new"] - y["J_new"]) <= 1e-6 * abs(y["J_new"]), (i, x["J_new"], y["J_new"])
+        assert x["t"] == y["t"]
     ba.close()
     bb.close()
