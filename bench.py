@@ -150,6 +150,9 @@ def main():
     ap.add_argument("--lbfgs", action="store_true",
                     help="L-BFGS iterations (m = 5, H0 = alpha C_H L^T L + tau I) on the same workload instead")
     ap.add_argument("--tau", type=float, default=10.0, help="tau of the L-BFGS initial Hessian")
+    ap.add_argument("--ls-max", type=int, default=30,
+                    help="Armijo trials at most per L-BFGS iteration (t >= 2^(1-n)); next to a fold the accepted "
+                         "t falls below 2^-9, so 10 trials end the run there")
     ap.add_argument("--keypoints", action="store_true",
                     help="keypoint stage instead: NGF matching cost of 3500 keypoints over 33^3 displacements "
                          "(1 mm images) and its regularisation by belief propagation on the keypoint MST")
@@ -352,7 +355,7 @@ def bench_lbfgs(args):
     zero = torch.zeros((3,) + tuple(ctx.nodes[::-1]), device=dev)
     D0 = ctx.ngf_eval(zero, 10.0).item()
     K0 = ctx.keypoint_penalty(1.0, zero, grad=False, diag=False)["K"].item()
-    params = disco.Params(eta=10.0, alpha=1.0, gamma=0.1, delta=D0 / K0 if K0 > 0 else 0.0, ls_max=10,
+    params = disco.Params(eta=10.0, alpha=1.0, gamma=0.1, delta=D0 / K0 if K0 > 0 else 0.0, ls_max=args.ls_max,
                           flags=disco.FLAG_LS_DEVICE)
     lb = disco.Lbfgs(m=5, tau=args.tau, h0_iters=30, h0_tol=1e-6)
     u = zero.clone()
@@ -404,7 +407,7 @@ def bench_lbfgs(args):
         "config": {
             "workload": f"{args.config}: R,T {d['shape'][0]}x{d['shape'][1]}x{d['shape'][2]}, node grid "
                         f"{nx}x{ny}x{nz}; step = one L-BFGS iteration (m 5, H0 tau {args.tau:g}, <= 30 H0 CG "
-                        f"iterations, Armijo on the device, 10 trials at most); the first {args.steps} "
+                        f"iterations, Armijo on the device, {args.ls_max} trials at most); the first {args.steps} "
                         f"iterations from u = 0",
             "storage": args.storage,
         },
