@@ -1543,47 +1543,52 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
     const int nl = cz1 - cz0;  // cell layers of this brick
     __syncthreads();
     // combine in a fixed order and write every node plane of the brick: interior nodes
-    // directly, brick-face nodes to the partial buffer
-    const int total = (nl + 1) * F * 3 * kNBOX;
-    for (int e = threadIdx.x; e < total; e += WGS) {
-      const int xl = e % 17, yl = (e / 17) % 5, fc = (e / kNBOX) % (F * 3), zl = e / (kNBOX * F * 3);
-      float val = 0.0f;
-      if (NGF_OUT) {
-        if (yl < 4) {
-          if (xl < 16) val += lds[zl][yl][0][fc][0][xl];
-          if (xl > 0) val += lds[zl][yl][0][fc][1][xl - 1];
-        }
-        if (yl > 0) {
-          if (xl < 16) val += lds[zl][yl - 1][1][fc][0][xl];
-          if (xl > 0) val += lds[zl][yl - 1][1][fc][1][xl - 1];
-        }
-      }
-      if (CELL_OUT) {
-        const int f = fc / 3, c = fc - 3 * f;
-#pragma unroll
-        for (int dk = 0; dk < 2; ++dk)
-#pragma unroll
-          for (int dj = 0; dj < 2; ++dj)
-#pragma unroll
-            for (int di = 0; di < 2; ++di) {
-              // cell (xl-1+di, yl-1+dj, zl-1+dk) touches this node at its corner (1-di, 1-dj, 1-dk)
-              const int ci = xl - 1 + di, cj = yl - 1 + dj, ck = zl - 1 + dk;
-              if (ci < 0 || ci >= 16 || cj < 0 || cj >= 4 || ck < 0 || ck >= nl) continue;
-              const int corner = (1 - di) + 2 * (1 - dj) + 4 * (1 - dk);
-              val += cbuf[f * 24 + corner * 3 + c][ck * 64 + cj * 16 + ci];
-            }
-      }
+    // directly, brick-face nodes to the partial buffer.  One thread per node of the brick's
+    // (nl + 1) x 5 x 17 box, all fields and components in turn, so that the node's position,
+    // its neighbour tests and its destination are worked out once.
+    for (int e = threadIdx.x; e < (nl + 1) * kNBOX; e += WGS) {
+      const int zl = e / kNBOX, pos = e - zl * kNBOX;
+      const int yl = pos / 17, xl = pos - yl * 17;
       const int pxn = bx * kBXC + xl, pyn = by * kBYC + yl, pzn = cz0 + zl;
       if (pxn > g.cx || pyn > g.cy) continue;
       const bool face = is_face(zl, bz, g.nbz, ZC) || is_face(xl, bx, g.nbx, kBXC) || is_face(yl, by, g.nby, kBYC);
-      if (face) {
-        float *pp = A.part + ((brick * (ZC + 1) + zl) * (F * 3) + fc) * kNBOX + yl * 17 + xl;
-        *pp = acc ? *pp + val : val;
-      } else {
+      float *pp = A.part + (brick * (ZC + 1) + zl) * (F * 3) * kNBOX + pos;
+      const int64_t node = ((int64_t)pzn * g.py + pyn) * g.px + pxn;
+#pragma unroll
+      for (int fc = 0; fc < F * 3; ++fc) {
         const int f = fc / 3, c = fc - 3 * f;
-        float *o = f == 0 ? A.out0 : A.out1;
-        float *po = o + c * g.nnodes + ((int64_t)pzn * g.py + pyn) * g.px + pxn;
-        *po = acc ? *po + val : val;
+        float val = 0.0f;
+        if (NGF_OUT) {
+          if (yl < 4) {
+            if (xl < 16) val += lds[zl][yl][0][fc][0][xl];
+            if (xl > 0) val += lds[zl][yl][0][fc][1][xl - 1];
+          }
+          if (yl > 0) {
+            if (xl < 16) val += lds[zl][yl - 1][1][fc][0][xl];
+            if (xl > 0) val += lds[zl][yl - 1][1][fc][1][xl - 1];
+          }
+        }
+        if (CELL_OUT) {
+#pragma unroll
+          for (int dk = 0; dk < 2; ++dk)
+#pragma unroll
+            for (int dj = 0; dj < 2; ++dj)
+#pragma unroll
+              for (int di = 0; di < 2; ++di) {
+                // cell (xl-1+di, yl-1+dj, zl-1+dk) touches this node at its corner (1-di, 1-dj, 1-dk)
+                const int ci = xl - 1 + di, cj = yl - 1 + dj, ck = zl - 1 + dk;
+                if (ci < 0 || ci >= 16 || cj < 0 || cj >= 4 || ck < 0 || ck >= nl) continue;
+                const int corner = (1 - di) + 2 * (1 - dj) + 4 * (1 - dk);
+                val += cbuf[f * 24 + corner * 3 + c][ck * 64 + cj * 16 + ci];
+              }
+        }
+        if (face) {
+          float *q = pp + fc * kNBOX;
+          *q = acc ? *q + val : val;
+        } else {
+          float *po = (f == 0 ? A.out0 : A.out1) + c * g.nnodes + node;
+          *po = acc ? *po + val : val;
+        }
       }
     }
   }
