@@ -18,6 +18,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_fp16.h>
+#include <cfloat>
 #include <stdint.h>
 
 namespace disco {
@@ -801,9 +802,10 @@ __device__ __forceinline__ void cell_edges(const float x[2][2][2][3], float hx, 
     for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        e1[t + 2 * r][c] = x[r][t][1][c] - x[r][t][0][c] + (c == 0 ? hx : 0.0f);
-        e2[t + 2 * r][c] = x[r][1][t][c] - x[r][0][t][c] + (c == 1 ? hy : 0.0f);
-        e3[t + 2 * r][c] = x[1][r][t][c] - x[0][r][t][c] + (c == 2 ? hz : 0.0f);
+        // the other components add -0, which x + (-0) = x lets the compiler drop
+        e1[t + 2 * r][c] = x[r][t][1][c] - x[r][t][0][c] + (c == 0 ? hx : -0.0f);
+        e2[t + 2 * r][c] = x[r][1][t][c] - x[r][0][t][c] + (c == 1 ? hy : -0.0f);
+        e3[t + 2 * r][c] = x[1][r][t][c] - x[0][r][t][c] + (c == 2 ? hz : -0.0f);
       }
 }
 
@@ -814,7 +816,7 @@ __device__ __forceinline__ void vcc_cell(const Geo &g, const float u[2][2][2][3]
   float e1[4][3], e2[4][3], e3[4][3];
   cell_edges(u, g.Hx, g.Hy, g.Hz, e1, e2, e3);
   float de1[4][3], de2[4][3], de3[4][3];
-  if (MODE == M_HV) cell_edges(v, 0.0f, 0.0f, 0.0f, de1, de2, de3);
+  if (MODE == M_HV) cell_edges(v, -0.0f, -0.0f, -0.0f, de1, de2, de3);
   const float iC = frcp(g.C);
   float G1[4][3] = {}, G2[4][3] = {}, G3[4][3] = {};  // dVhat/d(edge) or GN product per edge
   float D1[MODE == M_GRAD ? 4 : 1][3] = {}, D2[MODE == M_GRAD ? 4 : 1][3] = {}, D3[MODE == M_GRAD ? 4 : 1][3] = {};
@@ -914,7 +916,7 @@ __device__ __forceinline__ void vcc_cell(const Geo &g, const float u[2][2][2][3]
   }
 }
 
-// GN product of the volume-change term for one cell: out += w C sum_t psi''(d_t)
+// GN product of the volume-change term for one cell: out = w C sum_t psi''(d_t)
 // (grad d_t . v) grad d_t over the 64 coefficients d_abc = det[e1_a, e2_b, e3_c] / C.
 // For fixed (b, c) the cross product x = e2_b x e3_c / C is shared by the four a, and
 // grad d . v = de1_a . x + e1_a . y with y = (de2_b x e3_c + e2_b x de3_c) / C.  The
@@ -925,7 +927,7 @@ __device__ __forceinline__ void vcc_cell_hv(const Geo &g, const float u[2][2][2]
   float e1[4][3], e2[4][3], e3[4][3];
   cell_edges(u, g.Hx, g.Hy, g.Hz, e1, e2, e3);
   float de1[4][3], de2[4][3], de3[4][3];
-  cell_edges(v, 0.0f, 0.0f, 0.0f, de1, de2, de3);
+  cell_edges(v, -0.0f, -0.0f, -0.0f, de1, de2, de3);
   const float iC = frcp(g.C);
   // k = w C psi''(d) (grad d . v) = 2 w C id^3 jv.  The factor w2 = 2 w C is put into the
   // v edges and 1/C into the z edges, so that x = e2 x e3' and y = de2' x e3' + e2 x de3'
@@ -940,7 +942,13 @@ __device__ __forceinline__ void vcc_cell_hv(const Geo &g, const float u[2][2][2]
       de3[a][c] *= w2 * iC;
       e3[a][c] *= iC;
     }
-  float G1[4][3] = {}, G2[4][3] = {}, G3[4][3] = {};  // G3 is accumulated times C
+  // accumulators start at -0, for which x + (-0) = x exactly: the first multiply-add of each
+  // then compiles to a plain multiply (a +0 start costs an extra addition)
+  float G1[4][3], G2[4][3], G3[4][3];  // G3 is accumulated times C
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) G1[a][c] = G2[a][c] = G3[a][c] = -0.0f;
 #pragma unroll
   for (int c3 = 0; c3 < 4; ++c3)
 #pragma unroll
@@ -956,14 +964,17 @@ __device__ __forceinline__ void vcc_cell_hv(const Geo &g, const float u[2][2][2]
         acc = __builtin_fmaf(e2[b][c1], de3[c3][c2], acc);
         y[c] = __builtin_fmaf(-e2[b][c2], de3[c3][c1], acc);
       }
-      float z[3] = {0.0f, 0.0f, 0.0f};
+      float z[3] = {-0.0f, -0.0f, -0.0f};
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
-        const float d = dot3(e1[a], x);
+        // d less the smallest normal float, so that d <= 0 (a fold, whose term does not
+        // count) gives a negative reciprocal and the maximum with zero drops it; for
+        // 0 < d < 1e-13 the cube of 1/d overflows in FP32 either way
+        const float d = __builtin_fmaf(e1[a][2], x[2], __builtin_fmaf(e1[a][1], x[1], __builtin_fmaf(e1[a][0], x[0], -FLT_MIN)));
         float jv = dot3(de1[a], x);
 #pragma unroll
         for (int c = 0; c < 3; ++c) jv = __builtin_fmaf(e1[a][c], y[c], jv);
-        const float id = d > 0.0f ? frcp(d) : 0.0f;  // terms with d <= 0 (a fold) do not count
+        const float id = fmaxf(frcp(d), 0.0f);
         const float k = id * id * id * jv;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -990,8 +1001,8 @@ __device__ __forceinline__ void vcc_cell_hv(const Geo &g, const float u[2][2][2]
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          out[k][j][i][c] += (i ? G1[j + 2 * k][c] : -G1[j + 2 * k][c]) + (j ? G2[i + 2 * k][c] : -G2[i + 2 * k][c]) +
-                             (k ? iC * G3[i + 2 * j][c] : -iC * G3[i + 2 * j][c]);
+          out[k][j][i][c] = (i ? G1[j + 2 * k][c] : -G1[j + 2 * k][c]) + (j ? G2[i + 2 * k][c] : -G2[i + 2 * k][c]) +
+                            (k ? iC * G3[i + 2 * j][c] : -iC * G3[i + 2 * j][c]);
 }
 
 template <int MODE>
@@ -1286,12 +1297,14 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
                     ST::loadp(sp + voff, A.sS_load, s);
                   else
                     ST::unpack(srow[kv][jv], sp + voff, A.sS_load, s);
+                  // moments over the row's voxels: accY[0][0] collects sum w s and accY[0][1]
+                  // sum wy w s; the lower node's share, sum (1 - wy) w s, is their difference
                   const float w = s[0] * f3[0] + s[1] * f3[1] + s[2] * f3[2];
+                  const float ww = wy * w;
     #pragma unroll
                   for (int c = 0; c < 3; ++c) {
-                    const float t = w * s[c];
-                    accY[0][0][c] += (1.0f - wy) * t;
-                    accY[0][1][c] += wy * t;
+                    accY[0][0][c] = __builtin_fmaf(w, s[c], accY[0][0][c]);
+                    accY[0][1][c] = __builtin_fmaf(ww, s[c], accY[0][1][c]);
                   }
                   if constexpr (MASK) {
                     // boundary term: only rows that touch the mask boundary carry vectors; the
@@ -1301,11 +1314,11 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
                     const float *bp = fl ? A.sbc + (vbase + kv * nxy + jv * g.nx) * 3 : A.zb + lane * 3;
                     const float sb[3] = {bp[0], bp[1], bp[2]};
                     const float wb = sb[0] * f3[0] + sb[1] * f3[1] + sb[2] * f3[2];
+                    const float wwb = wy * wb;
     #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                      const float t = wb * sb[c];
-                      accY[0][0][c] += (1.0f - wy) * t;
-                      accY[0][1][c] += wy * t;
+                      accY[0][0][c] = __builtin_fmaf(wb, sb[c], accY[0][0][c]);
+                      accY[0][1][c] = __builtin_fmaf(wwb, sb[c], accY[0][1][c]);
                     }
                   }
                 } else {
@@ -1384,6 +1397,10 @@ __device__ __forceinline__ void brick_body(const BrickArgs<ST> &A, const Blk &B,
                     }
                   }
                 }
+              }
+              if constexpr (MODE == M_HV) {
+    #pragma unroll
+                for (int c = 0; c < 3; ++c) accY[0][0][c] -= accY[0][1][c];
               }
               if (F > 0) {
     #pragma unroll
