@@ -1434,14 +1434,21 @@ int ngf_grad_T(disco_ctx *c, double eta, const float *u, float *dT, disco_stream
   ProfScope ps(c, 4, s);
   hipLaunchKernelGGL(k_fill, dim3(nblk(3 * g.nvox)), dim3(256), 0, s, 3 * g.nvox, c->adjW, 0.0f);
   const float h3x2 = (float)(2.0 * h3_of(c));
+  // tiles of kAdjTX x kAdjTY x kAdjTZ voxels; fixed-point scale of the LDS box (the
+  // kernel's header derives the bound; no scale when eta = 0)
+  const dim3 adj_grid((g.nx + kAdjTX - 1) / kAdjTX, (g.ny + kAdjTY - 1) / kAdjTY, (g.nz + kAdjTZ - 1) / kAdjTZ);
+  const double wbound = eta > 0.0 ? 2.0 * (double)h3x2 / eta : 0.0;
+  double qs = wbound > 0.0 ? std::ldexp(1.0, 62) / (1.01 * kAdjTX * kAdjTY * kAdjTZ * wbound) : 0.0;
+  if (!(qs > 0.0 && qs < 1e38 && 1.0 / qs > 1e-38)) qs = 0.0;
+  const float fqs = (float)qs, fiqs = qs > 0.0 ? (float)(1.0 / qs) : 0.0f;
   if (c->storage == DISCO_STORAGE_FP16)
-    hipLaunchKernelGGL(k_adjT_scatter<F16x3>, vox_grid(g), dim3(256), 0, s, g,
+    hipLaunchKernelGGL(k_adjT_scatter<F16x3>, adj_grid, dim3(256), 0, s, g,
                        reinterpret_cast<const __half *>(c->gR), reinterpret_cast<const __half *>(c->gT), c->sR, c->sT,
-                       u, (float)(eta * eta), h3x2, c->adjW);
+                       u, (float)(eta * eta), h3x2, fqs, fiqs, c->adjW);
   else
-    hipLaunchKernelGGL(k_adjT_scatter<F32x3>, vox_grid(g), dim3(256), 0, s, g,
+    hipLaunchKernelGGL(k_adjT_scatter<F32x3>, adj_grid, dim3(256), 0, s, g,
                        reinterpret_cast<const float *>(c->gR), reinterpret_cast<const float *>(c->gT), 1.0f, 1.0f, u,
-                       (float)(eta * eta), h3x2, c->adjW);
+                       (float)(eta * eta), h3x2, fqs, fiqs, c->adjW);
   hipLaunchKernelGGL(k_adjT_stencil, vox_grid(g), dim3(256), 0, s, g, c->adjW, dT);
   HIP_TRY(hipGetLastError());
   return DISCO_OK;

@@ -60,6 +60,29 @@ def test_ngf_grad_T_matches_oracle(mods, shape, spacing, seed, storage):
     check_field("dD/dT", dT, ref, None, 1e-4 if storage == "fp32" else 2e-2)
 
 
+@pytest.mark.parametrize("amp", [0.3, 12.0])
+def test_ngf_grad_T_field_strength(mods, amp):
+    """dD/dT under node displacements drawn uniformly in +-amp voxels.  With amp = 0.3 the
+    sample corners of a 16 x 4 x 8 voxel tile fit the kernel's LDS box (at most 18 x 6 x 10
+    of its 1600 points) and are added there in fixed point; with amp = 12 the box of most
+    tiles spans tens of voxels in every axis (far over 1600 points) and the voxels add their
+    corners to the field directly."""
+    disco, _ = mods
+    say(f"[grad_T] random node field +-{amp} voxels")
+    shape, spacing = (76, 36, 28), (1.2, 1.4, 2.2)
+    d = synth.small_pair(shape=shape, spacing=spacing, seed=33, n_tubes=8, n_kp=10, field_max=4.0)
+    rng = np.random.default_rng(3300 + int(amp))
+    u = (rng.uniform(-amp, amp, size=d["u_true"].shape)
+         * np.asarray(spacing, np.float64)[:, None, None, None]).astype(np.float32)
+    ctx = disco.Disco(d["shape"], d["spacing"], device=DEV)
+    ctx.set_images(torch.from_numpy(d["R"]).to(DEV), torch.from_numpy(d["T"]).to(DEV))
+    dT = ctx.ngf_grad_T(torch.from_numpy(u).to(DEV), ETA).cpu().numpy()
+    gR = oracle.image_gradient(d["R"], d["spacing"])
+    gT = oracle.image_gradient(d["T"], d["spacing"])
+    ref = oracle.ngf_grad_T(gR, gT, d["spacing"], ETA, u.astype(np.float64))
+    check_field("dD/dT", dT, ref, None, 1e-4)
+
+
 def test_ngf_loss_matches_oracle_small(mods):
     disco, loss = mods
     say("[NGFLoss small]")
