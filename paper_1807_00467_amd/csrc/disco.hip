@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/disco.h: context and workspace
 // management, argument validation, kernel launches on the caller's stream.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cmath>
@@ -162,24 +163,54 @@ inline size_t image_tiles(const Geo &g) {
   return (size_t)t.x * t.y * t.z;
 }
 
+// event stamps of a profiled brick pass, taken by the kernels' own dispatches (as a kernel
+// trace records them, without the event packets' own dispatch): the first kernel of the
+// pass stamps its start, the last one its end
+struct Stamp {
+  hipEvent_t a = nullptr, b = nullptr;
+  bool first = true;  // no kernel launched yet
+};
+
+template <class K, class A>
+void brick_go(K kernel, dim3 grid, dim3 block, hipStream_t s, Stamp *st, bool last, const A &a) {
+  if (st && st->a) {
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, st->first ? st->a : nullptr, last ? st->b : nullptr, 0u, a);
+    st->first = false;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, a);
+  }
+}
+
+// times one pass of kind k while profiling is on: with a Stamp, by the kernels' own
+// dispatch stamps; otherwise by events recorded around the pass on its stream
 struct ProfScope {
   disco_ctx *c;
   int k;
   hipStream_t s;
+  Stamp *st;
   EventPair e{};
   bool on;
-  ProfScope(disco_ctx *c_, int k_, hipStream_t s_) : c(c_), k(k_), s(s_), on(c_->prof) {
+  ProfScope(disco_ctx *c_, int k_, hipStream_t s_, Stamp *st_ = nullptr) : c(c_), k(k_), s(s_), st(st_), on(c_->prof) {
     if (on) {
       (void)hipEventCreate(&e.a);
       (void)hipEventCreate(&e.b);
-      (void)hipEventRecord(e.a, s);
+      if (st) {
+        st->a = e.a;
+        st->b = e.b;
+      } else {
+        (void)hipEventRecord(e.a, s);
+      }
     }
   }
   ~ProfScope() {
-    if (on) {
-      (void)hipEventRecord(e.b, s);
-      c->ev[k].push_back(e);
+    if (!on) return;
+    if (st && st->first) {  // the pass launched nothing
+      (void)hipEventDestroy(e.a);
+      (void)hipEventDestroy(e.b);
+      return;
     }
+    if (!st) (void)hipEventRecord(e.b, s);
+    c->ev[k].push_back(e);
   }
 };
 
@@ -198,45 +229,45 @@ void clear_profile(disco_ctx *c) {
 // ------------------------------------------------------------------------------
 template <class ST, int MODE>
 void launch_brick_mode(disco_ctx *c, bool ngf, bool vcc, bool kp, bool mask, const BrickArgs<ST> &a,
-                       hipStream_t s) {
+                       hipStream_t s, Stamp *st = nullptr, bool last = true) {
   dim3 grid(c->g.nbx, c->g.nby, c->g.nbz);
   const int key = (ngf ? 4 : 0) | (vcc ? 2 : 0) | (kp ? 1 : 0);
   if (MODE != M_HV && ngf && (vcc || kp)) {
     // objective and gradient passes: the cell terms (VALU-heavy, many registers) and the
     // NGF voxel pass (memory-bound) run as two launches with their own occupancy; the
     // second adds to the outputs of the first
-    launch_brick_mode<ST, MODE>(c, false, vcc, kp, false, a, s);
+    launch_brick_mode<ST, MODE>(c, false, vcc, kp, false, a, s, st, false);
     BrickArgs<ST> b = a;
     b.acc = 1;
     if (mask)
-      hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC, true>), grid, dim3(brick_threads<MODE, true, false>()), 0, s, b);
+      brick_go((k_brick<ST, MODE, true, false, false, kZC, true>), grid, dim3(brick_threads<MODE, true, false>()), s, st, last, b);
     else
-      hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(brick_threads<MODE, true, false>()), 0, s, b);
+      brick_go((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(brick_threads<MODE, true, false>()), s, st, last, b);
     return;
   }
   if (mask && ngf) {
     // the lung-boundary term rides on the voxel pass
     switch (key) {
-      case 7: if constexpr (MODE == M_HV) { hipLaunchKernelGGL((k_brick<ST, MODE, true, true, true, kZC, true>), grid, dim3(brick_threads<MODE, true, true>()), 0, s, a); return; } break;
-      case 6: if constexpr (MODE == M_HV) { hipLaunchKernelGGL((k_brick<ST, MODE, true, true, false, kZC, true>), grid, dim3(brick_threads<MODE, true, true>()), 0, s, a); return; } break;
-      case 5: if constexpr (MODE == M_HV) { hipLaunchKernelGGL((k_brick<ST, MODE, true, false, true, kZC, true>), grid, dim3(brick_threads<MODE, true, true>()), 0, s, a); return; } break;
-      case 4: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC, true>), grid, dim3(brick_threads<MODE, true, false>()), 0, s, a); return;
+      case 7: if constexpr (MODE == M_HV) { brick_go((k_brick<ST, MODE, true, true, true, kZC, true>), grid, dim3(brick_threads<MODE, true, true>()), s, st, last, a); return; } break;
+      case 6: if constexpr (MODE == M_HV) { brick_go((k_brick<ST, MODE, true, true, false, kZC, true>), grid, dim3(brick_threads<MODE, true, true>()), s, st, last, a); return; } break;
+      case 5: if constexpr (MODE == M_HV) { brick_go((k_brick<ST, MODE, true, false, true, kZC, true>), grid, dim3(brick_threads<MODE, true, true>()), s, st, last, a); return; } break;
+      case 4: brick_go((k_brick<ST, MODE, true, false, false, kZC, true>), grid, dim3(brick_threads<MODE, true, false>()), s, st, last, a); return;
       default: break;
     }
   }
   if constexpr (MODE == M_HV) {
     switch (key) {
-      case 7: hipLaunchKernelGGL((k_brick<ST, MODE, true, true, true, kZC>), grid, dim3(brick_threads<MODE, true, true || true>()), 0, s, a); return;
-      case 6: hipLaunchKernelGGL((k_brick<ST, MODE, true, true, false, kZC>), grid, dim3(brick_threads<MODE, true, true || false>()), 0, s, a); return;
-      case 5: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, true, kZC>), grid, dim3(brick_threads<MODE, true, false || true>()), 0, s, a); return;
+      case 7: brick_go((k_brick<ST, MODE, true, true, true, kZC>), grid, dim3(brick_threads<MODE, true, true || true>()), s, st, last, a); return;
+      case 6: brick_go((k_brick<ST, MODE, true, true, false, kZC>), grid, dim3(brick_threads<MODE, true, true || false>()), s, st, last, a); return;
+      case 5: brick_go((k_brick<ST, MODE, true, false, true, kZC>), grid, dim3(brick_threads<MODE, true, false || true>()), s, st, last, a); return;
       default: break;
     }
   }
   switch (key) {
-    case 4: hipLaunchKernelGGL((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(brick_threads<MODE, true, false || false>()), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_brick<ST, MODE, false, true, true, kZC>), grid, dim3(brick_threads<MODE, false, true || true>()), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_brick<ST, MODE, false, true, false, kZC>), grid, dim3(brick_threads<MODE, false, true || false>()), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_brick<ST, MODE, false, false, true, kZC>), grid, dim3(brick_threads<MODE, false, false || true>()), 0, s, a); break;
+    case 4: brick_go((k_brick<ST, MODE, true, false, false, kZC>), grid, dim3(brick_threads<MODE, true, false || false>()), s, st, last, a); break;
+    case 3: brick_go((k_brick<ST, MODE, false, true, true, kZC>), grid, dim3(brick_threads<MODE, false, true || true>()), s, st, last, a); break;
+    case 2: brick_go((k_brick<ST, MODE, false, true, false, kZC>), grid, dim3(brick_threads<MODE, false, true || false>()), s, st, last, a); break;
+    case 1: brick_go((k_brick<ST, MODE, false, false, true, kZC>), grid, dim3(brick_threads<MODE, false, false || true>()), s, st, last, a); break;
     default: break;
   }
 }
@@ -289,18 +320,20 @@ BrickArgs<ST> make_args(disco_ctx *c, const BrickCall &b) {
 
 void launch_brick(disco_ctx *c, const BrickCall &b, hipStream_t s) {
   const int pk = b.mode == M_HV ? 0 : (b.mode == M_GRAD ? 1 : 2);
-  ProfScope ps(c, pk, s);
+  Stamp st;
+  ProfScope ps(c, pk, s, &st);
+  Stamp *sp = c->prof ? &st : nullptr;
   const bool mask = b.ngf && b.beta != 0.0 && c->masks;
   if (c->storage == DISCO_STORAGE_FP16) {
     auto a = make_args<F16x3>(c, b);
-    if (b.mode == M_EVAL) launch_brick_mode<F16x3, M_EVAL>(c, b.ngf, b.vcc, b.kp, mask, a, s);
-    if (b.mode == M_GRAD) launch_brick_mode<F16x3, M_GRAD>(c, b.ngf, b.vcc, b.kp, mask, a, s);
-    if (b.mode == M_HV) launch_brick_mode<F16x3, M_HV>(c, b.ngf, b.vcc, b.kp, mask, a, s);
+    if (b.mode == M_EVAL) launch_brick_mode<F16x3, M_EVAL>(c, b.ngf, b.vcc, b.kp, mask, a, s, sp);
+    if (b.mode == M_GRAD) launch_brick_mode<F16x3, M_GRAD>(c, b.ngf, b.vcc, b.kp, mask, a, s, sp);
+    if (b.mode == M_HV) launch_brick_mode<F16x3, M_HV>(c, b.ngf, b.vcc, b.kp, mask, a, s, sp);
   } else {
     auto a = make_args<F32x3>(c, b);
-    if (b.mode == M_EVAL) launch_brick_mode<F32x3, M_EVAL>(c, b.ngf, b.vcc, b.kp, mask, a, s);
-    if (b.mode == M_GRAD) launch_brick_mode<F32x3, M_GRAD>(c, b.ngf, b.vcc, b.kp, mask, a, s);
-    if (b.mode == M_HV) launch_brick_mode<F32x3, M_HV>(c, b.ngf, b.vcc, b.kp, mask, a, s);
+    if (b.mode == M_EVAL) launch_brick_mode<F32x3, M_EVAL>(c, b.ngf, b.vcc, b.kp, mask, a, s, sp);
+    if (b.mode == M_GRAD) launch_brick_mode<F32x3, M_GRAD>(c, b.ngf, b.vcc, b.kp, mask, a, s, sp);
+    if (b.mode == M_HV) launch_brick_mode<F32x3, M_HV>(c, b.ngf, b.vcc, b.kp, mask, a, s, sp);
   }
 }
 
