@@ -205,11 +205,14 @@ int objective_linearise(disco_ctx *ctx, const disco_params *p, const float *u, d
 int objective_eval(disco_ctx *ctx, const disco_params *p, const float *u, double *terms_dev, disco_stream stream);
 
 /* Derivative of the NGF distance of eq. 1 with respect to the moving image values at
-   displacement u: dT (device float32 [Nz][Ny][Nx]) = dD/dT, through the trilinear
-   sampling of grad T and its central-difference stencil.  The scatter to warped
-   positions uses float atomics, so the last bits of dT may differ between runs.  Needs
+   displacement u: dT (device float32 [Nz][Ny][Nx]) = scale * dD/dT, through the
+   trilinear sampling of grad T and its central-difference stencil.  scale_dev (nullable:
+   1) is one device double read by the kernels, so that a caller's upstream gradient
+   needs no host round trip and no extra pass.  The scatter to warped positions adds to
+   the field with float atomics, so the last bits of dT may differ between runs.  Needs
    images set; allocates a [N][3] float32 work volume on the first call. */
-int ngf_grad_T(disco_ctx *ctx, double eta, const float *u, float *dT, disco_stream stream);
+int ngf_grad_T(disco_ctx *ctx, double eta, const float *u, const double *scale_dev, float *dT,
+               disco_stream stream);
 
 /* Curvature term of eq. 5 with weight alpha: w = u - u_ref (u_ref nullable: 0),
    *S_dev = alpha S(u) (nullable), out = alpha C_H L^T L w (the gradient; nullable),

@@ -256,8 +256,9 @@ __global__ __launch_bounds__(256) void k_adjT_scatter(Geo g, const typename ST::
   }
 }
 
-// dT = transpose of (grad I)_a[i] = (I[clamp(i+e_a)] - I[clamp(i-e_a)]) / (2 h_a) applied to W
-__global__ __launch_bounds__(256) void k_adjT_stencil(Geo g, const float *W, float *dT) {
+// dT = transpose of (grad I)_a[i] = (I[clamp(i+e_a)] - I[clamp(i-e_a)]) / (2 h_a) applied to W,
+// times *scale when given
+__global__ __launch_bounds__(256) void k_adjT_stencil(Geo g, const float *W, const double *scale, float *dT) {
   const int i = blockIdx.x * 256 + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
   if (i >= g.nx) return;
   const int64_t v = ((int64_t)k * g.ny + j) * g.nx + i;
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(256) void k_adjT_stencil(Geo g, const float *W, flo
     if (idx[a] == 0) s -= Wa[v];                 // replicated border: i's "-" neighbour is i itself
     acc += s * ih2[a];
   }
-  dT[v] = acc;
+  dT[v] = scale ? (float)((double)acc * *scale) : acc;
 }
 
 }  // namespace disco

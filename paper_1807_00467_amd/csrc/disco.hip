@@ -1448,7 +1448,7 @@ int objective_eval(disco_ctx *c, const disco_params *p, const float *u, double *
   return DISCO_OK;
 }
 
-int ngf_grad_T(disco_ctx *c, double eta, const float *u, float *dT, disco_stream stream) {
+int ngf_grad_T(disco_ctx *c, double eta, const float *u, const double *scale, float *dT, disco_stream stream) {
   if (!c) return DISCO_ERR_ARG;
   int e;
   if ((e = check_field(u)) || (e = check_field(dT))) return e;
@@ -1482,7 +1482,7 @@ int ngf_grad_T(disco_ctx *c, double eta, const float *u, float *dT, disco_stream
     hipLaunchKernelGGL(k_adjT_scatter<F32x3>, adj_grid, dim3(256), 0, s, g,
                        reinterpret_cast<const float *>(c->gR), reinterpret_cast<const float *>(c->gT), 1.0f, 1.0f, u,
                        (float)(eta * eta), h3x2, fqs, fiqs, c->adjW);
-  hipLaunchKernelGGL(k_adjT_stencil, vox_grid(g), dim3(256), 0, s, g, c->adjW, dT);
+  hipLaunchKernelGGL(k_adjT_stencil, vox_grid(g), dim3(256), 0, s, g, c->adjW, scale, dT);
   HIP_TRY(hipGetLastError());
   return DISCO_OK;
 }

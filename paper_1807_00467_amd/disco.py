@@ -79,7 +79,7 @@ _SIGS = {
     "ngf_eval": ([_P, _D, _P, _P, _P], ctypes.c_int),
     "ngf_grad": ([_P, _D, _P, _P, _P, _P, _P], ctypes.c_int),
     "ngf_hessvec": ([_P, _P, _P, _P], ctypes.c_int),
-    "ngf_grad_T": ([_P, _D, _P, _P, _P], ctypes.c_int),
+    "ngf_grad_T": ([_P, _D, _P, _P, _P, _P], ctypes.c_int),
     "curvature_apply": ([_P, _D, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "volchange_eval": ([_P, _D, _P, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
     "keypoint_penalty": ([_P, _D, _P, _P, _P, _P, _P, _P, _P], ctypes.c_int),
@@ -343,12 +343,22 @@ class Disco:
         _check(_lib.ngf_hessvec(self._h, _ptr(self._field(v, "v")), _ptr(out), self._stream()), "ngf_hessvec")
         return out
 
-    def ngf_grad_T(self, u: torch.Tensor, eta: float, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-        """dD/dT at displacement u (volume [Nz][Ny][Nx], into `out` when given)."""
+    def ngf_grad_T(self, u: torch.Tensor, eta: float, out: Optional[torch.Tensor] = None,
+                   scale: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """scale * dD/dT at displacement u (volume [Nz][Ny][Nx], into `out` when given);
+        scale (optional) is a one-element float64 tensor on the context's device, read by the
+        kernels (an upstream gradient, without a host round trip)."""
         nx, ny, nz = self.shape
         out = torch.empty((nz, ny, nx), dtype=torch.float32, device=self.device) if out is None \
             else self._volume(out, "out")
-        _check(_lib.ngf_grad_T(self._h, eta, _ptr(self._field(u, "u")), _ptr(out), self._stream()), "ngf_grad_T")
+        sp = None
+        if scale is not None:
+            if scale.dtype != torch.float64 or scale.numel() != 1 or scale.device != self.device:
+                raise ValueError("scale must be a one-element float64 tensor on the context's device")
+            scale = scale.contiguous()
+            sp = _ptr(scale)
+        _check(_lib.ngf_grad_T(self._h, eta, _ptr(self._field(u, "u")), sp, _ptr(out), self._stream()),
+               "ngf_grad_T")
         return out
 
     def curvature_apply(self, alpha: float, u: torch.Tensor, u_ref: Optional[torch.Tensor] = None,

@@ -54,7 +54,8 @@ class NGFLossFn(torch.autograd.Function):
         if need_u:
             gu = ctx.objective_linearise(params, u, grad=True, diag=False, terms=False)["g"] * grad_out
         if need_T:
-            gT = ctx.ngf_grad_T(u, params.eta) * grad_out
+            # the upstream gradient scales dL/dT inside the stencil pass
+            gT = ctx.ngf_grad_T(u, params.eta, scale=grad_out.detach().to(device=u.device, dtype=torch.float64).reshape(1))
         return gu, gT, None, None, None, None, None
 
 
@@ -91,16 +92,16 @@ class NGFLossBatchFn(torch.autograd.Function):
         need_u, need_T = fctx.needs_input_grad[0], fctx.needs_input_grad[1]
         gu = torch.empty_like(u) if need_u else None
         gT = torch.empty_like(T) if need_T else None
+        scale = grad_out.detach().to(device=u.device, dtype=torch.float64).reshape(1)
         for b, (ctx, R) in enumerate(zip(fctx.ctxs, Rs)):
             ctx.use_images(R, T[b])
             if need_u:
                 ctx.objective_linearise(params, u[b], grad=True, diag=False, terms=False, g_out=gu[b])
             if need_T:
-                ctx.ngf_grad_T(u[b], params.eta, out=gT[b])
+                # the upstream gradient scales dL/dT inside the stencil pass
+                ctx.ngf_grad_T(u[b], params.eta, out=gT[b], scale=scale)
         if need_u:
             gu.mul_(grad_out)
-        if need_T:
-            gT.mul_(grad_out)
         return gu, gT, None, None, None, None, None
 
 

@@ -260,3 +260,28 @@ def test_ngf_loss_module_batch_of_pairs(mods):
         check_field(f"dL/du pair {b}", u.grad[b], gu, ties["g"], 1e-4)
         check_field(f"dL/dT pair {b}", T.grad[b], gT, None, 1e-4)
     assert abs(L.item() - Js) / abs(Js) < 1e-5
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_ngf_loss_upstream_gradient(mods, batched):
+    """A non-unit upstream gradient (L scaled by -2.5 before backward): dL/du and dL/dT are
+    the oracle's times -2.5 (dL/dT takes the factor inside its stencil pass)."""
+    disco, loss = mods
+    say(f"[NGFLoss upstream gradient, batched={batched}]")
+    k = -2.5
+    pairs = [synth.small_pair(shape=(32, 24, 20), spacing=(1.5, 1.5, 2.0), seed=50 + b, n_tubes=8, n_kp=10,
+                              field_max=4.0) for b in range(2 if batched else 1)]
+    shape, spacing = pairs[0]["shape"], pairs[0]["spacing"]
+    Rs = [torch.from_numpy(p["R"]).to(DEV) for p in pairs]
+    u = torch.stack([torch.from_numpy(p["u_true"]) for p in pairs]).to(DEV).requires_grad_(True)
+    T = torch.stack([torch.from_numpy(p["T"]) for p in pairs]).to(DEV).requires_grad_(True)
+    if batched:
+        L = loss.NGFLoss(shape, spacing, Rs, eta=ETA, alpha=ALPHA, gamma=GAMMA)(u, T)
+    else:
+        ctx = disco.Disco(shape, spacing, device=DEV)
+        L = loss.ngf_loss(ctx, u[0], T[0], Rs[0], ETA, ALPHA, GAMMA)
+    (k * L).backward()
+    for b, p in enumerate(pairs):
+        J, gu, gT, ties = oracle_loss_grads(p, p["u_true"].astype(np.float64))
+        check_field(f"dL/du pair {b}", u.grad[b], k * gu, abs(k) * ties["g"], 1e-4)
+        check_field(f"dL/dT pair {b}", T.grad[b], k * gT, None, 1e-4)
