@@ -81,6 +81,20 @@ __global__ __launch_bounds__(256, 1) void k_b_brick(const PairDesc<ST> *D,
   }
 }
 
+// GN product pass with one workgroup per work item in the role split of the single-pair
+// kernel (four waves stream the voxels, four compute the cell terms): 8-wave workgroups
+// that fit two to a compute unit.  The same brick body, so the same sums as k_b_brick.
+template <class ST, bool VCC, bool KP, int ZC>
+__global__ __launch_bounds__(512) void k_b_brick_split(const PairDesc<ST> *D, const int *start, int npairs, int sel,
+                                                      int acc) {
+  const int item = blockIdx.x;
+  if (item >= start[npairs]) return;
+  const int pr = find_pair(start, npairs, item);
+  const PairDesc<ST> &P = D[pr];
+  const BrickArgs<ST> &A = P.hv[sel - 1];
+  brick_body<ST, M_HV, true, VCC, KP, ZC, false, false>(A, grid_blk(item - start[pr], A.g.nbx, A.g.nby), acc);
+}
+
 // ---- node-parallel passes -----------------------------------------------------------
 // sel: 0 = after linearisation, 1/2 = after the product with p[0]/p[1]; ZC as in k_b_brick
 template <class ST, int F, int NF, bool CURV, int ZC>

@@ -1721,6 +1721,15 @@ template <class ST, int MODE, bool NGF, bool VCC, bool KP>
 static void b_brick_go(disco_batch *b, unsigned grid, const PairDesc<ST> *D, const int *st, int n, int sel, int acc,
                        hipStream_t s) {
   constexpr int threads = 256;
+  if constexpr (MODE == M_HV && NGF && (VCC || KP)) {
+    if (b->wpc[0] == 0) {  // one workgroup per item (grid = the items): the role-split product pass
+      if (b->zc == 2)
+        hipLaunchKernelGGL((k_b_brick_split<ST, VCC, KP, 2>), dim3(grid), dim3(512), 0, s, D, st, n, sel, acc);
+      else
+        hipLaunchKernelGGL((k_b_brick_split<ST, VCC, KP, 4>), dim3(grid), dim3(512), 0, s, D, st, n, sel, acc);
+      return;
+    }
+  }
   if (b->zc == 2) {
     const unsigned gr = b_cap(b, 0, k_b_brick<ST, MODE, NGF, VCC, KP, 2>, threads, grid);
     hipLaunchKernelGGL((k_b_brick<ST, MODE, NGF, VCC, KP, 2>), dim3(gr), dim3(threads), 0, s, D, st, n, sel, acc);
