@@ -81,6 +81,19 @@ __global__ __launch_bounds__(256, 1) void k_b_brick(const PairDesc<ST> *D,
   }
 }
 
+// A brick pass with one workgroup per work item (grid = the items): the same body as
+// k_b_brick without its work-item loop, whose addressing costs registers.
+template <class ST, int MODE, bool NGF, bool VCC, bool KP, int ZC>
+__global__ __launch_bounds__(256, (MODE == M_EVAL && NGF) ? 4 : 1) void k_b_brick_item(const PairDesc<ST> *D, const int *start, int npairs, int sel,
+                                                     int acc) {
+  const int item = blockIdx.x;
+  if (item >= start[npairs]) return;
+  const int pr = find_pair(start, npairs, item);
+  const PairDesc<ST> &P = D[pr];
+  const BrickArgs<ST> &A = sel == 0 ? P.lin : (sel == 3 ? P.eval : P.hv[sel - 1]);
+  brick_body<ST, MODE, NGF, VCC, KP, ZC, false, true>(A, grid_blk(item - start[pr], A.g.nbx, A.g.nby), acc);
+}
+
 // GN product pass with one workgroup per work item in the role split of the single-pair
 // kernel (four waves stream the voxels, four compute the cell terms): 8-wave workgroups
 // that fit two to a compute unit.  The same brick body, so the same sums as k_b_brick.

@@ -1730,6 +1730,13 @@ static void b_brick_go(disco_batch *b, unsigned grid, const PairDesc<ST> *D, con
       return;
     }
   }
+  if (b->wpc[0] == 0) {  // one workgroup per item (grid = the items): no work-item loop
+    if (b->zc == 2)
+      hipLaunchKernelGGL((k_b_brick_item<ST, MODE, NGF, VCC, KP, 2>), dim3(grid), dim3(threads), 0, s, D, st, n, sel, acc);
+    else
+      hipLaunchKernelGGL((k_b_brick_item<ST, MODE, NGF, VCC, KP, 4>), dim3(grid), dim3(threads), 0, s, D, st, n, sel, acc);
+    return;
+  }
   if (b->zc == 2) {
     const unsigned gr = b_cap(b, 0, k_b_brick<ST, MODE, NGF, VCC, KP, 2>, threads, grid);
     hipLaunchKernelGGL((k_b_brick<ST, MODE, NGF, VCC, KP, 2>), dim3(gr), dim3(threads), 0, s, D, st, n, sel, acc);
